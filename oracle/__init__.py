@@ -1,0 +1,281 @@
+"""Reference oracle for Partial Neighbor Search sampling (TEST INFRASTRUCTURE).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path never imports it and
+shares no code with it.
+
+``pns_oracle.c`` holds the plain single-threaded FP64/int64 chain simulation
+(Rejection-Free Alg 2, Basic PNS Alg 3, Unbiased PNS Alg 6 on the QUBO target
+of Sec 4) and its own Philox4x32-10; this module loads it with ctypes and
+``exact.py`` holds the enumeration-based exact laws used as pins.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pns_oracle.c")
+_LIB = os.path.join(_HERE, "_pns_oracle.so")
+
+MODE_RF = 0
+MODE_BASIC = 1
+MODE_UNBIASED_SYS = 2
+MODE_UNBIASED_RAND = 3
+LAYOUT_SYMMETRIC = 0
+LAYOUT_UPPER = 1
+STAY = -1
+
+
+def load_mutant(replacements, workdir: str) -> ctypes.CDLL:
+    """Compile a copy of the oracle with textual replacements applied (used by
+    tests that plant a mistake in the oracle to show a pin catches it)."""
+    src = open(_SRC).read()
+    for old, new in replacements:
+        if old not in src:
+            raise ValueError(f"mutation anchor not found: {old!r}")
+        src = src.replace(old, new, 1)
+    cpath = os.path.join(workdir, "mutant.c")
+    so = os.path.join(workdir, "mutant.so")
+    with open(cpath, "w") as f:
+        f.write(src)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", so, cpath, "-lm"])
+    L = ctypes.CDLL(so)
+    _declare(L)
+    return L
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE semantics: no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+class _RunArgs(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int32), ("is_int", ctypes.c_int32), ("layout", ctypes.c_int32),
+        ("Qi", ctypes.c_void_p), ("Qf", ctypes.c_void_p),
+        ("mode", ctypes.c_int32), ("n", ctypes.c_int32), ("L0", ctypes.c_int64),
+        ("seed", ctypes.c_uint64),
+        ("num_chains", ctypes.c_int32), ("chain_ids", ctypes.c_void_p), ("betas", ctypes.c_void_p),
+        ("x0", ctypes.c_void_p), ("K", ctypes.c_int64), ("step0", ctypes.c_int64),
+        ("log_action", ctypes.c_void_p), ("log_M", ctypes.c_void_p), ("log_Ei", ctypes.c_void_p),
+        ("log_Ef", ctypes.c_void_p), ("log_p", ctypes.c_void_p), ("log_q", ctypes.c_void_p),
+        ("log_tmargin", ctypes.c_void_p),
+        ("x_final", ctypes.c_void_p), ("hi_final", ctypes.c_void_p), ("hf_final", ctypes.c_void_p),
+        ("Ei_final", ctypes.c_void_p), ("Ef_final", ctypes.c_void_p), ("L_final", ctypes.c_void_p),
+        ("sub_final", ctypes.c_void_p),
+        ("hist_w", ctypes.c_void_p), ("hist_v", ctypes.c_void_p), ("hist_from", ctypes.c_int64),
+        ("n_flips", ctypes.c_void_p), ("n_stays", ctypes.c_void_p), ("n_saturated", ctypes.c_void_p),
+    ]
+
+
+def _declare(L: ctypes.CDLL) -> None:
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    L.orc_philox4x32_10.restype = None
+    L.orc_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.orc_uniforms.restype = None
+    L.orc_random_subset.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    L.orc_random_subset.restype = None
+    L.orc_sys_subset.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p]
+    L.orc_sys_subset.restype = None
+    L.orc_sys_count.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.orc_sys_count.restype = ctypes.c_int64
+    L.orc_random_state.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p]
+    L.orc_random_state.restype = None
+    L.orc_energy_i.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    L.orc_energy_i.restype = ctypes.c_int64
+    L.orc_energy_f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    L.orc_energy_f.restype = ctypes.c_double
+    L.orc_run.argtypes = [ctypes.POINTER(_RunArgs)]
+    L.orc_run.restype = ctypes.c_int
+    L.orc_enumerate_energies_i.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    L.orc_enumerate_energies_i.restype = ctypes.c_int
+    L.orc_enumerate_energies_f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    L.orc_enumerate_energies_f.restype = ctypes.c_int
+    L.orc_basic_onestep.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    L.orc_basic_onestep.restype = ctypes.c_int
+
+
+def _ptr(a: Optional[np.ndarray]) -> Optional[int]:
+    return None if a is None else a.ctypes.data
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def uniforms(seed: int, chain: int, step: int):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib().orc_uniforms(seed, chain, step, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def random_subset(seed: int, chain: int, step: int, N: int, n: int) -> np.ndarray:
+    m = np.zeros(N, dtype=np.uint8)
+    lib().orc_random_subset(seed, chain, step, N, n, m.ctypes.data)
+    return m.astype(bool)
+
+
+def sys_subset(N: int, n: int, i: int) -> np.ndarray:
+    m = np.zeros(N, dtype=np.uint8)
+    lib().orc_sys_subset(N, n, i, m.ctypes.data)
+    return m.astype(bool)
+
+
+def sys_count(N: int, n: int) -> int:
+    return int(lib().orc_sys_count(N, n))
+
+
+def random_state(seed: int, chain: int, N: int) -> np.ndarray:
+    x = np.zeros(N, dtype=np.uint8)
+    lib().orc_random_state(seed, chain, N, x.ctypes.data)
+    return x
+
+
+def _as_q(Q: np.ndarray):
+    Q = np.asarray(Q)
+    if np.issubdtype(Q.dtype, np.integer):
+        return 1, np.ascontiguousarray(Q, dtype=np.int64)
+    return 0, np.ascontiguousarray(Q, dtype=np.float64)
+
+
+def energy(Q: np.ndarray, x: np.ndarray, layout: int = LAYOUT_SYMMETRIC):
+    is_int, Qc = _as_q(Q)
+    xc = np.ascontiguousarray(x, dtype=np.uint8)
+    if is_int:
+        return int(lib().orc_energy_i(Qc.ctypes.data, Qc.shape[0], layout, xc.ctypes.data))
+    return float(lib().orc_energy_f(Qc.ctypes.data, Qc.shape[0], layout, xc.ctypes.data))
+
+
+def enumerate_energies(Q: np.ndarray, layout: int = LAYOUT_SYMMETRIC) -> np.ndarray:
+    is_int, Qc = _as_q(Q)
+    N = Qc.shape[0]
+    if is_int:
+        E = np.zeros(1 << N, dtype=np.int64)
+        rc = lib().orc_enumerate_energies_i(Qc.ctypes.data, N, layout, E.ctypes.data)
+    else:
+        E = np.zeros(1 << N, dtype=np.float64)
+        rc = lib().orc_enumerate_energies_f(Qc.ctypes.data, N, layout, E.ctypes.data)
+    if rc != 0:
+        raise ValueError("enumeration needs 1 <= N <= 24")
+    return E
+
+
+@dataclass
+class RunResult:
+    action: Optional[np.ndarray] = None
+    M: Optional[np.ndarray] = None
+    E: Optional[np.ndarray] = None      # int64 for integer Q, float64 otherwise
+    p: Optional[np.ndarray] = None
+    q: Optional[np.ndarray] = None
+    tmargin: Optional[np.ndarray] = None
+    x: Optional[np.ndarray] = None
+    h: Optional[np.ndarray] = None
+    E_final: Optional[np.ndarray] = None
+    L: Optional[np.ndarray] = None
+    sub: Optional[np.ndarray] = None
+    hist_w: Optional[np.ndarray] = None
+    hist_v: Optional[np.ndarray] = None
+    flips: Optional[np.ndarray] = None
+    stays: Optional[np.ndarray] = None
+    saturated: Optional[np.ndarray] = None
+
+
+def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, seed: int = 0,
+        num_chains: int = 1, chain_ids=None, x0: Optional[np.ndarray] = None, init: str = "zero",
+        layout: int = LAYOUT_SYMMETRIC, log: bool = True, hist: bool = False, hist_from: int = 0,
+        step0: int = 0, lib_handle: Optional[ctypes.CDLL] = None) -> RunResult:
+    """Run ``num_chains`` independent chains for ``K`` steps each.
+
+    ``beta`` is a scalar or one value per chain; ``init`` is ``"zero"``,
+    ``"random"`` (the Bernoulli(1/2) stream) or ignored when ``x0`` is given.
+    """
+    is_int, Qc = _as_q(Q)
+    N = Qc.shape[0]
+    C = num_chains
+    cids = np.arange(C, dtype=np.uint32) if chain_ids is None else np.ascontiguousarray(chain_ids, dtype=np.uint32)
+    betas = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, dtype=np.float64), (C,)))
+    if x0 is None:
+        if init == "zero":
+            x0 = np.zeros((C, N), dtype=np.uint8)
+        elif init == "random":
+            x0 = np.stack([random_state(seed, int(c), N) for c in cids])
+        else:
+            raise ValueError(init)
+    x0 = np.ascontiguousarray(np.broadcast_to(np.asarray(x0, dtype=np.uint8), (C, N)))
+    r = RunResult()
+    if log:
+        r.action = np.zeros((C, K), dtype=np.int32)
+        r.M = np.zeros((C, K), dtype=np.int64)
+        r.E = np.zeros((C, K), dtype=np.int64 if is_int else np.float64)
+        r.p = np.zeros((C, K))
+        r.q = np.zeros((C, K))
+        r.tmargin = np.zeros((C, K))
+    r.x = np.zeros((C, N), dtype=np.uint8)
+    r.h = np.zeros((C, N), dtype=np.int64 if is_int else np.float64)
+    r.E_final = np.zeros(C, dtype=np.int64 if is_int else np.float64)
+    Ef_dummy = np.zeros(C)
+    r.L = np.zeros(C, dtype=np.int64)
+    r.sub = np.zeros(C, dtype=np.int64)
+    r.flips = np.zeros(C, dtype=np.int64)
+    r.stays = np.zeros(C, dtype=np.int64)
+    r.saturated = np.zeros(C, dtype=np.int64)
+    if hist:
+        if N > 24:
+            raise ValueError("histograms need N <= 24")
+        r.hist_w = np.zeros(1 << N, dtype=np.uint64)
+        r.hist_v = np.zeros(1 << N, dtype=np.uint64)
+    a = _RunArgs()
+    a.N, a.is_int, a.layout = N, is_int, layout
+    a.Qi = Qc.ctypes.data if is_int else None
+    a.Qf = None if is_int else Qc.ctypes.data
+    a.mode, a.n, a.L0, a.seed = mode, (N if mode == MODE_RF else n), L0, seed
+    a.num_chains, a.chain_ids, a.betas, a.x0, a.K, a.step0 = C, cids.ctypes.data, betas.ctypes.data, x0.ctypes.data, K, step0
+    a.log_action = _ptr(r.action)
+    a.log_M = _ptr(r.M)
+    a.log_Ei = _ptr(r.E) if (log and is_int) else None
+    a.log_Ef = _ptr(r.E) if (log and not is_int) else None
+    a.log_p, a.log_q, a.log_tmargin = _ptr(r.p), _ptr(r.q), _ptr(r.tmargin)
+    a.x_final = _ptr(r.x)
+    a.hi_final = _ptr(r.h) if is_int else None
+    a.hf_final = None if is_int else _ptr(r.h)
+    a.Ei_final = _ptr(r.E_final) if is_int else None
+    a.Ef_final = _ptr(Ef_dummy) if is_int else _ptr(r.E_final)
+    a.L_final, a.sub_final = _ptr(r.L), _ptr(r.sub)
+    a.hist_w, a.hist_v, a.hist_from = _ptr(r.hist_w), _ptr(r.hist_v), hist_from
+    a.n_flips, a.n_stays, a.n_saturated = _ptr(r.flips), _ptr(r.stays), _ptr(r.saturated)
+    rc = (lib_handle or lib()).orc_run(ctypes.byref(a))
+    if rc != 0:
+        raise ValueError(f"oracle run rejected its arguments (code {rc})")
+    return r

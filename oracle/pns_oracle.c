@@ -1,0 +1,588 @@
+/*
+ * Reference oracle for Partial Neighbor Search sampling on QUBO targets.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this file's library.  The product
+ * path (the HIP library and its Python binding) never links, imports or calls
+ * it, and this file shares no code, header, table or constant generator with
+ * the product path.
+ *
+ * A deliberately plain, slow, single-threaded implementation in FP64 / int64
+ * of what the paper computes:
+ *   - Rejection-Free for the discrete case (Alg 2, Sec 1.2, eqs. (1)-(2));
+ *   - Basic Partial Neighbor Search (Alg 3, Sec 2), with the proposal of a
+ *     step restricted to a fresh random subset and normalised on it;
+ *   - Unbiased Partial Neighbor Search (Alg 6, Sec 3.2), with L0-original-
+ *     sample blocks per partial neighbor set, systematic or random sets
+ *     (Sec 5);
+ *   - on the QUBO target of Sec 4 with single-bit-flip neighbours and a
+ *     uniform proposal 1/N (so the proposal cancels in every ratio);
+ *   - proportional choice by the inverse-CDF rule of App. C (first index
+ *     whose running sum exceeds U times the total).
+ * Conventions (each one a reading of the paper where it is silent):
+ *   - target pi_beta(x) proportional to exp(-beta * x^T Q x); the paper's
+ *     pi(x) = exp{x^T Q x} is beta = 1 with Q replaced by -Q;
+ *   - Q is given either symmetric (full matrix) or upper triangular
+ *     (only entries i <= j are read), as Sec 4 allows both;
+ *   - a subset is scanned in increasing bit index;
+ *   - multiplicity M = 1 + G with G counting failures (M = 1 when p = 1,
+ *     as in Example 1 of Sec 2.1);
+ *   - in Basic PNS p is the average of the subset's acceptance
+ *     probabilities (proposal normalised on the subset, Sec 2);
+ *   - random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
+ *     written here from its published definition.
+ * Energies, local fields and multiplicities are exact (int64) for integer Q;
+ * everything else is IEEE double.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MODE_RF 0
+#define ORC_MODE_BASIC 1
+#define ORC_MODE_UNBIASED_SYS 2
+#define ORC_MODE_UNBIASED_RAND 3
+
+#define ORC_LAYOUT_SYMMETRIC 0
+#define ORC_LAYOUT_UPPER 1
+
+#define ORC_STAY (-1)
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10, from the description in Salmon et al., SC'11, Sec 3.3:      */
+/* each round multiplies counter words 0 and 2 by two fixed odd constants,    */
+/* swaps/xors the high and low halves with the other two words and the key,  */
+/* and the key is bumped by two Weyl constants between rounds.                */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Counter layout: (chain id, step low word, step high word, stream word). */
+static void draw4(uint64_t seed, uint32_t chain, uint64_t step, uint32_t stream, uint32_t out[4])
+{
+    uint32_t ctr[4] = {chain, (uint32_t)step, (uint32_t)(step >> 32), stream};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* 53 random bits from two words: ((hi << 32) | lo) >> 11. */
+static uint64_t bits53(uint32_t hi, uint32_t lo)
+{
+    return (((uint64_t)hi << 32) | (uint64_t)lo) >> 11;
+}
+
+/* Uniform on (0, 1] from words 0 and 1; uniform on [0, 1) from words 2, 3. */
+void orc_uniforms(uint64_t seed, uint32_t chain, uint64_t step, double* u_open_closed, double* u_closed_open)
+{
+    uint32_t w[4];
+    draw4(seed, chain, step, 0u, w);
+    *u_open_closed = (double)(bits53(w[0], w[1]) + 1u) * 0x1p-53;
+    *u_closed_open = (double)bits53(w[2], w[3]) * 0x1p-53;
+}
+
+/* Uniformly random n-subset of {0..N-1} (Sec 2 "random subset", Sec 5 random
+ * partial neighbor sets): take a stream of i.i.d. uniform indices and keep the
+ * first n distinct values.  Candidate s uses stream word 0x40000000 | (s/2),
+ * words (0,1) for even s and (2,3) for odd s, mapped to an index as
+ * floor(u64 * N / 2^64).  n == N takes every index without drawing. */
+void orc_random_subset(uint64_t seed, uint32_t chain, uint64_t step, int32_t N, int32_t n, uint8_t* member)
+{
+    memset(member, 0, (size_t)N);
+    if (n >= N) {
+        memset(member, 1, (size_t)N);
+        return;
+    }
+    int32_t distinct = 0;
+    for (uint32_t s = 0; distinct < n; ++s) {
+        uint32_t w[4];
+        draw4(seed, chain, step, 0x40000000u | (s >> 1), w);
+        uint32_t hi = (s & 1u) ? w[2] : w[0];
+        uint32_t lo = (s & 1u) ? w[3] : w[1];
+        uint64_t u = ((uint64_t)hi << 32) | (uint64_t)lo;
+        int32_t cand = (int32_t)(((unsigned __int128)u * (unsigned __int128)(uint64_t)N) >> 64);
+        if (!member[cand]) {
+            member[cand] = 1;
+            ++distinct;
+        }
+    }
+}
+
+/* Systematic partial neighbor set i (Sec 4 halves; Sec 5 wrap-around sets
+ * for n not dividing N): bits (i*n + t) mod N for t = 0..n-1. */
+void orc_sys_subset(int32_t N, int32_t n, int64_t i, uint8_t* member)
+{
+    memset(member, 0, (size_t)N);
+    int64_t start = (int64_t)(((__int128)i * n) % N);
+    for (int32_t t = 0; t < n; ++t) member[(start + t) % N] = 1;
+}
+
+static int64_t gcd64(int64_t a, int64_t b)
+{
+    while (b) {
+        int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+/* Number of distinct systematic sets: N / gcd(N, n). */
+int64_t orc_sys_count(int32_t N, int32_t n)
+{
+    return (int64_t)N / gcd64(N, n);
+}
+
+/* Bernoulli(1/2) initial bit j of a chain: stream 0x20000000 | (j / 128),
+ * word (j / 32) mod 4, bit j mod 32, step 0. */
+void orc_random_state(uint64_t seed, uint32_t chain, int32_t N, uint8_t* x)
+{
+    for (int32_t j = 0; j < N; ++j) {
+        uint32_t w[4];
+        draw4(seed, chain, 0, 0x20000000u | ((uint32_t)j >> 7), w);
+        x[j] = (uint8_t)((w[((uint32_t)j >> 5) & 3u] >> ((uint32_t)j & 31u)) & 1u);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* QUBO energy and local fields (Sec 4, pi(x) = exp{x^T Q x}).                */
+/* ------------------------------------------------------------------------- */
+
+/* Coefficient c(i, j) of x_i x_j in x^T Q x for i != j, counting both orders:
+ * symmetric Q -> Q_ij + Q_ji = 2 Q_ij; upper triangular Q -> Q_min,max. */
+static int64_t pair_coef_i(const int64_t* Q, int32_t N, int32_t layout, int32_t i, int32_t j)
+{
+    if (layout == ORC_LAYOUT_SYMMETRIC) return Q[(size_t)i * N + j] + Q[(size_t)j * N + i];
+    return i < j ? Q[(size_t)i * N + j] : Q[(size_t)j * N + i];
+}
+
+static double pair_coef_f(const double* Q, int32_t N, int32_t layout, int32_t i, int32_t j)
+{
+    if (layout == ORC_LAYOUT_SYMMETRIC) return 2.0 * Q[(size_t)i * N + j];
+    return i < j ? Q[(size_t)i * N + j] : Q[(size_t)j * N + i];
+}
+
+/* x^T Q x written out as a double sum over the entries the layout defines. */
+int64_t orc_energy_i(const int64_t* Q, int32_t N, int32_t layout, const uint8_t* x)
+{
+    int64_t e = 0;
+    for (int32_t i = 0; i < N; ++i) {
+        if (!x[i]) continue;
+        for (int32_t j = 0; j < N; ++j) {
+            if (!x[j]) continue;
+            if (layout == ORC_LAYOUT_UPPER && j < i) continue;
+            e += Q[(size_t)i * N + j];
+        }
+    }
+    return e;
+}
+
+double orc_energy_f(const double* Q, int32_t N, int32_t layout, const uint8_t* x)
+{
+    double e = 0.0;
+    for (int32_t i = 0; i < N; ++i) {
+        if (!x[i]) continue;
+        for (int32_t j = 0; j < N; ++j) {
+            if (!x[j]) continue;
+            if (layout == ORC_LAYOUT_UPPER && j < i) continue;
+            e += Q[(size_t)i * N + j];
+        }
+    }
+    return e;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Chain simulation.                                                         */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    /* problem */
+    int32_t N;
+    int32_t is_int;           /* 1: Qi (int64) is used, 0: Qf (double) */
+    int32_t layout;           /* ORC_LAYOUT_* */
+    const int64_t* Qi;        /* N*N row-major */
+    const double* Qf;         /* N*N row-major */
+    /* method */
+    int32_t mode;             /* ORC_MODE_* */
+    int32_t n;                /* subset size (ignored for RF) */
+    int64_t L0;               /* block length in original samples (Unbiased) */
+    uint64_t seed;
+    /* chains */
+    int32_t num_chains;
+    const uint32_t* chain_ids;  /* [num_chains] counter word 0 of each chain */
+    const double* betas;        /* [num_chains] */
+    const uint8_t* x0;          /* [num_chains][N] */
+    int64_t K;                  /* steps (records) per chain */
+    int64_t step0;              /* index of the first step (for resumed runs) */
+    /* per-step outputs [num_chains][K], each may be NULL */
+    int32_t* log_action;        /* flipped bit, or ORC_STAY */
+    int64_t* log_M;             /* multiplicity of the record */
+    int64_t* log_Ei;            /* energy of the record's state (integer Q) */
+    double* log_Ef;             /* energy of the record's state (double) */
+    double* log_p;              /* escape probability p */
+    double* log_q;              /* log(U1) / log1p(-p) (+inf when p == 0) */
+    double* log_tmargin;        /* distance of U2*S to the chosen interval's ends, / S */
+    /* final state outputs, each may be NULL */
+    uint8_t* x_final;           /* [num_chains][N] */
+    int64_t* hi_final;          /* [num_chains][N] local fields (integer Q) */
+    double* hf_final;           /* [num_chains][N] local fields (double Q) */
+    int64_t* Ei_final;          /* [num_chains] */
+    double* Ef_final;           /* [num_chains] */
+    int64_t* L_final;           /* [num_chains] remaining budget */
+    int64_t* sub_final;         /* [num_chains] systematic set index */
+    /* multiplicity-weighted and visit histograms over 2^N states, N <= 24 */
+    uint64_t* hist_w;
+    uint64_t* hist_v;
+    int64_t hist_from;          /* first step index counted */
+    /* counters [num_chains], each may be NULL */
+    int64_t* n_flips;
+    int64_t* n_stays;
+    int64_t* n_saturated;
+} orc_run_args;
+
+/* Local field of bit j: the part of dE_j that depends on the other bits,
+ * h_j = sum_{i != j} c(i, j) x_i / s where s = 2 for symmetric Q (so that
+ * dE_j = (1 - 2 x_j)(Q_jj + 2 h_j) as in the symmetric form) and s = 1 for
+ * upper-triangular Q (dE_j = (1 - 2 x_j)(Q_jj + h_j)). */
+static void fields_init(const orc_run_args* a, const uint8_t* x, int64_t* hi, double* hf)
+{
+    int32_t N = a->N;
+    for (int32_t j = 0; j < N; ++j) {
+        if (a->is_int) {
+            int64_t acc = 0;
+            for (int32_t i = 0; i < N; ++i) {
+                if (i == j || !x[i]) continue;
+                acc += a->layout == ORC_LAYOUT_SYMMETRIC ? a->Qi[(size_t)j * N + i]
+                                                         : pair_coef_i(a->Qi, N, a->layout, i, j);
+            }
+            hi[j] = acc;
+        } else {
+            double acc = 0.0;
+            for (int32_t i = 0; i < N; ++i) {
+                if (i == j || !x[i]) continue;
+                acc += a->layout == ORC_LAYOUT_SYMMETRIC ? a->Qf[(size_t)j * N + i]
+                                                         : pair_coef_f(a->Qf, N, a->layout, i, j);
+            }
+            hf[j] = acc;
+        }
+    }
+}
+
+/* Change of the field of bit j when bit c flips by delta = +-1. */
+static int64_t field_step_i(const orc_run_args* a, int32_t j, int32_t c)
+{
+    if (a->layout == ORC_LAYOUT_SYMMETRIC) return a->Qi[(size_t)j * a->N + c];
+    return pair_coef_i(a->Qi, a->N, a->layout, j, c);
+}
+
+static double field_step_f(const orc_run_args* a, int32_t j, int32_t c)
+{
+    if (a->layout == ORC_LAYOUT_SYMMETRIC) return a->Qf[(size_t)j * a->N + c];
+    return pair_coef_f(a->Qf, a->N, a->layout, j, c);
+}
+
+/* Energy difference E(x with bit j flipped) - E(x). */
+static int64_t delta_i(const orc_run_args* a, const uint8_t* x, const int64_t* hi, int32_t j)
+{
+    int64_t d = a->Qi[(size_t)j * a->N + j];
+    int64_t s = a->layout == ORC_LAYOUT_SYMMETRIC ? 2 : 1;
+    return (x[j] ? -1 : 1) * (d + s * hi[j]);
+}
+
+static double delta_f(const orc_run_args* a, const uint8_t* x, const double* hf, int32_t j)
+{
+    double d = a->Qf[(size_t)j * a->N + j];
+    double s = a->layout == ORC_LAYOUT_SYMMETRIC ? 2.0 : 1.0;
+    return (x[j] ? -1.0 : 1.0) * (d + s * hf[j]);
+}
+
+static uint64_t sat_add(uint64_t a, uint64_t b)
+{
+    uint64_t r = a + b;
+    return r < a ? UINT64_MAX : r;
+}
+
+int orc_run(const orc_run_args* a)
+{
+    const int32_t N = a->N;
+    if (N <= 0) return -1;
+    if (a->mode != ORC_MODE_RF && (a->n < 1 || a->n > N)) return -2;
+    const int32_t n = a->mode == ORC_MODE_RF ? N : a->n;
+    const int64_t I = orc_sys_count(N, n);
+
+    uint8_t* x = (uint8_t*)malloc((size_t)N);
+    uint8_t* member = (uint8_t*)malloc((size_t)N);
+    int64_t* hi = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
+    double* hf = (double*)malloc(sizeof(double) * (size_t)N);
+    int64_t* dEi = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
+    double* dEf = (double*)malloc(sizeof(double) * (size_t)N);
+    double* lw = (double*)malloc(sizeof(double) * (size_t)N);
+    double* w = (double*)malloc(sizeof(double) * (size_t)N);
+    if (!x || !member || !hi || !hf || !dEi || !dEf || !lw || !w) return -3;
+
+    for (int32_t ch = 0; ch < a->num_chains; ++ch) {
+        const uint32_t cid = a->chain_ids[ch];
+        const double beta = a->betas[ch];
+        memcpy(x, a->x0 + (size_t)ch * N, (size_t)N);
+        fields_init(a, x, hi, hf);
+        int64_t Ei = a->is_int ? orc_energy_i(a->Qi, N, a->layout, x) : 0;
+        double Ef = a->is_int ? (double)Ei : orc_energy_f(a->Qf, N, a->layout, x);
+        int64_t L = a->L0;
+        int64_t sub = 0;
+        int64_t flips = 0, stays = 0, saturated = 0;
+
+        /* Alg 6: the first partial neighbor set is N_0 (systematic) or a
+         * fresh random set drawn for the step where the block starts. */
+        if (a->mode == ORC_MODE_UNBIASED_SYS) orc_sys_subset(N, n, sub, member);
+        if (a->mode == ORC_MODE_UNBIASED_RAND) orc_random_subset(a->seed, cid, (uint64_t)a->step0, N, n, member);
+        if (a->mode == ORC_MODE_RF) memset(member, 1, (size_t)N);
+
+        for (int64_t kk = 0; kk < a->K; ++kk) {
+            const int64_t k = a->step0 + kk;
+            const size_t rec = (size_t)ch * (size_t)a->K + (size_t)kk;
+
+            /* Alg 3: a fresh partial neighbor set every step. */
+            if (a->mode == ORC_MODE_BASIC) orc_random_subset(a->seed, cid, (uint64_t)k, N, n, member);
+
+            /* Acceptance probabilities min{1, pi(y)/pi(x)} of the subset's
+             * neighbours (the uniform proposal cancels), kept as logs. */
+            for (int32_t j = 0; j < N; ++j) {
+                if (!member[j]) continue;
+                double dE;
+                if (a->is_int) {
+                    dEi[j] = delta_i(a, x, hi, j);
+                    dE = (double)dEi[j];
+                } else {
+                    dEf[j] = delta_f(a, x, hf, j);
+                    dE = dEf[j];
+                }
+                double l = -beta * dE;
+                lw[j] = l < 0.0 ? l : 0.0;
+            }
+            /* Sum in subset order.  If every term underflows, rescale by the
+             * largest term so the proportional choice stays defined; the
+             * escape probability then carries the scale back. */
+            double S = 0.0;
+            for (int32_t j = 0; j < N; ++j) {
+                if (!member[j]) continue;
+                w[j] = exp(lw[j]);
+                S += w[j];
+            }
+            double p;
+            if (S < 0x1p-1000) {
+                double mx = -INFINITY;
+                for (int32_t j = 0; j < N; ++j)
+                    if (member[j] && lw[j] > mx) mx = lw[j];
+                S = 0.0;
+                for (int32_t j = 0; j < N; ++j) {
+                    if (!member[j]) continue;
+                    w[j] = exp(lw[j] - mx);
+                    S += w[j];
+                }
+                p = exp(mx) * S / (double)n;
+            } else {
+                p = S / (double)n;
+            }
+
+            /* Multiplicity 1 + G, G ~ Geometric(p) counting failures:
+             * G = floor(log U1 / log(1 - p)) with U1 uniform on (0, 1]. */
+            double U1, U2;
+            orc_uniforms(a->seed, cid, (uint64_t)k, &U1, &U2);
+            double q;
+            if (p >= 1.0) q = 0.0;
+            else if (p <= 0.0) q = INFINITY;
+            else q = log(U1) / log1p(-p);
+            int64_t m;
+            int sat = 0;
+            if (!(q < 0x1p63)) {
+                m = INT64_MAX;
+                sat = 1;
+            } else {
+                m = (int64_t)floor(q) + 1;
+            }
+
+            const int unbiased = a->mode == ORC_MODE_UNBIASED_SYS || a->mode == ORC_MODE_UNBIASED_RAND;
+            int32_t action;
+            int64_t M;
+            double tmargin = 0.0;
+            if (unbiased && q >= (double)L) {
+                /* Alg 6 "else" branch: not enough remaining original
+                 * samples; stay L times and move to the next set. */
+                M = L;
+                action = ORC_STAY;
+                L = a->L0;
+                ++sub;
+                if (a->mode == ORC_MODE_UNBIASED_SYS) orc_sys_subset(N, n, sub % I, member);
+                else orc_random_subset(a->seed, cid, (uint64_t)(k + 1), N, n, member);
+                ++stays;
+            } else {
+                M = m;
+                if (unbiased) L -= m;
+                saturated += sat;
+                /* Proportional choice, App. C: the first index whose running
+                 * sum exceeds U2 * S; rounding fallback: last positive one. */
+                double t = U2 * S;
+                double run = 0.0, prev = 0.0;
+                int32_t c = -1, last_pos = -1;
+                for (int32_t j = 0; j < N; ++j) {
+                    if (!member[j]) continue;
+                    if (w[j] > 0.0) last_pos = j;
+                    prev = run;
+                    run += w[j];
+                    if (run > t && w[j] > 0.0) {
+                        c = j;
+                        break;
+                    }
+                }
+                if (c < 0) {
+                    c = last_pos;
+                    tmargin = 0.0;
+                } else {
+                    double lo = t - prev, hi2 = run - t;
+                    tmargin = (lo < hi2 ? lo : hi2) / S;
+                }
+                action = c;
+                /* Move: flip bit c and update energy and every other field. */
+                if (a->is_int) {
+                    int64_t delta = x[c] ? -1 : 1;
+                    Ei += dEi[c];
+                    for (int32_t j = 0; j < N; ++j)
+                        if (j != c) hi[j] += delta * field_step_i(a, j, c);
+                } else {
+                    double delta = x[c] ? -1.0 : 1.0;
+                    Ef += dEf[c];
+                    for (int32_t j = 0; j < N; ++j)
+                        if (j != c) hf[j] += delta * field_step_f(a, j, c);
+                }
+                x[c] ^= 1u;
+                ++flips;
+            }
+
+            /* Record k is (J_k-before, M_k) with its energy. */
+            double Erec = a->is_int ? (double)(Ei - (action >= 0 ? dEi[action] : 0))
+                                    : (action >= 0 ? Ef - dEf[action] : Ef);
+            if (a->log_action) a->log_action[rec] = action;
+            if (a->log_M) a->log_M[rec] = M;
+            if (a->log_Ei) a->log_Ei[rec] = a->is_int ? Ei - (action >= 0 ? dEi[action] : 0) : 0;
+            if (a->log_Ef) a->log_Ef[rec] = Erec;
+            if (a->log_p) a->log_p[rec] = p;
+            if (a->log_q) a->log_q[rec] = q;
+            if (a->log_tmargin) a->log_tmargin[rec] = tmargin;
+            if ((a->hist_w || a->hist_v) && N <= 24 && k >= a->hist_from) {
+                uint32_t idx = 0;
+                for (int32_t j = 0; j < N; ++j) {
+                    uint8_t bit = x[j];
+                    if (j == action) bit ^= 1u; /* the record's state is before the flip */
+                    idx |= (uint32_t)bit << j;
+                }
+                if (a->hist_w) a->hist_w[idx] = sat_add(a->hist_w[idx], (uint64_t)M);
+                if (a->hist_v) a->hist_v[idx] += 1u;
+            }
+        }
+
+        if (a->x_final) memcpy(a->x_final + (size_t)ch * N, x, (size_t)N);
+        if (a->hi_final && a->is_int) memcpy(a->hi_final + (size_t)ch * N, hi, sizeof(int64_t) * (size_t)N);
+        if (a->hf_final && !a->is_int) memcpy(a->hf_final + (size_t)ch * N, hf, sizeof(double) * (size_t)N);
+        if (a->Ei_final) a->Ei_final[ch] = Ei;
+        if (a->Ef_final) a->Ef_final[ch] = Ef;
+        if (a->L_final) a->L_final[ch] = L;
+        if (a->sub_final) a->sub_final[ch] = sub;
+        if (a->n_flips) a->n_flips[ch] = flips;
+        if (a->n_stays) a->n_stays[ch] = stays;
+        if (a->n_saturated) a->n_saturated[ch] = saturated;
+    }
+
+    free(x); free(member); free(hi); free(hf); free(dEi); free(dEf); free(lw); free(w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Exact quantities by enumeration (test pins, N <= 24).                      */
+/* ------------------------------------------------------------------------- */
+
+/* Energy x^T Q x of every state x = sum_j x_j 2^j. */
+int orc_enumerate_energies_i(const int64_t* Q, int32_t N, int32_t layout, int64_t* E)
+{
+    if (N <= 0 || N > 24) return -1;
+    uint8_t x[24];
+    for (uint32_t s = 0; s < (1u << N); ++s) {
+        for (int32_t j = 0; j < N; ++j) x[j] = (uint8_t)((s >> j) & 1u);
+        E[s] = orc_energy_i(Q, N, layout, x);
+    }
+    return 0;
+}
+
+int orc_enumerate_energies_f(const double* Q, int32_t N, int32_t layout, double* E)
+{
+    if (N <= 0 || N > 24) return -1;
+    uint8_t x[24];
+    for (uint32_t s = 0; s < (1u << N); ++s) {
+        for (int32_t j = 0; j < N; ++j) x[j] = (uint8_t)((s >> j) & 1u);
+        E[s] = orc_energy_f(Q, N, layout, x);
+    }
+    return 0;
+}
+
+/* Exact one-step quantities of Basic PNS (Alg 3) on a regular neighbour graph
+ * with D neighbours per state and a uniformly random n-subset of them each
+ * step, p = average over the subset:
+ *   T[s*D + j] = P(next = nbr[s][j]) = E_S[ 1{j in S} w_j / sum_{i in S} w_i ]
+ *   EM[s]      = E[M | s]            = E_S[ n / sum_{i in S} w_i ]
+ * with w_j = min(1, pi(nbr)/pi(s)) given as logpi.  Enumerates all C(D, n)
+ * subsets (small D only). */
+int orc_basic_onestep(int64_t num_states, int32_t D, const int64_t* nbr, const double* logpi,
+                      int32_t n, double* T, double* EM)
+{
+    if (D <= 0 || D > 30 || n < 1 || n > D) return -1;
+    int32_t idx[32];
+    double wv[32];
+    double nsub = 0.0;
+    /* count subsets */
+    {
+        double c = 1.0;
+        for (int32_t r = 0; r < n; ++r) c = c * (double)(D - r) / (double)(r + 1);
+        nsub = floor(c + 0.5);
+    }
+    for (int64_t s = 0; s < num_states; ++s) {
+        for (int32_t j = 0; j < D; ++j) {
+            double l = logpi[nbr[s * D + j]] - logpi[s];
+            wv[j] = l < 0.0 ? exp(l) : 1.0;
+            T[s * D + j] = 0.0;
+        }
+        double em = 0.0;
+        for (int32_t r = 0; r < n; ++r) idx[r] = r;
+        for (;;) {
+            double sw = 0.0;
+            for (int32_t r = 0; r < n; ++r) sw += wv[idx[r]];
+            for (int32_t r = 0; r < n; ++r) T[s * D + idx[r]] += wv[idx[r]] / sw / nsub;
+            em += (double)n / sw / nsub;
+            /* next combination in lexicographic order */
+            int32_t r = n - 1;
+            while (r >= 0 && idx[r] == D - n + r) --r;
+            if (r < 0) break;
+            ++idx[r];
+            for (int32_t t = r + 1; t < n; ++t) idx[t] = idx[t - 1] + 1;
+        }
+        EM[s] = em;
+    }
+    return 0;
+}

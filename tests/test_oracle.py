@@ -1,0 +1,402 @@
+"""Pins for the CPU oracle: each test checks the oracle against something the
+paper or the mathematics fixes (published test vectors, the paper's worked
+examples, brute-force enumeration, closed forms, special cases), never
+against a retyping of the oracle's own formula.  CPU only."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+from paper_2210_10513_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_json(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _small_int_q(N, seed, lo=-50, hi=50):
+    return inputs.symmetric_int(N, lo, hi, np.int64, seed=seed)
+
+
+def _states_from_actions(x0, actions):
+    """Record states J_0 .. J_{K-1} of one chain rebuilt from its actions."""
+    x = np.array(x0, dtype=np.uint8)
+    out = np.empty((len(actions), len(x)), dtype=np.uint8)
+    for k, a in enumerate(actions):
+        out[k] = x
+        if a >= 0:
+            x[a] ^= 1
+    return out, x
+
+
+# --------------------------------------------------------------------------
+# Random numbers
+# --------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        out = oracle.philox4x32_10(v[0:4], v[4:6])
+        assert [int(o) for o in out] == v[6:10]
+
+
+def test_uniforms_ranges_and_moments():
+    u1 = np.array([oracle.uniforms(11, c, k)[0] for c in range(20) for k in range(500)])
+    u2 = np.array([oracle.uniforms(11, c, k)[1] for c in range(20) for k in range(500)])
+    assert u1.min() > 0.0 and u1.max() <= 1.0
+    assert u2.min() >= 0.0 and u2.max() < 1.0
+    for u in (u1, u2):
+        assert abs(u.mean() - 0.5) < 4 * np.sqrt(1 / 12 / len(u))
+        assert abs((u ** 2).mean() - 1 / 3) < 0.01
+
+
+def test_random_subset_exact_size_and_uniform():
+    N, n, T = 20, 5, 6000
+    counts = np.zeros(N)
+    pair = np.zeros((N, N))
+    for k in range(T):
+        m = oracle.random_subset(3, 1, k, N, n)
+        assert m.sum() == n
+        counts += m
+        mi = m.astype(float)
+        pair += np.outer(mi, mi)
+    # inclusion probability n/N for each index (chi-square, N-1 dof)
+    exp_c = T * n / N
+    chi2 = ((counts - exp_c) ** 2 / exp_c).sum()
+    assert chi2 < 55  # 99.99% quantile of chi2(19) is ~ 50.8
+    # pairwise inclusion n(n-1)/(N(N-1)) (uniform n-subset, not independent bits)
+    off = pair[~np.eye(N, dtype=bool)] / T
+    assert abs(off.mean() - n * (n - 1) / (N * (N - 1))) < 0.003
+    # n == N takes everything
+    assert oracle.random_subset(3, 1, 0, N, N).all()
+
+
+def test_random_state_bernoulli_half():
+    x = np.concatenate([oracle.random_state(5, c, 257) for c in range(40)])
+    assert abs(x.mean() - 0.5) < 4 * 0.5 / np.sqrt(len(x))
+
+
+# --------------------------------------------------------------------------
+# Partial neighbor sets
+# --------------------------------------------------------------------------
+
+def test_systematic_sets_match_paper_listing():
+    g = _golden_json("paper_examples.json")["systematic_sets"]
+    N, n = g["N"], g["n"]
+    assert oracle.sys_count(N, n) == g["count"]
+    for i, bits in enumerate(g["first_three_one_indexed"]):
+        m = oracle.sys_subset(N, n, i)
+        assert sorted(np.nonzero(m)[0] + 1) == sorted(bits)
+    # the schedule is periodic with the stated number of sets and covers all bits
+    cover = np.zeros(N, dtype=bool)
+    for i in range(g["count"]):
+        cover |= oracle.sys_subset(N, n, i)
+    assert cover.all()
+    assert (oracle.sys_subset(N, n, g["count"]) == oracle.sys_subset(N, n, 0)).all()
+
+
+def test_systematic_halves():
+    N = _golden_json("paper_examples.json")["halves"]["N"]
+    assert oracle.sys_count(N, N // 2) == 2
+    assert (np.nonzero(oracle.sys_subset(N, N // 2, 0))[0] == np.arange(N // 2)).all()
+    assert (np.nonzero(oracle.sys_subset(N, N // 2, 1))[0] == np.arange(N // 2, N)).all()
+
+
+# --------------------------------------------------------------------------
+# Energies, local fields and the recorded trajectory
+# --------------------------------------------------------------------------
+
+def test_energy_matches_matrix_product_and_layouts():
+    rng = np.random.default_rng(0)
+    N = 9
+    Q = _small_int_q(N, 4)
+    U = np.triu(Q) + np.triu(Q, 1)  # upper-triangular form of the same quadratic form
+    E_sym = oracle.enumerate_energies(Q, oracle.LAYOUT_SYMMETRIC)
+    E_up = oracle.enumerate_energies(U, oracle.LAYOUT_UPPER)
+    X = ((np.arange(1 << N)[:, None] >> np.arange(N)[None, :]) & 1).astype(np.int64)
+    E_mat = np.einsum("si,ij,sj->s", X, Q, X)
+    assert (E_sym == E_mat).all() and (E_up == E_mat).all()
+    Qf = rng.standard_normal((N, N))
+    Qf = (Qf + Qf.T) / 2
+    Ef = oracle.enumerate_energies(Qf, oracle.LAYOUT_SYMMETRIC)
+    assert np.allclose(Ef, np.einsum("si,ij,sj->s", X, Qf, X), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("mode,n", [(oracle.MODE_RF, 0), (oracle.MODE_BASIC, 3), (oracle.MODE_UNBIASED_SYS, 4),
+                                    (oracle.MODE_UNBIASED_RAND, 5)])
+@pytest.mark.parametrize("kind", ["int_sym", "int_upper", "float_sym"])
+def test_trajectory_energies_and_fields(mode, n, kind):
+    """Every record's energy equals x^T Q x of the record's state (brute force
+    with a matrix product), every move is a single-bit flip inside the
+    declared subset rules, and the final local fields equal the off-diagonal
+    matrix-vector product."""
+    N, K = 10, 600
+    rng = np.random.default_rng(1)
+    if kind == "float_sym":
+        A = rng.standard_normal((N, N))
+        Q = (A + A.T) / 2
+        layout = oracle.LAYOUT_SYMMETRIC
+        Qsym = Q
+    elif kind == "int_sym":
+        Q = _small_int_q(N, 2)
+        layout = oracle.LAYOUT_SYMMETRIC
+        Qsym = Q.astype(np.float64)
+    else:
+        Q = np.triu(_small_int_q(N, 3))
+        layout = oracle.LAYOUT_UPPER
+        Qsym = (Q + Q.T) / 2.0
+    r = oracle.run(Q, 0.05, mode, K, n=n, L0=7, seed=9, num_chains=3, init="random", layout=layout)
+    for c in range(3):
+        x0 = oracle.random_state(9, c, N)
+        states, xf = _states_from_actions(x0, r.action[c])
+        E_bf = np.einsum("si,ij,sj->s", states.astype(float), Qsym, states.astype(float))
+        assert np.allclose(r.E[c], E_bf, rtol=1e-12, atol=1e-9)
+        assert (r.x[c] == xf).all()
+        E_final = xf.astype(float) @ Qsym @ xf.astype(float)
+        assert np.isclose(float(r.E_final[c]), E_final, rtol=1e-12, atol=1e-9)
+        off = Qsym - np.diag(np.diag(Qsym))
+        scale = 2.0 if layout == oracle.LAYOUT_SYMMETRIC else 1.0
+        h_expect = (2.0 / scale) * (off @ xf.astype(float))
+        assert np.allclose(r.h[c].astype(float), h_expect, rtol=1e-12, atol=1e-9)
+        # energy differences of the flips equal brute-force E(x ^ e_c) - E(x)
+        moves = np.nonzero(r.action[c] >= 0)[0][:-1]
+        assert np.allclose(np.diff(r.E[c].astype(float))[moves], (E_bf[moves + 1] - E_bf[moves]), atol=1e-9)
+        if mode == oracle.MODE_UNBIASED_SYS:
+            # every flip stays inside the set in force at that step
+            sub = 0
+            for k, a in enumerate(r.action[c]):
+                if a == oracle.STAY:
+                    sub += 1
+                else:
+                    assert oracle.sys_subset(N, n, sub % oracle.sys_count(N, n))[a]
+        if mode == oracle.MODE_BASIC:
+            for k, a in enumerate(r.action[c][:50]):
+                assert oracle.random_subset(9, c, k, N, n)[a]
+    if kind.startswith("int"):
+        assert r.E.dtype == np.int64
+
+
+# --------------------------------------------------------------------------
+# Multiplicities
+# --------------------------------------------------------------------------
+
+def test_multiplicity_is_one_plus_geometric():
+    """M | p ~ 1 + Geometric(p) counting failures (Sec 1.2, eq. (2) and the
+    jump-chain example): E[p M] = 1, P(M = 1) = p, and M = 1 whenever p = 1."""
+    Q = _small_int_q(12, 7, -20, 20)
+    r = oracle.run(Q, 0.05, oracle.MODE_RF, 20000, seed=3, num_chains=8)
+    p = r.p.ravel()
+    M = r.M.ravel().astype(float)
+    assert (M >= 1).all()
+    assert (M[p == 1.0] == 1).all()
+    k = len(p)
+    z1 = (p * M).mean() - 1.0
+    assert abs(z1) < 5 * np.sqrt(np.mean(1 - p) / k) + 1e-12
+    z2 = ((M == 1).astype(float) - p).mean()
+    assert abs(z2) < 5 * np.sqrt(np.mean(p * (1 - p)) / k) + 1e-12
+    # the geometric tail: P(M > m | p) = (1-p)^m, checked through the
+    # probability-integral transform of M on the grid of p values
+    sel = (p > 0.05) & (p < 0.95)
+    tail = (1 - p[sel]) ** M[sel]           # P(M' > M) for an independent copy
+    u = tail + (1 - p[sel]) ** (M[sel] - 1) * p[sel] * 0.5  # mid-P transform
+    assert abs(u.mean() - 0.5) < 0.02
+
+
+def test_saturation_when_every_weight_underflows():
+    """A frozen chain (every uphill move has weight below 2^-1000): p
+    underflows to 0, M saturates at 2^63-1 and the choice still picks the
+    largest weight (the least uphill neighbour)."""
+    N = 6
+    Q = np.diag(np.arange(1, N + 1, dtype=np.int64)) * 1000   # x = 0 is the minimum
+    r = oracle.run(Q, 10.0, oracle.MODE_RF, 3, seed=1)
+    assert r.M[0, 0] == np.iinfo(np.int64).max
+    assert r.saturated[0] >= 1
+    assert r.action[0, 0] == 0  # bit 0 costs least (1000)
+
+
+# --------------------------------------------------------------------------
+# Stationary laws against brute-force enumeration
+# --------------------------------------------------------------------------
+
+def _c1_like(N=12):
+    return inputs.symmetric_int(N, -50, 50, np.int64, seed=11)
+
+
+def test_rejection_free_converges_to_pi():
+    Q = _c1_like()
+    pi = exact.target(Q, 0.05)
+    r = oracle.run(Q, 0.05, oracle.MODE_RF, 50000, seed=5, num_chains=16, log=False, hist=True, hist_from=5000)
+    assert exact.tv(exact.empirical(r.hist_w), pi) < 0.01
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_UNBIASED_SYS, oracle.MODE_UNBIASED_RAND])
+def test_unbiased_pns_converges_to_pi(mode):
+    Q = _c1_like()
+    pi = exact.target(Q, 0.05)
+    r = oracle.run(Q, 0.05, mode, 50000, n=4, L0=100, seed=5, num_chains=16, log=False, hist=True, hist_from=5000)
+    assert exact.tv(exact.empirical(r.hist_w), pi) < 0.01
+
+
+def test_jump_chain_visits_follow_alpha_pi():
+    """Thm 3 item 4: the jump chain's stationary law is proportional to
+    alpha(x) pi(x), alpha(x) = P(leave x) = (1/N) sum_j min(1, pi(y)/pi(x))."""
+    Q = _c1_like(10)
+    N = 10
+    E = oracle.enumerate_energies(Q).astype(float)
+    nbr = exact.hypercube_neighbours(N)
+    lw = np.minimum(0.0, -0.05 * (E[nbr] - E[:, None]))
+    alpha = np.exp(lw).mean(axis=1)
+    pi = exact.target(Q, 0.05)
+    law = alpha * pi / (alpha * pi).sum()
+    r = oracle.run(Q, 0.05, oracle.MODE_RF, 40000, seed=8, num_chains=8, log=False, hist=True, hist_from=2000)
+    assert exact.tv(exact.empirical(r.hist_v), law) < 0.01
+
+
+def test_basic_pns_follows_its_exact_law_not_pi():
+    Q = _c1_like(10)
+    P, mu, EM, pi = exact.basic_law_qubo(Q, 0.05, 3)
+    assert exact.tv(P, pi) > 0.2  # Basic PNS is biased (Sec 2)
+    r = oracle.run(Q, 0.05, oracle.MODE_BASIC, 40000, n=3, seed=4, num_chains=16, log=False, hist=True, hist_from=2000)
+    assert exact.tv(exact.empirical(r.hist_v), mu) < 0.015
+
+
+def _mean_multiplicity_error(lib_handle=None):
+    """Largest relative gap between the chain's mean multiplicity per state and
+    the exact E[M | x] = E_S[n / sum_S w] of Basic PNS (Sec 2, p = subset
+    average), over well-visited states of Example 2 with two neighbours a step.
+    A uniform rescaling of every multiplicity leaves the normalised law alone,
+    so only this absolute check pins the 1/n normalisation."""
+    Q = inputs.example2()
+    _, _, EM, _ = exact.basic_law_qubo(Q, 1.0, 2)
+    r = oracle.run(Q, 1.0, oracle.MODE_BASIC, 60000, n=2, seed=12, num_chains=4, log=False, hist=True,
+                   lib_handle=lib_handle)
+    v = r.hist_v.astype(float)
+    ok = v > 2000
+    return float(np.max(np.abs(r.hist_w[ok] / v[ok] / EM[ok] - 1.0)))
+
+
+def test_basic_mean_multiplicity_matches_exact():
+    assert _mean_multiplicity_error() < 0.05
+
+
+# --------------------------------------------------------------------------
+# The paper's worked examples
+# --------------------------------------------------------------------------
+
+def test_example1_exact_basic_law():
+    g = _golden_json("paper_examples.json")["example1"]
+    nbr = np.array([[1, 2], [0, 2], [0, 1]])
+    logpi = np.log(np.array(g["pi_unnormalised"], dtype=float))
+    P, mu, EM = exact.basic_law_graph(nbr, logpi, g["subset_size"])
+    assert np.isclose(EM[0], g["printed_E_M_A"]) and np.isclose(EM[2], g["printed_E_M_C"])
+    assert np.allclose(EM, g["derived_E_M"])
+    assert np.allclose(P, g["derived_limit"])
+    pi = np.exp(logpi) / np.exp(logpi).sum()
+    assert not np.allclose(P, pi, atol=0.04)  # the limit differs from pi (Sec 2.1)
+
+
+def test_example2_basic_limit_about_point_three():
+    g = _golden_json("paper_examples.json")["example2"]
+    Q = inputs.example2()
+    tvs = []
+    for n in range(1, g["N"] + 1):
+        P, mu, EM, pi = exact.basic_law_qubo(Q, 1.0, n)
+        tvs.append(exact.tv(P, pi))
+    assert abs(tvs[0] - g["printed_tvd_subset1"]) < g["printed_tvd_tolerance"]
+    assert tvs[0] > tvs[1] > tvs[2] > tvs[3]
+    assert tvs[-1] < 1e-12
+    # and the simulated Basic PNS chain reaches that limit
+    P1, _, _, pi = exact.basic_law_qubo(Q, 1.0, 1)
+    r = oracle.run(Q, 1.0, oracle.MODE_BASIC, 100000, n=1, seed=2, num_chains=8, log=False, hist=True, hist_from=1000)
+    emp = exact.empirical(r.hist_w)
+    assert exact.tv(emp, P1) < 0.01
+    assert abs(exact.tv(emp, pi) - g["printed_tvd_subset1"]) < 0.02
+    # the target itself: pi proportional to e^{level}
+    level = np.array([bin(s).count("1") for s in range(16)])
+    assert np.allclose(pi, np.exp(level) / (1 + np.e) ** 4)
+
+
+# --------------------------------------------------------------------------
+# Special cases that must coincide bit for bit
+# --------------------------------------------------------------------------
+
+def test_basic_with_full_subset_is_rejection_free():
+    Q = _small_int_q(11, 5)
+    a = oracle.run(Q, 0.05, oracle.MODE_RF, 3000, seed=6, num_chains=4)
+    b = oracle.run(Q, 0.05, oracle.MODE_BASIC, 3000, n=11, seed=6, num_chains=4)
+    assert (a.action == b.action).all() and (a.M == b.M).all() and (a.E == b.E).all()
+
+
+def test_unbiased_with_full_set_and_huge_budget_is_rejection_free():
+    Q = _small_int_q(11, 5)
+    a = oracle.run(Q, 0.05, oracle.MODE_RF, 3000, seed=6, num_chains=4)
+    for mode in (oracle.MODE_UNBIASED_SYS, oracle.MODE_UNBIASED_RAND):
+        b = oracle.run(Q, 0.05, mode, 3000, n=11, L0=2 ** 62, seed=6, num_chains=4)
+        assert (a.action == b.action).all() and (a.M == b.M).all() and (a.E == b.E).all()
+
+
+def test_unbiased_budget_schedule_at_infinite_temperature():
+    """beta = 0: every move is accepted (p = 1, M = 1), so with L0 = 3 the
+    budget runs out after three moves and Alg 6 emits a stay record with
+    M = L = 0 and switches to the next set."""
+    Q = _small_int_q(8, 1)
+    r = oracle.run(Q, 0.0, oracle.MODE_UNBIASED_SYS, 40, n=2, L0=3, seed=1)
+    acts, M = r.action[0], r.M[0]
+    for k in range(40):
+        if k % 4 == 3:
+            assert acts[k] == oracle.STAY and M[k] == 0
+        else:
+            assert acts[k] >= 0 and M[k] == 1
+            assert oracle.sys_subset(8, 2, (k // 4) % 4)[acts[k]]
+    assert r.sub[0] == 10
+
+
+def test_resume_is_bit_identical():
+    """Counter-based randomness: K steps then K more from the saved state equal
+    2K steps in one go."""
+    Q = _small_int_q(9, 8)
+    full = oracle.run(Q, 0.05, oracle.MODE_BASIC, 400, n=3, seed=2, num_chains=2)
+    half = oracle.run(Q, 0.05, oracle.MODE_BASIC, 200, n=3, seed=2, num_chains=2)
+    rest = oracle.run(Q, 0.05, oracle.MODE_BASIC, 200, n=3, seed=2, num_chains=2, x0=half.x, step0=200)
+    assert (np.concatenate([half.action, rest.action], 1) == full.action).all()
+    assert (np.concatenate([half.M, rest.M], 1) == full.M).all()
+
+
+# --------------------------------------------------------------------------
+# Planted mistakes: each must be caught by one of the pins above
+# --------------------------------------------------------------------------
+
+MUTANTS = {
+    "p_over_N_not_n": [("p = S / (double)n;", "p = S / (double)N;")],
+    "M_without_plus_one": [("m = (int64_t)floor(q) + 1;", "m = (int64_t)floor(q) + (q > 1.0 ? 0 : 1);")],
+    "dE_wrong_sign": [("return (x[j] ? -1 : 1) * (d + s * hi[j]);", "return (x[j] ? 1 : -1) * (d + s * hi[j]);")],
+    "field_dropped_diagonal": [("int64_t d = a->Qi[(size_t)j * a->N + j];", "int64_t d = 0;")],
+    "stay_keeps_subset": [("++sub;\n", "")],
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    L = oracle.load_mutant(MUTANTS[name], str(tmp_path))
+    caught = []
+    Q2 = inputs.example2()
+    P1, _, _, pi2 = exact.basic_law_qubo(Q2, 1.0, 1)
+    r = oracle.run(Q2, 1.0, oracle.MODE_BASIC, 60000, n=1, seed=2, num_chains=4, log=False, hist=True,
+                   hist_from=1000, lib_handle=L)
+    caught.append(exact.tv(exact.empirical(r.hist_w), P1) > 0.01)
+    Q = _c1_like(10)
+    pi = exact.target(Q, 0.05)
+    for mode in (oracle.MODE_RF, oracle.MODE_UNBIASED_SYS):
+        r = oracle.run(Q, 0.05, mode, 30000, n=4, L0=100, seed=5, num_chains=8, log=False, hist=True,
+                       hist_from=3000, lib_handle=L)
+        caught.append(exact.tv(exact.empirical(r.hist_w), pi) > 0.01)
+    caught.append(_mean_multiplicity_error(L) > 0.05)
+    assert any(caught), f"planted mistake {name} was not caught"
