@@ -1,0 +1,234 @@
+/*
+ * pns.h - C ABI of the MI355X (gfx950) Partial Neighbor Search sampler.
+ *
+ * The library samples many independent chains on QUBO targets
+ *     pi_beta(x) proportional to exp(-beta * x^T Q x),  x in {0,1}^N
+ * with the single-bit-flip neighbourhood and uniform proposal of the paper's
+ * QUBO application (Sec 4), by one of
+ *   PNS_MODE_RF             Rejection-Free, discrete case (Alg 2, Sec 1.2):
+ *                           every step considers all N neighbours;
+ *   PNS_MODE_BASIC          Basic Partial Neighbor Search (Alg 3, Sec 2): a
+ *                           fresh uniformly random subset of n neighbours
+ *                           every step, p = average over the subset;
+ *   PNS_MODE_UNBIASED_SYS   Unbiased PNS (Alg 6, Sec 3.2) with the systematic
+ *                           partial neighbor sets of Secs 4-5: set i holds
+ *                           bits (i*n + t) mod N, t < n; N/gcd(N,n) sets;
+ *   PNS_MODE_UNBIASED_RAND  Unbiased PNS with a fresh uniformly random set
+ *                           after each block of L0 original samples (Sec 5).
+ * A step (one pass of the loop of Alg 2/3/6) emits one jump-chain record
+ * (J, M): the state before the step and its multiplicity M = 1 + G,
+ * G ~ Geometric(p) counting failures (Sec 1.2, eq. (2)).  In the Unbiased
+ * modes a step whose multiplicity exceeds the remaining budget L emits
+ * (J, M = L), keeps the state and switches to the next set (Alg 6).
+ * The next state is chosen with probability proportional to
+ * min(1, exp(-beta dE_i)) by the inverse-CDF rule of App. C over the subset
+ * in increasing bit order.  Randomness: Philox4x32-10 keyed by the 64-bit
+ * seed, counter (chain id, step low, step high, stream); the draws of a step
+ * depend only on (seed, chain id, step), so results are identical whatever
+ * the launch form, workgroup size or chunking.
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns PNS_OK (0) or a PNS_E* code; the message of the
+ *     last failure on the calling thread is returned by pns_last_error().
+ *     No C++ exception crosses the ABI.
+ *   - A context is not thread-safe: calls on one context must not overlap.
+ *     Work is queued on the context's stream; pns_run is asynchronous and
+ *     every pns_read* call synchronises the stream before returning.
+ *   - Pointers named "host or device" may point to host memory or to memory
+ *     allocated on the context's GPU (hipMalloc, torch tensors); the library
+ *     detects which.  Caller-owned buffers stay owned by the caller.
+ *   - Arrays indexed [chain][bit] are dense row-major with row length N.
+ */
+#ifndef PNS_H
+#define PNS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define PNS_OK 0
+#define PNS_EINVAL 1       /* an argument is out of range or inconsistent   */
+#define PNS_ENOMEM 2       /* device or host allocation failed              */
+#define PNS_EDEVICE 3      /* a HIP runtime call or kernel launch failed    */
+#define PNS_EUNSUPPORTED 4 /* valid request this build does not implement   */
+
+/* ---- methods (Alg 2, Alg 3, Alg 6) ---- */
+#define PNS_MODE_RF 0
+#define PNS_MODE_BASIC 1
+#define PNS_MODE_UNBIASED_SYS 2
+#define PNS_MODE_UNBIASED_RAND 3
+
+/* ---- Q element types ---- */
+#define PNS_I16 0 /* int16 entries: exact int32 fields, int64 energies     */
+#define PNS_I32 1 /* int32 entries: exact int32 or int64 fields            */
+#define PNS_F32 2 /* float entries: fields and energies accumulated in FP64 */
+
+/* ---- Q layouts (Sec 4: "usually symmetric or upper triangular") ---- */
+#define PNS_SYMMETRIC 0 /* full N x N matrix with Q = Q^T (checked)        */
+#define PNS_UPPER 1     /* entries i <= j define x^T Q x; i > j ignored    */
+
+/* ---- initial states J_0 ---- */
+#define PNS_INIT_ZERO 0   /* x = 0                                          */
+#define PNS_INIT_RANDOM 1 /* Bernoulli(1/2) bits from Philox stream 2^29    */
+#define PNS_INIT_GIVEN 2  /* opts->x0                                       */
+
+/* ---- launch forms ---- */
+#define PNS_LAUNCH_PLAIN 0      /* one kernel launch per step; chain state
+                                   round-trips through HBM every step     */
+#define PNS_LAUNCH_PERSISTENT 1 /* one launch runs `chunk` steps with the
+                                   chain state held in registers and LDS  */
+#define PNS_LAUNCH_GRAPH 2      /* the persistent chunk launches captured
+                                   once in a HIP graph and replayed       */
+
+/* Record action of a stay (Unbiased block end). */
+#define PNS_STAY (-1)
+
+typedef struct pns_ctx pns_ctx;
+
+typedef struct pns_opts {
+    int32_t dtype;          /* PNS_I16 / PNS_I32 / PNS_F32 (default I32)          */
+    int32_t layout;         /* PNS_SYMMETRIC / PNS_UPPER (default SYMMETRIC)      */
+    int32_t num_chains;     /* independent chains (default 1)                     */
+    const double* betas;    /* host [num_chains] inverse temperatures (temperature
+                               replicas), or NULL: every chain uses `beta`        */
+    int64_t L0;             /* Unbiased block length in original samples
+                               (default 100, the value of Secs 4-5)               */
+    uint64_t seed;          /* Philox key                                         */
+    uint32_t chain_id_base; /* chain c uses counter word chain_id_base + c        */
+    int32_t init;           /* PNS_INIT_* (default ZERO)                          */
+    const uint8_t* x0;      /* host or device [num_chains][N] for INIT_GIVEN      */
+    int32_t launch;         /* PNS_LAUNCH_* (default PERSISTENT)                  */
+    int32_t chunk;          /* steps per launch in PERSISTENT / GRAPH; 0 = all
+                               steps of a pns_run in one launch                   */
+    int32_t block;          /* threads per workgroup (one workgroup per chain);
+                               0 = chosen from the tuned table                    */
+    int32_t groups;         /* 4-field groups per lane; 0 = chosen with `block`   */
+    void* stream;           /* hipStream_t to queue work on; NULL = a stream the
+                               context creates and owns                           */
+    int64_t log_capacity;   /* per-chain per-step record log, ring of this many
+                               steps (0 = off); read with pns_read_log           */
+    int32_t hist;           /* 1: accumulate, pooled over chains, the multiplicity-
+                               weighted and the visit histograms over all 2^N
+                               states (N <= 24); read with pns_read_hist          */
+    int32_t snapshot_every; /* > 0: every this many steps store the record (state
+                               bits, M, E) of each chain; read with
+                               pns_read_snapshots (0 = off)                       */
+    int32_t snapshot_capacity; /* snapshots kept per chain (ring)               */
+    int32_t reserved[8];    /* must be zero                                       */
+} pns_opts;
+
+/* Per-chain counters since creation. */
+typedef struct pns_chain_stats {
+    int64_t steps;      /* records emitted (jump sample size K)                 */
+    int64_t flips;      /* moves                                                */
+    int64_t stays;      /* Unbiased block-end stays                             */
+    int64_t saturated;  /* records whose multiplicity saturated at 2^63-1 (p
+                           underflowed to 0)                                     */
+    double sum_M;       /* original sample size sum of M (effective MH steps)    */
+    int64_t anomalies;  /* selections that found no positive weight in the
+                           chosen interval (rounding safeguard; expected 0)     */
+} pns_chain_stats;
+
+/* Fill *opts with the defaults documented above. */
+void pns_opts_default(pns_opts* opts);
+
+/*
+ * Create a sampler for Q (N x N, row-major, element type opts->dtype, host or
+ * device), copied into device memory (the caller keeps Q).  beta >= 0 is
+ * used for every chain unless opts->betas is given.  subset_size is n in
+ * [1, N] for BASIC and the UNBIASED modes and is ignored by RF (n = N).
+ * The initial fields h = Q_offdiag x0 and energies x0^T Q x0 are computed on
+ * the GPU.  On success *out owns all device memory of the sampler until
+ * pns_destroy.
+ * Errors: PNS_EINVAL (N <= 0, n outside [1, N], beta < 0 or not finite,
+ *         unknown dtype/layout/mode/launch, SYMMETRIC Q not symmetric, a field
+ *         bound overflowing 62 bits, hist with N > 24), PNS_ENOMEM,
+ *         PNS_EDEVICE, PNS_EUNSUPPORTED (N above the largest tuned tile).
+ */
+int pns_create(pns_ctx** out, const void* Q, int32_t N, double beta, int32_t subset_size, int32_t mode,
+               const pns_opts* opts);
+
+/*
+ * Advance every chain by `steps` steps (records), queued on the context's
+ * stream; returns before the GPU finishes.  steps >= 0.
+ * Errors: PNS_EINVAL (steps < 0), PNS_EDEVICE (launch failure).
+ */
+int pns_run(pns_ctx* ctx, int64_t steps);
+
+/*
+ * Last completed record of every chain (the paper's (J_{k-1}, M_{k-1})):
+ * states [num_chains][N] (uint8 0/1), multiplicities [num_chains] and
+ * energies x^T Q x of those states [num_chains] (FP64; exact for integer Q
+ * while |E| < 2^53).  Any pointer may be NULL; each is host or device.
+ * Before the first step the record is (J_0, 0, E(J_0)).  Synchronises.
+ */
+int pns_read(pns_ctx* ctx, uint8_t* states, int64_t* multiplicities, double* energies);
+
+/*
+ * Current state J_k (the state after the last step) of every chain:
+ * states [num_chains][N], energies [num_chains], fields [num_chains][N] of the
+ * context's field type (int32 for I16 and bounded I32, int64 for other I32,
+ * double for F32; query with pns_field_type), remaining budgets L
+ * [num_chains], systematic set indices [num_chains] and step counters
+ * [num_chains].  Any pointer may be NULL; each is host or device.
+ * The field of bit j is h_j = sum_{i != j} Q_ji x_i for SYMMETRIC Q and
+ * sum_{i != j} Q_min(i,j),max(i,j) x_i for UPPER Q, so that
+ * dE_j = (1 - 2 x_j)(Q_jj + s h_j), s = 2 (SYMMETRIC) or 1 (UPPER).
+ * Synchronises.
+ */
+int pns_read_current(pns_ctx* ctx, uint8_t* states, double* energies, void* fields, int64_t* L, int64_t* set_index,
+                     int64_t* step);
+
+/* Field element type of pns_read_current: 0 = int32, 1 = int64, 2 = double. */
+int pns_field_type(const pns_ctx* ctx);
+
+/*
+ * Per-step log ring [num_chains][log_capacity]: step k of a chain is at slot
+ * k mod log_capacity.  actions: flipped bit or PNS_STAY; multiplicities M;
+ * energies of the record's state (FP64); p = escape probability of the step
+ * (subset average of min(1, pi(y)/pi(x))).  Any pointer may be NULL; each is
+ * host or device.  Errors: PNS_EINVAL if the log is off.  Synchronises.
+ */
+int pns_read_log(pns_ctx* ctx, int32_t* actions, int64_t* multiplicities, double* energies, double* p);
+
+/* Histograms [2^N] (uint64, pooled over chains): sum of M and number of
+ * records per state x = sum_j x_j 2^j.  Host or device.  Synchronises. */
+int pns_read_hist(pns_ctx* ctx, uint64_t* hist_weighted, uint64_t* hist_visits);
+
+/* Zero both histograms (e.g. after burn-in), queued on the stream. */
+int pns_hist_clear(pns_ctx* ctx);
+
+/*
+ * Snapshots [num_chains][count]: states [num_chains][count][N] (uint8),
+ * multiplicities and energies of the records taken every snapshot_every
+ * steps; *count receives the number stored per chain (at most
+ * snapshot_capacity).  Synchronises.
+ */
+int pns_read_snapshots(pns_ctx* ctx, uint8_t* states, int64_t* multiplicities, double* energies, int32_t* count);
+
+/* Per-chain counters [num_chains] into host memory.  Synchronises. */
+int pns_stats(pns_ctx* ctx, pns_chain_stats* stats);
+
+/* Wait for all queued work of the context. */
+int pns_sync(pns_ctx* ctx);
+
+/* Release every resource of the context (NULL is accepted). */
+int pns_destroy(pns_ctx* ctx);
+
+/* Workgroup size and 4-field groups per lane the context runs with. */
+int pns_tile(const pns_ctx* ctx, int32_t* block, int32_t* groups);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* pns_last_error(void);
+
+/* Library version, e.g. "0.1.0". */
+const char* pns_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PNS_H */

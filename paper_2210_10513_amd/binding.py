@@ -1,0 +1,322 @@
+"""Thin ctypes binding of libpns.so (declarations in include/pns.h).
+
+Functions keep the C names (``pns_create``, ``pns_run``, ``pns_read`` ...) and
+only marshal arguments: numpy arrays and torch tensors (host or device) are
+passed as raw pointers, every step of the sampler runs in the library's HIP
+kernels.  There is no fallback: if the library is missing or fails to load,
+importing this module raises.
+
+``Sampler`` is a small convenience wrapper that owns one context and returns
+numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libpns.so")
+
+PNS_OK, PNS_EINVAL, PNS_ENOMEM, PNS_EDEVICE, PNS_EUNSUPPORTED = 0, 1, 2, 3, 4
+PNS_MODE_RF, PNS_MODE_BASIC, PNS_MODE_UNBIASED_SYS, PNS_MODE_UNBIASED_RAND = 0, 1, 2, 3
+PNS_I16, PNS_I32, PNS_F32 = 0, 1, 2
+PNS_SYMMETRIC, PNS_UPPER = 0, 1
+PNS_INIT_ZERO, PNS_INIT_RANDOM, PNS_INIT_GIVEN = 0, 1, 2
+PNS_LAUNCH_PLAIN, PNS_LAUNCH_PERSISTENT, PNS_LAUNCH_GRAPH = 0, 1, 2
+PNS_STAY = -1
+
+MODES = {"rf": PNS_MODE_RF, "basic": PNS_MODE_BASIC, "unbiased_sys": PNS_MODE_UNBIASED_SYS,
+         "unbiased_rand": PNS_MODE_UNBIASED_RAND}
+LAUNCHES = {"plain": PNS_LAUNCH_PLAIN, "persistent": PNS_LAUNCH_PERSISTENT, "graph": PNS_LAUNCH_GRAPH}
+INITS = {"zero": PNS_INIT_ZERO, "random": PNS_INIT_RANDOM, "given": PNS_INIT_GIVEN}
+LAYOUTS = {"symmetric": PNS_SYMMETRIC, "upper": PNS_UPPER}
+
+EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_current", "pns_field_type",
+           "pns_read_log", "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync",
+           "pns_destroy", "pns_tile", "pns_last_error", "pns_version"]
+
+
+class pns_opts(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int32), ("layout", ctypes.c_int32), ("num_chains", ctypes.c_int32),
+        ("betas", ctypes.c_void_p), ("L0", ctypes.c_int64), ("seed", ctypes.c_uint64),
+        ("chain_id_base", ctypes.c_uint32), ("init", ctypes.c_int32), ("x0", ctypes.c_void_p),
+        ("launch", ctypes.c_int32), ("chunk", ctypes.c_int32), ("block", ctypes.c_int32),
+        ("groups", ctypes.c_int32), ("stream", ctypes.c_void_p), ("log_capacity", ctypes.c_int64),
+        ("hist", ctypes.c_int32), ("snapshot_every", ctypes.c_int32), ("snapshot_capacity", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 8),
+    ]
+
+
+class pns_chain_stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("flips", ctypes.c_int64), ("stays", ctypes.c_int64),
+                ("saturated", ctypes.c_int64), ("sum_M", ctypes.c_double), ("anomalies", ctypes.c_int64)]
+
+
+class PNSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pns error {code}: {msg}")
+        self.code = code
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2210_10513_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.pns_opts_default.argtypes = [ctypes.POINTER(pns_opts)]
+    L.pns_opts_default.restype = None
+    L.pns_create.argtypes = [ctypes.POINTER(vp), vp, i32, dbl, i32, i32, ctypes.POINTER(pns_opts)]
+    L.pns_run.argtypes = [vp, i64]
+    L.pns_read.argtypes = [vp, vp, vp, vp]
+    L.pns_read_current.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.pns_field_type.argtypes = [vp]
+    L.pns_read_log.argtypes = [vp, vp, vp, vp, vp]
+    L.pns_read_hist.argtypes = [vp, vp, vp]
+    L.pns_hist_clear.argtypes = [vp]
+    L.pns_read_snapshots.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i32)]
+    L.pns_stats.argtypes = [vp, ctypes.POINTER(pns_chain_stats)]
+    L.pns_sync.argtypes = [vp]
+    L.pns_destroy.argtypes = [vp]
+    L.pns_tile.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.pns_last_error.argtypes = []
+    L.pns_last_error.restype = ctypes.c_char_p
+    L.pns_version.argtypes = []
+    L.pns_version.restype = ctypes.c_char_p
+    for name in ("pns_create", "pns_run", "pns_read", "pns_read_current", "pns_field_type", "pns_read_log",
+                 "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync", "pns_destroy",
+                 "pns_tile"):
+        getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int) -> None:
+    if rc != PNS_OK:
+        raise PNSError(rc, lib.pns_last_error().decode())
+
+
+def _addr(a) -> Optional[int]:
+    """Raw pointer of a numpy array or torch tensor (host or device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays passed to the library must be C-contiguous")
+        return a.ctypes.data
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensors passed to the library must be contiguous")
+        return a.data_ptr()
+    raise TypeError(f"cannot pass {type(a)} to the library")
+
+
+# ---- C-named wrappers (argument marshalling only) ----
+
+def pns_opts_default() -> pns_opts:
+    o = pns_opts()
+    lib.pns_opts_default(ctypes.byref(o))
+    return o
+
+
+def pns_create(Q, N: int, beta: float, subset_size: int, mode: int, opts: Optional[pns_opts] = None) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(lib.pns_create(ctypes.byref(ctx), _addr(Q), N, beta, subset_size, mode,
+                          ctypes.byref(opts) if opts is not None else None))
+    return ctx
+
+
+def pns_run(ctx, steps: int) -> None:
+    _check(lib.pns_run(ctx, steps))
+
+
+def pns_read(ctx, states=None, multiplicities=None, energies=None) -> None:
+    _check(lib.pns_read(ctx, _addr(states), _addr(multiplicities), _addr(energies)))
+
+
+def pns_read_current(ctx, states=None, energies=None, fields=None, L=None, set_index=None, step=None) -> None:
+    _check(lib.pns_read_current(ctx, _addr(states), _addr(energies), _addr(fields), _addr(L), _addr(set_index),
+                                _addr(step)))
+
+
+def pns_field_type(ctx) -> int:
+    return int(lib.pns_field_type(ctx))
+
+
+def pns_read_log(ctx, actions=None, multiplicities=None, energies=None, p=None) -> None:
+    _check(lib.pns_read_log(ctx, _addr(actions), _addr(multiplicities), _addr(energies), _addr(p)))
+
+
+def pns_read_hist(ctx, hist_weighted=None, hist_visits=None) -> None:
+    _check(lib.pns_read_hist(ctx, _addr(hist_weighted), _addr(hist_visits)))
+
+
+def pns_hist_clear(ctx) -> None:
+    _check(lib.pns_hist_clear(ctx))
+
+
+def pns_read_snapshots(ctx, states=None, multiplicities=None, energies=None) -> int:
+    cnt = ctypes.c_int32()
+    _check(lib.pns_read_snapshots(ctx, _addr(states), _addr(multiplicities), _addr(energies), ctypes.byref(cnt)))
+    return cnt.value
+
+
+def pns_stats(ctx, num_chains: int):
+    arr = (pns_chain_stats * num_chains)()
+    _check(lib.pns_stats(ctx, arr))
+    return arr
+
+
+def pns_sync(ctx) -> None:
+    _check(lib.pns_sync(ctx))
+
+
+def pns_destroy(ctx) -> None:
+    _check(lib.pns_destroy(ctx))
+
+
+def pns_tile(ctx):
+    b, g = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.pns_tile(ctx, ctypes.byref(b), ctypes.byref(g)))
+    return b.value, g.value
+
+
+def pns_last_error() -> str:
+    return lib.pns_last_error().decode()
+
+
+def pns_version() -> str:
+    return lib.pns_version().decode()
+
+
+# ---- convenience wrapper ----
+
+_DTYPES = {np.dtype(np.int16): PNS_I16, np.dtype(np.int32): PNS_I32, np.dtype(np.float32): PNS_F32}
+_FIELD_DTYPES = {0: np.int32, 1: np.int64, 2: np.float64}
+
+
+class Sampler:
+    """One sampler context.  ``Q`` is a numpy array or torch tensor of int16,
+    int32 or float32 (host or device); results come back as numpy arrays."""
+
+    def __init__(self, Q, beta=1.0, subset_size: int = 0, mode="rf", *, num_chains: int = 1, L0: int = 100,
+                 seed: int = 0, init="zero", x0=None, layout="symmetric", launch="persistent", chunk: int = 0,
+                 block: int = 0, groups: int = 0, stream=None, log_capacity: int = 0, hist: bool = False,
+                 snapshot_every: int = 0, snapshot_capacity: int = 0, chain_id_base: int = 0):
+        if hasattr(Q, "data_ptr"):
+            import torch
+            dt = {torch.int16: PNS_I16, torch.int32: PNS_I32, torch.float32: PNS_F32}[Q.dtype]
+            self.N = int(Q.shape[0])
+            self._Q = Q.contiguous()
+        else:
+            Qa = np.ascontiguousarray(Q)
+            if Qa.dtype not in _DTYPES:
+                raise TypeError("Q must be int16, int32 or float32")
+            dt = _DTYPES[Qa.dtype]
+            self.N = int(Qa.shape[0])
+            self._Q = Qa
+        self.num_chains = num_chains
+        self.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        o = pns_opts_default()
+        o.dtype = dt
+        o.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+        o.num_chains = num_chains
+        betas = np.broadcast_to(np.asarray(beta, dtype=np.float64), (num_chains,)).copy()
+        self._betas = betas
+        o.betas = betas.ctypes.data
+        o.L0 = L0
+        o.seed = seed
+        o.chain_id_base = chain_id_base
+        o.init = INITS[init] if isinstance(init, str) else int(init)
+        if x0 is not None:
+            o.init = PNS_INIT_GIVEN
+            self._x0 = np.ascontiguousarray(np.broadcast_to(np.asarray(x0, dtype=np.uint8), (num_chains, self.N)))
+            o.x0 = self._x0.ctypes.data
+        o.launch = LAUNCHES[launch] if isinstance(launch, str) else int(launch)
+        o.chunk = chunk
+        o.block = block
+        o.groups = groups
+        if stream is not None:
+            o.stream = stream if isinstance(stream, int) else stream.cuda_stream
+        o.log_capacity = log_capacity
+        o.hist = 1 if hist else 0
+        o.snapshot_every = snapshot_every
+        o.snapshot_capacity = snapshot_capacity
+        self.log_capacity = log_capacity
+        self.snapshot_capacity = snapshot_capacity
+        self.ctx = pns_create(self._Q, self.N, float(betas[0]), subset_size, self.mode, o)
+
+    def run(self, steps: int) -> "Sampler":
+        pns_run(self.ctx, steps)
+        return self
+
+    def sync(self) -> None:
+        pns_sync(self.ctx)
+
+    def read(self):
+        C, N = self.num_chains, self.N
+        s = np.zeros((C, N), np.uint8)
+        m = np.zeros(C, np.int64)
+        e = np.zeros(C, np.float64)
+        pns_read(self.ctx, s, m, e)
+        return s, m, e
+
+    def read_current(self):
+        C, N = self.num_chains, self.N
+        s = np.zeros((C, N), np.uint8)
+        e = np.zeros(C, np.float64)
+        h = np.zeros((C, N), _FIELD_DTYPES[pns_field_type(self.ctx)])
+        L = np.zeros(C, np.int64)
+        sub = np.zeros(C, np.int64)
+        k = np.zeros(C, np.int64)
+        pns_read_current(self.ctx, s, e, h, L, sub, k)
+        return {"x": s, "E": e, "h": h, "L": L, "sub": sub, "step": k}
+
+    def read_log(self):
+        C, K = self.num_chains, self.log_capacity
+        a = np.zeros((C, K), np.int32)
+        m = np.zeros((C, K), np.int64)
+        e = np.zeros((C, K), np.float64)
+        p = np.zeros((C, K), np.float64)
+        pns_read_log(self.ctx, a, m, e, p)
+        return {"action": a, "M": m, "E": e, "p": p}
+
+    def read_hist(self):
+        w = np.zeros(1 << self.N, np.uint64)
+        v = np.zeros(1 << self.N, np.uint64)
+        pns_read_hist(self.ctx, w, v)
+        return w, v
+
+    def hist_clear(self) -> None:
+        pns_hist_clear(self.ctx)
+
+    def read_snapshots(self):
+        C, S, N = self.num_chains, self.snapshot_capacity, self.N
+        x = np.zeros((C, S, N), np.uint8)
+        m = np.zeros((C, S), np.int64)
+        e = np.zeros((C, S), np.float64)
+        cnt = pns_read_snapshots(self.ctx, x, m, e)
+        return x, m, e, cnt
+
+    def stats(self):
+        arr = pns_stats(self.ctx, self.num_chains)
+        return {k: np.array([getattr(s, k) for s in arr]) for k in ("steps", "flips", "stays", "saturated", "sum_M", "anomalies")}
+
+    def tile(self):
+        return pns_tile(self.ctx)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            pns_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,106 @@
+// Internal interface between the C-ABI runtime (pns_runtime.cpp) and the
+// HIP kernels (pns_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pns {
+
+enum QType : int32_t { Q_I16 = 0, Q_I32 = 1, Q_F32 = 2 };
+enum HType : int32_t { H_I32 = 0, H_I64 = 1, H_F64 = 2 };
+
+// One QUBO problem as the kernels see it.  A holds the off-diagonal part of
+// the coefficient matrix with a zero diagonal, row-major with `pitch`
+// elements per row (pitch is a multiple of 64, padding entries are zero);
+// diag holds Q_jj widened to int32 (integer Q) or float (F32 Q).  A bit flip
+// of c changes the field of j by +-A[c][j] and dE_j = (1-2x_j)(diag_j + s h_j).
+struct Problem {
+    const void* A;
+    const void* diag;
+    int64_t pitch;
+    int64_t num_sets;  // systematic sets N / gcd(N, n)
+    int64_t L0;
+    int32_t N;
+    int32_t n;
+    int32_t s;         // 2 for symmetric input, 1 for upper-triangular input
+    int32_t qtype;     // QType
+};
+
+// Everything a step kernel launch needs.  Chain c of the context stores its
+// state at field offset foff[c] (fields x, h, rand-set membership) and at
+// index c in the per-chain arrays.
+struct StepArgs {
+    const Problem* problems;
+    const int32_t* chain_problem;   // [C]
+    const int64_t* foff;            // [C]
+    const int32_t* chain_list;      // chains of this launch (NULL: chain_first + blockIdx.x)
+    int32_t chain_first;
+    int32_t mode;
+    int64_t steps;                  // steps per chain in this launch
+    uint64_t seed;
+    const double* beta;             // [C]
+    const uint32_t* chain_id;       // [C]
+    // chain state
+    uint8_t* x;                     // [fields]
+    void* h;                        // [fields] of the field type
+    uint8_t* rmem;                  // [fields] random-set membership (UNBIASED_RAND)
+    int64_t* E;                     // [C] energy bits (int64 or double)
+    int64_t* L;                     // [C]
+    int64_t* sub;                   // [C]
+    int64_t* step;                  // [C]
+    int32_t* last_action;           // [C]
+    int64_t* last_M;                // [C]
+    int64_t* last_E;                // [C] energy bits of the last record
+    // counters [C][6]: steps, flips, stays, saturated, sum_M (double bits),
+    // anomalies (selection found no positive weight; must stay 0)
+    int64_t* counters;
+    // optional outputs
+    int32_t* log_action;            // [C][log_cap]
+    int64_t* log_M;
+    int64_t* log_E;                 // energy bits
+    double* log_p;
+    int64_t log_cap;
+    unsigned long long* hist_w;     // [2^N]
+    unsigned long long* hist_v;
+    int32_t snap_every;
+    int32_t snap_cap;
+    uint8_t* snap_x;                // [C][snap_cap][snap_pitch]
+    int64_t* snap_M;                // [C][snap_cap]
+    int64_t* snap_E;                // [C][snap_cap]
+    int32_t* snap_count;            // [C]
+    int64_t snap_pitch;
+};
+
+struct InitArgs {
+    const Problem* problems;
+    const int32_t* chain_problem;
+    const int64_t* foff;
+    int32_t num_chains;
+    int32_t init;                   // 0 zero, 1 random, 2 given (x already in place)
+    uint64_t seed;
+    const uint32_t* chain_id;
+    uint8_t* x;
+    void* h;
+    int64_t* E;
+    int64_t* last_E;
+};
+
+// Step kernel launch for one (block, groups) tile shape, field type and Q
+// type.  Returns hipSuccess or the launch error.  dyn_lds is the dynamic LDS
+// byte count (random-subset modes).
+hipError_t launch_steps(int32_t qtype, int32_t htype, int32_t block, int32_t groups, int32_t grid,
+                        size_t dyn_lds, hipStream_t stream, const StepArgs& args);
+
+// True if a kernel exists for this tile shape and types.
+bool have_tile(int32_t qtype, int32_t htype, int32_t block, int32_t groups);
+
+// Initial bits (random policy), fields h = A x and energies of every chain.
+// host_chain_problem mirrors args.chain_problem on the host.
+hipError_t launch_init_with_map(int32_t qtype, int32_t htype, int32_t max_pitch, hipStream_t stream,
+                                const InitArgs& args, const int32_t* host_chain_problem);
+
+// Fill `count` 64-bit words with a value (graph-safe alternative to memset).
+hipError_t launch_fill64(void* p, int64_t count, int64_t value, hipStream_t stream);
+
+}  // namespace pns

@@ -1,0 +1,218 @@
+"""GPU parity: the HIP sampler against the CPU oracle on the same seeded
+inputs, element by element (records, final states, fields, energies), plus
+the enumeration checks of the stationary laws on GPU output."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+from paper_2210_10513_amd import inputs
+
+from parity_util import compare_final, compare_logs, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(Q, beta, mode, K, *, chains, rows=None, is_int=True, **kw):
+    g = gpu_run(Q, beta, mode, K, chains=chains, **kw)
+    rows = list(range(chains)) if rows is None else list(rows)
+    okw = {k: v for k, v in kw.items() if k in ("n", "L0", "seed", "init", "layout")}
+    o = oracle_run(Q, beta, mode, K, chains=[kw.get("chain_id_base", 0) + r for r in rows], **okw)
+    n = compare_logs(g["log"], o, chain_rows=rows, is_int=is_int)
+    if n == len(rows) * K:
+        compare_final(g["cur"], o, chain_rows=rows, is_int=is_int)
+    assert (g["stats"]["anomalies"] == 0).all()
+    return g, o
+
+
+# ---------------------------------------------------------------------------
+# Bit-exact records on small and ragged shapes, every mode
+# ---------------------------------------------------------------------------
+
+def test_basic_n16_int32_config_shape():
+    """Basic PNS, N=16 int32 U{-50..50}, beta=0.05, subset 4."""
+    Q = inputs.c1_basic_n16().Q
+    _both(Q, 0.05, "basic", 3000, chains=8, n=4, seed=11)
+
+
+@pytest.mark.parametrize("mode,n", [("rf", 0), ("basic", 5), ("unbiased_sys", 7), ("unbiased_rand", 6)])
+@pytest.mark.parametrize("N", [1, 5, 16, 67, 300])
+def test_all_modes_ragged_int(mode, n, N):
+    n = min(max(n, 1), N)
+    Q = inputs.symmetric_int(N, -50, 50, np.int32, seed=100 + N)
+    _both(Q, 0.05, mode, 600, chains=3, n=n, L0=13, seed=5)
+
+
+@pytest.mark.parametrize("mode,n", [("rf", 0), ("basic", 64), ("unbiased_sys", 100), ("unbiased_rand", 100)])
+def test_int16_n1000_ragged_tile(mode, n):
+    Q = inputs.symmetric_int(1000, -100, 100, np.int16, seed=7)
+    _both(Q, 0.01, mode, 400, chains=2, n=n, L0=100, seed=3)
+
+
+@pytest.mark.parametrize("mode,n", [("rf", 0), ("unbiased_sys", 50), ("basic", 20)])
+def test_float32_fields_in_fp64(mode, n):
+    Q = inputs.symmetric_gauss(500, seed=9)
+    _both(Q, 3.0, mode, 500, chains=2, n=n, L0=100, seed=8, is_int=False)
+
+
+def test_upper_triangular_layout():
+    rng = np.random.default_rng(4)
+    U = np.triu(rng.integers(-40, 41, size=(70, 70))).astype(np.int32)
+    _both(U, 0.05, "unbiased_sys", 800, chains=2, n=16, L0=20, seed=2, layout="upper")
+
+
+def test_random_initial_state_and_fields():
+    Q = inputs.symmetric_int(200, -100, 100, np.int32, seed=12)
+    _both(Q, 0.02, "rf", 300, chains=3, seed=21, init="random")
+    Qf = inputs.symmetric_gauss(300, seed=13)
+    _both(Qf, 2.0, "unbiased_sys", 300, chains=2, n=32, seed=22, init="random", is_int=False)
+
+
+def test_int32_wide_fields_use_int64():
+    Q = inputs.symmetric_int(64, -2_000_000_000, 2_000_000_000, np.int32, seed=3)
+    g, o = _both(Q, 1e-9, "rf", 300, chains=2, seed=4)
+
+
+# ---------------------------------------------------------------------------
+# Independence of tile shape, launch form and chunking
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tile", [(64, 4), (128, 4), (256, 1), (256, 4), (512, 2)])
+def test_tile_shape_does_not_change_results(tile):
+    Q = inputs.symmetric_int(1000, -100, 100, np.int16, seed=31)
+    ref = gpu_run(Q, 0.01, "basic", 300, chains=2, n=64, seed=1)
+    got = gpu_run(Q, 0.01, "basic", 300, chains=2, n=64, seed=1, block=tile[0], groups=tile[1])
+    assert got["tile"] == tile
+    for key in ("action", "M", "E"):
+        assert np.array_equal(ref["log"][key], got["log"][key])
+
+
+@pytest.mark.parametrize("launch,chunk", [("plain", 0), ("persistent", 37), ("graph", 50), ("graph", 0)])
+def test_launch_forms_agree(launch, chunk):
+    Q = inputs.symmetric_int(300, -100, 100, np.int16, seed=32)
+    ref = gpu_run(Q, 0.02, "unbiased_rand", 200, chains=3, n=40, L0=30, seed=1)
+    got = gpu_run(Q, 0.02, "unbiased_rand", 200, chains=3, n=40, L0=30, seed=1, launch=launch, chunk=chunk)
+    for key in ("action", "M", "E", "p"):
+        assert np.array_equal(ref["log"][key], got["log"][key])
+    assert np.array_equal(ref["cur"]["h"], got["cur"]["h"])
+
+
+def test_graph_replays_continue_the_chain():
+    from paper_2210_10513_amd.binding import Sampler
+    Q = inputs.symmetric_int(128, -100, 100, np.int32, seed=33)
+    a = Sampler(Q, 0.03, 0, "rf", num_chains=4, seed=9, launch="graph", chunk=25, log_capacity=300)
+    for _ in range(3):
+        a.run(100)
+    la = a.read_log()
+    b = Sampler(Q, 0.03, 0, "rf", num_chains=4, seed=9, launch="persistent", log_capacity=300)
+    b.run(300)
+    lb = b.read_log()
+    for key in ("action", "M", "E"):
+        assert np.array_equal(la[key], lb[key])
+    a.close()
+    b.close()
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+# ---------------------------------------------------------------------------
+
+def test_infinite_temperature_unbiased_schedule():
+    Q = inputs.symmetric_int(8, -5, 5, np.int32, seed=1)
+    g = gpu_run(Q, 0.0, "unbiased_sys", 40, chains=1, n=2, L0=3, seed=1)
+    a, M = g["log"]["action"][0], g["log"]["M"][0]
+    assert all((a[k] == -1 and M[k] == 0) if k % 4 == 3 else (a[k] >= 0 and M[k] == 1) for k in range(40))
+
+
+def test_frozen_chain_saturates():
+    Q = (np.diag(np.arange(1, 7)) * 1000).astype(np.int32)
+    g = gpu_run(Q, 10.0, "rf", 3, chains=1, seed=1)
+    o = oracle_run(Q, 10.0, "rf", 3, chains=[0], seed=1)
+    assert g["log"]["M"][0, 0] == np.iinfo(np.int64).max == o.M[0, 0]
+    assert g["log"]["action"][0, 0] == o.action[0, 0] == 0
+    assert g["stats"]["saturated"][0] >= 1
+
+
+def test_basic_full_subset_equals_rf_and_stats_sum():
+    Q = inputs.symmetric_int(90, -50, 50, np.int32, seed=14)
+    a = gpu_run(Q, 0.05, "rf", 500, chains=2, seed=3)
+    b = gpu_run(Q, 0.05, "basic", 500, chains=2, n=90, seed=3)
+    assert np.array_equal(a["log"]["action"], b["log"]["action"]) and np.array_equal(a["log"]["M"], b["log"]["M"])
+    assert np.allclose(a["stats"]["sum_M"], a["log"]["M"].astype(float).sum(axis=1))
+    assert (a["stats"]["flips"] == 500).all() and (a["stats"]["steps"] == 500).all()
+    # pns_read returns the last record
+    s, m, e = a["rec"]
+    assert np.array_equal(m, a["log"]["M"][:, -1]) and np.array_equal(e, a["log"]["E"][:, -1])
+
+
+def test_device_buffers_in_and_out():
+    torch = pytest.importorskip("torch")
+    from paper_2210_10513_amd import binding as b
+    Qn = inputs.symmetric_int(100, -50, 50, np.int32, seed=15)
+    Qd = torch.from_numpy(Qn).cuda()
+    s = b.Sampler(Qd, 0.05, 10, "unbiased_sys", num_chains=2, seed=4, log_capacity=50,
+                  stream=torch.cuda.current_stream())
+    s.run(50)
+    st = torch.zeros((2, 100), dtype=torch.uint8, device="cuda")
+    m = torch.zeros(2, dtype=torch.int64, device="cuda")
+    e = torch.zeros(2, dtype=torch.float64, device="cuda")
+    b.pns_read(s.ctx, st, m, e)
+    s2, m2, e2 = s.read()
+    assert np.array_equal(st.cpu().numpy(), s2) and np.array_equal(m.cpu().numpy(), m2)
+    assert np.array_equal(e.cpu().numpy(), e2)
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# Stationary laws of GPU output against brute-force enumeration
+# ---------------------------------------------------------------------------
+
+def _gpu_hist(Q, beta, mode, burn, K, chains, n=0, L0=100, seed=1):
+    from paper_2210_10513_amd.binding import Sampler
+    s = Sampler(Q, beta, n, mode, num_chains=chains, L0=L0, seed=seed, hist=True)
+    s.run(burn)
+    s.hist_clear()
+    s.run(K)
+    w, v = s.read_hist()
+    s.close()
+    return w, v
+
+
+@pytest.mark.parametrize("mode,n", [("rf", 0), ("unbiased_sys", 4), ("unbiased_rand", 4)])
+def test_enumeration_tv_rf_and_unbiased(mode, n):
+    Q = inputs.c1_basic_n16().Q
+    pi = exact.target(Q.astype(np.int64), 0.05)
+    w, _ = _gpu_hist(Q, 0.05, mode, 20000, 200000, chains=64, n=n)
+    assert exact.tv(exact.empirical(w), pi) < 0.01
+
+
+def test_basic_pns_jump_law_on_gpu():
+    Q = inputs.c1_basic_n16().Q
+    P, mu, EM, pi = exact.basic_law_qubo(Q.astype(np.int64), 0.05, 4)
+    w, v = _gpu_hist(Q, 0.05, "basic", 20000, 200000, chains=64, n=4)
+    assert exact.tv(exact.empirical(v), mu) < 0.01
+    assert exact.tv(exact.empirical(w), pi) > 0.5  # Basic PNS stays biased
+
+
+# ---------------------------------------------------------------------------
+# Full configuration sizes, sampled chains in the benchmark's launch shape
+# ---------------------------------------------------------------------------
+
+def test_rf_n1024_int16_full_batch_sampled_chains():
+    w = inputs.c2_rf_n1024()
+    g = gpu_run(w.Q, 0.01, "rf", 300, chains=1024, seed=2210105130)
+    rows = [0, 1, 511, 1023]
+    o = oracle_run(w.Q, 0.01, "rf", 300, chains=rows, seed=2210105130)
+    assert compare_logs(g["log"], o, chain_rows=rows, is_int=True) == len(rows) * 300
+    compare_final(g["cur"], o, chain_rows=rows, is_int=True)
+
+
+def test_unbiased_n8192_f32_sampled_chains():
+    w = inputs.c3_unbiased_n8192(replicas=16)
+    betas = w.betas
+    g = gpu_run(w.Q, betas, "unbiased_sys", 150, chains=len(betas), n=512, L0=100, seed=2210105133)
+    rows = [0, 7, 15, 200, 255]
+    Q64 = w.Q
+    o = oracle_run(Q64, betas[rows], "unbiased_sys", 150, chains=rows, n=512, L0=100, seed=2210105133)
+    assert compare_logs(g["log"], o, chain_rows=rows, is_int=False) == len(rows) * 150
+    compare_final(g["cur"], o, chain_rows=rows, is_int=False)
