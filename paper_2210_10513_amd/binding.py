@@ -63,6 +63,14 @@ class PNSError(RuntimeError):
 
 
 def _load() -> ctypes.CDLL:
+    # PyTorch-ROCm ships its own HIP runtime under the same soname; loading it
+    # first makes libpns.so bind to that one runtime, so torch's streams and
+    # device pointers are the library's too (a second runtime in the process
+    # would leave torch without a device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2210_10513_amd.build`")
     L = ctypes.CDLL(LIB_PATH)
