@@ -43,13 +43,13 @@ def _workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def _time_sampler(wl, chain_steps: int, steps: int, warmup: int, launch: str, seed: int):
+def _time_sampler(wl, chain_steps: int, steps: int, warmup: int, launch: str, seed: int, tile=(0, 0)):
     """Returns (seconds per bench step, flips per bench step, sum M per bench step)."""
     import torch
     from paper_2210_10513_amd.binding import Sampler
     stream = torch.cuda.current_stream()
     s = Sampler(wl["Q"], wl["betas"], wl["n"], wl["mode"], num_chains=len(wl["betas"]), L0=wl["L0"], seed=seed,
-                launch=launch, stream=stream)
+                launch=launch, stream=stream, block=tile[0], groups=tile[1])
     for _ in range(warmup):
         s.run(chain_steps)
     s.sync()
@@ -104,6 +104,7 @@ def main():
     ap.add_argument("--workload", default="rf_n1024_int16")
     ap.add_argument("--chain-steps", type=int, default=0, help="sampler steps per chain per bench step (0 = workload)")
     ap.add_argument("--launch", default="persistent")
+    ap.add_argument("--tile", default="", help="workgroup size and 4-field groups per lane, e.g. 64,4")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -121,7 +122,9 @@ def main():
     chain_steps = args.chain_steps or wl["steps"]
     C = len(wl["betas"])
     N = wl["Q"].shape[0]
-    sec, flips, recs, summ, wall, tile = _time_sampler(wl, chain_steps, args.steps, args.warmup, args.launch, seed=1)
+    tile_req = tuple(int(v) for v in args.tile.split(",")) if args.tile else (0, 0)
+    sec, flips, recs, summ, wall, tile = _time_sampler(wl, chain_steps, args.steps, args.warmup, args.launch, seed=1,
+                                                       tile=tile_req)
     value = flips / sec
     bytes_per_flip = N * wl["qbytes"]
     achieved = flips * bytes_per_flip / sec / 1e9

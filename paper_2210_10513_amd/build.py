@@ -20,7 +20,8 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libpns.so")
 ARCH = os.environ.get("PNS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["pns_kernels.hip", "pns_runtime.cpp"]
+SOURCES = ["pns_step_i16.hip", "pns_step_i32.hip", "pns_step_i64.hip", "pns_step_f32.hip", "pns_kernels.hip",
+           "pns_runtime.cpp"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

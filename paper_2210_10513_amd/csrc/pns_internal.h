@@ -87,10 +87,20 @@ struct InitArgs {
 };
 
 // Step kernel launch for one (block, groups) tile shape, field type and Q
-// type.  Returns hipSuccess or the launch error.  dyn_lds is the dynamic LDS
-// byte count (random-subset modes).
-hipError_t launch_steps(int32_t qtype, int32_t htype, int32_t block, int32_t groups, int32_t grid,
-                        size_t dyn_lds, hipStream_t stream, const StepArgs& args);
+// type.  flav: 0 every bit, 1 systematic window, 2 random subset drawn in
+// LDS; instr: per-step log / histograms / snapshots compiled in.  Returns
+// hipSuccess or the launch error; with probe = true only reports whether
+// the tile exists.  dyn_lds is the dynamic LDS byte count (random subsets).
+hipError_t launch_steps(int32_t qtype, int32_t htype, int32_t flav, bool instr, int32_t block, int32_t groups,
+                        int32_t grid, size_t dyn_lds, hipStream_t stream, const StepArgs& args);
+hipError_t launch_steps_i16(int flav, bool instr, int block, int groups, int grid, size_t dyn, hipStream_t st,
+                            const StepArgs& a, bool probe);
+hipError_t launch_steps_i32(int flav, bool instr, int block, int groups, int grid, size_t dyn, hipStream_t st,
+                            const StepArgs& a, bool probe);
+hipError_t launch_steps_i64(int flav, bool instr, int block, int groups, int grid, size_t dyn, hipStream_t st,
+                            const StepArgs& a, bool probe);
+hipError_t launch_steps_f32(int flav, bool instr, int block, int groups, int grid, size_t dyn, hipStream_t st,
+                            const StepArgs& a, bool probe);
 
 // True if a kernel exists for this tile shape and types.
 bool have_tile(int32_t qtype, int32_t htype, int32_t block, int32_t groups);

@@ -212,12 +212,25 @@ struct pns_ctx {
         return a;
     }
 
+    // How the step kernel forms the subset: 0 every bit, 1 systematic window,
+    // 2 random subset drawn in LDS.
+    int32_t flavour() const
+    {
+        if (mode == PNS_MODE_RF) return 0;
+        if (mode == PNS_MODE_BASIC) return n < N ? 2 : 0;
+        if (mode == PNS_MODE_UNBIASED_SYS) return 1;
+        return n < N ? 2 : 1;
+    }
+
+    bool instrumented() const { return log_cap > 0 || hist_w != nullptr || snap_every > 0; }
+
     int launch_chunk(int64_t steps)
     {
         // host-side check that the launch matches what the kernel assumes
         if ((int64_t)block * 4 * groups < N || num_chains < 1 || !have_tile(qtype, htype, block, groups))
             return fail(PNS_EINVAL, "tile %dx%d does not cover N=%d", block, groups, N);
-        hipError_t e = launch_steps(qtype, htype, block, groups, num_chains, dyn_lds, stream, args(steps));
+        hipError_t e = launch_steps(qtype, htype, flavour(), instrumented(), block, groups, num_chains, dyn_lds, stream,
+                                    args(steps));
         if (e != hipSuccess) return hip_fail(e, "step kernel launch");
         return PNS_OK;
     }

@@ -1,0 +1,841 @@
+// Step kernel of the Partial Neighbor Search sampler for gfx950 (MI355X).
+// Included by one translation unit per matrix element type.
+//
+// One workgroup runs one chain.  The chain's N bits are spread over the
+// workgroup in groups of four consecutive bits per lane:
+//     field f = (g * BLOCK + tid) * 4 + v,   g < G, v < 4,
+// so group g covers the contiguous bit range [g*BLOCK*4, (g+1)*BLOCK*4) and a
+// row of the coefficient matrix is read with one 8- or 16-byte load per lane
+// and group, fully coalesced.  Fields, bits and the diagonal stay in
+// registers for the whole launch; only the row of the flipped bit is read
+// from memory each step.
+//
+// Per step (loop body of Alg 2 / Alg 3 / Alg 6):
+//   subset  : all bits (RF), systematic window (Unbiased-sys), random n-subset
+//             (Basic every step, Unbiased-rand per block) drawn in LDS;
+//   weights : w_j = min(1, exp(-beta dE_j)), dE_j = (1-2x_j)(Q_jj + s h_j);
+//             for integer Q, dE is an integer and exp(-beta dE) is read from
+//             two LDS tables, exp(-beta*64a) * exp(-beta*b) for dE = 64a + b;
+//   reduce  : sums of four consecutive bits -> wave inclusive scans (DPP) ->
+//             one LDS exchange -> every wave scans the 256-bit segment sums
+//             the same way, so the rounding of every prefix is fixed by the
+//             bit order alone, whatever the tile shape;
+//   p, M    : p = S / n, M = 1 + floor(log U1 / log1p(-p)) in FP64;
+//   budget  : Unbiased: stay with M = L when M > L, else L -= M (Alg 6);
+//   select  : inverse CDF (App. C) over the subset in increasing bit order,
+//             resolved segment -> lane -> bit, published through LDS;
+//   update  : flip, E += dE_c, h_j +-= A[c][j] from one coalesced row read,
+//             overlapped with the next step's random numbers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "pns_internal.h"
+
+namespace pns {
+namespace step {
+
+constexpr uint32_t kStreamStep = 0u;
+constexpr uint32_t kStreamSubset = 0x40000000u;
+constexpr int kModeRF = 0, kModeBasic = 1, kModeSys = 2, kModeRand = 3;
+
+// Kernel flavours: how the subset of a step is formed.
+constexpr int FLAV_ALL = 0;     // every bit (RF, and Basic with n = N)
+constexpr int FLAV_WINDOW = 1;  // systematic window (Unbiased-sys, Unbiased-rand with n = N)
+constexpr int FLAV_DRAWN = 2;   // random n-subset drawn in LDS (Basic, Unbiased-rand)
+
+// Weight tables for integer energy differences: dE = 64 a + b, b < 64, a < 1024.
+constexpr int kTabLo = 64;
+constexpr int kTabHi = 1024;
+constexpr int64_t kTabMax = (int64_t)kTabLo * kTabHi;
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplications whose halves are mixed with the other counter words and the
+// key; the key advances by the two Weyl increments between rounds.
+struct Words {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t key)
+{
+    uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// The two uniforms of step k: U1 in (0, 1] from words 0, 1 (kept as log U1)
+// and U2 in [0, 1) from words 2, 3, each from the top 53 bits of 64.
+struct StepUniforms {
+    double logU1;
+    double U2;
+};
+
+__device__ __forceinline__ StepUniforms step_uniforms(uint32_t cid, int64_t k, uint64_t seed, bool want_log)
+{
+    const Words o = philox(cid, (uint32_t)k, (uint32_t)((uint64_t)k >> 32), kStreamStep, seed);
+    const double U1 = (double)(((((uint64_t)o.w0 << 32) | o.w1) >> 11) + 1u) * 0x1p-53;
+    const double U2 = (double)((((uint64_t)o.w2 << 32) | o.w3) >> 11) * 0x1p-53;
+    return {want_log ? log(U1) : 0.0, U2};
+}
+
+// ---- wave64 primitives (DPP) ----
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Inclusive prefix sum over the 64 lanes: within rows of 16 by shifts of 1, 2,
+// 4, 8, then the row totals by the broadcasts of lanes 15 and 31.  The order
+// of additions for lane l depends only on l.
+__device__ __forceinline__ double wave_scan(double v)
+{
+    v += dpp_f64<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_f64<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_f64<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_f64<0x118, 0xF>(v);  // row_shr:8
+    v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v |= (uint32_t)__shfl_xor((int)v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int r)
+{
+    for (int i = 0; i < r; ++i) m &= m - 1;
+    return __builtin_ctzll(m);
+}
+
+// ---- four consecutive elements ----
+template <typename T>
+struct Four {
+    T v[4];
+};
+
+__device__ __forceinline__ Four<int32_t> load_row4(const int16_t* p)
+{
+    const uint2 r = *reinterpret_cast<const uint2*>(p);
+    Four<int32_t> o;
+    o.v[0] = (int32_t)(int16_t)(r.x & 0xFFFFu);
+    o.v[1] = (int32_t)(int16_t)(r.x >> 16);
+    o.v[2] = (int32_t)(int16_t)(r.y & 0xFFFFu);
+    o.v[3] = (int32_t)(int16_t)(r.y >> 16);
+    return o;
+}
+__device__ __forceinline__ Four<int32_t> load_row4(const int32_t* p)
+{
+    const int4 r = *reinterpret_cast<const int4*>(p);
+    return {{r.x, r.y, r.z, r.w}};
+}
+__device__ __forceinline__ Four<float> load_row4(const float* p)
+{
+    const float4 r = *reinterpret_cast<const float4*>(p);
+    return {{r.x, r.y, r.z, r.w}};
+}
+
+template <typename T>
+__device__ __forceinline__ Four<T> load4(const T* p)
+{
+    Four<T> o;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) o.v[v] = p[v];
+    return o;
+}
+template <>
+__device__ __forceinline__ Four<int32_t> load4(const int32_t* p)
+{
+    const int4 r = *reinterpret_cast<const int4*>(p);
+    return {{r.x, r.y, r.z, r.w}};
+}
+template <>
+__device__ __forceinline__ Four<float> load4(const float* p)
+{
+    const float4 r = *reinterpret_cast<const float4*>(p);
+    return {{r.x, r.y, r.z, r.w}};
+}
+template <typename T>
+__device__ __forceinline__ void store4(T* p, const T* v)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) p[i] = v[i];
+}
+template <>
+__device__ __forceinline__ void store4(int32_t* p, const int32_t* v)
+{
+    *reinterpret_cast<int4*>(p) = make_int4(v[0], v[1], v[2], v[3]);
+}
+
+template <typename QT>
+struct Wide {
+    using T = int32_t;
+};
+template <>
+struct Wide<float> {
+    using T = float;
+};
+
+// Energy difference of flipping a bit with value xbit: integer or FP64.
+// (int32 fields: |Q_jj| + s |h_j| < 2^31 is checked on creation.)
+template <typename HT>
+__device__ __forceinline__ HT delta_int(int32_t d, HT h, int s, uint32_t xbit)
+{
+    const HT e = (HT)d + (s == 2 ? (HT)(h + h) : h);
+    return xbit ? -e : e;
+}
+__device__ __forceinline__ double delta_f64(float d, double h, int s, uint32_t xbit)
+{
+    const double e = (double)d + (double)s * h;
+    return xbit ? -e : e;
+}
+
+// Uniformly random n-subset of {0..N-1}: the first n distinct values of the
+// i.i.d. candidate stream, candidate s drawn from Philox stream
+// 0x40000000 | (s/2) of step `k` (words 0,1 for even s, 2,3 for odd s) and
+// mapped to floor(u64 * N / 2^64).  Positions are processed BLOCK at a time;
+// own[f] keeps the first position where f appeared (LDS atomicMin), so f is in
+// the subset iff own[f] <= pos_n, the position of the n-th first occurrence.
+template <int BLOCK, int G>
+__device__ uint32_t draw_subset(uint32_t* own, uint64_t* masks, int tid, int64_t pitch, int32_t N, int32_t n,
+                                uint64_t seed, uint32_t cid, int64_t k)
+{
+    constexpr int W = BLOCK / 64;
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
+        if (fb < pitch) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) own[fb + v] = 0xFFFFFFFFu;
+        }
+    }
+    __syncthreads();
+    uint32_t base = 0;
+    int32_t have = 0;
+    for (;;) {
+        const uint32_t pos = base + (uint32_t)tid;
+        const Words o = philox(cid, (uint32_t)k, (uint32_t)((uint64_t)k >> 32), kStreamSubset | (pos >> 1), seed);
+        const uint32_t hi = (pos & 1u) ? o.w2 : o.w0;
+        const uint32_t lo = (pos & 1u) ? o.w3 : o.w1;
+        const uint64_t u = ((uint64_t)hi << 32) | (uint64_t)lo;
+        const uint32_t cand = (uint32_t)__umul64hi(u, (uint64_t)(uint32_t)N);
+        atomicMin(&own[cand], pos);
+        __syncthreads();
+        const bool first = own[cand] == pos;
+        const uint64_t bal = __ballot(first);
+        if (lane == 0) masks[wave] = bal;
+        __syncthreads();
+        const int32_t need = n - have;
+        int32_t tot = 0;
+        uint32_t pos_n = 0xFFFFFFFFu;
+        for (int w = 0; w < W; ++w) {
+            const uint64_t m = masks[w];
+            const int c = __popcll(m);
+            if (pos_n == 0xFFFFFFFFu && tot + c >= need) pos_n = base + (uint32_t)(w * 64 + nth_set_bit(m, need - tot - 1));
+            tot += c;
+        }
+        __syncthreads();  // masks are rewritten by the next round or draw
+        if (pos_n != 0xFFFFFFFFu) return pos_n;
+        have += tot;
+        base += BLOCK;
+        // n < N distinct values appear within ~N ln N draws; this bound is
+        // never reached by a correct stream and only keeps the loop finite.
+        if (base >= (1u << 24)) return 0xFFFFFFFEu;
+    }
+}
+
+template <typename QT, typename HT, int BLOCK, int G, int FLAV, bool INSTR>
+__global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
+{
+    using QW = typename Wide<QT>::T;
+    constexpr bool kInt = !std::is_floating_point<HT>::value;
+    constexpr int F = 4 * G;
+    constexpr int W = BLOCK / 64;
+    constexpr int NSEG = G * W;
+    static_assert(NSEG <= 64, "segment scan needs at most 64 segments");
+    static_assert(F <= 32, "bit masks are 32 bits");
+
+    extern __shared__ uint32_t own[];  // random-subset table (FLAV_DRAWN), pitch entries
+    __shared__ double seg_sum[NSEG];
+    __shared__ double mx_part[W];
+    __shared__ uint64_t masks[W];
+    __shared__ int64_t sel[2];
+    __shared__ int32_t stay_flag;
+    __shared__ uint32_t hist_idx;
+    __shared__ double tab_lo[kInt ? kTabLo + 1 : 1];
+    __shared__ double tab_hi[kInt ? kTabHi : 1];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int chain = a.chain_list ? a.chain_list[blockIdx.x] : a.chain_first + (int)blockIdx.x;
+    // The leader wave keeps the chain's scalars (energy, budget, records) and
+    // does the per-step FP64 work; it rotates with the workgroup so that the
+    // leaders of co-resident chains fall on different SIMDs.
+    const int leader = (int)(blockIdx.x % (unsigned)W);
+    const bool lead = wave == leader;
+    const int lead_tid = leader * 64;
+    const Problem P = a.problems[a.chain_problem[chain]];
+    const int32_t N = P.N;
+    const int64_t pitch = P.pitch;
+    const int mode = a.mode;
+    const bool unbiased = mode == kModeSys || mode == kModeRand;
+    const int32_t n = FLAV == FLAV_ALL ? N : P.n;
+    const int s = P.s;
+    const int64_t off = a.foff[chain];
+    const double beta = a.beta[chain];
+    const uint32_t cid = a.chain_id[chain];
+    const uint64_t seed = a.seed;
+
+    if constexpr (kInt) {
+        // tab_lo[kTabLo] = 0 is the weight of a bit outside the subset
+        for (int i = tid; i < kTabLo + 1 + kTabHi; i += BLOCK) {
+            if (i < kTabLo) tab_lo[i] = exp(-beta * (double)i);
+            else if (i == kTabLo) tab_lo[i] = 0.0;
+            else tab_hi[i - kTabLo - 1] = exp(-beta * (double)(kTabLo * (i - kTabLo - 1)));
+        }
+    }
+
+    // ---- chain state into registers ----
+    HT h[F];
+    QW dg[F];
+    uint32_t xb = 0;
+    HT* hbase = reinterpret_cast<HT*>(a.h) + off;
+    const QW* dbase = reinterpret_cast<const QW*>(P.diag);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
+        if (fb < pitch) {
+            const Four<HT> hv = load4(hbase + fb);
+            const Four<QW> dv = load4(dbase + fb);
+            const uint32_t xw = *reinterpret_cast<const uint32_t*>(a.x + off + fb);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                h[g * 4 + v] = hv.v[v];
+                dg[g * 4 + v] = dv.v[v];
+                xb |= ((xw >> (8 * v)) & 1u) << (g * 4 + v);
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                h[g * 4 + v] = (HT)0;
+                dg[g * 4 + v] = (QW)0;
+            }
+        }
+    }
+    // bits of this lane that exist (f < N)
+    uint32_t valid = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) valid |= (uint32_t)(((int64_t)g * BLOCK + tid) * 4 + v < N) << (g * 4 + v);
+
+    int64_t k = a.step[chain];
+    const int64_t kend = k + a.steps;
+    int64_t Ei = a.E[chain];
+    double Ef = __longlong_as_double(Ei);
+    int64_t L = a.L[chain];
+    int64_t sub = a.sub[chain];
+    int32_t last_action = a.last_action[chain];
+    int64_t last_M = a.last_M[chain];
+    int64_t last_E = a.last_E[chain];
+    int64_t c_steps = 0, c_flips = 0, c_stays = 0, c_sat = 0, c_bad = 0;
+    double c_sumM = 0.0;
+    int32_t snap_n = 0;
+    if constexpr (INSTR) snap_n = a.snap_every > 0 ? a.snap_count[chain] : 0;
+    uint32_t pos_n = 0;
+    const bool full = n >= N;
+    int64_t sys_start = FLAV == FLAV_WINDOW ? (int64_t)(((sub % P.num_sets) * (int64_t)n) % N) : 0;
+
+    if constexpr (FLAV == FLAV_DRAWN) {
+        if (mode == kModeRand) {
+            if (k == 0) {
+                pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k);
+            } else {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
+                    if (fb < pitch) {
+                        const uint32_t mw = *reinterpret_cast<const uint32_t*>(a.rmem + off + fb);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) own[fb + v] = ((mw >> (8 * v)) & 1u) ? 0u : 0xFFFFFFFFu;
+                    }
+                }
+                pos_n = 0;
+            }
+        }
+    }
+    __syncthreads();  // tables and subset table ready
+
+    StepUniforms U = step_uniforms(cid, k, seed, lead);
+
+    for (; k < kend; ++k) {
+        if constexpr (FLAV == FLAV_DRAWN) {
+            if (mode == kModeBasic) pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k);
+        }
+
+        // membership of this lane's bits in the step's subset
+        uint32_t mem = valid;
+        if constexpr (FLAV == FLAV_WINDOW) {
+            if (!full) {
+                mem = 0;
+#pragma unroll
+                for (int i = 0; i < F; ++i) {
+                    int64_t d = ((int64_t)(i >> 2) * BLOCK + tid) * 4 + (i & 3) - sys_start;
+                    if (d < 0) d += N;
+                    mem |= (uint32_t)(d < n) << i;
+                }
+                mem &= valid;
+            }
+        } else if constexpr (FLAV == FLAV_DRAWN) {
+            mem = 0;
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                const int64_t f = ((int64_t)(i >> 2) * BLOCK + tid) * 4 + (i & 3);
+                if ((valid >> i) & 1u) mem |= (uint32_t)(own[f] <= pos_n) << i;
+            }
+        }
+
+        // acceptance weights of the subset, summed four bits at a time
+        double w[F];
+        double ls[G];
+        if constexpr (kInt) {
+            // w = 1 for dE <= 0, table product for 0 < dE < 65536 (branch-free);
+            // larger differences take the exp path below, once per wave.
+            // exp(-beta * max(e, 0)) = tab_hi[e >> 6] * tab_lo[e & 63]; exp(-0) = 1
+            // covers e <= 0, and a bit outside the subset reads the zero slot.
+            HT emax = 0;
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                const HT e = delta_int(dg[i], h[i], s, (xb >> i) & 1u);
+                const HT ep = e > 0 ? e : 0;
+                emax = emax > ep ? emax : ep;
+                const uint32_t hi = (uint32_t)(ep >> 6) < (uint32_t)kTabHi ? (uint32_t)(ep >> 6) : (uint32_t)(kTabHi - 1);
+                const uint32_t lo = ((mem >> i) & 1u) ? (uint32_t)ep & 63u : (uint32_t)kTabLo;
+                w[i] = tab_hi[hi] * tab_lo[lo];
+            }
+            if (__ballot(emax >= (HT)kTabMax)) {
+#pragma unroll
+                for (int i = 0; i < F; ++i) {
+                    const HT e = delta_int(dg[i], h[i], s, (xb >> i) & 1u);
+                    if (((mem >> i) & 1u) && e >= (HT)kTabMax) w[i] = exp(-beta * (double)e);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const uint32_t mg = (mem >> (4 * g)) & 0xFu;
+                if (__ballot(mg != 0)) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = g * 4 + v;
+                        double l = -beta * delta_f64(dg[i], h[i], s, (xb >> i) & 1u);
+                        l = l < 0.0 ? l : 0.0;
+                        const double e = exp(l);
+                        w[i] = ((mg >> v) & 1u) ? e : 0.0;
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) w[g * 4 + v] = 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) ls[g] = ((w[g * 4] + w[g * 4 + 1]) + w[g * 4 + 2]) + w[g * 4 + 3];
+        double inc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) inc[g] = wave_scan(ls[g]);
+        if (lane == 63) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) seg_sum[g * W + wave] = inc[g];
+        }
+        __syncthreads();
+        double sv = lane < NSEG ? seg_sum[lane] : 0.0;
+        double sinc = wave_scan(sv);
+        double S = read_lane(sinc, NSEG - 1);
+        double mx = 0.0;
+        bool scaled = false;
+        if (S < 0x1p-1000) {
+            // Every weight underflowed: rescale by the largest log-weight.
+            double lm = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                if ((mem >> i) & 1u) {
+                    double l;
+                    if constexpr (kInt) l = -beta * (double)delta_int(dg[i], h[i], s, (xb >> i) & 1u);
+                    else l = -beta * delta_f64(dg[i], h[i], s, (xb >> i) & 1u);
+                    l = l < 0.0 ? l : 0.0;
+                    lm = fmax(lm, l);
+                }
+            }
+            lm = wave_max(lm);
+            if (lane == 0) mx_part[wave] = lm;
+            __syncthreads();
+            mx = -INFINITY;
+            for (int ww = 0; ww < W; ++ww) mx = fmax(mx, mx_part[ww]);
+            scaled = true;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                ls[g] = 0.0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = g * 4 + v;
+                    double wi = 0.0;
+                    if ((mem >> i) & 1u) {
+                        double l;
+                        if constexpr (kInt) l = -beta * (double)delta_int(dg[i], h[i], s, (xb >> i) & 1u);
+                        else l = -beta * delta_f64(dg[i], h[i], s, (xb >> i) & 1u);
+                        l = l < 0.0 ? l : 0.0;
+                        wi = exp(l - mx);
+                    }
+                    w[i] = wi;
+                    ls[g] += wi;
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) inc[g] = wave_scan(ls[g]);
+            if (lane == 63) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) seg_sum[g * W + wave] = inc[g];
+            }
+            __syncthreads();
+            sv = lane < NSEG ? seg_sum[lane] : 0.0;
+            sinc = wave_scan(sv);
+            S = read_lane(sinc, NSEG - 1);
+        }
+
+        // Escape probability and multiplicity M = 1 + G, G ~ Geometric(p)
+        // counting failures; uniform FP64 work done by wave 0 only.
+        double p = 0.0, q = 0.0;
+        int64_t m = 0;
+        bool sat = false;
+        auto multiplicity = [&]() {
+            p = scaled ? exp(mx) * S / (double)n : S / (double)n;
+            if (p >= 1.0) q = 0.0;
+            else if (p <= 0.0) q = INFINITY;
+            else q = U.logU1 / log1p(-p);
+            if (!(q < 0x1p63)) {
+                m = INT64_MAX;
+                sat = true;
+            } else {
+                m = (int64_t)floor(q) + 1;
+                sat = false;
+            }
+        };
+        // Unbiased: wave 0 takes the budget decision of Alg 6 while the winner
+        // wave resolves the (speculative) choice; both meet at the barrier.
+        if (unbiased && lead) {
+            multiplicity();
+            if (tid == lead_tid) stay_flag = q >= (double)L ? 1 : 0;
+        }
+
+        const int64_t Erec = kInt ? Ei : __double_as_longlong(Ef);
+        uint32_t rec_idx = 0;
+        bool snap = false;
+        if constexpr (INSTR) {
+            // state index of the record for the histograms (N <= 24: lanes 0..5 of
+            // wave 0), handed to the leader through LDS
+            if (a.hist_w != nullptr) {
+                if (wave == 0) {
+                    rec_idx = wave_or(tid < 8 ? ((xb & 0xFu) << (4 * tid)) : 0u);
+                    if (tid == 0) hist_idx = rec_idx;
+                }
+            }
+            snap = a.snap_every > 0 && ((k + 1) % a.snap_every) == 0;
+            if (snap) {
+                const int32_t slot = snap_n % a.snap_cap;
+                uint8_t* sx = a.snap_x + ((int64_t)chain * a.snap_cap + slot) * a.snap_pitch;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
+                    if (fb < a.snap_pitch) {
+                        uint32_t wv = 0;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) wv |= ((xb >> (g * 4 + v)) & 1u) << (8 * v);
+                        *reinterpret_cast<uint32_t*>(sx + fb) = wv;
+                    }
+                }
+            }
+        }
+
+        // Proportional choice (App. C): first bit whose running sum exceeds
+        // U2 * S, resolved segment -> lane -> bit.
+        {
+            const double t = U.U2 * S;
+            const bool pos_seg = lane < NSEG && sv > 0.0;
+            const uint64_t bseg = __ballot(pos_seg && sinc > t);
+            const uint64_t bpos = __ballot(pos_seg);
+            int jstar = bseg ? __builtin_ctzll(bseg) : (bpos ? 63 - __builtin_clzll(bpos) : 0);
+            jstar = jstar < NSEG ? jstar : NSEG - 1;
+            const int gstar = jstar / W, wstar = jstar % W;
+            if (wave == wstar) {
+                const double base = jstar > 0 ? __shfl(sinc, jstar - 1, 64) : 0.0;
+                double my_inc = 0.0, my_ls = 0.0;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    if (g == gstar) {
+                        my_inc = inc[g];
+                        my_ls = ls[g];
+                    }
+                }
+                const double Gl = base + my_inc;
+                const uint64_t bl = __ballot(my_ls > 0.0 && Gl > t);
+                const uint64_t blp = __ballot(my_ls > 0.0);
+                const int lstar = bl ? __builtin_ctzll(bl) : (blp ? 63 - __builtin_clzll(blp) : 0);
+                const double prev_l = __shfl(my_inc, lstar > 0 ? lstar - 1 : 0, 64);
+                if (lane == lstar) {
+                    double run = lstar > 0 ? base + prev_l : base;
+                    int vstar = -1, vlast = -1;
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        if (g == gstar) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const double wv = w[g * 4 + v];
+                                if (wv > 0.0) {
+                                    vlast = v;
+                                    run += wv;
+                                    if (vstar < 0 && run > t) vstar = v;
+                                }
+                            }
+                        }
+                    }
+                    if (vstar < 0) vstar = vlast;
+                    // No positive weight in the chosen lane cannot happen when S > 0;
+                    // keep the address in range and report it.
+                    int64_t bad = 0;
+                    if (vstar < 0) {
+                        vstar = 0;
+                        bad = 1;
+                    }
+                    const int i = gstar * 4 + vstar;
+                    HT hc = (HT)0;
+                    QW dc = (QW)0;
+#pragma unroll
+                    for (int ii = 0; ii < F; ++ii) {
+                        if (ii == i) {
+                            hc = h[ii];
+                            dc = dg[ii];
+                        }
+                    }
+                    int64_t dEc;
+                    if constexpr (kInt) dEc = (int64_t)delta_int(dc, hc, s, (xb >> i) & 1u);
+                    else dEc = __double_as_longlong(delta_f64(dc, hc, s, (xb >> i) & 1u));
+                    int64_t c = ((int64_t)gstar * BLOCK + tid) * 4 + vstar;
+                    if (c >= N) {
+                        c = 0;
+                        bad = 1;
+                    }
+                    sel[0] = c | ((int64_t)((xb >> i) & 1u) << 40) | (bad << 41);
+                    sel[1] = dEc;
+                }
+            }
+        }
+        __syncthreads();
+        const bool stay = unbiased && stay_flag != 0;
+
+        int32_t action;
+        int64_t M;
+        if (stay) {
+            // Alg 6: not enough remaining original samples; stay L times and
+            // switch to the next partial neighbor set.
+            M = L;
+            action = -1;
+            L = P.L0;
+            ++sub;
+            ++c_stays;
+            if constexpr (FLAV == FLAV_DRAWN) {
+                pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k + 1);
+            } else if constexpr (FLAV == FLAV_WINDOW) {
+                sys_start = (int64_t)(((sub % P.num_sets) * (int64_t)n) % N);
+            }
+            U = step_uniforms(cid, k + 1, seed, lead);
+        } else {
+            const int64_t sv0 = sel[0];
+            const int64_t dEc = sel[1];
+            const int32_t c = (int32_t)(sv0 & 0xFFFFFFFFll);
+            const bool xc = (sv0 >> 40) & 1;
+            // field update from row c; the record and the next step's random
+            // numbers are computed while the row is in flight
+            const QT* row = reinterpret_cast<const QT*>(P.A) + (int64_t)c * pitch;
+            decltype(load_row4(row)) r[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
+                if (fb < pitch) r[g] = load_row4(row + fb);
+                else r[g] = {};
+            }
+            action = c;
+            if (lead) {
+                if (!unbiased) multiplicity();
+                if (unbiased) L -= m;
+                c_sat += sat ? 1 : 0;
+                c_bad += (sv0 >> 41) & 1;
+                if constexpr (kInt) Ei += dEc;
+                else Ef += __longlong_as_double(dEc);
+            }
+            M = m;
+            U = step_uniforms(cid, k + 1, seed, lead);
+            const int cl = (c >> 2) % BLOCK;
+            const int cg = (c >> 2) / BLOCK;
+            if (tid == cl) xb ^= 1u << (cg * 4 + (c & 3));
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if (xc) h[g * 4 + v] -= (HT)r[g].v[v];
+                    else h[g * 4 + v] += (HT)r[g].v[v];
+                }
+            }
+            ++c_flips;
+        }
+
+        // record k = (state before the step, M), kept by the leader wave
+        if (lead) {
+            ++c_steps;
+            c_sumM += (double)M;
+            last_action = action;
+            last_M = M;
+            last_E = Erec;
+        }
+        if constexpr (INSTR) {
+            if (snap) ++snap_n;
+            if (tid == lead_tid) {
+                if (a.hist_w != nullptr) rec_idx = hist_idx;
+                if (a.log_cap > 0) {
+                    const int64_t slot = (int64_t)chain * a.log_cap + (k % a.log_cap);
+                    a.log_action[slot] = action;
+                    a.log_M[slot] = M;
+                    a.log_E[slot] = Erec;
+                    a.log_p[slot] = p;
+                }
+                if (a.hist_w != nullptr) {
+                    atomicAdd(&a.hist_w[rec_idx], (unsigned long long)M);
+                    atomicAdd(&a.hist_v[rec_idx], 1ull);
+                }
+                if (snap) {
+                    const int32_t slot = (snap_n - 1) % a.snap_cap;
+                    a.snap_M[(int64_t)chain * a.snap_cap + slot] = M;
+                    a.snap_E[(int64_t)chain * a.snap_cap + slot] = Erec;
+                }
+            }
+        }
+    }
+
+    // ---- chain state back to memory ----
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
+        if (fb < pitch) {
+            HT hv[4];
+            uint32_t xw = 0, mw = 0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                hv[v] = h[g * 4 + v];
+                xw |= ((xb >> (g * 4 + v)) & 1u) << (8 * v);
+                if constexpr (FLAV == FLAV_DRAWN) mw |= (uint32_t)(own[fb + v] <= pos_n) << (8 * v);
+            }
+            store4(hbase + fb, hv);
+            *reinterpret_cast<uint32_t*>(a.x + off + fb) = xw;
+            if constexpr (FLAV == FLAV_DRAWN) {
+                if (mode == kModeRand) *reinterpret_cast<uint32_t*>(a.rmem + off + fb) = mw;
+            }
+        }
+    }
+    if (tid == lead_tid) {
+        a.step[chain] = kend;
+        a.E[chain] = kInt ? Ei : __double_as_longlong(Ef);
+        a.L[chain] = L;
+        a.sub[chain] = sub;
+        a.last_action[chain] = last_action;
+        a.last_M[chain] = last_M;
+        a.last_E[chain] = last_E;
+        if constexpr (INSTR) {
+            if (a.snap_every > 0) a.snap_count[chain] = snap_n;
+        }
+        int64_t* cn = a.counters + (int64_t)chain * 6;
+        cn[0] += c_steps;
+        cn[1] += c_flips;
+        cn[2] += c_stays;
+        cn[3] += c_sat;
+        cn[4] = __double_as_longlong(__longlong_as_double(cn[4]) + c_sumM);
+        cn[5] += c_bad;
+    }
+}
+
+template <typename QT, typename HT, int BLOCK, int G, int FLAV, bool INSTR>
+hipError_t launch_one(int32_t grid, size_t dyn, hipStream_t st, const StepArgs& a)
+{
+    hipLaunchKernelGGL((step_kernel<QT, HT, BLOCK, G, FLAV, INSTR>), dim3(grid), dim3(BLOCK), dyn, st, a);
+    return hipGetLastError();
+}
+
+// Tile shapes (workgroup size, 4-bit groups per lane) compiled for every type.
+#define PNS_TILE_LIST(X, QT, HT) \
+    X(QT, HT, 64, 1)             \
+    X(QT, HT, 64, 2)             \
+    X(QT, HT, 64, 4)             \
+    X(QT, HT, 128, 2)            \
+    X(QT, HT, 128, 4)            \
+    X(QT, HT, 256, 1)            \
+    X(QT, HT, 256, 2)            \
+    X(QT, HT, 256, 4)            \
+    X(QT, HT, 512, 2)            \
+    X(QT, HT, 512, 4)            \
+    X(QT, HT, 1024, 4)
+
+// One tile of the dispatch: `probe` only asks whether the tile exists.
+#define PNS_DISPATCH_TILE(QT, HT, B, GG)                                                                     \
+    if (block == B && groups == GG) {                                                                       \
+        if (probe) return hipSuccess;                                                                       \
+        if (flav == FLAV_ALL)                                                                               \
+            return instr ? launch_one<QT, HT, B, GG, FLAV_ALL, true>(grid, dyn, st, a)                      \
+                         : launch_one<QT, HT, B, GG, FLAV_ALL, false>(grid, dyn, st, a);                    \
+        if (flav == FLAV_WINDOW)                                                                            \
+            return instr ? launch_one<QT, HT, B, GG, FLAV_WINDOW, true>(grid, dyn, st, a)                   \
+                         : launch_one<QT, HT, B, GG, FLAV_WINDOW, false>(grid, dyn, st, a);                 \
+        if (flav == FLAV_DRAWN)                                                                             \
+            return instr ? launch_one<QT, HT, B, GG, FLAV_DRAWN, true>(grid, dyn, st, a)                    \
+                         : launch_one<QT, HT, B, GG, FLAV_DRAWN, false>(grid, dyn, st, a);                  \
+        return hipErrorInvalidConfiguration;                                                                \
+    }
+
+}  // namespace step
+}  // namespace pns
