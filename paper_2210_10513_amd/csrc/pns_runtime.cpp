@@ -213,13 +213,38 @@ struct pns_ctx {
     }
 
     // How the step kernel forms the subset: 0 every bit, 1 systematic window,
-    // 2 random subset drawn in LDS.
+    // 2 random subset drawn in LDS, 3 systematic window that reaches at most
+    // one 4-bit group of any lane (weights kept for that group only).
     int32_t flavour() const
     {
         if (mode == PNS_MODE_RF) return 0;
         if (mode == PNS_MODE_BASIC) return n < N ? 2 : 0;
-        if (mode == PNS_MODE_UNBIASED_SYS) return 1;
-        return n < N ? 2 : 1;
+        if (mode == PNS_MODE_UNBIASED_SYS || n >= N) return window_compact_ok(N, n, block, groups) ? 3 : 1;
+        return 2;
+    }
+
+    // True if no window of n cyclically consecutive bits holds bits of two
+    // different 4-bit groups within one wave: the wave's lanes of group g
+    // hold the contiguous range [(g*block + 64w)*4, +256) of bits.
+    static bool window_compact_ok(int32_t N, int32_t n, int32_t block, int32_t groups)
+    {
+        if (groups == 1) return true;
+        if (n >= N) return false;
+        for (int32_t w = 0; w < block / 64; ++w) {
+            for (int32_t ga = 0; ga < groups; ++ga) {
+                const int64_t a0 = ((int64_t)ga * block + 64 * w) * 4;
+                if (a0 >= N) continue;
+                const int64_t a1 = std::min<int64_t>(a0 + 255, N - 1);
+                for (int32_t gb = 0; gb < groups; ++gb) {
+                    if (gb == ga) continue;
+                    const int64_t b0 = ((int64_t)gb * block + 64 * w) * 4;
+                    if (b0 >= N) continue;
+                    // shortest forward distance from a bit of range a to a bit of range b
+                    if (((b0 - a1) % N + N) % N < n) return false;
+                }
+            }
+        }
+        return true;
     }
 
     bool instrumented() const { return log_cap > 0 || hist_w != nullptr || snap_every > 0; }
@@ -229,7 +254,9 @@ struct pns_ctx {
         // host-side check that the launch matches what the kernel assumes
         if ((int64_t)block * 4 * groups < N || num_chains < 1 || !have_tile(qtype, htype, block, groups))
             return fail(PNS_EINVAL, "tile %dx%d does not cover N=%d", block, groups, N);
-        hipError_t e = launch_steps(qtype, htype, flavour(), instrumented(), block, groups, num_chains, dyn_lds, stream,
+        const int32_t flav = flavour();
+        const size_t dyn = flav == 2 ? (size_t)pitch * 4 : flav == 3 ? (size_t)pitch * 4 : 0;
+        hipError_t e = launch_steps(qtype, htype, flav, instrumented(), block, groups, num_chains, dyn, stream,
                                     args(steps));
         if (e != hipSuccess) return hip_fail(e, "step kernel launch");
         return PNS_OK;

@@ -47,6 +47,9 @@ constexpr int kModeRF = 0, kModeBasic = 1, kModeSys = 2, kModeRand = 3;
 constexpr int FLAV_ALL = 0;     // every bit (RF, and Basic with n = N)
 constexpr int FLAV_WINDOW = 1;  // systematic window (Unbiased-sys, Unbiased-rand with n = N)
 constexpr int FLAV_DRAWN = 2;   // random n-subset drawn in LDS (Basic, Unbiased-rand)
+constexpr int FLAV_WINDOW_C = 3; // systematic window touching at most one 4-bit group in any
+                                 // wave (checked on the host): one scan per wave, four weights
+                                 // per lane, diagonal read from LDS
 
 // Weight tables for integer energy differences: dE = 64 a + b, b < 64, a < 1024.
 constexpr int kTabLo = 64;
@@ -79,19 +82,24 @@ __device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return {c0, c1, c2, c3};
 }
 
-// The two uniforms of step k: U1 in (0, 1] from words 0, 1 (kept as log U1)
-// and U2 in [0, 1) from words 2, 3, each from the top 53 bits of 64.
+// Step uniforms: U1 in (0, 1] from words 0, 1 (kept as log U1) and U2 in
+// [0, 1) from words 2, 3, each from the top 53 bits of 64.
 struct StepUniforms {
     double logU1;
     double U2;
 };
 
-__device__ __forceinline__ StepUniforms step_uniforms(uint32_t cid, int64_t k, uint64_t seed, bool want_log)
+// Uniforms of 64 consecutive steps kb .. kb+63, one step per lane: lane j
+// holds step kb + j.  A step then reads its pair with two lane reads, so the
+// counter-based draws and the logarithm cost one pass per 64 steps.
+__device__ __forceinline__ void batch_uniforms(uint32_t cid, int64_t kb, uint64_t seed, int lane, bool want_log,
+                                               double* logU1, double* U2)
 {
+    const int64_t k = kb + lane;
     const Words o = philox(cid, (uint32_t)k, (uint32_t)((uint64_t)k >> 32), kStreamStep, seed);
-    const double U1 = (double)(((((uint64_t)o.w0 << 32) | o.w1) >> 11) + 1u) * 0x1p-53;
-    const double U2 = (double)((((uint64_t)o.w2 << 32) | o.w3) >> 11) * 0x1p-53;
-    return {want_log ? log(U1) : 0.0, U2};
+    const double u1 = (double)(((((uint64_t)o.w0 << 32) | o.w1) >> 11) + 1u) * 0x1p-53;
+    *U2 = (double)((((uint64_t)o.w2 << 32) | o.w3) >> 11) * 0x1p-53;
+    *logU1 = want_log ? log(u1) : 0.0;
 }
 
 // ---- wave64 primitives (DPP) ----
@@ -281,8 +289,17 @@ __device__ uint32_t draw_subset(uint32_t* own, uint64_t* masks, int tid, int64_t
     }
 }
 
+// Occupancy asked of the compiler (waves per SIMD): compact-window kernels
+// of 512 or more lanes target two co-resident chains per compute unit.
+template <int BLOCK, int FLAV>
+constexpr int min_waves_per_eu()
+{
+    return (FLAV == FLAV_WINDOW_C && BLOCK >= 512) ? 2 * (BLOCK / 256) : 1;
+}
+
 template <typename QT, typename HT, int BLOCK, int G, int FLAV, bool INSTR>
-__global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
+__global__ __attribute__((amdgpu_flat_work_group_size(1, BLOCK), amdgpu_waves_per_eu(min_waves_per_eu<BLOCK, FLAV>())))
+void step_kernel(const StepArgs a)
 {
     using QW = typename Wide<QT>::T;
     constexpr bool kInt = !std::is_floating_point<HT>::value;
@@ -292,7 +309,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
     static_assert(NSEG <= 64, "segment scan needs at most 64 segments");
     static_assert(F <= 32, "bit masks are 32 bits");
 
-    extern __shared__ uint32_t own[];  // random-subset table (FLAV_DRAWN), pitch entries
+    extern __shared__ uint32_t own[];  // random-subset table (FLAV_DRAWN) or diagonal (FLAV_WINDOW_C), pitch entries
     __shared__ double seg_sum[NSEG];
     __shared__ double mx_part[W];
     __shared__ uint64_t masks[W];
@@ -317,6 +334,8 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
     const int64_t pitch = P.pitch;
     const int mode = a.mode;
     const bool unbiased = mode == kModeSys || mode == kModeRand;
+    constexpr bool kWin = FLAV == FLAV_WINDOW || FLAV == FLAV_WINDOW_C;
+    constexpr bool kCompact = FLAV == FLAV_WINDOW_C;
     const int32_t n = FLAV == FLAV_ALL ? N : P.n;
     const int s = P.s;
     const int64_t off = a.foff[chain];
@@ -335,7 +354,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
 
     // ---- chain state into registers ----
     HT h[F];
-    QW dg[F];
+    QW dg[kCompact ? 1 : F];
     uint32_t xb = 0;
     HT* hbase = reinterpret_cast<HT*>(a.h) + off;
     const QW* dbase = reinterpret_cast<const QW*>(P.diag);
@@ -349,14 +368,15 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 h[g * 4 + v] = hv.v[v];
-                dg[g * 4 + v] = dv.v[v];
+                if constexpr (kCompact) reinterpret_cast<QW*>(own)[fb + v] = dv.v[v];
+                else dg[g * 4 + v] = dv.v[v];
                 xb |= ((xw >> (8 * v)) & 1u) << (g * 4 + v);
             }
         } else {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 h[g * 4 + v] = (HT)0;
-                dg[g * 4 + v] = (QW)0;
+                if constexpr (!kCompact) dg[g * 4 + v] = (QW)0;
             }
         }
     }
@@ -365,7 +385,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) valid |= (uint32_t)(((int64_t)g * BLOCK + tid) * 4 + v < N) << (g * 4 + v);
+        for (int v = 0; v < 4; ++v) valid |= (uint32_t)((g * BLOCK + tid) * 4 + v < N) << (g * 4 + v);
 
     int64_t k = a.step[chain];
     const int64_t kend = k + a.steps;
@@ -382,7 +402,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
     if constexpr (INSTR) snap_n = a.snap_every > 0 ? a.snap_count[chain] : 0;
     uint32_t pos_n = 0;
     const bool full = n >= N;
-    int64_t sys_start = FLAV == FLAV_WINDOW ? (int64_t)(((sub % P.num_sets) * (int64_t)n) % N) : 0;
+    int64_t sys_start = kWin ? (int64_t)(((sub % P.num_sets) * (int64_t)n) % N) : 0;
 
     if constexpr (FLAV == FLAV_DRAWN) {
         if (mode == kModeRand) {
@@ -404,22 +424,37 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
     }
     __syncthreads();  // tables and subset table ready
 
-    StepUniforms U = step_uniforms(cid, k, seed, lead);
+    double ubLog = 0.0, ubU2 = 0.0;
+    int64_t ub_base = k;
+    batch_uniforms(cid, ub_base, seed, lane, lead, &ubLog, &ubU2);
+    // p = S / n: for a power-of-two n the product by 1/n is the same number
+    const bool n_pow2 = (n & (n - 1)) == 0;
+    const double inv_n = 1.0 / (double)n;
 
     for (; k < kend; ++k) {
+        if (k - ub_base >= 64) {
+            ub_base = k;
+            batch_uniforms(cid, ub_base, seed, lane, lead, &ubLog, &ubU2);
+        }
+        const int uj = (int)(k - ub_base);
+        StepUniforms U;
+        U.U2 = read_lane(ubU2, uj);
+        U.logU1 = lead ? read_lane(ubLog, uj) : 0.0;
         if constexpr (FLAV == FLAV_DRAWN) {
             if (mode == kModeBasic) pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k);
         }
 
         // membership of this lane's bits in the step's subset
         uint32_t mem = valid;
-        if constexpr (FLAV == FLAV_WINDOW) {
+        if constexpr (kWin) {
             if (!full) {
+                // bit f is in the window iff (f - start) mod N < n
                 mem = 0;
+                const int32_t d0 = tid * 4 - (int32_t)sys_start;
 #pragma unroll
                 for (int i = 0; i < F; ++i) {
-                    int64_t d = ((int64_t)(i >> 2) * BLOCK + tid) * 4 + (i & 3) - sys_start;
-                    if (d < 0) d += N;
+                    int32_t d = d0 + (i >> 2) * (BLOCK * 4) + (i & 3);
+                    d += d < 0 ? N : 0;
                     mem |= (uint32_t)(d < n) << i;
                 }
                 mem &= valid;
@@ -428,17 +463,87 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
             mem = 0;
 #pragma unroll
             for (int i = 0; i < F; ++i) {
-                const int64_t f = ((int64_t)(i >> 2) * BLOCK + tid) * 4 + (i & 3);
+                const int32_t f = ((i >> 2) * BLOCK + tid) * 4 + (i & 3);
                 if ((valid >> i) & 1u) mem |= (uint32_t)(own[f] <= pos_n) << i;
             }
         }
 
         // acceptance weights of the subset, summed four bits at a time
-        double w[F];
-        double ls[G];
-        if constexpr (kInt) {
-            // w = 1 for dE <= 0, table product for 0 < dE < 65536 (branch-free);
-            // larger differences take the exp path below, once per wave.
+        auto member_weight = [&](int i, double shift) -> double {
+            const QW di = dg[i % (kCompact ? 1 : F)];
+            if constexpr (kInt) {
+                const HT e = delta_int(di, h[i], s, (xb >> i) & 1u);
+                if (shift == 0.0) {
+                    const HT ep = e > 0 ? e : 0;
+                    if (ep < (HT)kTabMax) return tab_hi[(uint32_t)(ep >> 6)] * tab_lo[(uint32_t)ep & 63u];
+                    return exp(-beta * (double)e);
+                }
+                double l = -beta * (double)e;
+                l = l < 0.0 ? l : 0.0;
+                return exp(l - shift);
+            } else {
+                double l = -beta * delta_f64(di, h[i], s, (xb >> i) & 1u);
+                l = l < 0.0 ? l : 0.0;
+                return shift == 0.0 ? exp(l) : exp(l - shift);
+            }
+        };
+        double w[kCompact ? 4 : F];  // compact: weights of the lane's four bits in group gw
+        double ls[kCompact ? 1 : G];
+        // Compact window: a wave's subset bits lie in one 4-bit group (gw) and
+        // each lane's in its four bits of that group.
+        double lsum = 0.0;
+        int gw = 0;
+        auto compact_weights = [&](double shift) {
+            const uint32_t gmask = (mem & 0x11111111u) | ((mem >> 1) & 0x11111111u) | ((mem >> 2) & 0x11111111u) |
+                                   ((mem >> 3) & 0x11111111u);
+            const int gs = gmask ? (__builtin_ctz(gmask) >> 2) : 0;
+            const uint32_t mg = (mem >> (4 * gs)) & 0xFu;
+            const uint64_t bm = __ballot(mg != 0);
+            gw = bm ? __builtin_amdgcn_readlane(gs, (int)__builtin_ctzll(bm)) : 0;
+            double w4[4] = {0.0, 0.0, 0.0, 0.0};
+            if (bm) {
+                HT h4[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) h4[v] = h[v];
+#pragma unroll
+                for (int g = 1; g < G; ++g) {
+                    if (gw == g) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) h4[v] = h[g * 4 + v];
+                    }
+                }
+                const int32_t fb = (gw * BLOCK + tid) * 4;
+                const Four<QW> d4 = load4(reinterpret_cast<const QW*>(own) + (fb < pitch ? fb : 0));
+                const uint32_t x4 = (xb >> (4 * gw)) & 0xFu;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double wv;
+                    if constexpr (kInt) {
+                        const HT e = delta_int(d4.v[v], h4[v], s, (x4 >> v) & 1u);
+                        if (shift == 0.0) {
+                            const HT ep = e > 0 ? e : 0;
+                            wv = ep < (HT)kTabMax ? tab_hi[(uint32_t)(ep >> 6)] * tab_lo[(uint32_t)ep & 63u]
+                                                  : exp(-beta * (double)e);
+                        } else {
+                            double l = -beta * (double)e;
+                            l = l < 0.0 ? l : 0.0;
+                            wv = exp(l - shift);
+                        }
+                    } else {
+                        double l = -beta * delta_f64(d4.v[v], h4[v], s, (x4 >> v) & 1u);
+                        l = l < 0.0 ? l : 0.0;
+                        wv = shift == 0.0 ? exp(l) : exp(l - shift);
+                    }
+                    w4[v] = ((mg >> v) & 1u) ? wv : 0.0;
+                }
+            }
+            lsum = ((w4[0] + w4[1]) + w4[2]) + w4[3];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) w[v] = w4[v];
+        };
+        if constexpr (kCompact) {
+            compact_weights(0.0);
+        } else if constexpr (kInt) {
             // exp(-beta * max(e, 0)) = tab_hi[e >> 6] * tab_lo[e & 63]; exp(-0) = 1
             // covers e <= 0, and a bit outside the subset reads the zero slot.
             HT emax = 0;
@@ -464,28 +569,35 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
                 const uint32_t mg = (mem >> (4 * g)) & 0xFu;
                 if (__ballot(mg != 0)) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = g * 4 + v;
-                        double l = -beta * delta_f64(dg[i], h[i], s, (xb >> i) & 1u);
-                        l = l < 0.0 ? l : 0.0;
-                        const double e = exp(l);
-                        w[i] = ((mg >> v) & 1u) ? e : 0.0;
-                    }
+                    for (int v = 0; v < 4; ++v) w[g * 4 + v] = ((mg >> v) & 1u) ? member_weight(g * 4 + v, 0.0) : 0.0;
                 } else {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) w[g * 4 + v] = 0.0;
                 }
             }
         }
+        if constexpr (!kCompact) {
 #pragma unroll
-        for (int g = 0; g < G; ++g) ls[g] = ((w[g * 4] + w[g * 4 + 1]) + w[g * 4 + 2]) + w[g * 4 + 3];
-        double inc[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) inc[g] = wave_scan(ls[g]);
-        if (lane == 63) {
-#pragma unroll
-            for (int g = 0; g < G; ++g) seg_sum[g * W + wave] = inc[g];
+            for (int g = 0; g < G; ++g) ls[g] = ((w[g * 4] + w[g * 4 + 1]) + w[g * 4 + 2]) + w[g * 4 + 3];
         }
+        double inc[kCompact ? 1 : G];
+        auto scan_and_publish = [&]() {
+            if constexpr (kCompact) {
+                inc[0] = wave_scan(lsum);
+                if (lane == 63) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) seg_sum[g * W + wave] = g == gw ? inc[0] : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int g = 0; g < G; ++g) inc[g] = wave_scan(ls[g]);
+                if (lane == 63) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) seg_sum[g * W + wave] = inc[g];
+                }
+            }
+        };
+        scan_and_publish();
         __syncthreads();
         double sv = lane < NSEG ? seg_sum[lane] : 0.0;
         double sinc = wave_scan(sv);
@@ -498,9 +610,11 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 if ((mem >> i) & 1u) {
+                    const QW di = kCompact ? reinterpret_cast<const QW*>(own)[((i >> 2) * BLOCK + tid) * 4 + (i & 3)]
+                                           : dg[i % (kCompact ? 1 : F)];
                     double l;
-                    if constexpr (kInt) l = -beta * (double)delta_int(dg[i], h[i], s, (xb >> i) & 1u);
-                    else l = -beta * delta_f64(dg[i], h[i], s, (xb >> i) & 1u);
+                    if constexpr (kInt) l = -beta * (double)delta_int(di, h[i], s, (xb >> i) & 1u);
+                    else l = -beta * delta_f64(di, h[i], s, (xb >> i) & 1u);
                     l = l < 0.0 ? l : 0.0;
                     lm = fmax(lm, l);
                 }
@@ -511,30 +625,20 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
             mx = -INFINITY;
             for (int ww = 0; ww < W; ++ww) mx = fmax(mx, mx_part[ww]);
             scaled = true;
+            if constexpr (kCompact) {
+                compact_weights(mx);
+            } else {
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                ls[g] = 0.0;
+                for (int g = 0; g < G; ++g) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = g * 4 + v;
-                    double wi = 0.0;
-                    if ((mem >> i) & 1u) {
-                        double l;
-                        if constexpr (kInt) l = -beta * (double)delta_int(dg[i], h[i], s, (xb >> i) & 1u);
-                        else l = -beta * delta_f64(dg[i], h[i], s, (xb >> i) & 1u);
-                        l = l < 0.0 ? l : 0.0;
-                        wi = exp(l - mx);
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = g * 4 + v;
+                        w[i] = ((mem >> i) & 1u) ? member_weight(i, mx) : 0.0;
                     }
-                    w[i] = wi;
-                    ls[g] += wi;
+                    ls[g] = ((w[g * 4] + w[g * 4 + 1]) + w[g * 4 + 2]) + w[g * 4 + 3];
                 }
             }
-#pragma unroll
-            for (int g = 0; g < G; ++g) inc[g] = wave_scan(ls[g]);
-            if (lane == 63) {
-#pragma unroll
-                for (int g = 0; g < G; ++g) seg_sum[g * W + wave] = inc[g];
-            }
+            scan_and_publish();
             __syncthreads();
             sv = lane < NSEG ? seg_sum[lane] : 0.0;
             sinc = wave_scan(sv);
@@ -547,7 +651,8 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
         int64_t m = 0;
         bool sat = false;
         auto multiplicity = [&]() {
-            p = scaled ? exp(mx) * S / (double)n : S / (double)n;
+            const double Ss = scaled ? exp(mx) * S : S;
+            p = n_pow2 ? Ss * inv_n : Ss / (double)n;
             if (p >= 1.0) q = 0.0;
             else if (p <= 0.0) q = INFINITY;
             else q = U.logU1 / log1p(-p);
@@ -608,11 +713,16 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
             if (wave == wstar) {
                 const double base = jstar > 0 ? __shfl(sinc, jstar - 1, 64) : 0.0;
                 double my_inc = 0.0, my_ls = 0.0;
+                if constexpr (kCompact) {
+                    my_inc = inc[0];
+                    my_ls = lsum;
+                } else {
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    if (g == gstar) {
-                        my_inc = inc[g];
-                        my_ls = ls[g];
+                    for (int g = 0; g < G; ++g) {
+                        if (g == gstar) {
+                            my_inc = inc[g];
+                            my_ls = ls[g];
+                        }
                     }
                 }
                 const double Gl = base + my_inc;
@@ -628,7 +738,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
                         if (g == gstar) {
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
-                                const double wv = w[g * 4 + v];
+                                const double wv = kCompact ? w[v] : w[(g * 4 + v) % (kCompact ? 4 : F)];
                                 if (wv > 0.0) {
                                     vlast = v;
                                     run += wv;
@@ -652,9 +762,10 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
                     for (int ii = 0; ii < F; ++ii) {
                         if (ii == i) {
                             hc = h[ii];
-                            dc = dg[ii];
+                            if constexpr (!kCompact) dc = dg[ii];
                         }
                     }
+                    if constexpr (kCompact) dc = reinterpret_cast<const QW*>(own)[(gstar * BLOCK + tid) * 4 + vstar];
                     int64_t dEc;
                     if constexpr (kInt) dEc = (int64_t)delta_int(dc, hc, s, (xb >> i) & 1u);
                     else dEc = __double_as_longlong(delta_f64(dc, hc, s, (xb >> i) & 1u));
@@ -683,10 +794,9 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
             ++c_stays;
             if constexpr (FLAV == FLAV_DRAWN) {
                 pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k + 1);
-            } else if constexpr (FLAV == FLAV_WINDOW) {
+            } else if constexpr (kWin) {
                 sys_start = (int64_t)(((sub % P.num_sets) * (int64_t)n) % N);
             }
-            U = step_uniforms(cid, k + 1, seed, lead);
         } else {
             const int64_t sv0 = sel[0];
             const int64_t dEc = sel[1];
@@ -712,7 +822,6 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(const StepArgs a)
                 else Ef += __longlong_as_double(dEc);
             }
             M = m;
-            U = step_uniforms(cid, k + 1, seed, lead);
             const int cl = (c >> 2) % BLOCK;
             const int cg = (c >> 2) / BLOCK;
             if (tid == cl) xb ^= 1u << (cg * 4 + (c & 3));
@@ -819,6 +928,7 @@ hipError_t launch_one(int32_t grid, size_t dyn, hipStream_t st, const StepArgs& 
     X(QT, HT, 256, 4)            \
     X(QT, HT, 512, 2)            \
     X(QT, HT, 512, 4)            \
+    X(QT, HT, 1024, 2)           \
     X(QT, HT, 1024, 4)
 
 // One tile of the dispatch: `probe` only asks whether the tile exists.
@@ -834,6 +944,9 @@ hipError_t launch_one(int32_t grid, size_t dyn, hipStream_t st, const StepArgs& 
         if (flav == FLAV_DRAWN)                                                                             \
             return instr ? launch_one<QT, HT, B, GG, FLAV_DRAWN, true>(grid, dyn, st, a)                    \
                          : launch_one<QT, HT, B, GG, FLAV_DRAWN, false>(grid, dyn, st, a);                  \
+        if (flav == FLAV_WINDOW_C)                                                                          \
+            return instr ? launch_one<QT, HT, B, GG, FLAV_WINDOW_C, true>(grid, dyn, st, a)                 \
+                         : launch_one<QT, HT, B, GG, FLAV_WINDOW_C, false>(grid, dyn, st, a);               \
         return hipErrorInvalidConfiguration;                                                                \
     }
 
