@@ -431,6 +431,35 @@ void step_kernel(const StepArgs a)
     const bool n_pow2 = (n & (n - 1)) == 0;
     const double inv_n = 1.0 / (double)n;
 
+    // Membership of this lane's bits in the current subset.  It changes only
+    // when the subset does (a new window or draw), so it is kept across steps.
+    auto compute_mem = [&]() -> uint32_t {
+        uint32_t m = valid;
+        if constexpr (kWin) {
+            if (!full) {
+                // bit f is in the window iff (f - start) mod N < n
+                m = 0;
+                const int32_t d0 = tid * 4 - (int32_t)sys_start;
+#pragma unroll
+                for (int i = 0; i < F; ++i) {
+                    int32_t d = d0 + (i >> 2) * (BLOCK * 4) + (i & 3);
+                    d += d < 0 ? N : 0;
+                    m |= (uint32_t)(d < n) << i;
+                }
+                m &= valid;
+            }
+        } else if constexpr (FLAV == FLAV_DRAWN) {
+            m = 0;
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                const int32_t f = ((i >> 2) * BLOCK + tid) * 4 + (i & 3);
+                if ((valid >> i) & 1u) m |= (uint32_t)(own[f] <= pos_n) << i;
+            }
+        }
+        return m;
+    };
+    uint32_t mem = (FLAV == FLAV_DRAWN && mode == kModeBasic) ? 0u : compute_mem();
+
     for (; k < kend; ++k) {
         if (k - ub_base >= 64) {
             ub_base = k;
@@ -441,30 +470,9 @@ void step_kernel(const StepArgs a)
         U.U2 = read_lane(ubU2, uj);
         U.logU1 = lead ? read_lane(ubLog, uj) : 0.0;
         if constexpr (FLAV == FLAV_DRAWN) {
-            if (mode == kModeBasic) pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k);
-        }
-
-        // membership of this lane's bits in the step's subset
-        uint32_t mem = valid;
-        if constexpr (kWin) {
-            if (!full) {
-                // bit f is in the window iff (f - start) mod N < n
-                mem = 0;
-                const int32_t d0 = tid * 4 - (int32_t)sys_start;
-#pragma unroll
-                for (int i = 0; i < F; ++i) {
-                    int32_t d = d0 + (i >> 2) * (BLOCK * 4) + (i & 3);
-                    d += d < 0 ? N : 0;
-                    mem |= (uint32_t)(d < n) << i;
-                }
-                mem &= valid;
-            }
-        } else if constexpr (FLAV == FLAV_DRAWN) {
-            mem = 0;
-#pragma unroll
-            for (int i = 0; i < F; ++i) {
-                const int32_t f = ((i >> 2) * BLOCK + tid) * 4 + (i & 3);
-                if ((valid >> i) & 1u) mem |= (uint32_t)(own[f] <= pos_n) << i;
+            if (mode == kModeBasic) {
+                pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k);
+                mem = compute_mem();
             }
         }
 
@@ -797,6 +805,7 @@ void step_kernel(const StepArgs a)
             } else if constexpr (kWin) {
                 sys_start = (int64_t)(((sub % P.num_sets) * (int64_t)n) % N);
             }
+            mem = compute_mem();
         } else {
             const int64_t sv0 = sel[0];
             const int64_t dEc = sel[1];
