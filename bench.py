@@ -40,7 +40,76 @@ def _workload(name: str):
     if name == "unbiased_n8192_f32":
         w = inputs.c3_unbiased_n8192()
         return dict(Q=w.Q, betas=w.betas, mode="unbiased_sys", n=512, L0=100, qbytes=4, steps=w.steps, desc=w.name)
+    if name == "batched64_uneven_int16":
+        w = inputs.c4_batched()
+        cp = int(w.extra["chains_per"])
+        probs = [{"Q": Q, "num_chains": cp, "beta": w.betas[i * cp:(i + 1) * cp], "subset_size": 0}
+                 for i, Q in enumerate(w.Q)]
+        return dict(problems=probs, betas=w.betas, mode="unbiased_sys", n=0, L0=100, qbytes=2, steps=20_000,
+                    desc=w.name, Ns=np.asarray(w.extra["Ns"]))
     raise SystemExit(f"unknown workload {name}")
+
+
+def _time_batch(wl, chain_steps: int, steps: int, warmup: int, launch: str, seed: int):
+    """Batched context over every problem of the workload (subset sizes and
+    tiles from the autotuner).  Returns (seconds per bench step, flips, Q
+    bytes streamed, records, sum M per bench step, problem infos)."""
+    import torch
+    from paper_2210_10513_amd.binding import BatchSampler
+    stream = torch.cuda.current_stream()
+    s = BatchSampler(wl["problems"], wl["mode"], L0=wl["L0"], seed=seed, launch=launch, stream=stream)
+    nbits = np.concatenate([np.full(i.num_chains, i.N) for i in s.info]).astype(np.float64)
+    for _ in range(warmup):
+        s.run(chain_steps)
+    s.sync()
+    st0 = s.stats()
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record(stream)
+    for _ in range(steps):
+        s.run(chain_steps)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms = t_start.elapsed_time(t_end)
+    st1 = s.stats()
+    info = [(i.N, i.subset_size, i.block, i.groups, i.flavour) for i in s.info]
+    s.close()
+    dflips = (st1["flips"] - st0["flips"]).astype(np.float64)
+    flips = float(dflips.sum()) / steps
+    qbytes = float((dflips * nbits).sum()) * wl["qbytes"] / steps
+    recs = float((st1["steps"] - st0["steps"]).sum()) / steps
+    summ = float((st1["sum_M"] - st0["sum_M"]).sum()) / steps
+    return ms / 1000.0 / steps, flips, qbytes, recs, summ, info
+
+
+def _bench_batch(args, wl):
+    chain_steps = args.chain_steps or wl["steps"]
+    launch = args.launch if args.launch != "persistent" else "graph"
+    t0 = time.perf_counter()
+    sec, flips, qb, recs, summ, info = _time_batch(wl, chain_steps, args.steps, args.warmup, launch, seed=1)
+    setup = time.perf_counter() - t0
+    achieved = qb / sec / 1e9
+    out = {
+        "metric": "flips/s", "value": flips / sec, "unit": "flips/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1000.0, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": wl["desc"], "problems": len(info), "chains": int(len(wl["betas"])),
+                   "N_min": int(min(i[0] for i in info)), "N_max": int(max(i[0] for i in info)),
+                   "mode": wl["mode"], "subset": "autotuned", "chain_steps_per_step": chain_steps, "launch": launch,
+                   "subset_sizes": [int(i[1]) for i in info], "tiles": sorted({f"{i[2]}x{i[3]}" for i in info})},
+        "effective_mh_steps_per_s": summ / sec,
+        "records_per_s": recs / sec,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_flip": "N_p * 2 for the flipping chain's problem", "kernel": "step_kernel (all classes)",
+                     "kernel_avg_ms": sec * 1000.0},
+        "setup_s": setup,
+    }
+    if not args.no_extras:
+        sp, fp, qp, _, _, _ = _time_batch(wl, 100, 1, 1, "plain", seed=3)
+        out["variants"] = {"plain_launch_flips_per_s": fp / sp, "batched_over_plain": (flips / sec) / (fp / sp)}
+    print(json.dumps(out))
 
 
 def _time_sampler(wl, chain_steps: int, steps: int, warmup: int, launch: str, seed: int, tile=(0, 0)):
@@ -119,6 +188,9 @@ def main():
     torch.cuda.set_device(0)
 
     wl = _workload(args.workload)
+    if "problems" in wl:
+        _bench_batch(args, wl)
+        return
     chain_steps = args.chain_steps or wl["steps"]
     C = len(wl["betas"])
     N = wl["Q"].shape[0]

@@ -117,8 +117,48 @@ typedef struct pns_opts {
                                bits, M, E) of each chain; read with
                                pns_read_snapshots (0 = off)                       */
     int32_t snapshot_capacity; /* snapshots kept per chain (ring)               */
-    int32_t reserved[8];    /* must be zero                                       */
+    int32_t autotune;       /* 1: choose the tile (and a subset size given as 0)
+                               from timed trials on the device (pns_autotune);
+                               results are cached per process                    */
+    int32_t reserved[7];    /* must be zero                                       */
 } pns_opts;
+
+/* One problem of a batched context (pns_create_batch). */
+typedef struct pns_problem {
+    const void* Q;          /* N x N row-major, element type opts->dtype, host or
+                               device; copied on creation                        */
+    int32_t N;
+    int32_t layout;         /* PNS_SYMMETRIC / PNS_UPPER                         */
+    int32_t subset_size;    /* n in [1, N]; 0 = chosen by the autotuner (subset
+                               modes) ; ignored by RF                            */
+    int32_t num_chains;     /* chains of this problem (>= 1)                     */
+    int64_t L0;             /* 0 = opts->L0                                      */
+    const double* betas;    /* host [num_chains] inverse temperatures, or NULL  */
+    double beta;            /* used when betas is NULL                           */
+} pns_problem;
+
+/* Tile and subset size of one problem as the library runs it. */
+typedef struct pns_problem_info {
+    int32_t N;
+    int32_t subset_size;
+    int32_t block;          /* workgroup size (threads)                          */
+    int32_t groups;         /* 4-bit groups per lane                             */
+    int32_t chain_begin;    /* first chain of the problem                        */
+    int32_t num_chains;
+    int32_t flavour;        /* 0 all bits, 1 window, 2 drawn subset, 3 compact
+                               window                                            */
+    int32_t reserved;
+} pns_problem_info;
+
+/* Result of pns_autotune. */
+typedef struct pns_tune {
+    int32_t block;
+    int32_t groups;
+    int32_t subset_size;
+    int32_t trials;         /* timed configurations                              */
+    double records_per_s;   /* records (steps x chains) per second of the choice */
+    double flips_per_s;
+} pns_tune;
 
 /* Per-chain counters since creation. */
 typedef struct pns_chain_stats {
@@ -150,6 +190,46 @@ void pns_opts_default(pns_opts* opts);
  */
 int pns_create(pns_ctx** out, const void* Q, int32_t N, double beta, int32_t subset_size, int32_t mode,
                const pns_opts* opts);
+
+/*
+ * Create one context over several problems of the same element type and
+ * method (QUBOs of uneven N, each with its own chains and temperatures):
+ * chain c of problem p is numbered problems[0..p-1].num_chains + c.  Problems
+ * are grouped by workgroup tile; each group runs in its own step kernel,
+ * launched concurrently (in the graph form as parallel graph nodes).
+ * Per-chain arrays of bits or fields (pns_read, pns_read_current,
+ * pns_read_snapshots) are concatenated, chain c occupying the N of its
+ * problem; pns_chain_offsets gives the offsets.  Histograms are not
+ * available for batches.  Problems with subset_size 0 (or opts->autotune)
+ * are tuned with pns_autotune on creation.
+ * Errors: as pns_create, PNS_EINVAL for num_problems < 1 or a bad problem.
+ */
+int pns_create_batch(pns_ctx** out, int32_t num_problems, const pns_problem* problems, int32_t mode,
+                     const pns_opts* opts);
+
+/*
+ * Choose the workgroup tile and, when subset_size is 0 in a subset mode, the
+ * subset size for one problem by timed trials on the device: every compiled
+ * tile that holds N is run for trial_steps steps (after a warmup) with the
+ * problem's chains (opts->num_chains, at most 4096), the tile with the most
+ * records per second is kept, then subset sizes 16, 32, ... up to N/2 are
+ * timed on it and the largest one within 10% of the best rate is chosen
+ * (Sec 5: on parallel hardware, take the largest affordable partial neighbor
+ * set).  Results are cached per process by (N, dtype, layout, mode, n,
+ * chains).  Synchronises the device.  Errors: as pns_create.
+ */
+int pns_autotune(const void* Q, int32_t N, double beta, int32_t subset_size, int32_t mode, const pns_opts* opts,
+                 int32_t trial_steps, pns_tune* out);
+
+/* Offsets [num_chains + 1] of each chain's bits in concatenated per-chain
+ * arrays (c * N for a single-problem context).  Host memory. */
+int pns_chain_offsets(const pns_ctx* ctx, int64_t* offsets);
+
+/* Number of problems of the context (1 unless created by pns_create_batch). */
+int pns_num_problems(const pns_ctx* ctx);
+
+/* Tile, subset size and chain range of problem p. */
+int pns_problem_info_get(const pns_ctx* ctx, int32_t p, pns_problem_info* info);
 
 /*
  * Advance every chain by `steps` steps (records), queued on the context's

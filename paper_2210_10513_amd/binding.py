@@ -6,7 +6,8 @@ passed as raw pointers, every step of the sampler runs in the library's HIP
 kernels.  There is no fallback: if the library is missing or fails to load,
 importing this module raises.
 
-``Sampler`` is a small convenience wrapper that owns one context and returns
+``Sampler`` (one problem) and ``BatchSampler`` (several problems of uneven N
+in one context) are small convenience wrappers that own a context and return
 numpy arrays.
 """
 from __future__ import annotations
@@ -36,7 +37,8 @@ LAYOUTS = {"symmetric": PNS_SYMMETRIC, "upper": PNS_UPPER}
 
 EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_current", "pns_field_type",
            "pns_read_log", "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync",
-           "pns_destroy", "pns_tile", "pns_last_error", "pns_version"]
+           "pns_destroy", "pns_tile", "pns_last_error", "pns_version", "pns_create_batch", "pns_autotune",
+           "pns_chain_offsets", "pns_num_problems", "pns_problem_info_get"]
 
 
 class pns_opts(ctypes.Structure):
@@ -47,8 +49,25 @@ class pns_opts(ctypes.Structure):
         ("launch", ctypes.c_int32), ("chunk", ctypes.c_int32), ("block", ctypes.c_int32),
         ("groups", ctypes.c_int32), ("stream", ctypes.c_void_p), ("log_capacity", ctypes.c_int64),
         ("hist", ctypes.c_int32), ("snapshot_every", ctypes.c_int32), ("snapshot_capacity", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 8),
+        ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
     ]
+
+
+class pns_problem(ctypes.Structure):
+    _fields_ = [("Q", ctypes.c_void_p), ("N", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("subset_size", ctypes.c_int32), ("num_chains", ctypes.c_int32), ("L0", ctypes.c_int64),
+                ("betas", ctypes.c_void_p), ("beta", ctypes.c_double)]
+
+
+class pns_problem_info(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("subset_size", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("groups", ctypes.c_int32), ("chain_begin", ctypes.c_int32), ("num_chains", ctypes.c_int32),
+                ("flavour", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class pns_tune(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("groups", ctypes.c_int32), ("subset_size", ctypes.c_int32),
+                ("trials", ctypes.c_int32), ("records_per_s", ctypes.c_double), ("flips_per_s", ctypes.c_double)]
 
 
 class pns_chain_stats(ctypes.Structure):
@@ -94,9 +113,15 @@ def _load() -> ctypes.CDLL:
     L.pns_last_error.restype = ctypes.c_char_p
     L.pns_version.argtypes = []
     L.pns_version.restype = ctypes.c_char_p
+    L.pns_create_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(pns_problem), i32, ctypes.POINTER(pns_opts)]
+    L.pns_autotune.argtypes = [vp, i32, dbl, i32, i32, ctypes.POINTER(pns_opts), i32, ctypes.POINTER(pns_tune)]
+    L.pns_chain_offsets.argtypes = [vp, vp]
+    L.pns_num_problems.argtypes = [vp]
+    L.pns_problem_info_get.argtypes = [vp, i32, ctypes.POINTER(pns_problem_info)]
     for name in ("pns_create", "pns_run", "pns_read", "pns_read_current", "pns_field_type", "pns_read_log",
                  "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync", "pns_destroy",
-                 "pns_tile"):
+                 "pns_tile", "pns_create_batch", "pns_autotune", "pns_chain_offsets", "pns_num_problems",
+                 "pns_problem_info_get"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -194,6 +219,39 @@ def pns_tile(ctx):
     return b.value, g.value
 
 
+def pns_create_batch(problems, mode: int, opts: Optional[pns_opts] = None) -> ctypes.c_void_p:
+    """``problems`` is a sequence of ``pns_problem`` (kept alive by the caller)."""
+    arr = (pns_problem * len(problems))(*problems)
+    ctx = ctypes.c_void_p()
+    _check(lib.pns_create_batch(ctypes.byref(ctx), len(problems), arr, mode,
+                                ctypes.byref(opts) if opts is not None else None))
+    return ctx
+
+
+def pns_autotune(Q, N: int, beta: float, subset_size: int, mode: int, opts: Optional[pns_opts] = None,
+                 trial_steps: int = 64) -> pns_tune:
+    out = pns_tune()
+    _check(lib.pns_autotune(_addr(Q), N, beta, subset_size, mode, ctypes.byref(opts) if opts is not None else None,
+                            trial_steps, ctypes.byref(out)))
+    return out
+
+
+def pns_chain_offsets(ctx, num_chains: int) -> np.ndarray:
+    off = np.zeros(num_chains + 1, np.int64)
+    _check(lib.pns_chain_offsets(ctx, off.ctypes.data))
+    return off
+
+
+def pns_num_problems(ctx) -> int:
+    return int(lib.pns_num_problems(ctx))
+
+
+def pns_problem_info_get(ctx, p: int) -> pns_problem_info:
+    info = pns_problem_info()
+    _check(lib.pns_problem_info_get(ctx, p, ctypes.byref(info)))
+    return info
+
+
 def pns_last_error() -> str:
     return lib.pns_last_error().decode()
 
@@ -215,7 +273,8 @@ class Sampler:
     def __init__(self, Q, beta=1.0, subset_size: int = 0, mode="rf", *, num_chains: int = 1, L0: int = 100,
                  seed: int = 0, init="zero", x0=None, layout="symmetric", launch="persistent", chunk: int = 0,
                  block: int = 0, groups: int = 0, stream=None, log_capacity: int = 0, hist: bool = False,
-                 snapshot_every: int = 0, snapshot_capacity: int = 0, chain_id_base: int = 0):
+                 snapshot_every: int = 0, snapshot_capacity: int = 0, chain_id_base: int = 0,
+                 autotune: bool = False):
         if hasattr(Q, "data_ptr"):
             import torch
             dt = {torch.int16: PNS_I16, torch.int32: PNS_I32, torch.float32: PNS_F32}[Q.dtype]
@@ -255,6 +314,7 @@ class Sampler:
         o.hist = 1 if hist else 0
         o.snapshot_every = snapshot_every
         o.snapshot_capacity = snapshot_capacity
+        o.autotune = 1 if autotune else 0
         self.log_capacity = log_capacity
         self.snapshot_capacity = snapshot_capacity
         self.ctx = pns_create(self._Q, self.N, float(betas[0]), subset_size, self.mode, o)
@@ -317,6 +377,147 @@ class Sampler:
 
     def tile(self):
         return pns_tile(self.ctx)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            pns_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _as_q(Q):
+    """(array kept alive, dtype code, N) of a numpy array or torch tensor."""
+    if hasattr(Q, "data_ptr"):
+        import torch
+        dt = {torch.int16: PNS_I16, torch.int32: PNS_I32, torch.float32: PNS_F32}[Q.dtype]
+        return Q.contiguous(), dt, int(Q.shape[0])
+    Qa = np.ascontiguousarray(Q)
+    if Qa.dtype not in _DTYPES:
+        raise TypeError("Q must be int16, int32 or float32")
+    return Qa, _DTYPES[Qa.dtype], int(Qa.shape[0])
+
+
+class BatchSampler:
+    """Several QUBO problems (possibly of different N) in one context.
+
+    ``problems`` is a list of dicts with keys ``Q`` (required), ``beta``
+    (scalar or one value per chain), ``num_chains``, ``subset_size`` (0: chosen
+    by the autotuner in subset modes), ``L0`` (0: the context default) and
+    ``layout``.  Per-chain results come back as lists with one entry per
+    problem."""
+
+    def __init__(self, problems, mode="rf", *, L0: int = 100, seed: int = 0, init="zero", x0=None,
+                 launch="persistent", chunk: int = 0, stream=None, log_capacity: int = 0, snapshot_every: int = 0,
+                 snapshot_capacity: int = 0, chain_id_base: int = 0, autotune: bool = False):
+        self.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        self._keep = []
+        structs = []
+        dtype = None
+        for pr in problems:
+            Qk, dt, N = _as_q(pr["Q"])
+            if dtype is None:
+                dtype = dt
+            elif dt != dtype:
+                raise TypeError("every problem of a batch must have the same Q dtype")
+            c = int(pr.get("num_chains", 1))
+            b = np.broadcast_to(np.asarray(pr.get("beta", 1.0), dtype=np.float64), (c,)).copy()
+            self._keep += [Qk, b]
+            lay = pr.get("layout", "symmetric")
+            structs.append(pns_problem(Q=_addr(Qk), N=N, layout=LAYOUTS[lay] if isinstance(lay, str) else int(lay),
+                                       subset_size=int(pr.get("subset_size", N if self.mode == PNS_MODE_RF else 0)),
+                                       num_chains=c, L0=int(pr.get("L0", 0)), betas=b.ctypes.data,
+                                       beta=float(b[0])))
+        o = pns_opts_default()
+        o.dtype = dtype
+        o.num_chains = 1
+        o.L0 = L0
+        o.seed = seed
+        o.chain_id_base = chain_id_base
+        o.init = INITS[init] if isinstance(init, str) else int(init)
+        if x0 is not None:
+            o.init = PNS_INIT_GIVEN
+            self._x0 = np.ascontiguousarray(np.asarray(x0, dtype=np.uint8).ravel())
+            o.x0 = self._x0.ctypes.data
+        o.launch = LAUNCHES[launch] if isinstance(launch, str) else int(launch)
+        o.chunk = chunk
+        if stream is not None:
+            o.stream = stream if isinstance(stream, int) else stream.cuda_stream
+        o.log_capacity = log_capacity
+        o.snapshot_every = snapshot_every
+        o.snapshot_capacity = snapshot_capacity
+        o.autotune = 1 if autotune else 0
+        self.log_capacity = log_capacity
+        self.snapshot_capacity = snapshot_capacity
+        self.ctx = pns_create_batch(structs, self.mode, o)
+        self.num_problems = pns_num_problems(self.ctx)
+        self.info = [pns_problem_info_get(self.ctx, p) for p in range(self.num_problems)]
+        self.num_chains = sum(i.num_chains for i in self.info)
+        self.offsets = pns_chain_offsets(self.ctx, self.num_chains)
+
+    def run(self, steps: int) -> "BatchSampler":
+        pns_run(self.ctx, steps)
+        return self
+
+    def sync(self) -> None:
+        pns_sync(self.ctx)
+
+    def _split_bits(self, flat, rows: Optional[int] = None):
+        out = []
+        r = rows or 1
+        for i in self.info:
+            c0, c1 = i.chain_begin, i.chain_begin + i.num_chains
+            seg = flat[self.offsets[c0] * r:self.offsets[c1] * r]
+            out.append(seg.reshape(i.num_chains, r, i.N) if rows else seg.reshape(i.num_chains, i.N))
+        return out
+
+    def _split_chains(self, arr):
+        return [arr[i.chain_begin:i.chain_begin + i.num_chains] for i in self.info]
+
+    def read(self):
+        s = np.zeros(self.offsets[-1], np.uint8)
+        m = np.zeros(self.num_chains, np.int64)
+        e = np.zeros(self.num_chains, np.float64)
+        pns_read(self.ctx, s, m, e)
+        return self._split_bits(s), self._split_chains(m), self._split_chains(e)
+
+    def read_current(self):
+        C = self.num_chains
+        s = np.zeros(self.offsets[-1], np.uint8)
+        e = np.zeros(C, np.float64)
+        h = np.zeros(self.offsets[-1], _FIELD_DTYPES[pns_field_type(self.ctx)])
+        L = np.zeros(C, np.int64)
+        sub = np.zeros(C, np.int64)
+        k = np.zeros(C, np.int64)
+        pns_read_current(self.ctx, s, e, h, L, sub, k)
+        return {"x": self._split_bits(s), "E": self._split_chains(e), "h": self._split_bits(h),
+                "L": self._split_chains(L), "sub": self._split_chains(sub), "step": self._split_chains(k)}
+
+    def read_log(self):
+        C, K = self.num_chains, self.log_capacity
+        a = np.zeros((C, K), np.int32)
+        m = np.zeros((C, K), np.int64)
+        e = np.zeros((C, K), np.float64)
+        p = np.zeros((C, K), np.float64)
+        pns_read_log(self.ctx, a, m, e, p)
+        return {"action": self._split_chains(a), "M": self._split_chains(m), "E": self._split_chains(e),
+                "p": self._split_chains(p)}
+
+    def read_snapshots(self):
+        C, S = self.num_chains, self.snapshot_capacity
+        x = np.zeros(self.offsets[-1] * S, np.uint8)
+        m = np.zeros((C, S), np.int64)
+        e = np.zeros((C, S), np.float64)
+        cnt = pns_read_snapshots(self.ctx, x, m, e)
+        return self._split_bits(x, S), self._split_chains(m), self._split_chains(e), cnt
+
+    def stats(self):
+        arr = pns_stats(self.ctx, self.num_chains)
+        return {k: np.array([getattr(s, k) for s in arr]) for k in ("steps", "flips", "stays", "saturated", "sum_M", "anomalies")}
 
     def close(self) -> None:
         if getattr(self, "ctx", None) is not None and self.ctx.value:

@@ -1,18 +1,24 @@
 // C-ABI runtime of the Partial Neighbor Search sampler (see include/pns.h).
 //
-// Owns the device memory of a sampler context, prepares the coefficient
+// Owns the device memory of a sampler context, prepares each coefficient
 // matrix (zero-diagonal off-diagonal part A with a padded pitch, diagonal
-// split off, symmetry and field-bound checks), chooses the workgroup tile,
-// queues the step kernels in the plain, persistent or HIP-graph form, and
-// copies results out to host or device buffers.
+// split off, symmetry and field-bound checks), chooses workgroup tiles (fixed
+// table or timed trials), groups the chains of uneven-N problems into launch
+// classes that run concurrently, queues the step kernels in the plain,
+// persistent or HIP-graph form, and copies results to host or device buffers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "pns.h"
@@ -40,9 +46,9 @@ int hip_fail(hipError_t e, const char* what)
     return fail(PNS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(call, what)                       \
-    do {                                          \
-        hipError_t e_ = (call);                   \
+#define HIP_TRY(call, what)                              \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
 
@@ -73,6 +79,7 @@ int copy_out(void* dst, const void* src, size_t bytes)
 // Copy `bytes` from a caller buffer (host or device) into host memory.
 int copy_in(void* dst, const void* src, size_t bytes)
 {
+    if (bytes == 0) return PNS_OK;
     if (is_device_ptr(src)) {
         HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost), "copy from device buffer");
     } else {
@@ -94,6 +101,15 @@ int dev_alloc(T** p, size_t count)
     return PNS_OK;
 }
 
+template <typename T>
+int d2h(std::vector<T>& v, const void* src, size_t count)
+{
+    v.resize(count);
+    if (count == 0) return PNS_OK;
+    HIP_TRY(hipMemcpy(v.data(), src, count * sizeof(T), hipMemcpyDeviceToHost), "download");
+    return PNS_OK;
+}
+
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 int64_t gcd64(int64_t a, int64_t b)
@@ -106,11 +122,13 @@ int64_t gcd64(int64_t a, int64_t b)
     return a;
 }
 
+size_t qsize(int32_t qtype) { return qtype == Q_I16 ? 2 : 4; }
+
 struct Tile {
     int32_t block, groups;
 };
 
-// Tile table: smallest capacity (block * 4 * groups) covering N.
+// Fixed tile table: smallest capacity (block * 4 * groups) covering N.
 Tile default_tile(int32_t N)
 {
     if (N <= 256) return {64, 1};
@@ -121,23 +139,204 @@ Tile default_tile(int32_t N)
     return {1024, 4};
 }
 
+// Every tile the step kernels are compiled for.
+const Tile kTiles[] = {{64, 1},  {64, 2},  {64, 4},  {128, 2}, {128, 4},  {256, 1},
+                       {256, 2}, {256, 4}, {512, 2}, {512, 4}, {1024, 2}, {1024, 4}};
+
+// True if no window of n cyclically consecutive bits holds bits of two
+// different 4-bit groups within one wave: the lanes of wave w in group g hold
+// the contiguous range [(g*block + 64w)*4, +256) of bits.
+bool window_compact_ok(int32_t N, int32_t n, int32_t block, int32_t groups)
+{
+    if (groups == 1) return true;
+    if (n >= N) return false;
+    for (int32_t w = 0; w < block / 64; ++w) {
+        for (int32_t ga = 0; ga < groups; ++ga) {
+            const int64_t a0 = ((int64_t)ga * block + 64 * w) * 4;
+            if (a0 >= N) continue;
+            const int64_t a1 = std::min<int64_t>(a0 + 255, N - 1);
+            for (int32_t gb = 0; gb < groups; ++gb) {
+                if (gb == ga) continue;
+                const int64_t b0 = ((int64_t)gb * block + 64 * w) * 4;
+                if (b0 >= N) continue;
+                // shortest forward distance from a bit of range a to a bit of range b
+                if (((b0 - a1) % N + N) % N < n) return false;
+            }
+        }
+    }
+    return true;
+}
+
+// How the step kernel forms the subset: 0 every bit, 1 systematic window,
+// 2 random subset drawn in LDS, 3 compact systematic window.
+int32_t flavour_of(int32_t mode, int32_t N, int32_t n, int32_t block, int32_t groups)
+{
+    if (mode == PNS_MODE_RF) return 0;
+    if (mode == PNS_MODE_BASIC) return n < N ? 2 : 0;
+    if (mode == PNS_MODE_UNBIASED_SYS || n >= N) return window_compact_ok(N, n, block, groups) ? 3 : 1;
+    return 2;
+}
+
+// A problem's matrix as the kernels read it, prepared on the host.
+struct Prepared {
+    std::vector<uint8_t> A, D;  // A: N x pitch, zero diagonal; D: diagonal [pitch]
+    double field_bound = 0.0;   // max_i sum_j |A_ij|
+    double diag_bound = 0.0;    // max_i |Q_ii|
+};
+
+// Build the zero-diagonal off-diagonal matrix A (pitch-padded) and the
+// diagonal from the caller's Q, check symmetry (SYMMETRIC) and finiteness,
+// and bound the fields.  Rows are split over host threads and walked in
+// 64 x 64 tiles so that the transposed reads stay in cache.
+template <typename QT>
+int prepare_matrix(const QT* Q, int32_t N, int32_t layout, int64_t pitch, Prepared* out)
+{
+    using DW = typename std::conditional<std::is_same<QT, float>::value, float, int32_t>::type;
+    constexpr bool kFloat = std::is_same<QT, float>::value;
+    out->A.assign((size_t)N * pitch * sizeof(QT), 0);
+    out->D.assign((size_t)pitch * sizeof(DW), 0);
+    QT* A = reinterpret_cast<QT*>(out->A.data());
+    DW* d = reinterpret_cast<DW*>(out->D.data());
+    constexpr int32_t T = 64;
+    const int32_t nblk = (N + T - 1) / T;
+    const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::string> errs((size_t)nthreads);
+    std::vector<double> fbs((size_t)nthreads, 0.0), dbs((size_t)nthreads, 0.0);
+    auto work = [&](int t) {
+        std::vector<double> rowsum(T);
+        for (int32_t bi = t; bi < nblk; bi += nthreads) {
+            const int32_t i0 = bi * T, i1 = std::min(N, i0 + T);
+            std::fill(rowsum.begin(), rowsum.end(), 0.0);
+            for (int32_t bj = 0; bj < nblk; ++bj) {
+                const int32_t j0 = bj * T, j1 = std::min(N, j0 + T);
+                for (int32_t i = i0; i < i1; ++i) {
+                    for (int32_t j = j0; j < j1; ++j) {
+                        if (i == j) {
+                            const QT q = Q[(size_t)i * N + i];
+                            if (kFloat && !std::isfinite((double)q)) {
+                                char b[96];
+                                snprintf(b, sizeof(b), "Q has a non-finite entry at (%d, %d)", i, i);
+                                if (errs[t].empty()) errs[t] = b;
+                            }
+                            d[i] = (DW)q;
+                            dbs[t] = std::max(dbs[t], std::fabs((double)q));
+                            continue;
+                        }
+                        QT v;
+                        if (layout == PNS_SYMMETRIC) {
+                            v = Q[(size_t)i * N + j];
+                            if (!(v == Q[(size_t)j * N + i]) && errs[t].empty()) {
+                                char b[96];
+                                snprintf(b, sizeof(b), "SYMMETRIC Q is not symmetric at (%d, %d)", i, j);
+                                errs[t] = b;
+                            }
+                        } else {
+                            v = i < j ? Q[(size_t)i * N + j] : Q[(size_t)j * N + i];
+                        }
+                        if (kFloat && !std::isfinite((double)v) && errs[t].empty()) {
+                            char b[96];
+                            snprintf(b, sizeof(b), "Q has a non-finite entry at (%d, %d)", i, j);
+                            errs[t] = b;
+                        }
+                        A[(size_t)i * pitch + j] = v;
+                        rowsum[i - i0] += std::fabs((double)v);
+                    }
+                }
+            }
+            for (int32_t i = i0; i < i1; ++i) fbs[t] = std::max(fbs[t], rowsum[i - i0]);
+        }
+    };
+    if (nthreads == 1 || (int64_t)N * N < (1 << 20)) {
+        for (int t = 0; t < nthreads; ++t) work(t);  // small matrices: no threads
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthreads; ++t) pool.emplace_back(work, t);
+        for (auto& th : pool) th.join();
+    }
+    for (int t = 0; t < nthreads; ++t)
+        if (!errs[t].empty()) return fail(PNS_EINVAL, "%s", errs[t].c_str());
+    out->field_bound = *std::max_element(fbs.begin(), fbs.end());
+    out->diag_bound = *std::max_element(dbs.begin(), dbs.end());
+    return PNS_OK;
+}
+
+// Copy a problem's Q in (host or device) and prepare it.
+int prepare_problem(const void* Q, int32_t N, int32_t layout, int32_t qtype, Prepared* out)
+{
+    const int64_t pitch = round_up(N, 64);
+    std::vector<uint8_t> qhost((size_t)N * N * qsize(qtype));
+    int rc = copy_in(qhost.data(), Q, qhost.size());
+    if (rc) return rc;
+    if (qtype == Q_I16) return prepare_matrix(reinterpret_cast<const int16_t*>(qhost.data()), N, layout, pitch, out);
+    if (qtype == Q_I32) return prepare_matrix(reinterpret_cast<const int32_t*>(qhost.data()), N, layout, pitch, out);
+    return prepare_matrix(reinterpret_cast<const float*>(qhost.data()), N, layout, pitch, out);
+}
+
+int check_opts(const pns_opts* o)
+{
+    for (int i = 0; i < 7; ++i)
+        if (o->reserved[i] != 0) return fail(PNS_EINVAL, "opts.reserved must be zero");
+    if (o->dtype < PNS_I16 || o->dtype > PNS_F32) return fail(PNS_EINVAL, "unknown dtype %d", o->dtype);
+    if (o->layout != PNS_SYMMETRIC && o->layout != PNS_UPPER) return fail(PNS_EINVAL, "unknown layout %d", o->layout);
+    if (o->num_chains < 1) return fail(PNS_EINVAL, "num_chains must be >= 1");
+    if (o->L0 < 0) return fail(PNS_EINVAL, "L0 must be >= 0");
+    if (o->init < PNS_INIT_ZERO || o->init > PNS_INIT_GIVEN) return fail(PNS_EINVAL, "unknown init %d", o->init);
+    if (o->init == PNS_INIT_GIVEN && o->x0 == nullptr) return fail(PNS_EINVAL, "INIT_GIVEN needs x0");
+    if (o->launch < PNS_LAUNCH_PLAIN || o->launch > PNS_LAUNCH_GRAPH) return fail(PNS_EINVAL, "unknown launch %d", o->launch);
+    if (o->chunk < 0) return fail(PNS_EINVAL, "chunk must be >= 0");
+    if (o->log_capacity < 0) return fail(PNS_EINVAL, "log_capacity must be >= 0");
+    if (o->snapshot_every < 0 || (o->snapshot_every > 0 && o->snapshot_capacity < 1))
+        return fail(PNS_EINVAL, "snapshots need snapshot_every >= 0 and snapshot_capacity >= 1");
+    return PNS_OK;
+}
+
+// One problem as the caller describes it, plus what the library derives.
+struct ProblemSpec {
+    const void* Q = nullptr;
+    int32_t N = 0, layout = 0, n = 0, chains = 0;
+    int64_t L0 = 100;
+    std::vector<double> betas;
+    Tile tile{0, 0};  // 0: default table
+};
+
+struct ProblemRun {
+    int32_t N, n, layout, s, flav;
+    int64_t pitch, L0, num_sets;
+    int32_t chain_begin, chains;
+    Tile tile;
+    void* A = nullptr;
+    void* diag = nullptr;
+};
+
+// Chains that share a tile shape and kernel flavour: one step-kernel launch.
+struct LaunchClass {
+    Tile tile;
+    int32_t flav;
+    size_t dyn;
+    std::vector<int32_t> chains;
+    int32_t* d_list = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+};
+
 }  // namespace
 
 struct pns_ctx {
-    int32_t N = 0, n = 0, mode = 0, qtype = 0, htype = 0, layout = 0;
+    int32_t mode = 0, qtype = 0, htype = 0;
     int32_t num_chains = 0;
-    int32_t block = 0, groups = 0;
-    int64_t pitch = 0;
     int32_t launch = PNS_LAUNCH_PERSISTENT;
     int32_t chunk = 0;
     uint64_t seed = 0;
-    int64_t L0 = 100;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    size_t dyn_lds = 0;
+    hipEvent_t fork = nullptr;
+    std::vector<ProblemRun> probs;
+    std::vector<int32_t> h_chain_problem;
+    std::vector<int64_t> h_foff;
+    std::vector<int64_t> h_offsets;  // concatenated per-chain bit arrays, [C+1]
+    int64_t fields = 0, max_pitch = 0;
+    std::vector<LaunchClass> classes;
     // device memory
-    void* A = nullptr;
-    void* diag = nullptr;
     Problem* problems = nullptr;
     int32_t* chain_problem = nullptr;
     int64_t* foff = nullptr;
@@ -170,6 +369,8 @@ struct pns_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int64_t graph_steps = -1;
+
+    bool instrumented() const { return log_cap > 0 || hist_w != nullptr || snap_every > 0; }
 
     StepArgs args(int64_t steps) const
     {
@@ -208,57 +409,39 @@ struct pns_ctx {
         a.snap_M = snap_M;
         a.snap_E = snap_E;
         a.snap_count = snap_count;
-        a.snap_pitch = pitch;
+        a.snap_pitch = max_pitch;
         return a;
     }
 
-    // How the step kernel forms the subset: 0 every bit, 1 systematic window,
-    // 2 random subset drawn in LDS, 3 systematic window that reaches at most
-    // one 4-bit group of any lane (weights kept for that group only).
-    int32_t flavour() const
+    int launch_class(const LaunchClass& k, int64_t steps, hipStream_t st)
     {
-        if (mode == PNS_MODE_RF) return 0;
-        if (mode == PNS_MODE_BASIC) return n < N ? 2 : 0;
-        if (mode == PNS_MODE_UNBIASED_SYS || n >= N) return window_compact_ok(N, n, block, groups) ? 3 : 1;
-        return 2;
-    }
-
-    // True if no window of n cyclically consecutive bits holds bits of two
-    // different 4-bit groups within one wave: the wave's lanes of group g
-    // hold the contiguous range [(g*block + 64w)*4, +256) of bits.
-    static bool window_compact_ok(int32_t N, int32_t n, int32_t block, int32_t groups)
-    {
-        if (groups == 1) return true;
-        if (n >= N) return false;
-        for (int32_t w = 0; w < block / 64; ++w) {
-            for (int32_t ga = 0; ga < groups; ++ga) {
-                const int64_t a0 = ((int64_t)ga * block + 64 * w) * 4;
-                if (a0 >= N) continue;
-                const int64_t a1 = std::min<int64_t>(a0 + 255, N - 1);
-                for (int32_t gb = 0; gb < groups; ++gb) {
-                    if (gb == ga) continue;
-                    const int64_t b0 = ((int64_t)gb * block + 64 * w) * 4;
-                    if (b0 >= N) continue;
-                    // shortest forward distance from a bit of range a to a bit of range b
-                    if (((b0 - a1) % N + N) % N < n) return false;
-                }
-            }
+        // host-side check that the launch matches what the kernels assume
+        for (int32_t c : {k.chains.front(), k.chains.back()}) {
+            const ProblemRun& P = probs[h_chain_problem[c]];
+            if ((int64_t)k.tile.block * 4 * k.tile.groups < P.N)
+                return fail(PNS_EINVAL, "tile %dx%d does not cover N=%d", k.tile.block, k.tile.groups, P.N);
         }
-        return true;
+        StepArgs a = args(steps);
+        if (classes.size() > 1 || (int32_t)k.chains.size() != num_chains) a.chain_list = k.d_list;
+        hipError_t e = launch_steps(qtype, htype, k.flav, instrumented(), k.tile.block, k.tile.groups,
+                                    (int32_t)k.chains.size(), k.dyn, st, a);
+        if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+        return PNS_OK;
     }
 
-    bool instrumented() const { return log_cap > 0 || hist_w != nullptr || snap_every > 0; }
-
+    // One chunk of `steps` steps for every chain: one launch per class; with
+    // several classes they run on their own streams between a fork and a join.
     int launch_chunk(int64_t steps)
     {
-        // host-side check that the launch matches what the kernel assumes
-        if ((int64_t)block * 4 * groups < N || num_chains < 1 || !have_tile(qtype, htype, block, groups))
-            return fail(PNS_EINVAL, "tile %dx%d does not cover N=%d", block, groups, N);
-        const int32_t flav = flavour();
-        const size_t dyn = flav == 2 ? (size_t)pitch * 4 : flav == 3 ? (size_t)pitch * 4 : 0;
-        hipError_t e = launch_steps(qtype, htype, flav, instrumented(), block, groups, num_chains, dyn, stream,
-                                    args(steps));
-        if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+        if (classes.size() == 1) return launch_class(classes[0], steps, stream);
+        HIP_TRY(hipEventRecord(fork, stream), "fork record");
+        for (auto& k : classes) {
+            HIP_TRY(hipStreamWaitEvent(k.stream, fork, 0), "fork wait");
+            int rc = launch_class(k, steps, k.stream);
+            if (rc) return rc;
+            HIP_TRY(hipEventRecord(k.done, k.stream), "join record");
+            HIP_TRY(hipStreamWaitEvent(stream, k.done, 0), "join wait");
+        }
         return PNS_OK;
     }
 
@@ -266,89 +449,26 @@ struct pns_ctx {
     {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
-        void* ptrs[] = {A, diag, problems, chain_problem, foff, beta, chain_id, x, h, rmem, E, L, sub, step,
-                        last_action, last_M, last_E, counters, log_action, log_M, log_E, log_p, hist_w, hist_v,
-                        snap_x, snap_M, snap_E, snap_count};
+        void* ptrs[] = {problems, chain_problem, foff, beta, chain_id, x, h, rmem, E, L, sub, step, last_action, last_M,
+                        last_E, counters, log_action, log_M, log_E, log_p, hist_w, hist_v, snap_x, snap_M, snap_E,
+                        snap_count};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
+        for (auto& P : probs) {
+            if (P.A) (void)hipFree(P.A);
+            if (P.diag) (void)hipFree(P.diag);
+        }
+        for (auto& k : classes) {
+            if (k.d_list) (void)hipFree(k.d_list);
+            if (k.stream) (void)hipStreamDestroy(k.stream);
+            if (k.done) (void)hipEventDestroy(k.done);
+        }
+        if (fork) (void)hipEventDestroy(fork);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
 
 namespace {
-
-size_t qsize(int32_t qtype) { return qtype == Q_I16 ? 2 : 4; }
-
-// Build the zero-diagonal off-diagonal matrix A (pitch-padded) and the
-// diagonal from the caller's Q, and bound the fields.
-template <typename QT>
-int prepare_matrix(const QT* Q, int32_t N, int32_t layout, int64_t pitch, std::vector<QT>& A,
-                   std::vector<uint8_t>& diag_bytes, double* field_bound, double* diag_bound)
-{
-    A.assign((size_t)N * pitch, (QT)0);
-    using DW = typename std::conditional<std::is_same<QT, float>::value, float, int32_t>::type;
-    std::vector<DW> d((size_t)pitch, (DW)0);
-    double fb = 0.0, db = 0.0;
-    for (int32_t i = 0; i < N; ++i) {
-        double rowsum = 0.0;
-        for (int32_t j = 0; j < N; ++j) {
-            QT v;
-            if (i == j) {
-                d[i] = (DW)Q[(size_t)i * N + i];
-                db = std::max(db, std::fabs((double)d[i]));
-                continue;
-            }
-            if (layout == PNS_SYMMETRIC) {
-                v = Q[(size_t)i * N + j];
-                if (!(v == Q[(size_t)j * N + i]))
-                    return fail(PNS_EINVAL, "SYMMETRIC Q is not symmetric at (%d, %d)", i, j);
-            } else {
-                v = i < j ? Q[(size_t)i * N + j] : Q[(size_t)j * N + i];
-            }
-            if (std::is_same<QT, float>::value && !std::isfinite((double)v))
-                return fail(PNS_EINVAL, "Q has a non-finite entry at (%d, %d)", i, j);
-            A[(size_t)i * pitch + j] = v;
-            rowsum += std::fabs((double)v);
-        }
-        fb = std::max(fb, rowsum);
-    }
-    diag_bytes.resize(d.size() * sizeof(DW));
-    std::memcpy(diag_bytes.data(), d.data(), diag_bytes.size());
-    *field_bound = fb;
-    *diag_bound = db;
-    return PNS_OK;
-}
-
-int check_opts(const pns_opts* o)
-{
-    for (int i = 0; i < 8; ++i)
-        if (o->reserved[i] != 0) return fail(PNS_EINVAL, "opts.reserved must be zero");
-    if (o->dtype < PNS_I16 || o->dtype > PNS_F32) return fail(PNS_EINVAL, "unknown dtype %d", o->dtype);
-    if (o->layout != PNS_SYMMETRIC && o->layout != PNS_UPPER) return fail(PNS_EINVAL, "unknown layout %d", o->layout);
-    if (o->num_chains < 1) return fail(PNS_EINVAL, "num_chains must be >= 1");
-    if (o->L0 < 0) return fail(PNS_EINVAL, "L0 must be >= 0");
-    if (o->init < PNS_INIT_ZERO || o->init > PNS_INIT_GIVEN) return fail(PNS_EINVAL, "unknown init %d", o->init);
-    if (o->init == PNS_INIT_GIVEN && o->x0 == nullptr) return fail(PNS_EINVAL, "INIT_GIVEN needs x0");
-    if (o->launch < PNS_LAUNCH_PLAIN || o->launch > PNS_LAUNCH_GRAPH) return fail(PNS_EINVAL, "unknown launch %d", o->launch);
-    if (o->chunk < 0) return fail(PNS_EINVAL, "chunk must be >= 0");
-    if (o->log_capacity < 0) return fail(PNS_EINVAL, "log_capacity must be >= 0");
-    if (o->snapshot_every < 0 || (o->snapshot_every > 0 && o->snapshot_capacity < 1))
-        return fail(PNS_EINVAL, "snapshots need snapshot_every >= 0 and snapshot_capacity >= 1");
-    return PNS_OK;
-}
-
-}  // namespace
-
-namespace {
-
-template <typename T>
-int d2h(std::vector<T>& v, const void* src, size_t count)
-{
-    v.resize(count);
-    if (count == 0) return PNS_OK;
-    HIP_TRY(hipMemcpy(v.data(), src, count * sizeof(T), hipMemcpyDeviceToHost), "download");
-    return PNS_OK;
-}
 
 std::vector<double> energies_to_double(const pns_ctx* ctx, const std::vector<int64_t>& bits)
 {
@@ -365,11 +485,479 @@ std::vector<double> energies_to_double(const pns_ctx* ctx, const std::vector<int
     return out;
 }
 
-int compact_states(const pns_ctx* ctx, const std::vector<uint8_t>& xp, std::vector<uint8_t>& xs)
+// Per-chain padded rows -> concatenated rows of each chain's own N.
+template <typename T>
+std::vector<T> compact_rows(const pns_ctx* ctx, const std::vector<T>& padded, int64_t row_pitch, int64_t rows_per_chain)
+{
+    std::vector<T> out((size_t)ctx->h_offsets.back() * rows_per_chain);
+    for (int32_t c = 0; c < ctx->num_chains; ++c) {
+        const int32_t N = ctx->probs[ctx->h_chain_problem[c]].N;
+        for (int64_t r = 0; r < rows_per_chain; ++r)
+            std::memcpy(&out[(size_t)(ctx->h_offsets[c] * rows_per_chain + r * N)],
+                        &padded[(size_t)((int64_t)c * rows_per_chain + r) * row_pitch], N * sizeof(T));
+    }
+    return out;
+}
+
+// Everything a context needs, for one or several problems.
+// `preps`, if not empty, holds each problem's prepared matrix (as
+// prepare_problem makes it); otherwise the matrices are prepared here.
+int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, const pns_opts& o,
+                const std::vector<const Prepared*>& preps = {})
+{
+    *out = nullptr;
+    if (mode < PNS_MODE_RF || mode > PNS_MODE_UNBIASED_RAND) return fail(PNS_EINVAL, "unknown mode %d", mode);
+    if (specs.empty()) return fail(PNS_EINVAL, "no problems");
+    const int32_t qtype = o.dtype;
+    const bool batch = specs.size() > 1;
+    int64_t total_chains = 0;
+    for (size_t p = 0; p < specs.size(); ++p) {
+        ProblemSpec& S = specs[p];
+        if (!S.Q) return fail(PNS_EINVAL, "Q of problem %zu is NULL", p);
+        if (S.N <= 0) return fail(PNS_EINVAL, "N must be positive");
+        if (S.layout != PNS_SYMMETRIC && S.layout != PNS_UPPER) return fail(PNS_EINVAL, "unknown layout %d", S.layout);
+        if (mode == PNS_MODE_RF) S.n = S.N;
+        if (S.n < 1 || S.n > S.N) return fail(PNS_EINVAL, "subset size %d outside [1, %d]", S.n, S.N);
+        if (S.chains < 1) return fail(PNS_EINVAL, "num_chains must be >= 1");
+        if (S.L0 < 0) return fail(PNS_EINVAL, "L0 must be >= 0");
+        if ((int32_t)S.betas.size() != S.chains) return fail(PNS_EINVAL, "betas size mismatch");
+        for (double b : S.betas)
+            if (!(b >= 0.0) || !std::isfinite(b)) return fail(PNS_EINVAL, "beta must be finite and >= 0");
+        if (S.tile.block == 0) S.tile = default_tile(S.N);
+        if ((int64_t)S.tile.block * 4 * S.tile.groups < S.N) {
+            if (S.N > 16384) return fail(PNS_EUNSUPPORTED, "N=%d exceeds the largest tile (16384)", S.N);
+            return fail(PNS_EINVAL, "tile %dx%d cannot hold N=%d", S.tile.block, S.tile.groups, S.N);
+        }
+        total_chains += S.chains;
+    }
+    if (total_chains > (1 << 30)) return fail(PNS_EINVAL, "too many chains");
+    if (o.hist && (batch || specs[0].N > 24)) return fail(PNS_EINVAL, "histograms need one problem with N <= 24");
+
+    // matrices: host preparation, field-type choice
+    std::vector<Prepared> own(preps.empty() ? specs.size() : 0);
+    std::vector<const Prepared*> pp(preps);
+    if (pp.empty()) {
+        for (size_t p = 0; p < specs.size(); ++p) {
+            int rc = prepare_problem(specs[p].Q, specs[p].N, specs[p].layout, qtype, &own[p]);
+            if (rc) return rc;
+            pp.push_back(&own[p]);
+        }
+    }
+    if (pp.size() != specs.size()) return fail(PNS_EINVAL, "prepared matrices do not match the problems");
+    double ebound_max = 0.0, fbound_max = 0.0;
+    for (size_t p = 0; p < specs.size(); ++p) {
+        const ProblemSpec& S = specs[p];
+        const int32_t s = S.layout == PNS_SYMMETRIC ? 2 : 1;
+        const double eb = pp[p]->diag_bound + s * pp[p]->field_bound;
+        if (qtype != Q_F32 && eb * (double)S.N > 9.0e18) return fail(PNS_EINVAL, "energy bound of Q overflows int64");
+        ebound_max = std::max(ebound_max, eb);
+        fbound_max = std::max(fbound_max, pp[p]->field_bound);
+    }
+    int32_t htype;
+    if (qtype == Q_F32) htype = H_F64;
+    else if (qtype == Q_I16) htype = H_I32;
+    else htype = (fbound_max < 2147483647.0 && ebound_max < 2147483647.0) ? H_I32 : H_I64;
+    for (const auto& S : specs)
+        if (!have_tile(qtype, htype, S.tile.block, S.tile.groups))
+            return fail(PNS_EINVAL, "no kernel for tile %dx%d", S.tile.block, S.tile.groups);
+
+    pns_ctx* ctx = new pns_ctx();
+    auto fail_free = [&](int r) {
+        ctx->free_all();
+        delete ctx;
+        return r;
+    };
+    ctx->mode = mode;
+    ctx->qtype = qtype;
+    ctx->htype = htype;
+    ctx->num_chains = (int32_t)total_chains;
+    ctx->launch = o.launch;
+    ctx->chunk = o.chunk;
+    ctx->seed = o.seed;
+    if (o.stream) {
+        ctx->stream = reinterpret_cast<hipStream_t>(o.stream);
+    } else {
+        hipError_t e = hipStreamCreate(&ctx->stream);
+        if (e != hipSuccess) return fail_free(hip_fail(e, "hipStreamCreate"));
+        ctx->own_stream = true;
+    }
+
+    // problems, chain tables, launch classes
+    const int64_t C = total_chains;
+    ctx->h_chain_problem.resize(C);
+    ctx->h_foff.resize(C);
+    ctx->h_offsets.assign(C + 1, 0);
+    std::vector<double> betas((size_t)C);
+    std::vector<Problem> dev_probs(specs.size());
+    int32_t c0 = 0;
+    int64_t f0 = 0;
+    std::map<std::pair<std::pair<int32_t, int32_t>, int32_t>, size_t> class_of;
+    for (size_t p = 0; p < specs.size(); ++p) {
+        const ProblemSpec& S = specs[p];
+        ProblemRun R{};
+        R.N = S.N;
+        R.n = S.n;
+        R.layout = S.layout;
+        R.s = S.layout == PNS_SYMMETRIC ? 2 : 1;
+        R.pitch = round_up(S.N, 64);
+        R.L0 = S.L0;
+        R.num_sets = S.N / gcd64(S.N, S.n);
+        R.chain_begin = c0;
+        R.chains = S.chains;
+        R.tile = S.tile;
+        R.flav = flavour_of(mode, S.N, S.n, S.tile.block, S.tile.groups);
+        ctx->probs.push_back(R);
+        ProblemRun& RR = ctx->probs.back();
+        int r = dev_alloc(reinterpret_cast<uint8_t**>(&RR.A), pp[p]->A.size());
+        if (!r) r = dev_alloc(reinterpret_cast<uint8_t**>(&RR.diag), pp[p]->D.size());
+        if (r) return fail_free(r);
+        hipError_t e = hipMemcpy(RR.A, pp[p]->A.data(), pp[p]->A.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(RR.diag, pp[p]->D.data(), pp[p]->D.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail_free(hip_fail(e, "upload"));
+        if (p < own.size()) {
+            own[p].A.clear();
+            own[p].A.shrink_to_fit();
+        }
+        Problem& D = dev_probs[p];
+        D.A = RR.A;
+        D.diag = RR.diag;
+        D.pitch = RR.pitch;
+        D.num_sets = RR.num_sets;
+        D.L0 = RR.L0;
+        D.N = RR.N;
+        D.n = RR.n;
+        D.s = RR.s;
+        D.qtype = qtype;
+        ctx->max_pitch = std::max(ctx->max_pitch, RR.pitch);
+        const auto key = std::make_pair(std::make_pair(RR.tile.block, RR.tile.groups), RR.flav);
+        if (!class_of.count(key)) {
+            class_of[key] = ctx->classes.size();
+            LaunchClass k;
+            k.tile = RR.tile;
+            k.flav = RR.flav;
+            k.dyn = 0;
+            ctx->classes.push_back(k);
+        }
+        LaunchClass& K = ctx->classes[class_of[key]];
+        if (RR.flav == 2 || RR.flav == 3) K.dyn = std::max(K.dyn, (size_t)RR.pitch * 4);
+        for (int32_t c = 0; c < S.chains; ++c) {
+            ctx->h_chain_problem[c0 + c] = (int32_t)p;
+            ctx->h_foff[c0 + c] = f0 + (int64_t)c * RR.pitch;
+            ctx->h_offsets[c0 + c + 1] = ctx->h_offsets[c0 + c] + S.N;
+            betas[c0 + c] = S.betas[c];
+            K.chains.push_back(c0 + c);
+        }
+        f0 += (int64_t)S.chains * RR.pitch;
+        c0 += S.chains;
+    }
+    ctx->fields = f0;
+    // longest problems first within a class: the last workgroups to start are short ones
+    for (auto& k : ctx->classes)
+        std::stable_sort(k.chains.begin(), k.chains.end(), [&](int32_t a, int32_t b) {
+            return ctx->probs[ctx->h_chain_problem[a]].N > ctx->probs[ctx->h_chain_problem[b]].N;
+        });
+
+    const size_t hbytes = htype == H_I32 ? 4 : 8;
+    const size_t fields = (size_t)ctx->fields;
+    const bool any_drawn = mode == PNS_MODE_UNBIASED_RAND;
+#define ALLOC(ptr, type, count)                                    \
+    do {                                                           \
+        int r_ = dev_alloc(reinterpret_cast<type**>(&ptr), count); \
+        if (r_) return fail_free(r_);                              \
+    } while (0)
+    ALLOC(ctx->problems, Problem, specs.size());
+    ALLOC(ctx->chain_problem, int32_t, C);
+    ALLOC(ctx->foff, int64_t, C);
+    ALLOC(ctx->beta, double, C);
+    ALLOC(ctx->chain_id, uint32_t, C);
+    ALLOC(ctx->x, uint8_t, fields);
+    ALLOC(ctx->h, uint8_t, fields * hbytes);
+    ALLOC(ctx->E, int64_t, C);
+    ALLOC(ctx->L, int64_t, C);
+    ALLOC(ctx->sub, int64_t, C);
+    ALLOC(ctx->step, int64_t, C);
+    ALLOC(ctx->last_action, int32_t, C);
+    ALLOC(ctx->last_M, int64_t, C);
+    ALLOC(ctx->last_E, int64_t, C);
+    ALLOC(ctx->counters, int64_t, C * 6);
+    if (any_drawn) ALLOC(ctx->rmem, uint8_t, fields);
+    if (o.log_capacity > 0) {
+        ctx->log_cap = o.log_capacity;
+        ALLOC(ctx->log_action, int32_t, (size_t)C * o.log_capacity);
+        ALLOC(ctx->log_M, int64_t, (size_t)C * o.log_capacity);
+        ALLOC(ctx->log_E, int64_t, (size_t)C * o.log_capacity);
+        ALLOC(ctx->log_p, double, (size_t)C * o.log_capacity);
+    }
+    if (o.hist) {
+        ALLOC(ctx->hist_w, unsigned long long, (size_t)1 << specs[0].N);
+        ALLOC(ctx->hist_v, unsigned long long, (size_t)1 << specs[0].N);
+    }
+    if (o.snapshot_every > 0) {
+        ctx->snap_every = o.snapshot_every;
+        ctx->snap_cap = o.snapshot_capacity;
+        ALLOC(ctx->snap_x, uint8_t, (size_t)C * o.snapshot_capacity * ctx->max_pitch);
+        ALLOC(ctx->snap_M, int64_t, (size_t)C * o.snapshot_capacity);
+        ALLOC(ctx->snap_E, int64_t, (size_t)C * o.snapshot_capacity);
+        ALLOC(ctx->snap_count, int32_t, C);
+    }
+    for (auto& k : ctx->classes) ALLOC(k.d_list, int32_t, k.chains.size());
+#undef ALLOC
+
+    std::vector<uint32_t> cidv((size_t)C);
+    for (int64_t c = 0; c < C; ++c) cidv[c] = o.chain_id_base + (uint32_t)c;
+    std::vector<int64_t> Lv((size_t)C), zeros64((size_t)C * 6, 0);
+    for (int64_t c = 0; c < C; ++c) Lv[c] = ctx->probs[ctx->h_chain_problem[c]].L0;
+    std::vector<int32_t> la((size_t)C, PNS_STAY);
+#define H2D(dst, src, bytes)                                               \
+    do {                                                                   \
+        hipError_t e_ = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice); \
+        if (e_ != hipSuccess) return fail_free(hip_fail(e_, "upload"));    \
+    } while (0)
+    H2D(ctx->problems, dev_probs.data(), dev_probs.size() * sizeof(Problem));
+    H2D(ctx->chain_problem, ctx->h_chain_problem.data(), C * sizeof(int32_t));
+    H2D(ctx->foff, ctx->h_foff.data(), C * sizeof(int64_t));
+    H2D(ctx->beta, betas.data(), C * sizeof(double));
+    H2D(ctx->chain_id, cidv.data(), C * sizeof(uint32_t));
+    H2D(ctx->L, Lv.data(), C * sizeof(int64_t));
+    H2D(ctx->sub, zeros64.data(), C * sizeof(int64_t));
+    H2D(ctx->step, zeros64.data(), C * sizeof(int64_t));
+    H2D(ctx->last_action, la.data(), C * sizeof(int32_t));
+    H2D(ctx->last_M, zeros64.data(), C * sizeof(int64_t));
+    H2D(ctx->counters, zeros64.data(), C * 6 * sizeof(int64_t));
+    if (ctx->snap_count) H2D(ctx->snap_count, zeros64.data(), C * sizeof(int32_t));
+    for (auto& k : ctx->classes) H2D(k.d_list, k.chains.data(), k.chains.size() * sizeof(int32_t));
+    hipError_t e;
+    if (ctx->hist_w) {
+        e = hipMemset(ctx->hist_w, 0, sizeof(unsigned long long) << specs[0].N);
+        if (e == hipSuccess) e = hipMemset(ctx->hist_v, 0, sizeof(unsigned long long) << specs[0].N);
+        if (e != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
+    }
+    if (ctx->rmem && (e = hipMemset(ctx->rmem, 0, fields)) != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
+    if (ctx->classes.size() > 1) {
+        if ((e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming)) != hipSuccess)
+            return fail_free(hip_fail(e, "hipEventCreate"));
+        for (auto& k : ctx->classes) {
+            if ((e = hipStreamCreateWithFlags(&k.stream, hipStreamNonBlocking)) != hipSuccess)
+                return fail_free(hip_fail(e, "hipStreamCreate"));
+            if ((e = hipEventCreateWithFlags(&k.done, hipEventDisableTiming)) != hipSuccess)
+                return fail_free(hip_fail(e, "hipEventCreate"));
+        }
+    }
+
+    // initial state
+    if (o.init == PNS_INIT_GIVEN) {
+        std::vector<uint8_t> x0((size_t)ctx->h_offsets.back()), xp(fields, 0);
+        int rc = copy_in(x0.data(), o.x0, x0.size());
+        if (rc) return fail_free(rc);
+        for (int64_t c = 0; c < C; ++c) {
+            const int32_t N = ctx->probs[ctx->h_chain_problem[c]].N;
+            for (int32_t j = 0; j < N; ++j) xp[ctx->h_foff[c] + j] = x0[ctx->h_offsets[c] + j] ? 1 : 0;
+        }
+        H2D(ctx->x, xp.data(), fields);
+    }
+#undef H2D
+    if (o.init == PNS_INIT_ZERO) {
+        if ((e = hipMemset(ctx->x, 0, fields)) != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
+        if ((e = hipMemset(ctx->h, 0, fields * hbytes)) != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
+        if ((e = hipMemset(ctx->E, 0, C * 8)) != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
+        if ((e = hipMemset(ctx->last_E, 0, C * 8)) != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
+    } else {
+        InitArgs ia{};
+        ia.problems = ctx->problems;
+        ia.chain_problem = ctx->chain_problem;
+        ia.foff = ctx->foff;
+        ia.num_chains = (int32_t)C;
+        ia.init = o.init == PNS_INIT_RANDOM ? 1 : 2;
+        ia.seed = o.seed;
+        ia.chain_id = ctx->chain_id;
+        ia.x = ctx->x;
+        ia.h = ctx->h;
+        ia.E = ctx->E;
+        ia.last_E = ctx->last_E;
+        e = launch_init_with_map(qtype, htype, (int32_t)ctx->max_pitch, ctx->stream, ia, ctx->h_chain_problem.data());
+        if (e != hipSuccess) return fail_free(hip_fail(e, "init kernels"));
+    }
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return fail_free(hip_fail(e, "create synchronize"));
+    *out = ctx;
+    return PNS_OK;
+}
+
+// ---- autotuner ----
+
+std::mutex g_tune_mu;
+std::map<std::string, pns_tune> g_tune_cache;
+
+// Chains back to x = 0 at step 0 (the state of a fresh INIT_ZERO context).
+int reset_zero_state(pns_ctx* ctx)
 {
     const int64_t C = ctx->num_chains;
-    xs.resize((size_t)C * ctx->N);
-    for (int64_t c = 0; c < C; ++c) std::memcpy(&xs[c * ctx->N], &xp[c * ctx->pitch], ctx->N);
+    const size_t hb = ctx->htype == H_I32 ? 4 : 8;
+    std::vector<int64_t> Lv((size_t)C);
+    for (int64_t c = 0; c < C; ++c) Lv[c] = ctx->probs[ctx->h_chain_problem[c]].L0;
+    std::vector<int32_t> la((size_t)C, PNS_STAY);
+    HIP_TRY(hipMemset(ctx->x, 0, (size_t)ctx->fields), "reset");
+    HIP_TRY(hipMemset(ctx->h, 0, (size_t)ctx->fields * hb), "reset");
+    if (ctx->rmem) HIP_TRY(hipMemset(ctx->rmem, 0, (size_t)ctx->fields), "reset");
+    int64_t* zero_arrs[] = {ctx->E, ctx->last_E, ctx->last_M, ctx->sub, ctx->step};
+    for (int64_t* p : zero_arrs) HIP_TRY(hipMemset(p, 0, C * 8), "reset");
+    HIP_TRY(hipMemset(ctx->counters, 0, C * 6 * 8), "reset");
+    HIP_TRY(hipMemcpy(ctx->L, Lv.data(), C * 8, hipMemcpyHostToDevice), "reset");
+    HIP_TRY(hipMemcpy(ctx->last_action, la.data(), C * 4, hipMemcpyHostToDevice), "reset");
+    return PNS_OK;
+}
+
+// Give the single problem of `ctx` another tile and subset size, and reset
+// its chains, as if the context had been created with them.
+int reconfigure(pns_ctx* ctx, Tile t, int32_t n)
+{
+    ProblemRun& R = ctx->probs[0];
+    R.tile = t;
+    R.n = n;
+    R.num_sets = R.N / gcd64(R.N, n);
+    R.flav = flavour_of(ctx->mode, R.N, n, t.block, t.groups);
+    Problem D{};
+    D.A = R.A;
+    D.diag = R.diag;
+    D.pitch = R.pitch;
+    D.num_sets = R.num_sets;
+    D.L0 = R.L0;
+    D.N = R.N;
+    D.n = R.n;
+    D.s = R.s;
+    D.qtype = ctx->qtype;
+    HIP_TRY(hipMemcpy(ctx->problems, &D, sizeof(Problem), hipMemcpyHostToDevice), "reconfigure");
+    LaunchClass& K = ctx->classes[0];
+    K.tile = t;
+    K.flav = R.flav;
+    K.dyn = (R.flav == 2 || R.flav == 3) ? (size_t)R.pitch * 4 : 0;
+    return reset_zero_state(ctx);
+}
+
+// Records per second (and flips per second) of the context's current
+// configuration, from a timed run on the device after a warmup.
+int time_config(pns_ctx* ctx, int32_t steps, double* rate, double* frate)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    const int warm = std::max(8, steps / 4);
+    int rc = PNS_OK;
+    if (e == hipSuccess) rc = ctx->launch_chunk(warm);
+    if (e == hipSuccess && !rc) e = hipEventRecord(a, ctx->stream);
+    if (e == hipSuccess && !rc) rc = ctx->launch_chunk(steps);
+    if (e == hipSuccess && !rc) e = hipEventRecord(b, ctx->stream);
+    if (e == hipSuccess && !rc) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, a, b);
+    std::vector<int64_t> cnt;
+    if (e == hipSuccess && !rc) rc = d2h(cnt, ctx->counters, (size_t)ctx->num_chains * 6);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    int64_t flips = 0;
+    for (int64_t c = 0; c < ctx->num_chains; ++c) flips += cnt[c * 6 + 1];
+    const double sec = std::max(1e-9, (double)ms * 1e-3);
+    *rate = (double)ctx->num_chains * steps / sec;
+    *frate = (double)flips * steps / (double)(steps + warm) / sec;
+    return PNS_OK;
+}
+
+int autotune_impl(const ProblemSpec& base, int32_t mode, const pns_opts& o, int32_t trial_steps, pns_tune* out,
+                  const Prepared* prep = nullptr)
+{
+    if (trial_steps <= 0) trial_steps = 64;
+    char key[256];
+    snprintf(key, sizeof(key), "N%d_q%d_l%d_m%d_n%d_c%d_s%d", base.N, o.dtype, base.layout, mode, base.n, base.chains,
+             trial_steps);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            return PNS_OK;
+        }
+    }
+    ProblemSpec spec = base;
+    spec.chains = std::min<int32_t>(base.chains, 4096);
+    spec.betas.assign(spec.chains, base.betas.empty() ? 1.0 : base.betas[0]);
+    for (int32_t c = 0; c < spec.chains && c < (int32_t)base.betas.size(); ++c) spec.betas[c] = base.betas[c];
+    const bool tune_n = mode != PNS_MODE_RF && base.n == 0;
+    // subset size used while choosing the tile
+    int32_t n0 = base.n;
+    if (mode == PNS_MODE_RF) n0 = base.N;
+    else if (tune_n) n0 = std::max(1, std::min(base.N, std::max(16, base.N / 8)));
+    spec.n = n0;
+    spec.tile = default_tile(base.N);
+    if ((int64_t)spec.tile.block * 4 * spec.tile.groups < base.N)
+        return fail(PNS_EUNSUPPORTED, "no tile holds N=%d", base.N);
+    pns_opts t = o;
+    t.log_capacity = 0;
+    t.hist = 0;
+    t.snapshot_every = 0;
+    t.launch = PNS_LAUNCH_PERSISTENT;
+    t.chunk = 0;
+    t.stream = nullptr;
+    t.init = PNS_INIT_ZERO;
+    t.x0 = nullptr;
+    std::vector<ProblemSpec> one{spec};
+    pns_ctx* ctx = nullptr;
+    std::vector<const Prepared*> preps;
+    if (prep) preps.push_back(prep);
+    int rc = create_impl(&ctx, one, mode, t, preps);
+    if (rc) return rc;
+    pns_tune best{};
+    best.records_per_s = -1.0;
+    int trials = 0;
+    for (const Tile& tl : kTiles) {
+        const int64_t cap = (int64_t)tl.block * 4 * tl.groups;
+        if (cap < base.N || cap > 4 * round_up(base.N, 256)) continue;
+        if (!have_tile(ctx->qtype, ctx->htype, tl.block, tl.groups)) continue;
+        double r = 0.0, fr = 0.0;
+        rc = reconfigure(ctx, tl, n0);
+        if (!rc) rc = time_config(ctx, trial_steps, &r, &fr);
+        if (rc) break;
+        ++trials;
+        if (r > best.records_per_s) {
+            best.block = tl.block;
+            best.groups = tl.groups;
+            best.subset_size = n0;
+            best.records_per_s = r;
+            best.flips_per_s = fr;
+        }
+    }
+    if (!rc && tune_n) {
+        // the largest subset whose step rate stays within 10% of the best (Sec 5)
+        const Tile bt{best.block, best.groups};
+        std::vector<std::pair<int32_t, std::pair<double, double>>> res;
+        double top = 0.0;
+        for (int32_t n = 16; n <= base.N / 2 && !rc; n *= 2) {
+            double r = 0.0, fr = 0.0;
+            rc = reconfigure(ctx, bt, n);
+            if (!rc) rc = time_config(ctx, trial_steps, &r, &fr);
+            if (rc) break;
+            ++trials;
+            res.push_back({n, {r, fr}});
+            top = std::max(top, r);
+        }
+        for (const auto& pr : res) {
+            if (pr.second.first >= 0.9 * top) {
+                best.subset_size = pr.first;
+                best.records_per_s = pr.second.first;
+                best.flips_per_s = pr.second.second;
+            }
+        }
+    }
+    ctx->free_all();
+    delete ctx;
+    if (rc) return rc;
+    if (best.records_per_s < 0.0) return fail(PNS_EUNSUPPORTED, "no tile holds N=%d", base.N);
+    best.trials = trials;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    *out = best;
     return PNS_OK;
 }
 
@@ -390,7 +978,7 @@ void pns_opts_default(pns_opts* o)
 
 const char* pns_last_error(void) { return g_error.c_str(); }
 
-const char* pns_version(void) { return "0.1.0"; }
+const char* pns_version(void) { return "0.2.0"; }
 
 int pns_create(pns_ctx** out, const void* Q, int32_t N, double beta, int32_t subset_size, int32_t mode,
                const pns_opts* opts)
@@ -406,238 +994,135 @@ int pns_create(pns_ctx** out, const void* Q, int32_t N, double beta, int32_t sub
     if (!Q) return fail(PNS_EINVAL, "Q is NULL");
     if (N <= 0) return fail(PNS_EINVAL, "N must be positive");
     if (mode < PNS_MODE_RF || mode > PNS_MODE_UNBIASED_RAND) return fail(PNS_EINVAL, "unknown mode %d", mode);
-    const int32_t n = mode == PNS_MODE_RF ? N : subset_size;
-    if (n < 1 || n > N) return fail(PNS_EINVAL, "subset size %d outside [1, %d]", subset_size, N);
     if (o.hist && N > 24) return fail(PNS_EINVAL, "histograms need N <= 24");
-    std::vector<double> betas((size_t)o.num_chains, beta);
-    if (o.betas) {
-        for (int32_t c = 0; c < o.num_chains; ++c) betas[c] = o.betas[c];
-    }
-    for (double b : betas)
+    const bool tune_n = o.autotune && mode != PNS_MODE_RF && subset_size == 0;
+    const int32_t n = mode == PNS_MODE_RF ? N : subset_size;
+    if (!tune_n && (n < 1 || n > N)) return fail(PNS_EINVAL, "subset size %d outside [1, %d]", subset_size, N);
+    ProblemSpec S;
+    S.Q = Q;
+    S.N = N;
+    S.layout = o.layout;
+    S.n = n;
+    S.chains = o.num_chains;
+    S.L0 = o.L0;
+    S.betas.assign((size_t)o.num_chains, beta);
+    if (o.betas)
+        for (int32_t c = 0; c < o.num_chains; ++c) S.betas[c] = o.betas[c];
+    for (double b : S.betas)
         if (!(b >= 0.0) || !std::isfinite(b)) return fail(PNS_EINVAL, "beta must be finite and >= 0");
-    const Tile def = default_tile(N);
-    Tile tile = def;
     if (o.block > 0 || o.groups > 0) {
-        tile.block = o.block > 0 ? o.block : def.block;
-        tile.groups = o.groups > 0 ? o.groups : std::max<int32_t>(1, (int32_t)((N + tile.block * 4 - 1) / (tile.block * 4)));
+        const Tile def = default_tile(N);
+        S.tile.block = o.block > 0 ? o.block : def.block;
+        S.tile.groups = o.groups > 0 ? o.groups
+                                     : std::max<int32_t>(1, (int32_t)((N + S.tile.block * 4 - 1) / (S.tile.block * 4)));
+    } else if (o.autotune) {
+        Prepared prep;
+        rc = prepare_problem(Q, N, o.layout, o.dtype, &prep);
+        if (rc) return rc;
+        pns_tune t{};
+        ProblemSpec T = S;
+        T.n = tune_n ? 0 : n;
+        rc = autotune_impl(T, mode, o, 64, &t, &prep);
+        if (rc) return rc;
+        S.tile = {t.block, t.groups};
+        if (tune_n) S.n = t.subset_size;
+        std::vector<ProblemSpec> specs{S};
+        return create_impl(out, specs, mode, o, {&prep});
     }
-    if ((int64_t)tile.block * 4 * tile.groups < N) {
-        if (N > 16384) return fail(PNS_EUNSUPPORTED, "N=%d exceeds the largest tile (16384)", N);
-        return fail(PNS_EINVAL, "tile %dx%d cannot hold N=%d", tile.block, tile.groups, N);
-    }
+    std::vector<ProblemSpec> specs{S};
+    return create_impl(out, specs, mode, o);
+}
 
-    const int32_t qtype = o.dtype;
-    const int64_t pitch = round_up(N, 64);
-    const size_t qbytes = (size_t)N * N * qsize(qtype);
-
-    // caller's Q into host memory
-    std::vector<uint8_t> qhost(qbytes);
-    rc = copy_in(qhost.data(), Q, qbytes);
+int pns_create_batch(pns_ctx** out, int32_t num_problems, const pns_problem* problems, int32_t mode,
+                     const pns_opts* opts)
+{
+    g_error.clear();
+    if (!out) return fail(PNS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (num_problems < 1 || !problems) return fail(PNS_EINVAL, "num_problems must be >= 1");
+    pns_opts o;
+    if (opts) o = *opts;
+    else pns_opts_default(&o);
+    int rc = check_opts(&o);
     if (rc) return rc;
-
-    std::vector<uint8_t> Abytes, dbytes;
-    double fbound = 0.0, dbound = 0.0;
-    if (qtype == Q_I16) {
-        std::vector<int16_t> A;
-        rc = prepare_matrix(reinterpret_cast<const int16_t*>(qhost.data()), N, o.layout, pitch, A, dbytes, &fbound, &dbound);
+    if (mode < PNS_MODE_RF || mode > PNS_MODE_UNBIASED_RAND) return fail(PNS_EINVAL, "unknown mode %d", mode);
+    std::vector<ProblemSpec> specs((size_t)num_problems);
+    std::vector<bool> tune((size_t)num_problems, false), tune_n((size_t)num_problems, false);
+    for (int32_t p = 0; p < num_problems; ++p) {
+        const pns_problem& q = problems[p];
+        ProblemSpec& S = specs[p];
+        if (!q.Q) return fail(PNS_EINVAL, "problem %d: Q is NULL", p);
+        if (q.N <= 0) return fail(PNS_EINVAL, "problem %d: N must be positive", p);
+        if (q.layout != PNS_SYMMETRIC && q.layout != PNS_UPPER)
+            return fail(PNS_EINVAL, "problem %d: unknown layout %d", p, q.layout);
+        if (q.num_chains < 1) return fail(PNS_EINVAL, "problem %d: num_chains must be >= 1", p);
+        if (q.L0 < 0) return fail(PNS_EINVAL, "problem %d: L0 must be >= 0", p);
+        tune_n[p] = mode != PNS_MODE_RF && q.subset_size == 0;
+        if (mode != PNS_MODE_RF && !tune_n[p] && (q.subset_size < 1 || q.subset_size > q.N))
+            return fail(PNS_EINVAL, "problem %d: subset size %d outside [1, %d]", p, q.subset_size, q.N);
+        S.Q = q.Q;
+        S.N = q.N;
+        S.layout = q.layout;
+        S.n = mode == PNS_MODE_RF ? q.N : q.subset_size;
+        S.chains = q.num_chains;
+        S.L0 = q.L0 > 0 ? q.L0 : o.L0;
+        S.betas.assign((size_t)S.chains, q.beta);
+        if (q.betas)
+            for (int32_t c = 0; c < S.chains; ++c) S.betas[c] = q.betas[c];
+        for (double b : S.betas)
+            if (!(b >= 0.0) || !std::isfinite(b)) return fail(PNS_EINVAL, "problem %d: beta must be finite and >= 0", p);
+        tune[p] = o.autotune || tune_n[p];
+        if (!tune[p] && o.block > 0 && (int64_t)o.block * 4 * std::max(1, o.groups) >= q.N)
+            S.tile = {o.block, std::max(1, o.groups)};
+    }
+    // every matrix is prepared once, for the trials and the context
+    std::vector<Prepared> preps((size_t)num_problems);
+    std::vector<const Prepared*> pp;
+    for (int32_t p = 0; p < num_problems; ++p) {
+        rc = prepare_problem(specs[p].Q, specs[p].N, specs[p].layout, o.dtype, &preps[p]);
         if (rc) return rc;
-        Abytes.resize(A.size() * 2);
-        std::memcpy(Abytes.data(), A.data(), Abytes.size());
-    } else if (qtype == Q_I32) {
-        std::vector<int32_t> A;
-        rc = prepare_matrix(reinterpret_cast<const int32_t*>(qhost.data()), N, o.layout, pitch, A, dbytes, &fbound, &dbound);
+        pp.push_back(&preps[p]);
+    }
+    for (int32_t p = 0; p < num_problems; ++p) {
+        if (!tune[p]) continue;
+        pns_opts t = o;
+        t.layout = specs[p].layout;
+        t.num_chains = specs[p].chains;
+        pns_tune r{};
+        ProblemSpec T = specs[p];
+        T.n = tune_n[p] ? 0 : specs[p].n;
+        rc = autotune_impl(T, mode, t, 64, &r, &preps[p]);
         if (rc) return rc;
-        Abytes.resize(A.size() * 4);
-        std::memcpy(Abytes.data(), A.data(), Abytes.size());
-    } else {
-        std::vector<float> A;
-        rc = prepare_matrix(reinterpret_cast<const float*>(qhost.data()), N, o.layout, pitch, A, dbytes, &fbound, &dbound);
-        if (rc) return rc;
-        Abytes.resize(A.size() * 4);
-        std::memcpy(Abytes.data(), A.data(), Abytes.size());
+        specs[p].tile = {r.block, r.groups};
+        if (tune_n[p]) specs[p].n = r.subset_size;
     }
-    qhost.clear();
-    qhost.shrink_to_fit();
-    const int32_t s = o.layout == PNS_SYMMETRIC ? 2 : 1;
-    int32_t htype;
-    if (qtype == Q_F32) {
-        htype = H_F64;
-    } else {
-        const double ebound = dbound + s * fbound;
-        if (ebound * (double)N > 9.0e18) return fail(PNS_EINVAL, "energy bound of Q overflows int64");
-        htype = (fbound < 2147483647.0 && ebound < 2147483647.0) ? H_I32 : H_I64;
-        if (qtype == Q_I16) htype = H_I32;
-    }
-    if (!have_tile(qtype, htype, tile.block, tile.groups))
-        return fail(PNS_EINVAL, "no kernel for tile %dx%d", tile.block, tile.groups);
+    return create_impl(out, specs, mode, o, pp);
+}
 
-    pns_ctx* ctx = new pns_ctx();
-    ctx->N = N;
-    ctx->n = n;
-    ctx->mode = mode;
-    ctx->qtype = qtype;
-    ctx->htype = htype;
-    ctx->layout = o.layout;
-    ctx->num_chains = o.num_chains;
-    ctx->block = tile.block;
-    ctx->groups = tile.groups;
-    ctx->pitch = pitch;
-    ctx->launch = o.launch;
-    ctx->chunk = o.chunk;
-    ctx->seed = o.seed;
-    ctx->L0 = o.L0;
-    ctx->dyn_lds = ((mode == PNS_MODE_BASIC || mode == PNS_MODE_UNBIASED_RAND) && n < N) ? (size_t)pitch * 4 : 0;
-    if (o.stream) {
-        ctx->stream = reinterpret_cast<hipStream_t>(o.stream);
-    } else {
-        hipError_t e = hipStreamCreate(&ctx->stream);
-        if (e != hipSuccess) {
-            delete ctx;
-            return hip_fail(e, "hipStreamCreate");
-        }
-        ctx->own_stream = true;
-    }
-    const int64_t C = o.num_chains;
-    const size_t hbytes = htype == H_I32 ? 4 : 8;
-    const size_t fields = (size_t)C * pitch;
-#define ALLOC(ptr, type, count)                                   \
-    do {                                                          \
-        int r_ = dev_alloc(reinterpret_cast<type**>(&ptr), count); \
-        if (r_) {                                                 \
-            ctx->free_all();                                      \
-            delete ctx;                                           \
-            return r_;                                            \
-        }                                                         \
-    } while (0)
-    ALLOC(ctx->A, uint8_t, Abytes.size());
-    ALLOC(ctx->diag, uint8_t, dbytes.size());
-    ALLOC(ctx->problems, Problem, 1);
-    ALLOC(ctx->chain_problem, int32_t, C);
-    ALLOC(ctx->foff, int64_t, C);
-    ALLOC(ctx->beta, double, C);
-    ALLOC(ctx->chain_id, uint32_t, C);
-    ALLOC(ctx->x, uint8_t, fields);
-    ALLOC(ctx->h, uint8_t, fields * hbytes);
-    ALLOC(ctx->E, int64_t, C);
-    ALLOC(ctx->L, int64_t, C);
-    ALLOC(ctx->sub, int64_t, C);
-    ALLOC(ctx->step, int64_t, C);
-    ALLOC(ctx->last_action, int32_t, C);
-    ALLOC(ctx->last_M, int64_t, C);
-    ALLOC(ctx->last_E, int64_t, C);
-    ALLOC(ctx->counters, int64_t, C * 6);
-    if (mode == PNS_MODE_UNBIASED_RAND) ALLOC(ctx->rmem, uint8_t, fields);
-    if (o.log_capacity > 0) {
-        ctx->log_cap = o.log_capacity;
-        ALLOC(ctx->log_action, int32_t, (size_t)C * o.log_capacity);
-        ALLOC(ctx->log_M, int64_t, (size_t)C * o.log_capacity);
-        ALLOC(ctx->log_E, int64_t, (size_t)C * o.log_capacity);
-        ALLOC(ctx->log_p, double, (size_t)C * o.log_capacity);
-    }
-    if (o.hist) {
-        ALLOC(ctx->hist_w, unsigned long long, (size_t)1 << N);
-        ALLOC(ctx->hist_v, unsigned long long, (size_t)1 << N);
-    }
-    if (o.snapshot_every > 0) {
-        ctx->snap_every = o.snapshot_every;
-        ctx->snap_cap = o.snapshot_capacity;
-        ALLOC(ctx->snap_x, uint8_t, (size_t)C * o.snapshot_capacity * pitch);
-        ALLOC(ctx->snap_M, int64_t, (size_t)C * o.snapshot_capacity);
-        ALLOC(ctx->snap_E, int64_t, (size_t)C * o.snapshot_capacity);
-        ALLOC(ctx->snap_count, int32_t, C);
-    }
-#undef ALLOC
-
-    // host-side tables
-    Problem P{};
-    P.A = ctx->A;
-    P.diag = ctx->diag;
-    P.pitch = pitch;
-    P.num_sets = N / gcd64(N, n);
-    P.L0 = o.L0;
-    P.N = N;
-    P.n = n;
-    P.s = s;
-    P.qtype = qtype;
-    std::vector<int32_t> cp((size_t)C, 0);
-    std::vector<int64_t> fo((size_t)C);
-    std::vector<uint32_t> cidv((size_t)C);
-    for (int64_t c = 0; c < C; ++c) {
-        fo[c] = c * pitch;
-        cidv[c] = o.chain_id_base + (uint32_t)c;
-    }
-    std::vector<int64_t> Lv((size_t)C, o.L0), zeros64((size_t)C * 6, 0);
-    std::vector<int32_t> la((size_t)C, PNS_STAY);
-    auto fail_free = [&](int r) {
-        ctx->free_all();
-        delete ctx;
-        return r;
-    };
-#define H2D(dst, src, bytes)                                                                   \
-    do {                                                                                       \
-        hipError_t e_ = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);                      \
-        if (e_ != hipSuccess) return fail_free(hip_fail(e_, "upload"));                        \
-    } while (0)
-    H2D(ctx->A, Abytes.data(), Abytes.size());
-    H2D(ctx->diag, dbytes.data(), dbytes.size());
-    H2D(ctx->problems, &P, sizeof(P));
-    H2D(ctx->chain_problem, cp.data(), C * sizeof(int32_t));
-    H2D(ctx->foff, fo.data(), C * sizeof(int64_t));
-    H2D(ctx->beta, betas.data(), C * sizeof(double));
-    H2D(ctx->chain_id, cidv.data(), C * sizeof(uint32_t));
-    H2D(ctx->L, Lv.data(), C * sizeof(int64_t));
-    H2D(ctx->sub, zeros64.data(), C * sizeof(int64_t));
-    H2D(ctx->step, zeros64.data(), C * sizeof(int64_t));
-    H2D(ctx->last_action, la.data(), C * sizeof(int32_t));
-    H2D(ctx->last_M, zeros64.data(), C * sizeof(int64_t));
-    H2D(ctx->counters, zeros64.data(), C * 6 * sizeof(int64_t));
-    if (ctx->snap_count) H2D(ctx->snap_count, zeros64.data(), C * sizeof(int32_t));
-    if (ctx->hist_w) {
-        hipError_t e1 = hipMemset(ctx->hist_w, 0, sizeof(unsigned long long) << N);
-        hipError_t e2 = hipMemset(ctx->hist_v, 0, sizeof(unsigned long long) << N);
-        if (e1 != hipSuccess || e2 != hipSuccess) return fail_free(hip_fail(e1 != hipSuccess ? e1 : e2, "hipMemset"));
-    }
-    if (ctx->rmem) {
-        hipError_t e1 = hipMemset(ctx->rmem, 0, fields);
-        if (e1 != hipSuccess) return fail_free(hip_fail(e1, "hipMemset"));
-    }
-
-    // initial state
-    hipError_t e;
-    if (o.init == PNS_INIT_GIVEN) {
-        std::vector<uint8_t> x0((size_t)C * N), xp(fields, 0);
-        rc = copy_in(x0.data(), o.x0, x0.size());
-        if (rc) return fail_free(rc);
-        for (int64_t c = 0; c < C; ++c)
-            for (int32_t j = 0; j < N; ++j) xp[c * pitch + j] = x0[c * N + j] ? 1 : 0;
-        H2D(ctx->x, xp.data(), fields);
-    } else if (o.init == PNS_INIT_ZERO) {
-        if ((e = hipMemset(ctx->x, 0, fields)) != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
-    }
-#undef H2D
-    if (o.init == PNS_INIT_ZERO) {
-        if ((e = hipMemset(ctx->h, 0, fields * hbytes)) != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
-        if ((e = hipMemset(ctx->E, 0, C * 8)) != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
-        if ((e = hipMemset(ctx->last_E, 0, C * 8)) != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
-    } else {
-        InitArgs ia{};
-        ia.problems = ctx->problems;
-        ia.chain_problem = ctx->chain_problem;
-        ia.foff = ctx->foff;
-        ia.num_chains = (int32_t)C;
-        ia.init = o.init == PNS_INIT_RANDOM ? 1 : 2;
-        ia.seed = o.seed;
-        ia.chain_id = ctx->chain_id;
-        ia.x = ctx->x;
-        ia.h = ctx->h;
-        ia.E = ctx->E;
-        ia.last_E = ctx->last_E;
-        e = launch_init_with_map(qtype, htype, (int32_t)pitch, ctx->stream, ia, cp.data());
-        if (e != hipSuccess) return fail_free(hip_fail(e, "init kernels"));
-    }
-    if ((e = hipDeviceSynchronize()) != hipSuccess) return fail_free(hip_fail(e, "create synchronize"));
-    *out = ctx;
-    return PNS_OK;
+int pns_autotune(const void* Q, int32_t N, double beta, int32_t subset_size, int32_t mode, const pns_opts* opts,
+                 int32_t trial_steps, pns_tune* out)
+{
+    g_error.clear();
+    if (!out || !Q) return fail(PNS_EINVAL, "NULL argument");
+    pns_opts o;
+    if (opts) o = *opts;
+    else pns_opts_default(&o);
+    int rc = check_opts(&o);
+    if (rc) return rc;
+    if (N <= 0) return fail(PNS_EINVAL, "N must be positive");
+    if (mode < PNS_MODE_RF || mode > PNS_MODE_UNBIASED_RAND) return fail(PNS_EINVAL, "unknown mode %d", mode);
+    if (subset_size < 0 || subset_size > N) return fail(PNS_EINVAL, "subset size %d outside [0, %d]", subset_size, N);
+    ProblemSpec S;
+    S.Q = Q;
+    S.N = N;
+    S.layout = o.layout;
+    S.n = mode == PNS_MODE_RF ? N : subset_size;
+    S.chains = o.num_chains;
+    S.L0 = o.L0;
+    S.betas.assign((size_t)o.num_chains, beta);
+    if (o.betas)
+        for (int32_t c = 0; c < o.num_chains; ++c) S.betas[c] = o.betas[c];
+    return autotune_impl(S, mode, o, trial_steps, out);
 }
 
 int pns_run(pns_ctx* ctx, int64_t steps)
@@ -694,7 +1179,6 @@ int pns_sync(pns_ctx* ctx)
     return PNS_OK;
 }
 
-
 int pns_read(pns_ctx* ctx, uint8_t* states, int64_t* multiplicities, double* energies)
 {
     g_error.clear();
@@ -702,13 +1186,16 @@ int pns_read(pns_ctx* ctx, uint8_t* states, int64_t* multiplicities, double* ene
     if (rc) return rc;
     const int64_t C = ctx->num_chains;
     if (states) {
-        std::vector<uint8_t> xp, xs;
+        std::vector<uint8_t> xp;
         std::vector<int32_t> la;
-        if ((rc = d2h(xp, ctx->x, (size_t)C * ctx->pitch))) return rc;
+        if ((rc = d2h(xp, ctx->x, (size_t)ctx->fields))) return rc;
         if ((rc = d2h(la, ctx->last_action, C))) return rc;
-        compact_states(ctx, xp, xs);
-        for (int64_t c = 0; c < C; ++c)
-            if (la[c] >= 0) xs[c * ctx->N + la[c]] ^= 1u;  // the record's state is before the last move
+        std::vector<uint8_t> xs((size_t)ctx->h_offsets.back());
+        for (int64_t c = 0; c < C; ++c) {
+            const int32_t N = ctx->probs[ctx->h_chain_problem[c]].N;
+            std::memcpy(&xs[ctx->h_offsets[c]], &xp[ctx->h_foff[c]], N);
+            if (la[c] >= 0) xs[ctx->h_offsets[c] + la[c]] ^= 1u;  // the record's state is before the last move
+        }
         if ((rc = copy_out(states, xs.data(), xs.size()))) return rc;
     }
     if (multiplicities) {
@@ -730,8 +1217,33 @@ int pns_field_type(const pns_ctx* ctx) { return ctx ? ctx->htype : -1; }
 int pns_tile(const pns_ctx* ctx, int32_t* block, int32_t* groups)
 {
     if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
-    if (block) *block = ctx->block;
-    if (groups) *groups = ctx->groups;
+    if (block) *block = ctx->probs[0].tile.block;
+    if (groups) *groups = ctx->probs[0].tile.groups;
+    return PNS_OK;
+}
+
+int pns_num_problems(const pns_ctx* ctx) { return ctx ? (int)ctx->probs.size() : 0; }
+
+int pns_problem_info_get(const pns_ctx* ctx, int32_t p, pns_problem_info* info)
+{
+    if (!ctx || !info) return fail(PNS_EINVAL, "NULL argument");
+    if (p < 0 || p >= (int32_t)ctx->probs.size()) return fail(PNS_EINVAL, "problem %d out of range", p);
+    const ProblemRun& R = ctx->probs[p];
+    info->N = R.N;
+    info->subset_size = R.n;
+    info->block = R.tile.block;
+    info->groups = R.tile.groups;
+    info->chain_begin = R.chain_begin;
+    info->num_chains = R.chains;
+    info->flavour = R.flav;
+    info->reserved = 0;
+    return PNS_OK;
+}
+
+int pns_chain_offsets(const pns_ctx* ctx, int64_t* offsets)
+{
+    if (!ctx || !offsets) return fail(PNS_EINVAL, "NULL argument");
+    std::memcpy(offsets, ctx->h_offsets.data(), ctx->h_offsets.size() * sizeof(int64_t));
     return PNS_OK;
 }
 
@@ -743,9 +1255,11 @@ int pns_read_current(pns_ctx* ctx, uint8_t* states, double* energies, void* fiel
     if (rc) return rc;
     const int64_t C = ctx->num_chains;
     if (states) {
-        std::vector<uint8_t> xp, xs;
-        if ((rc = d2h(xp, ctx->x, (size_t)C * ctx->pitch))) return rc;
-        compact_states(ctx, xp, xs);
+        std::vector<uint8_t> xp;
+        if ((rc = d2h(xp, ctx->x, (size_t)ctx->fields))) return rc;
+        std::vector<uint8_t> xs((size_t)ctx->h_offsets.back());
+        for (int64_t c = 0; c < C; ++c)
+            std::memcpy(&xs[ctx->h_offsets[c]], &xp[ctx->h_foff[c]], ctx->probs[ctx->h_chain_problem[c]].N);
         if ((rc = copy_out(states, xs.data(), xs.size()))) return rc;
     }
     if (energies) {
@@ -756,9 +1270,10 @@ int pns_read_current(pns_ctx* ctx, uint8_t* states, double* energies, void* fiel
     }
     if (fields) {
         const size_t hb = ctx->htype == H_I32 ? 4 : 8;
-        std::vector<uint8_t> hp, hs((size_t)C * ctx->N * hb);
-        if ((rc = d2h(hp, ctx->h, (size_t)C * ctx->pitch * hb))) return rc;
-        for (int64_t c = 0; c < C; ++c) std::memcpy(&hs[c * ctx->N * hb], &hp[c * ctx->pitch * hb], ctx->N * hb);
+        std::vector<uint8_t> hp, hs((size_t)ctx->h_offsets.back() * hb);
+        if ((rc = d2h(hp, ctx->h, (size_t)ctx->fields * hb))) return rc;
+        for (int64_t c = 0; c < C; ++c)
+            std::memcpy(&hs[ctx->h_offsets[c] * hb], &hp[ctx->h_foff[c] * hb], ctx->probs[ctx->h_chain_problem[c]].N * hb);
         if ((rc = copy_out(fields, hs.data(), hs.size()))) return rc;
     }
     const std::pair<int64_t*, int64_t*> arrs[] = {{L, ctx->L}, {set_index, ctx->sub}, {step, ctx->step}};
@@ -807,7 +1322,7 @@ int pns_read_hist(pns_ctx* ctx, uint64_t* hist_weighted, uint64_t* hist_visits)
     if (!ctx->hist_w) return fail(PNS_EINVAL, "histograms are off (opts.hist = 0)");
     int rc = pns_sync(ctx);
     if (rc) return rc;
-    const size_t cnt = (size_t)1 << ctx->N;
+    const size_t cnt = (size_t)1 << ctx->probs[0].N;
     if (hist_weighted) {
         std::vector<uint64_t> v;
         if ((rc = d2h(v, ctx->hist_w, cnt)) || (rc = copy_out(hist_weighted, v.data(), cnt * 8))) return rc;
@@ -824,7 +1339,7 @@ int pns_hist_clear(pns_ctx* ctx)
     g_error.clear();
     if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
     if (!ctx->hist_w) return fail(PNS_EINVAL, "histograms are off (opts.hist = 0)");
-    const int64_t cnt = (int64_t)1 << ctx->N;
+    const int64_t cnt = (int64_t)1 << ctx->probs[0].N;
     hipError_t e = launch_fill64(ctx->hist_w, cnt, 0, ctx->stream);
     if (e == hipSuccess) e = launch_fill64(ctx->hist_v, cnt, 0, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "histogram clear");
@@ -841,13 +1356,13 @@ int pns_read_snapshots(pns_ctx* ctx, uint8_t* states, int64_t* multiplicities, d
     const int64_t C = ctx->num_chains, S = ctx->snap_cap;
     std::vector<int32_t> cnt;
     if ((rc = d2h(cnt, ctx->snap_count, C))) return rc;
-    int32_t stored = S;
+    int32_t stored = (int32_t)S;
     for (int32_t v : cnt) stored = std::min<int32_t>(stored, v);
     if (count) *count = stored;
     if (states) {
-        std::vector<uint8_t> xp, xs((size_t)C * S * ctx->N);
-        if ((rc = d2h(xp, ctx->snap_x, (size_t)C * S * ctx->pitch))) return rc;
-        for (int64_t r = 0; r < C * S; ++r) std::memcpy(&xs[r * ctx->N], &xp[r * ctx->pitch], ctx->N);
+        std::vector<uint8_t> xp;
+        if ((rc = d2h(xp, ctx->snap_x, (size_t)C * S * ctx->max_pitch))) return rc;
+        std::vector<uint8_t> xs = compact_rows(ctx, xp, ctx->max_pitch, S);
         if ((rc = copy_out(states, xs.data(), xs.size()))) return rc;
     }
     if (multiplicities) {

@@ -22,16 +22,31 @@ def _rng(tag: int, seed: int | None) -> np.random.Generator:
     return np.random.default_rng(SEED_BASE + tag if seed is None else seed)
 
 
+def _mirror_upper(Q: np.ndarray, block: int = 256) -> np.ndarray:
+    """Copy the strict upper triangle of Q onto the lower one, in place, in
+    square blocks (a whole-matrix transpose is slow at N = 16384)."""
+    N = Q.shape[0]
+    for i0 in range(0, N, block):
+        i1 = min(N, i0 + block)
+        d = Q[i0:i1, i0:i1]
+        d += np.triu(d, 1).T
+        for j0 in range(i1, N, block):
+            j1 = min(N, j0 + block)
+            Q[j0:j1, i0:i1] = Q[i0:i1, j0:j1].T
+    return Q
+
+
 def symmetric_int(N: int, lo: int, hi: int, dtype=np.int32, seed: int | None = None, density: float = 1.0,
                   tag: int = 0) -> np.ndarray:
     """Dense symmetric integer QUBO: entries i <= j iid uniform on {lo..hi}
     (optionally kept with probability ``density``), mirrored below."""
     rng = _rng(tag, seed)
-    U = rng.integers(lo, hi + 1, size=(N, N), dtype=np.int64)
+    draw = np.int16 if -32768 <= lo and hi <= 32766 else np.int64
+    U = rng.integers(lo, hi + 1, size=(N, N), dtype=draw)
     if density < 1.0:
-        U = U * (rng.random((N, N)) < density)
-    Q = np.triu(U) + np.triu(U, 1).T
-    return Q.astype(dtype)
+        U *= rng.random((N, N), dtype=np.float32) < np.float32(density)
+    Q = _mirror_upper(np.triu(U))
+    return Q.astype(dtype, copy=False)
 
 
 def symmetric_gauss(N: int, seed: int | None = None, tag: int = 0, dtype=np.float32) -> np.ndarray:

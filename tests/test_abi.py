@@ -71,3 +71,73 @@ def test_create_rejects_bad_arguments(kw, expect):
         b.pns_create(Q, N, kw.get("beta", 0.1), kw.get("n", 4), kw.get("mode", b.PNS_MODE_RF), o)
     assert ei.value.code == b.PNS_EINVAL
     assert expect in str(ei.value)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(problems=0), "num_problems"),
+    (dict(N=0), "N must be positive"),
+    (dict(chains=0), "num_chains"),
+    (dict(n=9, mode=2), "subset size"),
+    (dict(beta=-2.0), "beta"),
+    (dict(mode=5), "unknown mode"),
+    (dict(layout=3), "unknown layout"),
+    (dict(reserved=True), "reserved"),
+])
+def test_create_batch_rejects_bad_arguments(kw, expect):
+    from paper_2210_10513_amd import binding as b
+    Qs = [np.zeros((8, 8), np.int32), np.zeros((12, 12), np.int32)]
+    probs = [b.pns_problem(Q=q.ctypes.data, N=q.shape[0], layout=0, subset_size=4, num_chains=2, L0=0,
+                           betas=None, beta=0.1) for q in Qs]
+    probs[1].N = kw.get("N", 12)
+    probs[1].num_chains = kw.get("chains", 2)
+    probs[1].beta = kw.get("beta", 0.1)
+    probs[1].layout = kw.get("layout", 0)
+    if "n" in kw:
+        probs[0].subset_size = kw["n"]
+    o = b.pns_opts_default()
+    if kw.get("reserved"):
+        o.reserved[6] = 1
+    if kw.get("problems") == 0:
+        probs = []
+        ctx = ctypes.c_void_p()
+        rc = b.lib.pns_create_batch(ctypes.byref(ctx), 0, None, 0, ctypes.byref(o))
+        assert rc == b.PNS_EINVAL and expect in b.pns_last_error()
+        return
+    with pytest.raises(b.PNSError) as ei:
+        b.pns_create_batch(probs, kw.get("mode", b.PNS_MODE_BASIC), o)
+    assert ei.value.code == b.PNS_EINVAL
+    assert expect in str(ei.value)
+
+
+def test_autotune_rejects_bad_arguments():
+    from paper_2210_10513_amd import binding as b
+    Q = np.zeros((8, 8), np.int32)
+    for n, mode, expect in ((9, b.PNS_MODE_BASIC, "subset size"), (-1, b.PNS_MODE_BASIC, "subset size"),
+                            (4, 6, "unknown mode")):
+        with pytest.raises(b.PNSError) as ei:
+            b.pns_autotune(Q, 8, 0.1, n, mode)
+        assert ei.value.code == b.PNS_EINVAL and expect in str(ei.value)
+
+
+def test_structs_match_header_layout(tmp_path):
+    """Every struct of the binding has the size and field offsets that a C
+    compiler gives the header's declaration."""
+    import subprocess
+    from paper_2210_10513_amd import binding as b
+    structs = {"pns_opts": b.pns_opts, "pns_problem": b.pns_problem, "pns_problem_info": b.pns_problem_info,
+               "pns_tune": b.pns_tune, "pns_chain_stats": b.pns_chain_stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pns.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, f"{name}.{fname}"

@@ -1,0 +1,203 @@
+"""GPU parity of batched contexts: several QUBOs of uneven N, each with its
+own chains and temperatures, in one context (pns_create_batch).  Every chain
+of a batch must produce exactly the records the oracle produces for it alone
+(same seed, chain id = its global index), whatever the grouping of problems
+into launch classes and the launch form; plus the autotuner."""
+import numpy as np
+import pytest
+
+from paper_2210_10513_amd import inputs
+
+from parity_util import compare_final, compare_logs, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(problems, mode, K, **kw):
+    from paper_2210_10513_amd.binding import BatchSampler
+    s = BatchSampler(problems, mode, log_capacity=K, **kw)
+    s.run(K)
+    out = {"log": s.read_log(), "cur": s.read_current(), "rec": s.read(), "stats": s.stats(), "info": s.info,
+           "offsets": s.offsets}
+    s.close()
+    return out
+
+
+def _check_problem(g, p, pr, mode, K, *, seed, L0, rows=None, is_int=True, init="zero", x0=None):
+    info = g["info"][p]
+    c0 = info.chain_begin
+    rows = list(range(info.num_chains)) if rows is None else list(rows)
+    betas = np.broadcast_to(np.asarray(pr.get("beta", 1.0), np.float64), (info.num_chains,))
+    o = oracle_run(pr["Q"], betas[rows], mode, K, n=info.subset_size, L0=pr.get("L0") or L0, seed=seed,
+                   chains=[c0 + r for r in rows], init=init, layout=pr.get("layout", "symmetric"),
+                   x0=None if x0 is None else x0[rows])
+    log = {k: v[p] for k, v in g["log"].items()}
+    cur = {k: v[p] for k, v in g["cur"].items()}
+    n = compare_logs(log, o, chain_rows=rows, is_int=is_int)
+    if n == len(rows) * K:
+        compare_final(cur, o, chain_rows=rows, is_int=is_int)
+    assert (g["stats"]["anomalies"][c0:c0 + info.num_chains] == 0).all()
+    return info
+
+
+def _uneven(Ns, dtype=np.int32, chains=3, seed0=300, lo=-50, hi=50, density=1.0):
+    probs = []
+    for i, N in enumerate(Ns):
+        Q = inputs.symmetric_int(N, lo, hi, dtype, seed=seed0 + i, density=density)
+        probs.append({"Q": Q, "num_chains": chains + (i % 2), "beta": 0.05 / (1 + i % 3)})
+    return probs
+
+
+@pytest.mark.parametrize("mode,n", [("rf", 0), ("basic", 9), ("unbiased_sys", 11), ("unbiased_rand", 10)])
+def test_uneven_batch_matches_oracle_per_chain(mode, n):
+    """Problems of N = 3 .. 1500 land in different tiles (several launch
+    classes run concurrently); every chain equals its solo oracle run."""
+    Ns = [3, 40, 130, 257, 700, 1500]
+    probs = _uneven(Ns)
+    for pr in probs:
+        pr["subset_size"] = min(n, pr["Q"].shape[0]) if mode != "rf" else pr["Q"].shape[0]
+    K = 300
+    g = _batch(probs, mode, K, L0=17, seed=21)
+    tiles = {(i.block, i.groups) for i in g["info"]}
+    assert len(tiles) >= 3
+    for p, pr in enumerate(probs):
+        _check_problem(g, p, pr, mode, K, seed=21, L0=17)
+
+
+def test_batch_offsets_and_chain_numbering():
+    probs = _uneven([10, 20, 33], chains=2)
+    from paper_2210_10513_amd.binding import BatchSampler
+    s = BatchSampler(probs, "rf")
+    assert s.num_problems == 3
+    assert [i.chain_begin for i in s.info] == [0, 2, 5]
+    assert list(s.offsets) == [0, 10, 20, 40, 60, 80, 113, 146]
+    x, m, e = s.run(5).read()
+    assert [a.shape for a in x] == [(2, 10), (3, 20), (2, 33)]
+    s.close()
+
+
+def test_batch_per_problem_L0_and_temperature_ladder():
+    """Per-problem L0 and per-chain beta ladders inside one batch (Unbiased)."""
+    probs = _uneven([64, 300, 555], chains=4)
+    ladder = inputs.beta_ladder(4, 0.02, 0.5)
+    for i, pr in enumerate(probs):
+        pr["num_chains"] = 4
+        pr["beta"] = ladder
+        pr["subset_size"] = 16 + 8 * i
+        pr["L0"] = 7 + 5 * i
+    K = 250
+    g = _batch(probs, "unbiased_sys", K, L0=100, seed=8)
+    for p, pr in enumerate(probs):
+        _check_problem(g, p, pr, "unbiased_sys", K, seed=8, L0=100)
+
+
+@pytest.mark.parametrize("launch,chunk", [("plain", 0), ("graph", 0), ("graph", 37)])
+def test_batch_launch_forms_agree(launch, chunk):
+    """Plain launches, and the graph form whose fork/join of the launch
+    classes is captured as parallel nodes, give the persistent results."""
+    probs = _uneven([50, 260, 900], chains=2)
+    for pr in probs:
+        pr["subset_size"] = 12
+    K = 120
+    ref = _batch(probs, "unbiased_sys", K, L0=20, seed=4)
+    got = _batch(probs, "unbiased_sys", K, L0=20, seed=4, launch=launch, chunk=chunk)
+    for p in range(len(probs)):
+        for key in ("action", "M", "E", "p"):
+            assert np.array_equal(ref["log"][key][p], got["log"][key][p]), (p, key)
+        assert np.array_equal(ref["cur"]["x"][p], got["cur"]["x"][p])
+
+
+def test_batch_graph_replays_continue_the_chain():
+    from paper_2210_10513_amd.binding import BatchSampler
+    probs = _uneven([70, 400], chains=2)
+    K = 60
+    a = BatchSampler(probs, "rf", launch="graph", seed=3)
+    for _ in range(4):
+        a.run(K)
+    b = BatchSampler(probs, "rf", seed=3)
+    b.run(4 * K)
+    for p in range(2):
+        assert np.array_equal(a.read_current()["x"][p], b.read_current()["x"][p])
+        assert np.array_equal(a.read_current()["E"][p], b.read_current()["E"][p])
+    a.close()
+    b.close()
+
+
+def test_batch_random_and_given_initial_states():
+    probs = _uneven([33, 140], chains=2)
+    K = 100
+    g = _batch(probs, "basic", K, L0=10, seed=6, init="random")
+    for p, pr in enumerate(probs):
+        pr["subset_size"] = g["info"][p].subset_size
+        _check_problem(g, p, pr, "basic", K, seed=6, L0=10, init="random")
+    rng = np.random.default_rng(0)
+    x0 = [rng.integers(0, 2, size=(pr["num_chains"], pr["Q"].shape[0])).astype(np.uint8) for pr in probs]
+    g = _batch(probs, "rf", K, seed=6, x0=np.concatenate([x.ravel() for x in x0]))
+    for p, pr in enumerate(probs):
+        _check_problem(g, p, pr, "rf", K, seed=6, L0=10, init="given", x0=x0[p])
+
+
+def test_batch_float32_problems():
+    probs = [{"Q": inputs.symmetric_gauss(N, seed=50 + N), "num_chains": 2, "beta": 2.0, "subset_size": 24}
+             for N in (48, 333, 1100)]
+    K = 200
+    g = _batch(probs, "unbiased_sys", K, L0=30, seed=12)
+    for p, pr in enumerate(probs):
+        _check_problem(g, p, pr, "unbiased_sys", K, seed=12, L0=30, is_int=False)
+
+
+def test_batch_snapshots_are_split_per_problem():
+    from paper_2210_10513_amd.binding import BatchSampler
+    probs = _uneven([20, 90], chains=2)
+    s = BatchSampler(probs, "rf", seed=1, snapshot_every=5, snapshot_capacity=4, log_capacity=20)
+    s.run(20)
+    xs, ms, es, cnt = s.read_snapshots()
+    log = s.read_log()
+    assert cnt == 4
+    for p in range(2):
+        assert xs[p].shape == (probs[p]["num_chains"], 4, probs[p]["Q"].shape[0])
+        # snapshot k holds the record of step 5k+4: its multiplicity and energy
+        assert np.array_equal(ms[p], log["M"][p][:, 4::5])
+        assert np.array_equal(es[p], log["E"][p][:, 4::5])
+    s.close()
+
+
+def test_autotune_choice_is_valid_and_does_not_change_results():
+    from paper_2210_10513_amd import binding as b
+    Q = inputs.symmetric_int(1000, -100, 100, np.int16, seed=7)
+    o = b.pns_opts_default()
+    o.dtype = b.PNS_I16
+    o.num_chains = 256
+    t = b.pns_autotune(Q, 1000, 0.01, 0, b.PNS_MODE_UNBIASED_SYS, o, 32)
+    assert t.block * 4 * t.groups >= 1000
+    assert 16 <= t.subset_size <= 500 and t.trials >= 2
+    assert t.records_per_s > 0
+    t2 = b.pns_autotune(Q, 1000, 0.01, 0, b.PNS_MODE_UNBIASED_SYS, o, 32)
+    assert (t2.block, t2.groups, t2.subset_size) == (t.block, t.groups, t.subset_size)  # cached
+    # the tuned tile gives the records of the fixed-table tile
+    probs = [{"Q": Q, "num_chains": 2, "beta": 0.01, "subset_size": t.subset_size}]
+    K = 150
+    g_auto = _batch(probs, "unbiased_sys", K, seed=5, autotune=True)
+    g_fix = _batch(probs, "unbiased_sys", K, seed=5)
+    assert g_auto["info"][0].block * 4 * g_auto["info"][0].groups >= 1000
+    for key in ("action", "M", "E"):
+        assert np.array_equal(g_auto["log"][key][0], g_fix["log"][key][0])
+    _check_problem(g_auto, 0, probs[0], "unbiased_sys", K, seed=5, L0=100)
+
+
+def test_batched_workload_sampled_chains():
+    """The 64-problem uneven-N int16 workload (N log-uniform in [256, 16384],
+    half the entries zero, 64 chains each), subset sizes from the
+    autotuner, graph launch form: sampled chains of sampled problems
+    against the oracle."""
+    w = inputs.c4_batched()
+    probs = [{"Q": Q, "num_chains": 64, "beta": float(w.betas[64 * i]), "subset_size": 0}
+             for i, Q in enumerate(w.Q)]
+    K = 60
+    g = _batch(probs, "unbiased_sys", K, seed=2210105134, launch="graph", L0=100)
+    Ns = [i.N for i in g["info"]]
+    order = np.argsort(Ns)
+    for p in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        info = g["info"][p]
+        assert 16 <= info.subset_size <= info.N // 2
+        _check_problem(g, p, probs[p], "unbiased_sys", K, seed=2210105134, L0=100, rows=[0, 63])
