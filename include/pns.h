@@ -210,10 +210,12 @@ int pns_create_batch(pns_ctx** out, int32_t num_problems, const pns_problem* pro
 /*
  * Choose the workgroup tile and, when subset_size is 0 in a subset mode, the
  * subset size for one problem by timed trials on the device: every compiled
- * tile that holds N is run for trial_steps steps (after a warmup) with the
- * problem's chains (opts->num_chains, at most 4096), the tile with the most
- * records per second is kept, then subset sizes 16, 32, ... up to N/2 are
- * timed on it and the largest one within 10% of the best rate is chosen
+ * tile that holds N (up to 4x the smallest such capacity) is run for
+ * trial_steps steps (after a warmup) from x = 0 with max(1024,
+ * opts->num_chains) chains, at most 4096 (the problem's betas repeated), so
+ * that the device is loaded as in a real run; the tile with the most records
+ * per second is kept, then subset sizes 16, 32, ... up to N/2 are timed on
+ * it and the largest one within 10% of the best rate is chosen
  * (Sec 5: on parallel hardware, take the largest affordable partial neighbor
  * set).  Results are cached per process by (N, dtype, layout, mode, n,
  * chains).  Synchronises the device.  Errors: as pns_create.

@@ -315,8 +315,18 @@ struct LaunchClass {
     size_t dyn;
     std::vector<int32_t> chains;
     int32_t* d_list = nullptr;
+    double cost = 0.0;  // estimated time of one step of every chain of the class
+};
+
+// Side streams of a context with several launch classes.  HIP spreads a
+// process's streams over 4 hardware queues by default, and kernels on one
+// queue run one after another, so classes are packed onto at most 4 streams.
+constexpr int kMaxSideStreams = 4;
+
+struct SideStream {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    std::vector<int32_t> classes;  // launched in this order
 };
 
 }  // namespace
@@ -330,6 +340,7 @@ struct pns_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipEvent_t fork = nullptr;
+    std::vector<SideStream> sides;
     std::vector<ProblemRun> probs;
     std::vector<int32_t> h_chain_problem;
     std::vector<int64_t> h_foff;
@@ -435,12 +446,14 @@ struct pns_ctx {
     {
         if (classes.size() == 1) return launch_class(classes[0], steps, stream);
         HIP_TRY(hipEventRecord(fork, stream), "fork record");
-        for (auto& k : classes) {
-            HIP_TRY(hipStreamWaitEvent(k.stream, fork, 0), "fork wait");
-            int rc = launch_class(k, steps, k.stream);
-            if (rc) return rc;
-            HIP_TRY(hipEventRecord(k.done, k.stream), "join record");
-            HIP_TRY(hipStreamWaitEvent(stream, k.done, 0), "join wait");
+        for (auto& sd : sides) {
+            HIP_TRY(hipStreamWaitEvent(sd.stream, fork, 0), "fork wait");
+            for (int32_t ki : sd.classes) {
+                int rc = launch_class(classes[ki], steps, sd.stream);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipEventRecord(sd.done, sd.stream), "join record");
+            HIP_TRY(hipStreamWaitEvent(stream, sd.done, 0), "join wait");
         }
         return PNS_OK;
     }
@@ -458,10 +471,11 @@ struct pns_ctx {
             if (P.A) (void)hipFree(P.A);
             if (P.diag) (void)hipFree(P.diag);
         }
-        for (auto& k : classes) {
+        for (auto& k : classes)
             if (k.d_list) (void)hipFree(k.d_list);
-            if (k.stream) (void)hipStreamDestroy(k.stream);
-            if (k.done) (void)hipEventDestroy(k.done);
+        for (auto& sd : sides) {
+            if (sd.stream) (void)hipStreamDestroy(sd.stream);
+            if (sd.done) (void)hipEventDestroy(sd.done);
         }
         if (fork) (void)hipEventDestroy(fork);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -647,6 +661,8 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
             betas[c0 + c] = S.betas[c];
             K.chains.push_back(c0 + c);
         }
+        // a step costs about the lane work of the tile: block * groups
+        K.cost += (double)S.chains * RR.tile.block * RR.tile.groups;
         f0 += (int64_t)S.chains * RR.pitch;
         c0 += S.chains;
     }
@@ -736,10 +752,22 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
     if (ctx->classes.size() > 1) {
         if ((e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming)) != hipSuccess)
             return fail_free(hip_fail(e, "hipEventCreate"));
-        for (auto& k : ctx->classes) {
-            if ((e = hipStreamCreateWithFlags(&k.stream, hipStreamNonBlocking)) != hipSuccess)
+        // longest-processing-time-first packing of the classes onto the side streams
+        std::vector<int32_t> order(ctx->classes.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return ctx->classes[a].cost > ctx->classes[b].cost; });
+        ctx->sides.resize(std::min<size_t>(kMaxSideStreams, ctx->classes.size()));
+        std::vector<double> load(ctx->sides.size(), 0.0);
+        for (int32_t ki : order) {
+            const size_t sdi = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+            ctx->sides[sdi].classes.push_back(ki);
+            load[sdi] += ctx->classes[ki].cost;
+        }
+        for (auto& sd : ctx->sides) {
+            if ((e = hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking)) != hipSuccess)
                 return fail_free(hip_fail(e, "hipStreamCreate"));
-            if ((e = hipEventCreateWithFlags(&k.done, hipEventDisableTiming)) != hipSuccess)
+            if ((e = hipEventCreateWithFlags(&sd.done, hipEventDisableTiming)) != hipSuccess)
                 return fail_free(hip_fail(e, "hipEventCreate"));
         }
     }
@@ -783,6 +811,8 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
 }
 
 // ---- autotuner ----
+
+constexpr int32_t kTrialSteps = 128;  // timed steps per trial on creation
 
 std::mutex g_tune_mu;
 std::map<std::string, pns_tune> g_tune_cache;
@@ -878,10 +908,14 @@ int autotune_impl(const ProblemSpec& base, int32_t mode, const pns_opts& o, int3
             return PNS_OK;
         }
     }
+    // Trials run at least 1024 chains (the problem's betas repeated) so that
+    // the device is loaded as in a real run: a few chains alone on an idle
+    // device measure step latency, not throughput.
     ProblemSpec spec = base;
-    spec.chains = std::min<int32_t>(base.chains, 4096);
-    spec.betas.assign(spec.chains, base.betas.empty() ? 1.0 : base.betas[0]);
-    for (int32_t c = 0; c < spec.chains && c < (int32_t)base.betas.size(); ++c) spec.betas[c] = base.betas[c];
+    spec.chains = std::min<int32_t>(4096, std::max<int32_t>(base.chains, 1024));
+    spec.betas.assign(spec.chains, 1.0);
+    for (int32_t c = 0; c < spec.chains; ++c)
+        spec.betas[c] = base.betas.empty() ? 1.0 : base.betas[c % base.betas.size()];
     const bool tune_n = mode != PNS_MODE_RF && base.n == 0;
     // subset size used while choosing the tile
     int32_t n0 = base.n;
@@ -1022,7 +1056,7 @@ int pns_create(pns_ctx** out, const void* Q, int32_t N, double beta, int32_t sub
         pns_tune t{};
         ProblemSpec T = S;
         T.n = tune_n ? 0 : n;
-        rc = autotune_impl(T, mode, o, 64, &t, &prep);
+        rc = autotune_impl(T, mode, o, kTrialSteps, &t, &prep);
         if (rc) return rc;
         S.tile = {t.block, t.groups};
         if (tune_n) S.n = t.subset_size;
@@ -1091,7 +1125,7 @@ int pns_create_batch(pns_ctx** out, int32_t num_problems, const pns_problem* pro
         pns_tune r{};
         ProblemSpec T = specs[p];
         T.n = tune_n[p] ? 0 : specs[p].n;
-        rc = autotune_impl(T, mode, t, 64, &r, &preps[p]);
+        rc = autotune_impl(T, mode, t, kTrialSteps, &r, &preps[p]);
         if (rc) return rc;
         specs[p].tile = {r.block, r.groups};
         if (tune_n[p]) specs[p].n = r.subset_size;
