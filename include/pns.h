@@ -309,6 +309,63 @@ const char* pns_last_error(void);
 /* Library version, e.g. "0.1.0". */
 const char* pns_version(void);
 
+/* ---- differentiation path ----
+ *
+ * The target pi_beta(x) = exp(-beta x^T Q x) / Z(Q, beta) gives
+ * d log Z / d Q_ij = -beta E_pi[x_i x_j] for every entry of Q (Sec 4 target;
+ * the derivative of the log of a sum of exponentials), and the jump chain
+ * estimates E_pi[f] by sum_k M_k f(J_k) / sum_k M_k (Sec 1.2, multiplicity
+ * list).  These entry points compute the multiplicity-weighted moment matrix
+ * of records and, for small N, log Z itself.
+ */
+
+/*
+ * G = X^T diag(m) X = sum_k m_k x_k x_k^T over K records.
+ *   X      [K][ldx] bytes, record k in row k, bit i in byte i (nonzero = 1),
+ *          ldx >= N; host or device.
+ *   m      [K] int64 weights (multiplicities; negative values count as 0),
+ *          host or device.
+ *   G      [N][N] FP64 output, overwritten, host or device.
+ *   sum_m  host pointer receiving sum_k m_k (exact), or NULL.
+ *   stream hipStream_t to queue on (NULL: the default stream); the call
+ *          synchronises it once (to size the kernels) and, for a host G, at
+ *          the end.
+ * Computed on the bf16 matrix cores with FP32 accumulation: x is exact in
+ * bf16 and each m_k is split into up to three bf16 pieces (exact for
+ * m_k < 2^24); records are cut into chunks whose FP32 partial sums of
+ * integers stay below 2^24 (exact), and chunk sums are added in FP64.  G is
+ * therefore exact whenever m_k <= 2^18 for every k; beyond that each chunk
+ * sum carries a relative error below 64 * 2^-24 and, for m_k >= 2^24, the
+ * weight itself is rounded to 24 bits.
+ * Errors: PNS_EINVAL (NULL X, m or G, N outside [1, 32768], K < 0,
+ * ldx < N), PNS_ENOMEM, PNS_EDEVICE.
+ */
+int pns_moments(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int32_t N, double* G, double* sum_m,
+                void* stream);
+
+/*
+ * pns_moments over the snapshot buffer of the chains of one problem of a
+ * context (every stored snapshot of every chain of the problem: the state J
+ * and multiplicity M of the record at each snapshot step; slots not yet
+ * written weigh 0).  G is [N][N] FP64, host or device.  Queued on the
+ * context's stream, which it synchronises.
+ * Errors: PNS_EINVAL (NULL ctx or G, snapshots off, problem out of range),
+ * PNS_ENOMEM, PNS_EDEVICE.
+ */
+int pns_snapshot_moments(pns_ctx* ctx, int32_t problem, double* G, double* sum_m);
+
+/*
+ * log Z(Q, beta) = log sum_x exp(-beta x^T Q x) by enumeration of all 2^N
+ * states on the device (Gray-code order, incremental energies: exact int64
+ * for integer Q, FP64 for float Q; FP64 log-sum-exp).  Q [N][N] of `dtype`
+ * in `layout`, host or device; *out is host or device.  Synchronises
+ * `stream` (NULL: the default stream).
+ * Errors: PNS_EINVAL (N outside [1, 32], bad dtype or layout, beta < 0 or
+ * not finite), PNS_ENOMEM, PNS_EDEVICE.
+ */
+int pns_log_partition(const void* Q, int32_t N, int32_t dtype, int32_t layout, double beta, double* out,
+                      void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,6 +19,7 @@ the estimate of E_pi[x x^T] from records (x_k, m_k) is G / sum_k m_k with
 Functions
 * ``weighted_moments(X, m)``: G, written out from that definition in int64
   (integer m) or float64.
+* ``weighted_moment_entries(X, m, pairs)``: chosen entries of G one by one.
 * ``log_partition_loop(Q, beta)``: log Z by a plain Python loop over the
   2^N states (small N), independent of the C enumerator.
 * ``grad_log_partition(Q, beta)``: -beta E_pi[x x^T] by enumeration.
@@ -46,6 +47,18 @@ def weighted_moments(X: np.ndarray, m: np.ndarray) -> np.ndarray:
         return (Xi * m.astype(np.int64)[:, None]).T @ Xi
     Xf = X.astype(np.float64)
     return (Xf * m.astype(np.float64)[:, None]).T @ Xf
+
+
+def weighted_moment_entries(X: np.ndarray, m: np.ndarray, pairs) -> np.ndarray:
+    """G_ij = sum of m_k over the records with bits i and j both set, for each
+    (i, j) in ``pairs`` (entries of a G too large to form)."""
+    X = np.asarray(X)
+    m = np.asarray(m)
+    out = []
+    for i, j in pairs:
+        both = (X[:, i] != 0) & (X[:, j] != 0)
+        out.append(m[both].sum())
+    return np.asarray(out)
 
 
 def log_partition_loop(Q: np.ndarray, beta: float) -> float:

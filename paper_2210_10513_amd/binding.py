@@ -38,7 +38,8 @@ LAYOUTS = {"symmetric": PNS_SYMMETRIC, "upper": PNS_UPPER}
 EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_current", "pns_field_type",
            "pns_read_log", "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync",
            "pns_destroy", "pns_tile", "pns_last_error", "pns_version", "pns_create_batch", "pns_autotune",
-           "pns_chain_offsets", "pns_num_problems", "pns_problem_info_get"]
+           "pns_chain_offsets", "pns_num_problems", "pns_problem_info_get", "pns_moments", "pns_snapshot_moments",
+           "pns_log_partition"]
 
 
 class pns_opts(ctypes.Structure):
@@ -118,10 +119,13 @@ def _load() -> ctypes.CDLL:
     L.pns_chain_offsets.argtypes = [vp, vp]
     L.pns_num_problems.argtypes = [vp]
     L.pns_problem_info_get.argtypes = [vp, i32, ctypes.POINTER(pns_problem_info)]
+    L.pns_moments.argtypes = [vp, i64, vp, i64, i32, vp, ctypes.POINTER(dbl), vp]
+    L.pns_snapshot_moments.argtypes = [vp, i32, vp, ctypes.POINTER(dbl)]
+    L.pns_log_partition.argtypes = [vp, i32, i32, i32, dbl, vp, vp]
     for name in ("pns_create", "pns_run", "pns_read", "pns_read_current", "pns_field_type", "pns_read_log",
                  "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync", "pns_destroy",
                  "pns_tile", "pns_create_batch", "pns_autotune", "pns_chain_offsets", "pns_num_problems",
-                 "pns_problem_info_get"):
+                 "pns_problem_info_get", "pns_moments", "pns_snapshot_moments", "pns_log_partition"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -252,6 +256,44 @@ def pns_problem_info_get(ctx, p: int) -> pns_problem_info:
     return info
 
 
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def pns_moments(X, m, G, *, N: Optional[int] = None, ldx: Optional[int] = None, stream=None) -> float:
+    """G[:] = X^T diag(m) X; returns sum(m).  X [K, ldx] uint8, m [K] int64,
+    G [N, N] float64 (numpy arrays or torch tensors, host or device)."""
+    K = int(X.shape[0])
+    ld = int(X.shape[1]) if ldx is None else ldx
+    n = int(G.shape[0]) if N is None else N
+    sm = ctypes.c_double()
+    _check(lib.pns_moments(_addr(X), ld, _addr(m), K, n, _addr(G), ctypes.byref(sm), _stream_handle(stream)))
+    return sm.value
+
+
+def pns_snapshot_moments(ctx, problem: int, G) -> float:
+    sm = ctypes.c_double()
+    _check(lib.pns_snapshot_moments(ctx, problem, _addr(G), ctypes.byref(sm)))
+    return sm.value
+
+
+def pns_log_partition(Q, beta: float, *, layout: int = PNS_SYMMETRIC, stream=None) -> float:
+    """log sum_x exp(-beta x^T Q x) by enumeration on the device (N <= 32)."""
+    if hasattr(Q, "data_ptr"):
+        import torch
+        dt = {torch.int16: PNS_I16, torch.int32: PNS_I32, torch.float32: PNS_F32}[Q.dtype]
+        Qk = Q.contiguous()
+    else:
+        Qk = np.ascontiguousarray(Q)
+        dt = _DTYPES[Qk.dtype]
+    out = np.zeros(1, np.float64)
+    _check(lib.pns_log_partition(_addr(Qk), int(Qk.shape[0]), dt, layout, float(beta), out.ctypes.data,
+                                 _stream_handle(stream)))
+    return float(out[0])
+
+
 def pns_last_error() -> str:
     return lib.pns_last_error().decode()
 
@@ -374,6 +416,13 @@ class Sampler:
     def stats(self):
         arr = pns_stats(self.ctx, self.num_chains)
         return {k: np.array([getattr(s, k) for s in arr]) for k in ("steps", "flips", "stays", "saturated", "sum_M", "anomalies")}
+
+    def snapshot_moments(self, G=None):
+        """(G, sum_m): G = X^T diag(m) X over every stored snapshot."""
+        if G is None:
+            G = np.zeros((self.N, self.N), np.float64)
+        sm = pns_snapshot_moments(self.ctx, 0, G)
+        return G, sm
 
     def tile(self):
         return pns_tile(self.ctx)

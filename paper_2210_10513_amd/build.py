@@ -21,7 +21,11 @@ LIB = os.path.join(LIBDIR, "libpns.so")
 ARCH = os.environ.get("PNS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["pns_step_i16.hip", "pns_step_i32.hip", "pns_step_i64.hip", "pns_step_f32.hip", "pns_kernels.hip",
-           "pns_runtime.cpp"]
+           "pns_moments.hip", "pns_runtime.cpp"]
+
+# Per-source additions: the moment kernel adds FP64 partial sums with the
+# hardware atomic add (device memory only).
+EXTRA_FLAGS = {"pns_moments.hip": ["-munsafe-fp-atomics"]}
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -39,7 +43,7 @@ def _hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(LIBDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -114,3 +114,20 @@ hipError_t launch_init_with_map(int32_t qtype, int32_t htype, int32_t max_pitch,
 hipError_t launch_fill64(void* p, int64_t count, int64_t value, hipStream_t stream);
 
 }  // namespace pns
+
+namespace pns {
+
+// Differentiation path (pns_moments.hip).
+// Weight pieces (3 x kpad bf16), exact sum and max of the weights.
+hipError_t launch_moments_prep(const int64_t* m, int64_t K, int64_t kpad, uint16_t* pieces, unsigned long long* sum_m,
+                               unsigned long long* max_m, hipStream_t st);
+// G += X^T diag(m) X over records [0, K), chunks of `chunk` records
+// (multiple of 64) accumulated in FP32, added into FP64 G [N][N].
+hipError_t launch_moments(int32_t pieces_used, const uint8_t* X, int64_t ldx, int64_t K, int32_t N,
+                          const uint16_t* pieces, int64_t kpad, int64_t chunk, double* G, hipStream_t st);
+// log Z by enumeration: `blocks` x 256 threads, thread t covers the states
+// with high bits t and all 2^lowbits low bits; part_* hold `blocks` pairs.
+hipError_t launch_logz(int32_t qtype, const void* Q, int32_t N, int32_t layout, double beta, double* part_max,
+                       double* part_sum, int32_t blocks, int32_t lowbits, int64_t nthreads, double* out, hipStream_t st);
+
+}  // namespace pns

@@ -749,6 +749,13 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         if (e != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
     }
     if (ctx->rmem && (e = hipMemset(ctx->rmem, 0, fields)) != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
+    if (ctx->snap_x) {
+        // slots not yet written read as x = 0 with weight 0
+        e = hipMemset(ctx->snap_x, 0, (size_t)C * ctx->snap_cap * ctx->max_pitch);
+        if (e == hipSuccess) e = hipMemset(ctx->snap_M, 0, (size_t)C * ctx->snap_cap * 8);
+        if (e == hipSuccess) e = hipMemset(ctx->snap_E, 0, (size_t)C * ctx->snap_cap * 8);
+        if (e != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
+    }
     if (ctx->classes.size() > 1) {
         if ((e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming)) != hipSuccess)
             return fail_free(hip_fail(e, "hipEventCreate"));
@@ -1438,6 +1445,172 @@ int pns_destroy(pns_ctx* ctx)
     ctx->free_all();
     delete ctx;
     return PNS_OK;
+}
+
+}  // extern "C"
+
+// ---- differentiation path ----
+
+namespace {
+
+// G (N x N, FP64, zeroed here) += X^T diag(m) X on `st`; device pointers.
+// Returns the exact sum of the weights in *sum_out.
+int moments_device(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int32_t N, double* G, hipStream_t st,
+                   double* sum_out)
+{
+    const int64_t kpad = std::max<int64_t>(64, round_up(K, 64));
+    uint16_t* pieces = nullptr;
+    unsigned long long* cnt = nullptr;
+    int rc = dev_alloc(&pieces, (size_t)3 * kpad);
+    if (!rc) rc = dev_alloc(&cnt, 2);
+    auto done = [&](int r) {
+        if (pieces) (void)hipFree(pieces);
+        if (cnt) (void)hipFree(cnt);
+        return r;
+    };
+    if (rc) return done(rc);
+    hipError_t e = launch_fill64(G, (int64_t)N * N, 0, st);
+    if (e == hipSuccess) e = launch_fill64(cnt, 2, 0, st);
+    if (e == hipSuccess) e = launch_moments_prep(m, K, kpad, pieces, cnt, cnt + 1, st);
+    unsigned long long hc[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return done(hip_fail(e, "moments preparation"));
+    const unsigned long long maxm = hc[1];
+    // pieces needed: m <= 256 is one bf16, m <= 65536 two, larger three
+    const int32_t P = maxm <= 256 ? 1 : (maxm <= 65536 ? 2 : 3);
+    // FP32 partial sums of integers stay exact below 2^24
+    int64_t chunk = 4096;
+    if (maxm > 0) chunk = std::min<int64_t>(chunk, (int64_t)((double)(1 << 24) / ((double)maxm * 1.01)) / 64 * 64);
+    chunk = std::max<int64_t>(64, chunk);
+    // enough workgroups to fill the device
+    const int nt = (N + 63) / 64;
+    const int64_t tiles = (int64_t)nt * (nt + 1) / 2;
+    while (chunk > 256 && tiles * ((K + chunk - 1) / chunk) < 2048) chunk /= 2;
+    chunk = std::max<int64_t>(64, chunk / 64 * 64);
+    if (K > 0 && (K + chunk - 1) / chunk > 65535) chunk = round_up((K + 65534) / 65535, 64);
+    if (K > 0) {
+        e = launch_moments(P, X, ldx, K, N, pieces, kpad, chunk, G, st);
+        if (e != hipSuccess) return done(hip_fail(e, "moments kernel"));
+    }
+    if (sum_out) *sum_out = (double)hc[0];
+    return done(PNS_OK);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pns_moments(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int32_t N, double* G, double* sum_m,
+                void* stream)
+{
+    g_error.clear();
+    if (!X || !m || !G) return fail(PNS_EINVAL, "NULL argument");
+    if (N < 1 || N > 32768) return fail(PNS_EINVAL, "N must be in [1, 32768]");
+    if (K < 0) return fail(PNS_EINVAL, "K must be >= 0");
+    if (ldx < N) return fail(PNS_EINVAL, "ldx must be >= N");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const bool xd = is_device_ptr(X), md = is_device_ptr(m), gd = is_device_ptr(G);
+    uint8_t* dX = nullptr;
+    int64_t* dm = nullptr;
+    double* dG = nullptr;
+    auto done = [&](int r) {
+        if (!xd && dX) (void)hipFree(dX);
+        if (!md && dm) (void)hipFree(dm);
+        if (!gd && dG) (void)hipFree(dG);
+        return r;
+    };
+    int rc = PNS_OK;
+    if (xd) dX = const_cast<uint8_t*>(X);
+    else if (!(rc = dev_alloc(&dX, (size_t)K * ldx)) && K > 0)
+        if (hipMemcpy(dX, X, (size_t)K * ldx, hipMemcpyHostToDevice) != hipSuccess) rc = fail(PNS_EDEVICE, "upload X");
+    if (rc) return done(rc);
+    if (md) dm = const_cast<int64_t*>(m);
+    else if (!(rc = dev_alloc(&dm, (size_t)K)) && K > 0)
+        if (hipMemcpy(dm, m, (size_t)K * 8, hipMemcpyHostToDevice) != hipSuccess) rc = fail(PNS_EDEVICE, "upload m");
+    if (rc) return done(rc);
+    if (gd) dG = G;
+    else if ((rc = dev_alloc(&dG, (size_t)N * N))) return done(rc);
+    double sm = 0.0;
+    rc = moments_device(dX, ldx, dm, K, N, dG, st, &sm);
+    if (rc) return done(rc);
+    if (!gd) {
+        hipError_t e = hipMemcpyAsync(G, dG, (size_t)N * N * 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return done(hip_fail(e, "download G"));
+    }
+    if (sum_m) *sum_m = sm;
+    return done(PNS_OK);
+}
+
+int pns_snapshot_moments(pns_ctx* ctx, int32_t problem, double* G, double* sum_m)
+{
+    g_error.clear();
+    if (!ctx || !G) return fail(PNS_EINVAL, "NULL argument");
+    if (!ctx->snap_x) return fail(PNS_EINVAL, "snapshots are off (snapshot_every = 0)");
+    if (problem < 0 || problem >= (int32_t)ctx->probs.size()) return fail(PNS_EINVAL, "problem %d out of range", problem);
+    const ProblemRun& R = ctx->probs[problem];
+    const int64_t row0 = (int64_t)R.chain_begin * ctx->snap_cap;
+    const int64_t K = (int64_t)R.chains * ctx->snap_cap;
+    const bool gd = is_device_ptr(G);
+    double* dG = G;
+    int rc = PNS_OK;
+    if (!gd && (rc = dev_alloc(&dG, (size_t)R.N * R.N))) return rc;
+    double sm = 0.0;
+    rc = moments_device(ctx->snap_x + row0 * ctx->max_pitch, ctx->max_pitch, ctx->snap_M + row0, K, R.N, dG,
+                        ctx->stream, &sm);
+    if (!rc && !gd) {
+        hipError_t e = hipMemcpyAsync(G, dG, (size_t)R.N * R.N * 8, hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "download G");
+    }
+    if (!gd) (void)hipFree(dG);
+    if (rc) return rc;
+    if (sum_m) *sum_m = sm;
+    return PNS_OK;
+}
+
+int pns_log_partition(const void* Q, int32_t N, int32_t dtype, int32_t layout, double beta, double* out, void* stream)
+{
+    g_error.clear();
+    if (!Q || !out) return fail(PNS_EINVAL, "NULL argument");
+    if (N < 1 || N > 32) return fail(PNS_EINVAL, "enumeration needs 1 <= N <= 32");
+    if (dtype < PNS_I16 || dtype > PNS_F32) return fail(PNS_EINVAL, "unknown dtype %d", dtype);
+    if (layout != PNS_SYMMETRIC && layout != PNS_UPPER) return fail(PNS_EINVAL, "unknown layout %d", layout);
+    if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(PNS_EINVAL, "beta must be finite and >= 0");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const size_t qbytes = (size_t)N * N * qsize(dtype);
+    // the kernels read Q from device memory: copy a host matrix in
+    std::vector<uint8_t> qh(qbytes);
+    int rc = copy_in(qh.data(), Q, qbytes);
+    if (rc) return rc;
+    const int32_t lowbits = std::max(std::min(N, 6), N - 14);
+    const int64_t nthreads = (int64_t)1 << (N - lowbits);
+    const int32_t blocks = (int32_t)((nthreads + 255) / 256);
+    uint8_t* dq = nullptr;
+    double* part = nullptr;
+    double* dout = nullptr;
+    auto done = [&](int r) {
+        if (dq) (void)hipFree(dq);
+        if (part) (void)hipFree(part);
+        if (dout) (void)hipFree(dout);
+        return r;
+    };
+    if ((rc = dev_alloc(&dq, qbytes)) || (rc = dev_alloc(&part, (size_t)2 * blocks)) || (rc = dev_alloc(&dout, 1)))
+        return done(rc);
+    hipError_t e = hipMemcpyAsync(dq, qh.data(), qbytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_logz(dtype, dq, N, layout, beta, part, part + blocks, blocks, lowbits, nthreads, dout, st);
+    double v = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&v, dout, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return done(hip_fail(e, "log partition"));
+    if (is_device_ptr(out)) {
+        if ((e = hipMemcpy(out, &v, 8, hipMemcpyHostToDevice)) != hipSuccess) return done(hip_fail(e, "copy out"));
+    } else {
+        *out = v;
+    }
+    return done(PNS_OK);
 }
 
 }  // extern "C"

@@ -39,6 +39,8 @@ def test_weighted_moments_invariants():
     # G_ij counts the weight of records with both bits set
     i, j = 2, 5
     assert G[i, j] == int(m[(X[:, i] == 1) & (X[:, j] == 1)].sum())
+    pairs = [(0, 0), (2, 5), (6, 1), (3, 3)]
+    assert np.array_equal(moments.weighted_moment_entries(X, m, pairs), [G[a, b] for a, b in pairs])
 
 
 @pytest.mark.parametrize("N,seed", [(1, 0), (4, 1), (7, 2)])
