@@ -47,7 +47,104 @@ def _workload(name: str):
                  for i, Q in enumerate(w.Q)]
         return dict(problems=probs, betas=w.betas, mode="unbiased_sys", n=0, L0=100, qbytes=2, steps=20_000,
                     desc=w.name, Ns=np.asarray(w.extra["Ns"]))
+    if name in ("fit_n64_f32", "fit_n512_f32"):
+        N = 64 if name == "fit_n64_f32" else 512
+        w = inputs.c5_fit(N)
+        return dict(fit=True, Q=w.Q, betas=w.betas, mode="rf", n=0, L0=100, qbytes=4, steps=0, desc=w.name)
     raise SystemExit(f"unknown workload {name}")
+
+
+def _bench_fit(args, wl):
+    """Maximum-likelihood fit of a QUBO to 2^20 weighted samples of a seeded
+    ground truth: one bench step is one gradient iteration (sampler forward on
+    8192 chains, 64 burn-in + 16 snapshots x 4 steps, warm-started; backward
+    on the bf16 MFMA moment kernel; momentum update).  Also times the
+    backward kernel alone over the 131072 records of one iteration."""
+    import torch
+    from paper_2210_10513_amd import binding
+    from paper_2210_10513_amd.autograd import ChainOptions, LogZ, moments_of_samples
+    dev = torch.device("cuda")
+    N = wl["Q"].shape[0]
+    beta = 1.0
+    Qt = torch.tensor(wl["Q"], device=dev)
+    D, nsamp = moments_of_samples(Qt, beta, ChainOptions(num_chains=8192, burn_in=512, samples=128, every=4,
+                                                         seed=1))
+    D = D.float()
+    chains, burn, samples, every = 8192, 64, 16, 4
+    state = {}
+    Q = torch.zeros((N, N), dtype=torch.float32, device=dev, requires_grad=True)
+    vel = torch.zeros_like(Q)
+    lr, mom = 0.5, 0.9
+    gaps = []
+
+    def one_iter(it):
+        o = ChainOptions(num_chains=chains, burn_in=burn, samples=samples, every=every, seed=100 + it, state=state,
+                         exact_max=0)
+        lz = LogZ.apply(Q, beta, o)
+        loss = beta * (Q * D).sum() + torch.nan_to_num(lz)
+        Q.grad = None
+        loss.backward()
+        with torch.no_grad():
+            vel.mul_(mom).add_(Q.grad)
+            Q.sub_(lr * vel)
+            Q.copy_((Q + Q.T) * 0.5)
+        return Q.grad
+
+    for it in range(args.warmup):
+        one_iter(it)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for it in range(args.steps):
+        g = one_iter(args.warmup + it)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    sec = t0.elapsed_time(t1) / 1000.0 / args.steps
+    gaps.append(float(g.abs().max()) / beta)
+    steps_per_iter = burn + samples * every
+    flips = chains * steps_per_iter  # Rejection-Free: every record is a flip
+
+    # backward kernel alone: the moments of one iteration's snapshots
+    s = binding.Sampler(Qt, beta, 0, "rf", num_chains=chains, seed=9, init="random", stream=stream,
+                        snapshot_every=every, snapshot_capacity=samples)
+    s.run(burn + samples * every)
+    G = torch.empty((N, N), dtype=torch.float64, device=dev)
+    sm = torch.empty(1, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        binding.pns_snapshot_moments(s.ctx, 0, G, sum_m=sm)
+    reps = 50
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        binding.pns_snapshot_moments(s.ctx, 0, G, sum_m=sm)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    s.close()
+    mom_ms = e0.elapsed_time(e1) / reps
+    K = chains * samples
+    mflops = 2.0 * K * N * N
+    mom_tf = mflops / (mom_ms * 1e-3) / 1e12
+    out = {
+        "metric": "flips/s", "value": flips / sec, "unit": "flips/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1000.0, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["desc"], "N": N, "chains": chains, "mode": "rf", "beta": beta,
+                   "data_samples": int(nsamp), "records_per_gradient": K, "steps_per_gradient": steps_per_iter},
+        "gradients_per_s": 1.0 / sec,
+        "moment_gap_last": gaps[-1],
+        "roofline": {"bound": "hbm", "achieved": flips * N * 4 / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": flips * N * 4 / sec / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_flip": N * 4, "kernel": "step_kernel + moments_kernel (whole iteration)",
+                     "kernel_avg_ms": sec * 1000.0},
+        "moments_roofline": {"bound": "mfma", "achieved": mom_tf, "peak": 2500.0, "unit": "TFLOP/s",
+                             "frac": mom_tf / 2500.0, "traffic": None, "flops_per_launch": mflops,
+                             "kernel": "moments (fill + prep + moments_kernel + sum)", "kernel_avg_ms": mom_ms},
+    }
+    print(json.dumps(out))
 
 
 def _time_batch(wl, chain_steps: int, steps: int, warmup: int, launch: str, seed: int):
@@ -188,6 +285,9 @@ def main():
     torch.cuda.set_device(0)
 
     wl = _workload(args.workload)
+    if wl.get("fit"):
+        _bench_fit(args, wl)
+        return
     if "problems" in wl:
         _bench_batch(args, wl)
         return

@@ -309,6 +309,25 @@ const char* pns_last_error(void);
 /* Library version, e.g. "0.1.0". */
 const char* pns_version(void);
 
+/*
+ * Replace the coefficient matrix of problem `problem` (same N, element type
+ * and layout as on creation; host or device, copied).  The chains keep their
+ * states, budgets and random-number positions; their local fields and
+ * energies are recomputed for the new matrix, so the next step samples the
+ * new target (a warm start, as a fitting loop needs).  The matrix is
+ * prepared and checked on the device in a staging buffer and swapped in
+ * only if valid.  Synchronises the context's stream.
+ * Errors: PNS_EINVAL (NULL Q, problem out of range, asymmetric SYMMETRIC Q,
+ * non-finite entries, int64 energy overflow), PNS_EUNSUPPORTED (integer Q
+ * whose fields no longer fit the context's 32-bit fields), PNS_ENOMEM,
+ * PNS_EDEVICE.
+ */
+int pns_set_q(pns_ctx* ctx, int32_t problem, const void* Q);
+
+/* Forget every stored snapshot (weights and counts to zero), queued on the
+ * context's stream.  Errors: PNS_EINVAL (NULL ctx, snapshots off). */
+int pns_snapshots_clear(pns_ctx* ctx);
+
 /* ---- differentiation path ----
  *
  * The target pi_beta(x) = exp(-beta x^T Q x) / Z(Q, beta) gives
@@ -326,17 +345,20 @@ const char* pns_version(void);
  *   m      [K] int64 weights (multiplicities; negative values count as 0),
  *          host or device.
  *   G      [N][N] FP64 output, overwritten, host or device.
- *   sum_m  host pointer receiving sum_k m_k (exact), or NULL.
- *   stream hipStream_t to queue on (NULL: the default stream); the call
- *          synchronises it once (to size the kernels) and, for a host G, at
- *          the end.
+ *   sum_m  receives sum_k m_k (exact below 2^53) as one FP64, host or
+ *          device, or NULL.
+ *   stream hipStream_t to queue on (NULL: the default stream).  With X, m,
+ *          G and sum_m all in device memory the call only queues work;
+ *          any host buffer makes it synchronise the stream before it
+ *          returns.
  * Computed on the bf16 matrix cores with FP32 accumulation: x is exact in
  * bf16 and each m_k is split into up to three bf16 pieces (exact for
- * m_k < 2^24); records are cut into chunks whose FP32 partial sums of
- * integers stay below 2^24 (exact), and chunk sums are added in FP64.  G is
- * therefore exact whenever m_k <= 2^18 for every k; beyond that each chunk
- * sum carries a relative error below 64 * 2^-24 and, for m_k >= 2^24, the
- * weight itself is rounded to 24 bits.
+ * m_k < 2^24), so every product is an exact integer.  The FP32
+ * accumulators are added into G (FP64) every F records with
+ * F * max(m) < 2^24 (F >= 64), so G is exact whenever m_k <= 2^18 for
+ * every k; beyond that each partial sum carries a relative error below
+ * 64 * 2^-24 and, for m_k >= 2^24, the weight itself is rounded to 24
+ * bits.
  * Errors: PNS_EINVAL (NULL X, m or G, N outside [1, 32768], K < 0,
  * ldx < N), PNS_ENOMEM, PNS_EDEVICE.
  */
@@ -347,8 +369,9 @@ int pns_moments(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int3
  * pns_moments over the snapshot buffer of the chains of one problem of a
  * context (every stored snapshot of every chain of the problem: the state J
  * and multiplicity M of the record at each snapshot step; slots not yet
- * written weigh 0).  G is [N][N] FP64, host or device.  Queued on the
- * context's stream, which it synchronises.
+ * written weigh 0).  G is [N][N] FP64 and sum_m one FP64, each host or
+ * device (or sum_m NULL).  Queued on the context's stream; synchronises it
+ * only when G or sum_m is in host memory.
  * Errors: PNS_EINVAL (NULL ctx or G, snapshots off, problem out of range),
  * PNS_ENOMEM, PNS_EDEVICE.
  */

@@ -43,8 +43,13 @@ def weighted_moments(X: np.ndarray, m: np.ndarray) -> np.ndarray:
     X = np.asarray(X)
     m = np.asarray(m)
     if np.issubdtype(m.dtype, np.integer):
+        mi = m.astype(np.int64)
+        if X.shape[0] == 0 or int(np.abs(mi).max()) * X.shape[0] < 2 ** 53:
+            # every partial sum is an integer below 2^53: FP64 is exact
+            Xf = X.astype(np.float64)
+            return np.rint((Xf * mi.astype(np.float64)[:, None]).T @ Xf).astype(np.int64)
         Xi = X.astype(np.int64)
-        return (Xi * m.astype(np.int64)[:, None]).T @ Xi
+        return (Xi * mi[:, None]).T @ Xi
     Xf = X.astype(np.float64)
     return (Xf * m.astype(np.float64)[:, None]).T @ Xf
 

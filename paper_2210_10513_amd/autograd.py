@@ -36,7 +36,7 @@ from . import binding
 class ChainOptions:
     """How LogZ samples: ``num_chains`` chains, ``burn_in`` steps, then
     ``samples`` snapshots every ``every`` steps per chain.  ``state``, if a
-    dict, carries the chains' final states between calls (warm start)."""
+    dict, keeps the sampler between calls (warm start, see LogZ)."""
     num_chains: int = 8192
     burn_in: int = 256
     samples: int = 16
@@ -49,8 +49,18 @@ class ChainOptions:
     state: Optional[dict] = None
 
 
+def _sampler_key(N: int, opts: ChainOptions):
+    return (N, opts.mode, opts.subset_size, opts.num_chains, opts.L0, opts.every, opts.samples)
+
+
 class LogZ(torch.autograd.Function):
-    """log Z(Q) with the sampled gradient -beta E_pi[x x^T] (see module doc)."""
+    """log Z(Q) with the sampled gradient -beta E_pi[x x^T] (see module doc).
+
+    With ``opts.state`` a dict, the sampler context lives in it across calls:
+    the next forward only swaps in the new Q (``pns_set_q``: chains keep
+    their states, fields and energies are recomputed on the device), clears
+    the snapshots and runs ``burn_in + samples * every`` more steps -- a warm
+    start with no host-side preparation.  ``release(state)`` frees it."""
 
     @staticmethod
     def forward(ctx, Q: torch.Tensor, beta: float, opts: ChainOptions):
@@ -60,21 +70,26 @@ class LogZ(torch.autograd.Function):
         Qd = Q.detach()
         Qs = ((Qd + Qd.T) * 0.5).to(torch.float32).contiguous()
         stream = torch.cuda.current_stream()
-        x0 = None
-        init = "random"
-        if opts.state is not None and "x" in opts.state:
-            x0 = opts.state["x"]
-        s = binding.Sampler(Qs, beta, opts.subset_size, opts.mode, num_chains=opts.num_chains, L0=opts.L0,
-                            seed=opts.seed, init=init, x0=x0, launch="persistent", stream=stream,
-                            snapshot_every=opts.every, snapshot_capacity=opts.samples)
+        st = opts.state
+        key = _sampler_key(N, opts)
+        s = st.get("sampler") if st is not None else None
+        if s is not None and st.get("key") == key and st.get("beta") == float(beta):
+            s.set_q(Qs)
+            s.snapshots_clear()
+        else:
+            if s is not None:
+                s.close()
+            s = binding.Sampler(Qs, beta, opts.subset_size, opts.mode, num_chains=opts.num_chains, L0=opts.L0,
+                                seed=opts.seed, init="random", launch="persistent", stream=stream,
+                                snapshot_every=opts.every, snapshot_capacity=opts.samples)
+            if st is not None:
+                st.update(sampler=s, key=key, beta=float(beta))
         s.run(opts.burn_in + opts.samples * opts.every)
-        if opts.state is not None:
-            opts.state["x"] = s.read_current()["x"]
-            opts.state["seed_step"] = opts.state.get("seed_step", 0) + 1
         value = float("nan")
         if N <= opts.exact_max:
             value = binding.pns_log_partition(Qs, beta, stream=stream)
         ctx.sampler = s
+        ctx.owned = st is None
         ctx.beta = float(beta)
         ctx.N = N
         ctx.qdtype = Q.dtype
@@ -85,13 +100,22 @@ class LogZ(torch.autograd.Function):
         s = ctx.sampler
         dev = grad_out.device
         G = torch.empty((ctx.N, ctx.N), dtype=torch.float64, device=dev)
-        sm = binding.pns_snapshot_moments(s.ctx, 0, G)
-        s.close()
-        ctx.sampler = None
-        if sm <= 0:
-            raise RuntimeError("no snapshot carries weight: run more steps")
+        sm = torch.empty(1, dtype=torch.float64, device=dev)
+        # queued on the sampler's stream (the current stream): no host wait
+        binding.pns_snapshot_moments(s.ctx, 0, G, sum_m=sm)
         grad = (G * (-ctx.beta / sm)).to(ctx.qdtype)
+        if ctx.owned:
+            s.close()
+        ctx.sampler = None
         return grad_out * grad, None, None
+
+
+def release(state: Optional[dict]) -> None:
+    """Free the sampler a LogZ state dict keeps."""
+    if state and state.get("sampler") is not None:
+        state["sampler"].close()
+        state["sampler"] = None
+        state["key"] = None
 
 
 def log_z(Q: torch.Tensor, beta: float, opts: Optional[ChainOptions] = None) -> torch.Tensor:
@@ -108,9 +132,11 @@ def moments_of_samples(Q_true: torch.Tensor, beta: float, opts: ChainOptions):
                         snapshot_every=opts.every, snapshot_capacity=opts.samples)
     s.run(opts.burn_in + opts.samples * opts.every)
     G = torch.empty((N, N), dtype=torch.float64, device=Q_true.device)
-    sm = binding.pns_snapshot_moments(s.ctx, 0, G)
+    sm = torch.empty(1, dtype=torch.float64, device=Q_true.device)
+    binding.pns_snapshot_moments(s.ctx, 0, G, sum_m=sm)
+    out = G / sm
     s.close()
-    return G / sm, opts.num_chains * opts.samples
+    return out, opts.num_chains * opts.samples
 
 
 @dataclass
@@ -132,19 +158,23 @@ def fit_qubo(data_moments: torch.Tensor, beta: float, iters: int, lr: float, opt
     vel = torch.zeros_like(Q)
     res = FitResult(Q=Q)
     state = opts.state if opts.state is not None else {}
-    for it in range(iters):
-        o = ChainOptions(**{**opts.__dict__, "seed": opts.seed + 7919 * (it + 1), "state": state})
-        lz = LogZ.apply(Q, beta, o)
-        loss = beta * (Q * D).sum() + lz
-        if Q.grad is not None:
-            Q.grad = None
-        loss.backward()
-        with torch.no_grad():
-            g = Q.grad
-            res.moment_gap.append(float((g.abs().max() / beta).item()))
-            res.loss.append(float(loss.item()) if not math.isnan(float(lz.item())) else float("nan"))
-            vel.mul_(momentum).add_(g)
-            Q.sub_(lr * vel)
-            Q.copy_((Q + Q.T) * 0.5)
+    o = ChainOptions(**{**opts.__dict__, "state": state})
+    try:
+        for it in range(iters):
+            lz = LogZ.apply(Q, beta, o)
+            loss = beta * (Q * D).sum() + lz
+            if Q.grad is not None:
+                Q.grad = None
+            loss.backward()
+            with torch.no_grad():
+                g = Q.grad
+                res.moment_gap.append(float((g.abs().max() / beta).item()))
+                res.loss.append(float(loss.item()) if not math.isnan(float(lz.item())) else float("nan"))
+                vel.mul_(momentum).add_(g)
+                Q.sub_(lr * vel)
+                Q.copy_((Q + Q.T) * 0.5)
+    finally:
+        if opts.state is None:
+            release(state)
     res.Q = Q.detach()
     return res

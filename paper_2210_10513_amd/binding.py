@@ -39,7 +39,7 @@ EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_cu
            "pns_read_log", "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync",
            "pns_destroy", "pns_tile", "pns_last_error", "pns_version", "pns_create_batch", "pns_autotune",
            "pns_chain_offsets", "pns_num_problems", "pns_problem_info_get", "pns_moments", "pns_snapshot_moments",
-           "pns_log_partition"]
+           "pns_log_partition", "pns_set_q", "pns_snapshots_clear"]
 
 
 class pns_opts(ctypes.Structure):
@@ -119,13 +119,16 @@ def _load() -> ctypes.CDLL:
     L.pns_chain_offsets.argtypes = [vp, vp]
     L.pns_num_problems.argtypes = [vp]
     L.pns_problem_info_get.argtypes = [vp, i32, ctypes.POINTER(pns_problem_info)]
-    L.pns_moments.argtypes = [vp, i64, vp, i64, i32, vp, ctypes.POINTER(dbl), vp]
-    L.pns_snapshot_moments.argtypes = [vp, i32, vp, ctypes.POINTER(dbl)]
+    L.pns_moments.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
+    L.pns_snapshot_moments.argtypes = [vp, i32, vp, vp]
     L.pns_log_partition.argtypes = [vp, i32, i32, i32, dbl, vp, vp]
+    L.pns_set_q.argtypes = [vp, i32, vp]
+    L.pns_snapshots_clear.argtypes = [vp]
     for name in ("pns_create", "pns_run", "pns_read", "pns_read_current", "pns_field_type", "pns_read_log",
                  "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync", "pns_destroy",
                  "pns_tile", "pns_create_batch", "pns_autotune", "pns_chain_offsets", "pns_num_problems",
-                 "pns_problem_info_get", "pns_moments", "pns_snapshot_moments", "pns_log_partition"):
+                 "pns_problem_info_get", "pns_moments", "pns_snapshot_moments", "pns_log_partition", "pns_set_q",
+                 "pns_snapshots_clear"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -262,21 +265,30 @@ def _stream_handle(stream) -> Optional[int]:
     return stream if isinstance(stream, int) else stream.cuda_stream
 
 
-def pns_moments(X, m, G, *, N: Optional[int] = None, ldx: Optional[int] = None, stream=None) -> float:
-    """G[:] = X^T diag(m) X; returns sum(m).  X [K, ldx] uint8, m [K] int64,
-    G [N, N] float64 (numpy arrays or torch tensors, host or device)."""
+def pns_moments(X, m, G, *, N: Optional[int] = None, ldx: Optional[int] = None, stream=None, sum_m=None):
+    """G[:] = X^T diag(m) X.  X [K, ldx] uint8, m [K] int64, G [N, N]
+    float64 (numpy arrays or torch tensors, host or device).  Returns sum(m)
+    as a float, or writes it into ``sum_m`` (a one-element float64 array or
+    tensor, host or device) and returns None."""
     K = int(X.shape[0])
     ld = int(X.shape[1]) if ldx is None else ldx
     n = int(G.shape[0]) if N is None else N
-    sm = ctypes.c_double()
-    _check(lib.pns_moments(_addr(X), ld, _addr(m), K, n, _addr(G), ctypes.byref(sm), _stream_handle(stream)))
-    return sm.value
+    if sum_m is not None:
+        _check(lib.pns_moments(_addr(X), ld, _addr(m), K, n, _addr(G), _addr(sum_m), _stream_handle(stream)))
+        return None
+    sm = np.zeros(1, np.float64)
+    _check(lib.pns_moments(_addr(X), ld, _addr(m), K, n, _addr(G), sm.ctypes.data, _stream_handle(stream)))
+    return float(sm[0])
 
 
-def pns_snapshot_moments(ctx, problem: int, G) -> float:
-    sm = ctypes.c_double()
-    _check(lib.pns_snapshot_moments(ctx, problem, _addr(G), ctypes.byref(sm)))
-    return sm.value
+def pns_snapshot_moments(ctx, problem: int, G, sum_m=None):
+    """Moments of the snapshots of one problem; like pns_moments."""
+    if sum_m is not None:
+        _check(lib.pns_snapshot_moments(ctx, problem, _addr(G), _addr(sum_m)))
+        return None
+    sm = np.zeros(1, np.float64)
+    _check(lib.pns_snapshot_moments(ctx, problem, _addr(G), sm.ctypes.data))
+    return float(sm[0])
 
 
 def pns_log_partition(Q, beta: float, *, layout: int = PNS_SYMMETRIC, stream=None) -> float:
@@ -292,6 +304,14 @@ def pns_log_partition(Q, beta: float, *, layout: int = PNS_SYMMETRIC, stream=Non
     _check(lib.pns_log_partition(_addr(Qk), int(Qk.shape[0]), dt, layout, float(beta), out.ctypes.data,
                                  _stream_handle(stream)))
     return float(out[0])
+
+
+def pns_set_q(ctx, problem: int, Q) -> None:
+    _check(lib.pns_set_q(ctx, problem, _addr(Q)))
+
+
+def pns_snapshots_clear(ctx) -> None:
+    _check(lib.pns_snapshots_clear(ctx))
 
 
 def pns_last_error() -> str:
@@ -416,6 +436,21 @@ class Sampler:
     def stats(self):
         arr = pns_stats(self.ctx, self.num_chains)
         return {k: np.array([getattr(s, k) for s in arr]) for k in ("steps", "flips", "stays", "saturated", "sum_M", "anomalies")}
+
+    def set_q(self, Q) -> "Sampler":
+        """New coefficient matrix (same N, dtype, layout); chains keep their
+        states (warm start)."""
+        if hasattr(Q, "data_ptr"):
+            Qk = Q.contiguous()
+        else:
+            Qk = np.ascontiguousarray(Q)
+        pns_set_q(self.ctx, 0, Qk)
+        self._Q = Qk
+        return self
+
+    def snapshots_clear(self) -> "Sampler":
+        pns_snapshots_clear(self.ctx)
+        return self
 
     def snapshot_moments(self, G=None):
         """(G, sum_m): G = X^T diag(m) X over every stored snapshot."""

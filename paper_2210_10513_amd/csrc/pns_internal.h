@@ -110,6 +110,12 @@ bool have_tile(int32_t qtype, int32_t htype, int32_t block, int32_t groups);
 hipError_t launch_init_with_map(int32_t qtype, int32_t htype, int32_t max_pitch, hipStream_t stream,
                                 const InitArgs& args, const int32_t* host_chain_problem);
 
+// A, diag of a coefficient matrix on the device (one workgroup per row) and
+// the checks of its entries: flags [4] (asymmetry, non-finite, max row sum
+// of |A| and max |diag| as FP64 bits), accumulated with atomics.
+hipError_t launch_prepare_rows(int32_t qtype, const void* Q, int32_t N, int32_t layout, int64_t pitch, void* A,
+                               void* diag, unsigned long long* flags, hipStream_t st);
+
 // Fill `count` 64-bit words with a value (graph-safe alternative to memset).
 hipError_t launch_fill64(void* p, int64_t count, int64_t value, hipStream_t stream);
 
@@ -121,10 +127,18 @@ namespace pns {
 // Weight pieces (3 x kpad bf16), exact sum and max of the weights.
 hipError_t launch_moments_prep(const int64_t* m, int64_t K, int64_t kpad, uint16_t* pieces, unsigned long long* sum_m,
                                unsigned long long* max_m, hipStream_t st);
-// G += X^T diag(m) X over records [0, K), chunks of `chunk` records
-// (multiple of 64) accumulated in FP32, added into FP64 G [N][N].
-hipError_t launch_moments(int32_t pieces_used, const uint8_t* X, int64_t ldx, int64_t K, int32_t N,
-                          const uint16_t* pieces, int64_t kpad, int64_t chunk, double* G, hipStream_t st);
+// Records X [K][ldx] bytes -> column-packed bits Xb [words][npad] u32,
+// words = ceil(K / 32), npad = N rounded up to 64.
+hipError_t launch_pack_bits(const uint8_t* X, int64_t ldx, int64_t K, int32_t N, int32_t npad, int64_t words,
+                            uint32_t* Xb, hipStream_t st);
+// G += X^T diag(m) X from packed records: one wave per (64 x 64 tile of the
+// upper triangle, chunk of chunk_words words), partial tiles in `part`
+// [chunks][tiles][64][64] FP32, then an FP64 reduction into G.
+hipError_t launch_moments(const uint32_t* Xb, int32_t npad, int64_t words, int32_t N, const uint16_t* pieces,
+                          int64_t kpad, int64_t chunk_words, const unsigned long long* max_m, float* part, double* G,
+                          hipStream_t st);
+// *out = (double)*sum_m on the device.
+hipError_t launch_moments_sum(const unsigned long long* sum_m, double* out, hipStream_t st);
 // log Z by enumeration: `blocks` x 256 threads, thread t covers the states
 // with high bits t and all 2^lowbits low bits; part_* hold `blocks` pairs.
 hipError_t launch_logz(int32_t qtype, const void* Q, int32_t N, int32_t layout, double beta, double* part_max,

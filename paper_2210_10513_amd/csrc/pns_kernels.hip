@@ -266,6 +266,54 @@ __global__ __launch_bounds__(256) void init_energy_kernel(InitArgs a)
     }
 }
 
+// Row i of a new coefficient matrix: A (zero diagonal, pitch-padded) and
+// the diagonal; flags[0] |= asymmetry (SYMMETRIC layout), flags[1] |= a
+// non-finite entry, flags[2] = max over rows of sum_j |A_ij|, flags[3] =
+// max |Q_ii| (both as FP64 bits; non-negative doubles order like integers).
+template <typename QT>
+__global__ __launch_bounds__(256) void prepare_row_kernel(const QT* __restrict__ Q, int32_t N, int32_t layout,
+                                                          int64_t pitch, QT* __restrict__ A,
+                                                          typename Wide<QT>::T* __restrict__ diag,
+                                                          unsigned long long* flags)
+{
+    const int i = blockIdx.x;
+    __shared__ double ssum[256];
+    double rs = 0.0;
+    unsigned long long asym = 0, nonfin = 0;
+    for (int64_t j = threadIdx.x; j < pitch; j += blockDim.x) {
+        QT v = (QT)0;
+        if (j < N) {
+            const QT q = Q[(int64_t)i * N + j];
+            if constexpr (std::is_floating_point<QT>::value) nonfin |= !isfinite(q);
+            if (j == i) {
+                diag[i] = (typename Wide<QT>::T)q;
+                const double dq = fabs((double)q);
+                atomicMax(&flags[3], (unsigned long long)__double_as_longlong(dq));
+            } else if (layout == 0) {
+                v = q;
+                asym |= !(q == Q[j * N + i]);
+            } else {
+                v = i < j ? q : Q[j * N + i];
+            }
+        }
+        A[(int64_t)i * pitch + j] = v;
+        rs += fabs((double)v);
+    }
+    if (threadIdx.x == 0 && i == 0) {
+        // padding entries of the diagonal
+        for (int64_t j = N; j < pitch; ++j) diag[j] = (typename Wide<QT>::T)0;
+    }
+    if (asym) atomicOr(&flags[0], 1ull);
+    if (nonfin) atomicOr(&flags[1], 1ull);
+    ssum[threadIdx.x] = rs;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) ssum[threadIdx.x] += ssum[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(&flags[2], (unsigned long long)__double_as_longlong(ssum[0]));
+}
+
 __global__ void fill64_kernel(int64_t* p, int64_t count, int64_t value)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -329,6 +377,21 @@ hipError_t launch_init_with_map(int32_t qtype, int32_t htype, int32_t max_pitch,
     if (qtype == Q_I32 && htype == H_I64) return init_typed<int32_t, int64_t>(max_pitch, stream, args, host_chain_problem);
     if (qtype == Q_F32 && htype == H_F64) return init_typed<float, double>(max_pitch, stream, args, host_chain_problem);
     return hipErrorInvalidConfiguration;
+}
+
+hipError_t launch_prepare_rows(int32_t qtype, const void* Q, int32_t N, int32_t layout, int64_t pitch, void* A,
+                               void* diag, unsigned long long* flags, hipStream_t st)
+{
+    if (qtype == Q_I16)
+        hipLaunchKernelGGL(prepare_row_kernel<int16_t>, dim3(N), dim3(256), 0, st, reinterpret_cast<const int16_t*>(Q), N,
+                           layout, pitch, reinterpret_cast<int16_t*>(A), reinterpret_cast<int32_t*>(diag), flags);
+    else if (qtype == Q_I32)
+        hipLaunchKernelGGL(prepare_row_kernel<int32_t>, dim3(N), dim3(256), 0, st, reinterpret_cast<const int32_t*>(Q), N,
+                           layout, pitch, reinterpret_cast<int32_t*>(A), reinterpret_cast<int32_t*>(diag), flags);
+    else
+        hipLaunchKernelGGL(prepare_row_kernel<float>, dim3(N), dim3(256), 0, st, reinterpret_cast<const float*>(Q), N,
+                           layout, pitch, reinterpret_cast<float*>(A), reinterpret_cast<float*>(diag), flags);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill64(void* p, int64_t count, int64_t value, hipStream_t stream)

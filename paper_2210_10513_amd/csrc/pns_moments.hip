@@ -69,9 +69,7 @@ __global__ void moments_prep_kernel(const int64_t* m, int64_t K, int64_t kpad, u
     }
 }
 
-constexpr int kTile = 64;   // output tile (rows and columns) per workgroup
-constexpr int kKT = 64;     // records staged per LDS round (two MFMA k-steps)
-constexpr int kPadT = 8;    // bytes of padding per transposed LDS row
+constexpr int kTile = 64;  // output tile (rows and columns) per wave
 
 // Upper-triangle tile t (row-major over ti <= tj) -> (ti, tj).
 __device__ __forceinline__ void upper_tile(int t, int nt, int* ti, int* tj)
@@ -85,129 +83,175 @@ __device__ __forceinline__ void upper_tile(int t, int nt, int* ti, int* tj)
     *tj = r + rem;
 }
 
-// One workgroup (4 waves) computes the 64 x 64 tile (ti, tj) of G over the
-// records [k0, k0 + chunk); wave w owns the 32 x 32 quarter (w >> 1, w & 1)
-// as 2 x 2 MFMA tiles of 16 x 16.
-//
-// MFMA operands (v_mfma_f32_16x16x32_bf16): lane l supplies row (A) or
-// column (B) l % 16 and eight values of the contraction index; A and B use
-// the same assignment of (lane / 16, element) to records, so the record order
-// inside the 32-wide step does not matter.  Lane l receives C rows
-// 4 * (l / 16) + e, column l % 16.
-template <int P>
-__global__ __launch_bounds__(256) void moments_kernel(const uint8_t* __restrict__ X, int64_t ldx, int64_t K, int32_t N,
-                                                      const uint16_t* __restrict__ pieces, int64_t kpad, int64_t chunk,
-                                                      double* __restrict__ G)
+// Records packed column by column: word (w, i) holds bit r = X[32 w + r][i]
+// (zero past K), so the eight records a lane feeds to one MFMA step are one
+// byte of one word.  One thread per (column, word).
+__global__ void pack_bits_kernel(const uint8_t* __restrict__ X, int64_t ldx, int64_t K, int32_t N, int32_t npad,
+                                 int64_t words, uint32_t* __restrict__ Xb)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t xi[kTile][kKT + kPadT];
-    __shared__ __attribute__((aligned(16))) uint8_t xj[kTile][kKT + kPadT];
-    __shared__ __attribute__((aligned(16))) uint16_t pw[P][kKT];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = t / npad;
+    const int32_t i = (int32_t)(t % npad);
+    if (w >= words) return;
+    uint32_t v = 0;
+    if (i < N) {
+        const int64_t k0 = w * 32;
+        const int rmax = K - k0 < 32 ? (int)(K - k0) : 32;
+        for (int r = 0; r < rmax; ++r) v |= (uint32_t)(X[(k0 + r) * ldx + i] != 0) << r;
+    }
+    Xb[w * npad + i] = v;
+}
 
+// 0xFFFF per set bit of a 2-bit field, in the matching half word.
+__device__ __forceinline__ uint32_t half_mask(uint32_t two_bits)
+{
+    return ((two_bits & 1u) ? 0x0000FFFFu : 0u) | ((two_bits & 2u) ? 0xFFFF0000u : 0u);
+}
+
+// One wave computes one 64 x 64 tile (ti, tj) of G over the records
+// [32 w0, 32 w1) as 4 x 4 MFMA tiles of 16 x 16 (v_mfma_f32_16x16x32_bf16).
+// Lane l supplies row (A) or column (B) l % 16 of each 16-block and the eight
+// records 8 (l / 16) .. + 7 of the 32-record step (the same assignment for A
+// and B, so their order inside the step does not matter); lane l receives C
+// rows 4 (l / 16) + e, column l % 16.  A = diag(piece_s(m)) x, B = x.
+// FP32 accumulation stays exact while flush * max(m) < 2^24: past that many
+// records the accumulators are added into G with FP64 atomics; the final
+// accumulators go to this wave's slot of `part` (FP32, exact integers).
+__global__ __launch_bounds__(256) void moments_kernel(const uint32_t* __restrict__ Xb, int32_t npad, int64_t words,
+                                                      int32_t N, const uint16_t* __restrict__ pieces, int64_t kpad,
+                                                      int64_t chunk_words, int32_t tiles,
+                                                      const unsigned long long* __restrict__ max_m,
+                                                      float* __restrict__ part, double* __restrict__ G)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t chunks = (words + chunk_words - 1) / chunk_words;
+    if (gw >= (int64_t)tiles * chunks) return;
+    const int t = (int)(gw % tiles);
+    const int64_t c = gw / tiles;
     const int nt = (N + kTile - 1) / kTile;
     int ti, tj;
-    upper_tile((int)blockIdx.x, nt, &ti, &tj);
+    upper_tile(t, nt, &ti, &tj);
     const int i0 = ti * kTile, j0 = tj * kTile;
-    const int64_t kbeg = (int64_t)blockIdx.y * chunk;
-    const int64_t kend = kbeg + chunk < K ? kbeg + chunk : K;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int64_t w0 = c * chunk_words;
+    const int64_t w1 = w0 + chunk_words < words ? w0 + chunk_words : words;
+    const unsigned long long mm = *max_m;
+    int64_t flush_words = w1 - w0;
+    if (mm > 0) {
+        const double lim = (double)(1 << 24) / ((double)mm * 1.01) / 32.0;
+        if (lim < (double)flush_words) flush_words = lim < 2.0 ? 2 : (int64_t)lim;
+    }
     const int l16 = lane & 15, lg = lane >> 4;
 
-    f32x4 acc[2][2];
+    f32x4 acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t k0 = kbeg; k0 < kend; k0 += kKT) {
-        __syncthreads();
-        // stage records [k0, k0 + 64) of the two column ranges, transposed:
-        // thread t loads column t % 64 of rows t / 64 + 4e (coalesced rows)
-        {
-            const int c = tid & 63;
-            const int rbase = tid >> 6;
-#pragma unroll 4
-            for (int e = 0; e < kKT / 4; ++e) {
-                const int r = rbase + 4 * e;
-                const int64_t k = k0 + r;
-                uint8_t bi = 0, bj = 0;
-                if (k < kend) {
-                    const uint8_t* row = X + k * ldx;
-                    if (i0 + c < N) bi = row[i0 + c] != 0;
-                    if (j0 + c < N) bj = row[j0 + c] != 0;
-                }
-                xi[c][r] = bi;
-                xj[c][r] = bj;
-            }
-            if (tid < kKT) {
-                const int64_t k = k0 + tid;
+    auto flush_atomic = [&]() {
 #pragma unroll
-                for (int s = 0; s < P; ++s) pw[s][tid] = k < kend ? pieces[s * kpad + k] : (uint16_t)0;
-            }
-        }
-        __syncthreads();
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int ks = 0; ks < kKT; ks += 32) {
-            const int kk = ks + lg * 8;  // this lane's eight records in the step
-            // B operands: x of the wave's two 16-column blocks
-            bf16x8 bop[2];
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const uint8_t* src = &xj[wc + b * 16 + l16][kk];
-                const uint2 raw = *reinterpret_cast<const uint2*>(src);
-                uint16_t v[8];
+            for (int b = 0; b < 4; ++b) {
+                const int j = j0 + b * 16 + l16;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    v[e] = (uint16_t)(((raw.x >> (8 * e)) & 1u) * 0x3F80u);
-                    v[4 + e] = (uint16_t)(((raw.y >> (8 * e)) & 1u) * 0x3F80u);
-                }
-                bop[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(v));
-            }
-#pragma unroll
-            for (int s = 0; s < P; ++s) {
-                uint16_t wv[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) wv[e] = pw[s][kk + e];
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    const uint8_t* src = &xi[wr + a * 16 + l16][kk];
-                    const uint2 raw = *reinterpret_cast<const uint2*>(src);
-                    uint16_t v[8];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        v[e] = ((raw.x >> (8 * e)) & 1u) ? wv[e] : (uint16_t)0;
-                        v[4 + e] = ((raw.y >> (8 * e)) & 1u) ? wv[4 + e] : (uint16_t)0;
+                    const int i = i0 + a * 16 + lg * 4 + e;
+                    const double v = (double)acc[a][b][e];
+                    if (i < N && j < N && v != 0.0) {
+                        atomicAdd(&G[(int64_t)i * N + j], v);
+                        if (ti != tj) atomicAdd(&G[(int64_t)j * N + i], v);
                     }
-                    const bf16x8 aop = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(v));
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[b], acc[a][b], 0, 0, 0);
                 }
+                acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
             }
-        }
-    }
+    };
 
-    // chunk result into FP64 G; an off-diagonal tile also feeds its mirror
+    const int sh = lg * 8;
+    int64_t since = 0;
+    for (int64_t w = w0; w < w1; ++w) {
+        const uint32_t* row = Xb + w * npad;
+        uint32_t ba[4], bb[4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+        for (int a = 0; a < 4; ++a) ba[a] = (row[i0 + a * 16 + l16] >> sh) & 0xFFu;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int j = j0 + wc + b * 16 + l16;
+        for (int b = 0; b < 4; ++b) bb[b] = (row[j0 + b * 16 + l16] >> sh) & 0xFFu;
+        // weights of this lane's eight records, as four pairs per piece
+        const int64_t kb = w * 32 + sh;
+        uint4 wp[3];
+        bool use[3];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int i = i0 + wr + a * 16 + lg * 4 + e;
-                const double v = (double)acc[a][b][e];
-                if (i < N && j < N && v != 0.0) {
-                    atomicAdd(&G[(int64_t)i * N + j], v);
-                    if (ti != tj) atomicAdd(&G[(int64_t)j * N + i], v);
-                }
+        for (int s = 0; s < 3; ++s) {
+            wp[s] = *reinterpret_cast<const uint4*>(pieces + s * kpad + kb);
+            const uint32_t any = (wp[s].x | wp[s].y | wp[s].z | wp[s].w) & 0x7FFF7FFFu;
+            use[s] = s == 0 || __ballot(any != 0) != 0;
+        }
+        bf16x8 bop[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            uint4 v;
+            v.x = half_mask(bb[b]) & 0x3F803F80u;
+            v.y = half_mask(bb[b] >> 2) & 0x3F803F80u;
+            v.z = half_mask(bb[b] >> 4) & 0x3F803F80u;
+            v.w = half_mask(bb[b] >> 6) & 0x3F803F80u;
+            bop[b] = __builtin_bit_cast(bf16x8, v);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const uint32_t m0 = half_mask(ba[a]), m1 = half_mask(ba[a] >> 2), m2 = half_mask(ba[a] >> 4),
+                           m3 = half_mask(ba[a] >> 6);
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                if (!use[s]) continue;
+                uint4 v;
+                v.x = m0 & wp[s].x;
+                v.y = m1 & wp[s].y;
+                v.z = m2 & wp[s].z;
+                v.w = m3 & wp[s].w;
+                const bf16x8 aop = __builtin_bit_cast(bf16x8, v);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[b], acc[a][b], 0, 0, 0);
             }
         }
+        if (++since >= flush_words && w + 1 < w1) {
+            flush_atomic();
+            since = 0;
+        }
     }
+    // this wave's partial tile: part[c][t][64][64]
+    float* dst = part + (c * tiles + t) * (int64_t)(kTile * kTile);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dst[(a * 16 + lg * 4 + e) * kTile + b * 16 + l16] = acc[a][b][e];
 }
+
+// G[i][j] += sum over chunks of the partial tiles (FP64; the partials are
+// exact integers), both triangles.  One thread per element of G.
+__global__ void moments_reduce_kernel(const float* __restrict__ part, int64_t chunks, int32_t tiles, int32_t N,
+                                      double* __restrict__ G)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * N) return;
+    const int i = (int)(e / N), j = (int)(e % N);
+    const int a = i < j ? i : j, b = i < j ? j : i;  // upper-triangle element (a, b)
+    const int nt = (N + kTile - 1) / kTile;
+    const int ti = a / kTile, tj = b / kTile;
+    const int t = ti * nt - ti * (ti - 1) / 2 + (tj - ti);
+    const int r = a - ti * kTile, q = b - tj * kTile;
+    const int64_t off = (int64_t)t * kTile * kTile + (ti == tj ? (i - ti * kTile) * kTile + (j - tj * kTile)
+                                                                 : r * kTile + q);
+    double s = 0.0;
+    for (int64_t c = 0; c < chunks; ++c) s += (double)part[c * tiles * (int64_t)(kTile * kTile) + off];
+    G[e] += s;
+}
+
+// sum of the weights as FP64 into a device word.
+__global__ void moments_sum_kernel(const unsigned long long* sum_m, double* out) { *out = (double)*sum_m; }
 
 // ---- log Z by enumeration ----
 
@@ -345,16 +389,36 @@ hipError_t launch_moments_prep(const int64_t* m, int64_t K, int64_t kpad, uint16
     return hipGetLastError();
 }
 
-hipError_t launch_moments(int32_t pieces_used, const uint8_t* X, int64_t ldx, int64_t K, int32_t N,
-                          const uint16_t* pieces, int64_t kpad, int64_t chunk, double* G, hipStream_t st)
+hipError_t launch_pack_bits(const uint8_t* X, int64_t ldx, int64_t K, int32_t N, int32_t npad, int64_t words,
+                            uint32_t* Xb, hipStream_t st)
+{
+    const int64_t n = words * npad;
+    hipLaunchKernelGGL(pack_bits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, ldx, K, N, npad, words,
+                       Xb);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const uint32_t* Xb, int32_t npad, int64_t words, int32_t N, const uint16_t* pieces,
+                          int64_t kpad, int64_t chunk_words, const unsigned long long* max_m, float* part, double* G,
+                          hipStream_t st)
 {
     const int nt = (N + kTile - 1) / kTile;
-    const unsigned tiles = (unsigned)(nt * (nt + 1) / 2);
-    const unsigned chunks = (unsigned)((K + chunk - 1) / chunk);
-    const dim3 grid(tiles, chunks);
-    if (pieces_used == 1) hipLaunchKernelGGL(moments_kernel<1>, grid, dim3(256), 0, st, X, ldx, K, N, pieces, kpad, chunk, G);
-    else if (pieces_used == 2) hipLaunchKernelGGL(moments_kernel<2>, grid, dim3(256), 0, st, X, ldx, K, N, pieces, kpad, chunk, G);
-    else hipLaunchKernelGGL(moments_kernel<3>, grid, dim3(256), 0, st, X, ldx, K, N, pieces, kpad, chunk, G);
+    const int32_t tiles = nt * (nt + 1) / 2;
+    const int64_t chunks = (words + chunk_words - 1) / chunk_words;
+    const int64_t waves = (int64_t)tiles * chunks;
+    hipLaunchKernelGGL(moments_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, Xb, npad, words, N, pieces,
+                       kpad, chunk_words, tiles, max_m, part, G);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)N * N;
+    hipLaunchKernelGGL(moments_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, chunks, tiles,
+                       N, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_sum(const unsigned long long* sum_m, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(moments_sum_kernel, dim3(1), dim3(1), 0, st, sum_m, out);
     return hipGetLastError();
 }
 

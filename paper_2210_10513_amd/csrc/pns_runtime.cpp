@@ -306,6 +306,8 @@ struct ProblemRun {
     Tile tile;
     void* A = nullptr;
     void* diag = nullptr;
+    void* A2 = nullptr;     // staging copies for pns_set_q (allocated on first use)
+    void* diag2 = nullptr;
 };
 
 // Chains that share a tile shape and kernel flavour: one step-kernel launch.
@@ -468,8 +470,9 @@ struct pns_ctx {
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         for (auto& P : probs) {
-            if (P.A) (void)hipFree(P.A);
-            if (P.diag) (void)hipFree(P.diag);
+            void* ps[] = {P.A, P.diag, P.A2, P.diag2};
+            for (void* q : ps)
+                if (q) (void)hipFree(q);
         }
         for (auto& k : classes)
             if (k.d_list) (void)hipFree(k.d_list);
@@ -714,7 +717,7 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         ALLOC(ctx->snap_x, uint8_t, (size_t)C * o.snapshot_capacity * ctx->max_pitch);
         ALLOC(ctx->snap_M, int64_t, (size_t)C * o.snapshot_capacity);
         ALLOC(ctx->snap_E, int64_t, (size_t)C * o.snapshot_capacity);
-        ALLOC(ctx->snap_count, int32_t, C);
+        ALLOC(ctx->snap_count, int32_t, (C + 1) / 2 * 2);  // whole 64-bit words (cleared as such)
     }
     for (auto& k : ctx->classes) ALLOC(k.d_list, int32_t, k.chains.size());
 #undef ALLOC
@@ -1453,48 +1456,57 @@ int pns_destroy(pns_ctx* ctx)
 
 namespace {
 
-// G (N x N, FP64, zeroed here) += X^T diag(m) X on `st`; device pointers.
-// Returns the exact sum of the weights in *sum_out.
+// G (N x N, FP64, overwritten) = X^T diag(m) X, queued on `st` without a
+// host synchronisation; device pointers.  The exact sum of the weights goes
+// to *sum_host (synchronising) and/or *sum_dev (queued), either may be NULL.
+// Workspace comes from the stream-ordered allocator and is released in
+// stream order.
 int moments_device(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int32_t N, double* G, hipStream_t st,
-                   double* sum_out)
+                   double* sum_host, double* sum_dev)
 {
     const int64_t kpad = std::max<int64_t>(64, round_up(K, 64));
+    const int32_t npad = (int32_t)round_up(N, 64);
+    const int64_t words = std::max<int64_t>(1, (K + 31) / 32);
+    const int nt = npad / 64;
+    const int64_t tiles = (int64_t)nt * (nt + 1) / 2;
+    // words per wave: at least 32 (1024 records), about 2048 waves in all
+    const int64_t chunk_words = std::max<int64_t>(32, (words * tiles + 2047) / 2048);
+    const int64_t chunks = (words + chunk_words - 1) / chunk_words;
     uint16_t* pieces = nullptr;
     unsigned long long* cnt = nullptr;
-    int rc = dev_alloc(&pieces, (size_t)3 * kpad);
-    if (!rc) rc = dev_alloc(&cnt, 2);
-    auto done = [&](int r) {
-        if (pieces) (void)hipFree(pieces);
-        if (cnt) (void)hipFree(cnt);
-        return r;
+    uint32_t* Xb = nullptr;
+    float* part = nullptr;
+    auto release = [&]() {
+        if (pieces) (void)hipFreeAsync(pieces, st);
+        if (cnt) (void)hipFreeAsync(cnt, st);
+        if (Xb) (void)hipFreeAsync(Xb, st);
+        if (part) (void)hipFreeAsync(part, st);
     };
-    if (rc) return done(rc);
-    hipError_t e = launch_fill64(G, (int64_t)N * N, 0, st);
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&pieces), (size_t)3 * kpad * sizeof(uint16_t), st);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&cnt), 2 * sizeof(unsigned long long), st);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&Xb), (size_t)words * npad * sizeof(uint32_t), st);
+    if (e == hipSuccess)
+        e = hipMallocAsync(reinterpret_cast<void**>(&part), (size_t)chunks * tiles * 64 * 64 * sizeof(float), st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        release();
+        return fail(PNS_ENOMEM, "workspace allocation failed: %s", hipGetErrorString(e));
+    }
+    e = launch_fill64(G, (int64_t)N * N, 0, st);
     if (e == hipSuccess) e = launch_fill64(cnt, 2, 0, st);
     if (e == hipSuccess) e = launch_moments_prep(m, K, kpad, pieces, cnt, cnt + 1, st);
-    unsigned long long hc[2] = {0, 0};
-    if (e == hipSuccess) e = hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return done(hip_fail(e, "moments preparation"));
-    const unsigned long long maxm = hc[1];
-    // pieces needed: m <= 256 is one bf16, m <= 65536 two, larger three
-    const int32_t P = maxm <= 256 ? 1 : (maxm <= 65536 ? 2 : 3);
-    // FP32 partial sums of integers stay exact below 2^24
-    int64_t chunk = 4096;
-    if (maxm > 0) chunk = std::min<int64_t>(chunk, (int64_t)((double)(1 << 24) / ((double)maxm * 1.01)) / 64 * 64);
-    chunk = std::max<int64_t>(64, chunk);
-    // enough workgroups to fill the device
-    const int nt = (N + 63) / 64;
-    const int64_t tiles = (int64_t)nt * (nt + 1) / 2;
-    while (chunk > 256 && tiles * ((K + chunk - 1) / chunk) < 2048) chunk /= 2;
-    chunk = std::max<int64_t>(64, chunk / 64 * 64);
-    if (K > 0 && (K + chunk - 1) / chunk > 65535) chunk = round_up((K + 65534) / 65535, 64);
-    if (K > 0) {
-        e = launch_moments(P, X, ldx, K, N, pieces, kpad, chunk, G, st);
-        if (e != hipSuccess) return done(hip_fail(e, "moments kernel"));
+    if (e == hipSuccess) e = launch_pack_bits(X, ldx, K, N, npad, words, Xb, st);
+    if (e == hipSuccess) e = launch_moments(Xb, npad, words, N, pieces, kpad, chunk_words, cnt + 1, part, G, st);
+    if (e == hipSuccess && sum_dev) e = launch_moments_sum(cnt, sum_dev, st);
+    unsigned long long hs = 0;
+    if (e == hipSuccess && sum_host) {
+        e = hipMemcpyAsync(&hs, cnt, sizeof(hs), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
-    if (sum_out) *sum_out = (double)hc[0];
-    return done(PNS_OK);
+    release();
+    if (e != hipSuccess) return hip_fail(e, "moments kernels");
+    if (sum_host) *sum_host = (double)hs;
+    return PNS_OK;
 }
 
 }  // namespace
@@ -1531,15 +1543,19 @@ int pns_moments(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int3
     if (rc) return done(rc);
     if (gd) dG = G;
     else if ((rc = dev_alloc(&dG, (size_t)N * N))) return done(rc);
-    double sm = 0.0;
-    rc = moments_device(dX, ldx, dm, K, N, dG, st, &sm);
+    const bool sd = sum_m && is_device_ptr(sum_m);
+    rc = moments_device(dX, ldx, dm, K, N, dG, st, sum_m && !sd ? sum_m : nullptr, sd ? sum_m : nullptr);
     if (rc) return done(rc);
     if (!gd) {
         hipError_t e = hipMemcpyAsync(G, dG, (size_t)N * N * 8, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return done(hip_fail(e, "download G"));
     }
-    if (sum_m) *sum_m = sm;
+    if (!xd || !md) {
+        // host inputs were staged in temporary device buffers
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return done(hip_fail(e, "moments"));
+    }
     return done(PNS_OK);
 }
 
@@ -1556,18 +1572,16 @@ int pns_snapshot_moments(pns_ctx* ctx, int32_t problem, double* G, double* sum_m
     double* dG = G;
     int rc = PNS_OK;
     if (!gd && (rc = dev_alloc(&dG, (size_t)R.N * R.N))) return rc;
-    double sm = 0.0;
+    const bool sd = sum_m && is_device_ptr(sum_m);
     rc = moments_device(ctx->snap_x + row0 * ctx->max_pitch, ctx->max_pitch, ctx->snap_M + row0, K, R.N, dG,
-                        ctx->stream, &sm);
+                        ctx->stream, sum_m && !sd ? sum_m : nullptr, sd ? sum_m : nullptr);
     if (!rc && !gd) {
         hipError_t e = hipMemcpyAsync(G, dG, (size_t)R.N * R.N * 8, hipMemcpyDeviceToHost, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) rc = hip_fail(e, "download G");
     }
     if (!gd) (void)hipFree(dG);
-    if (rc) return rc;
-    if (sum_m) *sum_m = sm;
-    return PNS_OK;
+    return rc;
 }
 
 int pns_log_partition(const void* Q, int32_t N, int32_t dtype, int32_t layout, double beta, double* out, void* stream)
@@ -1611,6 +1625,104 @@ int pns_log_partition(const void* Q, int32_t N, int32_t dtype, int32_t layout, d
         *out = v;
     }
     return done(PNS_OK);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int pns_set_q(pns_ctx* ctx, int32_t problem, const void* Q)
+{
+    g_error.clear();
+    if (!ctx || !Q) return fail(PNS_EINVAL, "NULL argument");
+    if (problem < 0 || problem >= (int32_t)ctx->probs.size()) return fail(PNS_EINVAL, "problem %d out of range", problem);
+    ProblemRun& R = ctx->probs[problem];
+    hipStream_t st = ctx->stream;
+    const size_t qb = qsize(ctx->qtype);
+    const size_t qbytes = (size_t)R.N * R.N * qb;
+    const size_t abytes = (size_t)R.N * R.pitch * qb;
+    const size_t dbytes = (size_t)R.pitch * 4;
+    int rc = PNS_OK;
+    if (!R.A2 && (rc = dev_alloc(reinterpret_cast<uint8_t**>(&R.A2), abytes))) return rc;
+    if (!R.diag2 && (rc = dev_alloc(reinterpret_cast<uint8_t**>(&R.diag2), dbytes))) return rc;
+    const void* dq = Q;
+    void* tmp = nullptr;
+    unsigned long long* flags = nullptr;
+    auto done = [&](int r) {
+        if (tmp) (void)hipFree(tmp);
+        if (flags) (void)hipFree(flags);
+        return r;
+    };
+    if (!is_device_ptr(Q)) {
+        if ((rc = dev_alloc(reinterpret_cast<uint8_t**>(&tmp), qbytes))) return done(rc);
+        HIP_TRY(hipMemcpyAsync(tmp, Q, qbytes, hipMemcpyHostToDevice, st), "upload Q");
+        dq = tmp;
+    }
+    if ((rc = dev_alloc(&flags, 4))) return done(rc);
+    hipError_t e = launch_fill64(flags, 4, 0, st);
+    if (e == hipSuccess) e = launch_prepare_rows(ctx->qtype, dq, R.N, R.layout, R.pitch, R.A2, R.diag2, flags, st);
+    unsigned long long hf[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return done(hip_fail(e, "prepare Q"));
+    if (hf[0]) return done(fail(PNS_EINVAL, "SYMMETRIC Q is not symmetric"));
+    if (hf[1]) return done(fail(PNS_EINVAL, "Q has a non-finite entry"));
+    double fb, db;
+    std::memcpy(&fb, &hf[2], 8);
+    std::memcpy(&db, &hf[3], 8);
+    const double eb = db + R.s * fb;
+    if (ctx->qtype != Q_F32) {
+        if (eb * (double)R.N > 9.0e18) return done(fail(PNS_EINVAL, "energy bound of Q overflows int64"));
+        if (ctx->htype == H_I32 && !(fb < 2147483647.0 && eb < 2147483647.0))
+            return done(fail(PNS_EUNSUPPORTED, "the new Q needs 64-bit fields; this context has 32-bit fields"));
+    }
+    std::swap(R.A, R.A2);
+    std::swap(R.diag, R.diag2);
+    Problem D{};
+    D.A = R.A;
+    D.diag = R.diag;
+    D.pitch = R.pitch;
+    D.num_sets = R.num_sets;
+    D.L0 = R.L0;
+    D.N = R.N;
+    D.n = R.n;
+    D.s = R.s;
+    D.qtype = ctx->qtype;
+    // the struct copy is staged through host memory the call keeps alive
+    // until the synchronisation below
+    HIP_TRY(hipMemcpyAsync(ctx->problems + problem, &D, sizeof(Problem), hipMemcpyHostToDevice, st), "upload problem");
+    // fields and energies of the problem's chains from their current states
+    InitArgs ia{};
+    const int32_t c0 = R.chain_begin;
+    ia.problems = ctx->problems;
+    ia.chain_problem = ctx->chain_problem + c0;
+    ia.foff = ctx->foff + c0;
+    ia.num_chains = R.chains;
+    ia.init = 2;
+    ia.seed = ctx->seed;
+    ia.chain_id = ctx->chain_id + c0;
+    ia.x = ctx->x;
+    ia.h = ctx->h;
+    ia.E = ctx->E + c0;
+    ia.last_E = ctx->last_E + c0;
+    e = launch_init_with_map(ctx->qtype, ctx->htype, (int32_t)R.pitch, st, ia, ctx->h_chain_problem.data() + c0);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return done(hip_fail(e, "recompute fields"));
+    return done(PNS_OK);
+}
+
+int pns_snapshots_clear(pns_ctx* ctx)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    if (!ctx->snap_x) return fail(PNS_EINVAL, "snapshots are off (snapshot_every = 0)");
+    const int64_t C = ctx->num_chains;
+    hipError_t e = launch_fill64(ctx->snap_M, C * ctx->snap_cap, 0, ctx->stream);
+    // counts are int32: clear them as 64-bit words, rounded up (the buffer
+    // holds whole 64-bit words)
+    if (e == hipSuccess) e = launch_fill64(ctx->snap_count, (C + 1) / 2, 0, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "clear snapshots");
+    return PNS_OK;
 }
 
 }  // extern "C"
