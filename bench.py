@@ -56,60 +56,49 @@ def _workload(name: str):
 
 def _bench_fit(args, wl):
     """Maximum-likelihood fit of a QUBO to 2^20 weighted samples of a seeded
-    ground truth: one bench step is one gradient iteration (sampler forward on
-    8192 chains, 64 burn-in + 16 snapshots x 4 steps, warm-started; backward
-    on the bf16 MFMA moment kernel; momentum update).  Also times the
-    backward kernel alone over the 131072 records of one iteration."""
+    ground truth (8192 chains, burn-in 8N steps, 128 snapshots 16 steps
+    apart).  One bench step is one gradient iteration of fit_qubo: the
+    warm-started sampler runs 8192 chains for 64 + 16 x 8 steps, the backward
+    pass runs the bf16 MFMA moment kernel on the 131072 snapshot records, and
+    the centered momentum update follows.  Also reported: the backward kernel
+    timed alone, and the quality of a 300-iteration fit (moment gap against
+    the sampling-noise floor of the true Q, relative parameter error)."""
     import torch
     from paper_2210_10513_amd import binding
-    from paper_2210_10513_amd.autograd import ChainOptions, LogZ, moments_of_samples
+    from paper_2210_10513_amd.autograd import ChainOptions, LogZ, fit_qubo, moments_of_samples, release
     dev = torch.device("cuda")
     N = wl["Q"].shape[0]
     beta = 1.0
     Qt = torch.tensor(wl["Q"], device=dev)
-    D, nsamp = moments_of_samples(Qt, beta, ChainOptions(num_chains=8192, burn_in=512, samples=128, every=4,
+    D, nsamp = moments_of_samples(Qt, beta, ChainOptions(num_chains=8192, burn_in=8 * N, samples=128, every=16,
                                                          seed=1))
-    D = D.float()
-    chains, burn, samples, every = 8192, 64, 16, 4
+    chains, burn, samples, every, lr = 8192, 64, 16, 8, 0.1
     state = {}
-    Q = torch.zeros((N, N), dtype=torch.float32, device=dev, requires_grad=True)
-    vel = torch.zeros_like(Q)
-    lr, mom = 0.5, 0.9
-    gaps = []
-
-    def one_iter(it):
-        o = ChainOptions(num_chains=chains, burn_in=burn, samples=samples, every=every, seed=100 + it, state=state,
-                         exact_max=0)
-        lz = LogZ.apply(Q, beta, o)
-        loss = beta * (Q * D).sum() + torch.nan_to_num(lz)
-        Q.grad = None
-        loss.backward()
-        with torch.no_grad():
-            vel.mul_(mom).add_(Q.grad)
-            Q.sub_(lr * vel)
-            Q.copy_((Q + Q.T) * 0.5)
-        return Q.grad
-
-    for it in range(args.warmup):
-        one_iter(it)
+    opts = ChainOptions(num_chains=chains, burn_in=burn, samples=samples, every=every, seed=3, state=state,
+                        exact_max=0)
+    res = fit_qubo(D, beta, max(1, args.warmup), lr, opts)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
-    for it in range(args.steps):
-        g = one_iter(args.warmup + it)
+    res = fit_qubo(D, beta, args.steps, lr, opts, Q0=res.Q)
     t1.record(stream)
     torch.cuda.synchronize()
     sec = t0.elapsed_time(t1) / 1000.0 / args.steps
-    gaps.append(float(g.abs().max()) / beta)
     steps_per_iter = burn + samples * every
     flips = chains * steps_per_iter  # Rejection-Free: every record is a flip
+    # fit quality over 300 iterations from zero, and the noise floor: the
+    # gap of the true Q's own sampled moments (long burn-in) to the data's
+    q = fit_qubo(D, beta, 300, lr, opts)
+    rel = float((q.Q - Qt).norm() / Qt.norm())
+    Qg = Qt.clone().requires_grad_(True)
+    LogZ.apply(Qg, beta, ChainOptions(num_chains=chains, burn_in=8 * N, samples=samples, every=every, seed=5,
+                                      exact_max=0)).backward()
+    floor = float((D.float() + Qg.grad / beta).abs().max())
 
     # backward kernel alone: the moments of one iteration's snapshots
-    s = binding.Sampler(Qt, beta, 0, "rf", num_chains=chains, seed=9, init="random", stream=stream,
-                        snapshot_every=every, snapshot_capacity=samples)
-    s.run(burn + samples * every)
+    s = state["sampler"]
     G = torch.empty((N, N), dtype=torch.float64, device=dev)
     sm = torch.empty(1, dtype=torch.float64, device=dev)
     for _ in range(3):
@@ -123,7 +112,7 @@ def _bench_fit(args, wl):
         binding.pns_snapshot_moments(s.ctx, 0, G, sum_m=sm)
     e1.record(stream)
     torch.cuda.synchronize()
-    s.close()
+    release(state)
     mom_ms = e0.elapsed_time(e1) / reps
     K = chains * samples
     mflops = 2.0 * K * N * N
@@ -133,16 +122,19 @@ def _bench_fit(args, wl):
         "warmup": args.warmup, "ms_per_step": sec * 1000.0, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["desc"], "N": N, "chains": chains, "mode": "rf", "beta": beta,
-                   "data_samples": int(nsamp), "records_per_gradient": K, "steps_per_gradient": steps_per_iter},
+                   "data_samples": int(nsamp), "records_per_gradient": K, "steps_per_gradient": steps_per_iter,
+                   "lr": lr, "update": "centered momentum 0.9"},
         "gradients_per_s": 1.0 / sec,
-        "moment_gap_last": gaps[-1],
+        "fit_300": {"moment_gap_mean_last50": float(np.mean(q.moment_gap[-50:])), "noise_floor": floor,
+                    "rel_param_error": rel},
         "roofline": {"bound": "hbm", "achieved": flips * N * 4 / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": flips * N * 4 / sec / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_flip": N * 4, "kernel": "step_kernel + moments_kernel (whole iteration)",
+                     "bytes_per_flip": N * 4, "kernel": "step_kernel + moments (whole iteration)",
                      "kernel_avg_ms": sec * 1000.0},
         "moments_roofline": {"bound": "mfma", "achieved": mom_tf, "peak": 2500.0, "unit": "TFLOP/s",
                              "frac": mom_tf / 2500.0, "traffic": None, "flops_per_launch": mflops,
-                             "kernel": "moments (fill + prep + moments_kernel + sum)", "kernel_avg_ms": mom_ms},
+                             "kernel": "moments (fill + prep + pack + moments_kernel + reduce + sum)",
+                             "kernel_avg_ms": mom_ms},
     }
     print(json.dumps(out))
 

@@ -12,9 +12,10 @@ library's moment kernel, G = X^T diag(m) X on the bf16 matrix cores, and
 returns -beta G / sum(m) (the multiplicity-weighted average of Sec 1.2).
 
 The forward value is log Z itself when N <= ``exact_max`` (enumeration on the
-device, ``pns_log_partition``); beyond that no exact value is available and
-the forward returns NaN -- the gradient, which is what maximum-likelihood
-fitting needs, is still the sampled estimate.
+device, ``pns_log_partition``).  Beyond that no exact value is available: the
+forward returns 0 (so that a loss built on it stays finite and its gradient
+flows) -- only the gradient, which is what maximum-likelihood fitting needs,
+is meaningful then.
 
 ``fit_qubo`` fits Q to data second moments by maximum likelihood: the average
 negative log-likelihood of data under pi_Q is beta <Q, E_data[x x^T]> + log Z,
@@ -85,7 +86,7 @@ class LogZ(torch.autograd.Function):
             if st is not None:
                 st.update(sampler=s, key=key, beta=float(beta))
         s.run(opts.burn_in + opts.samples * opts.every)
-        value = float("nan")
+        value = 0.0  # unknown beyond exact_max: see the module doc
         if N <= opts.exact_max:
             value = binding.pns_log_partition(Qs, beta, stream=stream)
         ctx.sampler = s
@@ -147,34 +148,62 @@ class FitResult:
 
 
 def fit_qubo(data_moments: torch.Tensor, beta: float, iters: int, lr: float, opts: ChainOptions,
-             Q0: Optional[torch.Tensor] = None, momentum: float = 0.9) -> FitResult:
-    """Maximum-likelihood fit of Q to data second moments by gradient descent
-    with momentum on beta <Q, D> + log Z(Q); every gradient of log Z comes
-    from LogZ's backward (sampled moments on the matrix cores)."""
+             Q0: Optional[torch.Tensor] = None, momentum: float = 0.9, centered: bool = True) -> FitResult:
+    """Maximum-likelihood fit of Q to data second moments D = E_data[x x^T]
+    by gradient descent with momentum on beta <Q, D> + log Z(Q); every
+    gradient of log Z comes from LogZ's backward (sampled moments on the
+    matrix cores).
+
+    With ``centered`` (default) the descent runs in centered coordinates:
+    Q_ij = W_ij off the diagonal and Q_ii = a_i - 2 sum_{j != i} W_ij mu_j
+    with mu = diag(D) (the data means), i.e. the energy is written as
+    (x - mu)^T W (x - mu) + a^T x + const.  The optimum is the
+    same (a fixed linear change of coordinates), but the gradient in W is
+    the difference of covariances instead of second moments, which removes
+    the collective direction driven by the means whose curvature grows like
+    N and would force a step size ~ 1/N."""
     D = data_moments.to(torch.float32)
     N = int(D.shape[0])
-    Q = (torch.zeros((N, N), dtype=torch.float32, device=D.device) if Q0 is None else Q0.clone().float())
-    Q.requires_grad_(True)
-    vel = torch.zeros_like(Q)
-    res = FitResult(Q=Q)
+    dev = D.device
+    eye = torch.eye(N, device=dev)
+    mu = torch.diagonal(D).clone()
+    Qinit = (torch.zeros((N, N), dtype=torch.float32, device=dev) if Q0 is None else Q0.clone().float())
+    if centered:
+        W = (Qinit * (1 - eye)).clone().requires_grad_(True)
+        a = (torch.diagonal(Qinit) + 2 * (Qinit * (1 - eye)) @ mu).clone().requires_grad_(True)
+        params = [W, a]
+    else:
+        Qp = Qinit.clone().requires_grad_(True)
+        params = [Qp]
+
+    def build_q():
+        if centered:
+            Ws = (W + W.T) * 0.5 * (1 - eye)
+            return Ws + torch.diag(a - 2 * (Ws @ mu))
+        return (Qp + Qp.T) * 0.5
+
+    vel = [torch.zeros_like(p) for p in params]
+    res = FitResult(Q=Qinit)
     state = opts.state if opts.state is not None else {}
     o = ChainOptions(**{**opts.__dict__, "state": state})
     try:
         for it in range(iters):
+            Q = build_q()
             lz = LogZ.apply(Q, beta, o)
             loss = beta * (Q * D).sum() + lz
-            if Q.grad is not None:
-                Q.grad = None
+            for p in params:
+                p.grad = None
+            Q.retain_grad()
             loss.backward()
             with torch.no_grad():
-                g = Q.grad
-                res.moment_gap.append(float((g.abs().max() / beta).item()))
-                res.loss.append(float(loss.item()) if not math.isnan(float(lz.item())) else float("nan"))
-                vel.mul_(momentum).add_(g)
-                Q.sub_(lr * vel)
-                Q.copy_((Q + Q.T) * 0.5)
+                res.moment_gap.append(float(Q.grad.abs().max().item() / beta))
+                res.loss.append(float(loss.item()) if N <= o.exact_max else float("nan"))
+                for p, v in zip(params, vel):
+                    v.mul_(momentum).add_(p.grad)
+                    p.sub_(lr * v)
     finally:
         if opts.state is None:
             release(state)
-    res.Q = Q.detach()
+    with torch.no_grad():
+        res.Q = build_q().detach()
     return res
