@@ -656,7 +656,8 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
             ctx->classes.push_back(k);
         }
         LaunchClass& K = ctx->classes[class_of[key]];
-        if (RR.flav == 2 || RR.flav == 3) K.dyn = std::max(K.dyn, (size_t)RR.pitch * 4);
+        // dynamic LDS: the diagonal, after the random-subset table for drawn subsets
+        K.dyn = std::max(K.dyn, (size_t)RR.pitch * 4 * (RR.flav == 2 ? 2 : 1));
         for (int32_t c = 0; c < S.chains; ++c) {
             ctx->h_chain_problem[c0 + c] = (int32_t)p;
             ctx->h_foff[c0 + c] = f0 + (int64_t)c * RR.pitch;
@@ -869,7 +870,7 @@ int reconfigure(pns_ctx* ctx, Tile t, int32_t n)
     LaunchClass& K = ctx->classes[0];
     K.tile = t;
     K.flav = R.flav;
-    K.dyn = (R.flav == 2 || R.flav == 3) ? (size_t)R.pitch * 4 : 0;
+    K.dyn = (size_t)R.pitch * 4 * (R.flav == 2 ? 2 : 1);
     return reset_zero_state(ctx);
 }
 

@@ -291,6 +291,10 @@ __device__ uint32_t draw_subset(uint32_t* own, uint64_t* masks, int tid, int64_t
 
 // Occupancy asked of the compiler (waves per SIMD): compact-window kernels
 // of 512 or more lanes target two co-resident chains per compute unit.
+// Words of the leader lane's LDS state.
+constexpr int kLsE = 0, kLsL = 1, kLsLastA = 2, kLsLastM = 3, kLsLastE = 4, kLsSteps = 5, kLsFlips = 6,
+              kLsStays = 7, kLsSat = 8, kLsBad = 9, kLsSumM = 10, kLeadWords = 11;
+
 template <int BLOCK, int FLAV>
 constexpr int min_waves_per_eu()
 {
@@ -309,7 +313,8 @@ void step_kernel(const StepArgs a)
     static_assert(NSEG <= 64, "segment scan needs at most 64 segments");
     static_assert(F <= 32, "bit masks are 32 bits");
 
-    extern __shared__ uint32_t own[];  // random-subset table (FLAV_DRAWN) or diagonal (FLAV_WINDOW_C), pitch entries
+    // dynamic LDS: [random-subset table, pitch entries (FLAV_DRAWN only)][diagonal, pitch entries]
+    extern __shared__ uint32_t own[];
     __shared__ double seg_sum[NSEG];
     __shared__ double mx_part[W];
     __shared__ uint64_t masks[W];
@@ -332,6 +337,13 @@ void step_kernel(const StepArgs a)
     const Problem P = a.problems[a.chain_problem[chain]];
     const int32_t N = P.N;
     const int64_t pitch = P.pitch;
+    // Register budget: with four or more bits per lane beyond one group
+    // (G >= 2) the diagonal lives in LDS and only four-bit weight sums are
+    // kept (the chosen lane recomputes its weights); one group keeps both in
+    // registers.  The compact window always reads the diagonal from LDS.
+    constexpr bool kLdsDiag = FLAV == FLAV_WINDOW_C || G >= 2;
+    constexpr bool kKeepW = FLAV == FLAV_WINDOW_C || G == 1;
+    QW* const dsh = reinterpret_cast<QW*>(own + (FLAV == FLAV_DRAWN ? pitch : 0));
     const int mode = a.mode;
     const bool unbiased = mode == kModeSys || mode == kModeRand;
     constexpr bool kWin = FLAV == FLAV_WINDOW || FLAV == FLAV_WINDOW_C;
@@ -354,7 +366,7 @@ void step_kernel(const StepArgs a)
 
     // ---- chain state into registers ----
     HT h[F];
-    QW dg[kCompact ? 1 : F];
+    QW dg[kLdsDiag ? 1 : F];
     uint32_t xb = 0;
     HT* hbase = reinterpret_cast<HT*>(a.h) + off;
     const QW* dbase = reinterpret_cast<const QW*>(P.diag);
@@ -368,7 +380,7 @@ void step_kernel(const StepArgs a)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 h[g * 4 + v] = hv.v[v];
-                if constexpr (kCompact) reinterpret_cast<QW*>(own)[fb + v] = dv.v[v];
+                if constexpr (kLdsDiag) dsh[fb + v] = dv.v[v];
                 else dg[g * 4 + v] = dv.v[v];
                 xb |= ((xw >> (8 * v)) & 1u) << (g * 4 + v);
             }
@@ -376,7 +388,7 @@ void step_kernel(const StepArgs a)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 h[g * 4 + v] = (HT)0;
-                if constexpr (!kCompact) dg[g * 4 + v] = (QW)0;
+                if constexpr (!kLdsDiag) dg[g * 4 + v] = (QW)0;
             }
         }
     }
@@ -389,15 +401,18 @@ void step_kernel(const StepArgs a)
 
     int64_t k = a.step[chain];
     const int64_t kend = k + a.steps;
-    int64_t Ei = a.E[chain];
-    double Ef = __longlong_as_double(Ei);
-    int64_t L = a.L[chain];
+    // Scalars only the leader lane uses (energy, budget, last record,
+    // counters) live in LDS, not in every lane's registers.
+    __shared__ int64_t lead_st[kLeadWords];
+    if (tid == lead_tid) {
+        lead_st[kLsE] = a.E[chain];
+        lead_st[kLsL] = a.L[chain];
+        lead_st[kLsLastA] = a.last_action[chain];
+        lead_st[kLsLastM] = a.last_M[chain];
+        lead_st[kLsLastE] = a.last_E[chain];
+        for (int q = kLsSteps; q < kLeadWords; ++q) lead_st[q] = 0;
+    }
     int64_t sub = a.sub[chain];
-    int32_t last_action = a.last_action[chain];
-    int64_t last_M = a.last_M[chain];
-    int64_t last_E = a.last_E[chain];
-    int64_t c_steps = 0, c_flips = 0, c_stays = 0, c_sat = 0, c_bad = 0;
-    double c_sumM = 0.0;
     int32_t snap_n = 0;
     if constexpr (INSTR) snap_n = a.snap_every > 0 ? a.snap_count[chain] : 0;
     uint32_t pos_n = 0;
@@ -477,8 +492,18 @@ void step_kernel(const StepArgs a)
         }
 
         // acceptance weights of the subset, summed four bits at a time
+        // the diagonal entry of the lane's bit i (i a compile-time index
+        // unless the diagonal is in LDS); 0 past the pitch
+        auto diag_of = [&](int i) -> QW {
+            if constexpr (kLdsDiag) {
+                const int64_t f = ((int64_t)(i >> 2) * BLOCK + tid) * 4 + (i & 3);
+                return f < pitch ? dsh[f] : (QW)0;
+            } else {
+                return dg[i % F];
+            }
+        };
         auto member_weight = [&](int i, double shift) -> double {
-            const QW di = dg[i % (kCompact ? 1 : F)];
+            const QW di = diag_of(i);
             if constexpr (kInt) {
                 const HT e = delta_int(di, h[i], s, (xb >> i) & 1u);
                 if (shift == 0.0) {
@@ -495,7 +520,7 @@ void step_kernel(const StepArgs a)
                 return shift == 0.0 ? exp(l) : exp(l - shift);
             }
         };
-        double w[kCompact ? 4 : F];  // compact: weights of the lane's four bits in group gw
+        double w[kKeepW ? 4 : 1];  // weights of the lane's four bits (compact: in group gw)
         double ls[kCompact ? 1 : G];
         // Compact window: a wave's subset bits lie in one 4-bit group (gw) and
         // each lane's in its four bits of that group.
@@ -521,7 +546,7 @@ void step_kernel(const StepArgs a)
                     }
                 }
                 const int32_t fb = (gw * BLOCK + tid) * 4;
-                const Four<QW> d4 = load4(reinterpret_cast<const QW*>(own) + (fb < pitch ? fb : 0));
+                const Four<QW> d4 = load4(dsh + (fb < pitch ? fb : 0));
                 const uint32_t x4 = (xb >> (4 * gw)) & 0xFu;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -554,39 +579,58 @@ void step_kernel(const StepArgs a)
         } else if constexpr (kInt) {
             // exp(-beta * max(e, 0)) = tab_hi[e >> 6] * tab_lo[e & 63]; exp(-0) = 1
             // covers e <= 0, and a bit outside the subset reads the zero slot.
-            HT emax = 0;
 #pragma unroll
-            for (int i = 0; i < F; ++i) {
-                const HT e = delta_int(dg[i], h[i], s, (xb >> i) & 1u);
-                const HT ep = e > 0 ? e : 0;
-                emax = emax > ep ? emax : ep;
-                const uint32_t hi = (uint32_t)(ep >> 6) < (uint32_t)kTabHi ? (uint32_t)(ep >> 6) : (uint32_t)(kTabHi - 1);
-                const uint32_t lo = ((mem >> i) & 1u) ? (uint32_t)ep & 63u : (uint32_t)kTabLo;
-                w[i] = tab_hi[hi] * tab_lo[lo];
-            }
-            if (__ballot(emax >= (HT)kTabMax)) {
+            for (int g = 0; g < G; ++g) {
+                Four<QW> d4;
+                if constexpr (kLdsDiag) {
+                    const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
+                    d4 = fb < pitch ? load4(dsh + fb) : Four<QW>{};
+                } else {
 #pragma unroll
-                for (int i = 0; i < F; ++i) {
-                    const HT e = delta_int(dg[i], h[i], s, (xb >> i) & 1u);
-                    if (((mem >> i) & 1u) && e >= (HT)kTabMax) w[i] = exp(-beta * (double)e);
+                    for (int v = 0; v < 4; ++v) d4.v[v] = dg[(g * 4 + v) % F];
+                }
+                double w4[4];
+                HT emax = 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = g * 4 + v;
+                    const HT e = delta_int(d4.v[v], h[i], s, (xb >> i) & 1u);
+                    const HT ep = e > 0 ? e : 0;
+                    emax = emax > ep ? emax : ep;
+                    const uint32_t hi =
+                        (uint32_t)(ep >> 6) < (uint32_t)kTabHi ? (uint32_t)(ep >> 6) : (uint32_t)(kTabHi - 1);
+                    const uint32_t lo = ((mem >> i) & 1u) ? (uint32_t)ep & 63u : (uint32_t)kTabLo;
+                    w4[v] = tab_hi[hi] * tab_lo[lo];
+                }
+                if (__ballot(emax >= (HT)kTabMax)) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = g * 4 + v;
+                        const HT e = delta_int(d4.v[v], h[i], s, (xb >> i) & 1u);
+                        if (((mem >> i) & 1u) && e >= (HT)kTabMax) w4[v] = exp(-beta * (double)e);
+                    }
+                }
+                ls[g] = ((w4[0] + w4[1]) + w4[2]) + w4[3];
+                if constexpr (kKeepW) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) w[v] = w4[v];
                 }
             }
         } else {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const uint32_t mg = (mem >> (4 * g)) & 0xFu;
+                double w4[4] = {0.0, 0.0, 0.0, 0.0};
                 if (__ballot(mg != 0)) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) w[g * 4 + v] = ((mg >> v) & 1u) ? member_weight(g * 4 + v, 0.0) : 0.0;
-                } else {
+                    for (int v = 0; v < 4; ++v) w4[v] = ((mg >> v) & 1u) ? member_weight(g * 4 + v, 0.0) : 0.0;
+                }
+                ls[g] = ((w4[0] + w4[1]) + w4[2]) + w4[3];
+                if constexpr (kKeepW) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) w[g * 4 + v] = 0.0;
+                    for (int v = 0; v < 4; ++v) w[v] = w4[v];
                 }
             }
-        }
-        if constexpr (!kCompact) {
-#pragma unroll
-            for (int g = 0; g < G; ++g) ls[g] = ((w[g * 4] + w[g * 4 + 1]) + w[g * 4 + 2]) + w[g * 4 + 3];
         }
         double inc[kCompact ? 1 : G];
         auto scan_and_publish = [&]() {
@@ -618,8 +662,7 @@ void step_kernel(const StepArgs a)
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 if ((mem >> i) & 1u) {
-                    const QW di = kCompact ? reinterpret_cast<const QW*>(own)[((i >> 2) * BLOCK + tid) * 4 + (i & 3)]
-                                           : dg[i % (kCompact ? 1 : F)];
+                    const QW di = diag_of(i);
                     double l;
                     if constexpr (kInt) l = -beta * (double)delta_int(di, h[i], s, (xb >> i) & 1u);
                     else l = -beta * delta_f64(di, h[i], s, (xb >> i) & 1u);
@@ -638,12 +681,17 @@ void step_kernel(const StepArgs a)
             } else {
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
+                    double w4[4];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int i = g * 4 + v;
-                        w[i] = ((mem >> i) & 1u) ? member_weight(i, mx) : 0.0;
+                        w4[v] = ((mem >> i) & 1u) ? member_weight(i, mx) : 0.0;
                     }
-                    ls[g] = ((w[g * 4] + w[g * 4 + 1]) + w[g * 4 + 2]) + w[g * 4 + 3];
+                    ls[g] = ((w4[0] + w4[1]) + w4[2]) + w4[3];
+                    if constexpr (kKeepW) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) w[v] = w4[v];
+                    }
                 }
             }
             scan_and_publish();
@@ -674,12 +722,10 @@ void step_kernel(const StepArgs a)
         };
         // Unbiased: wave 0 takes the budget decision of Alg 6 while the winner
         // wave resolves the (speculative) choice; both meet at the barrier.
-        if (unbiased && lead) {
+        if (unbiased && tid == lead_tid) {
             multiplicity();
-            if (tid == lead_tid) stay_flag = q >= (double)L ? 1 : 0;
+            stay_flag = q >= (double)lead_st[kLsL] ? 1 : 0;
         }
-
-        const int64_t Erec = kInt ? Ei : __double_as_longlong(Ef);
         uint32_t rec_idx = 0;
         bool snap = false;
         if constexpr (INSTR) {
@@ -741,18 +787,25 @@ void step_kernel(const StepArgs a)
                 if (lane == lstar) {
                     double run = lstar > 0 ? base + prev_l : base;
                     int vstar = -1, vlast = -1;
+                    // the chosen lane's four weights in group gstar: kept, or
+                    // recomputed (the same values as summed above)
+                    double wsel[4];
+                    if constexpr (kKeepW) {
 #pragma unroll
-                    for (int g = 0; g < G; ++g) {
-                        if (g == gstar) {
+                        for (int v = 0; v < 4; ++v) wsel[v] = w[v];
+                    } else {
+                        const uint32_t mg = (mem >> (4 * gstar)) & 0xFu;
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const double wv = kCompact ? w[v] : w[(g * 4 + v) % (kCompact ? 4 : F)];
-                                if (wv > 0.0) {
-                                    vlast = v;
-                                    run += wv;
-                                    if (vstar < 0 && run > t) vstar = v;
-                                }
-                            }
+                        for (int v = 0; v < 4; ++v)
+                            wsel[v] = ((mg >> v) & 1u) ? member_weight(gstar * 4 + v, scaled ? mx : 0.0) : 0.0;
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const double wv = wsel[v];
+                        if (wv > 0.0) {
+                            vlast = v;
+                            run += wv;
+                            if (vstar < 0 && run > t) vstar = v;
                         }
                     }
                     if (vstar < 0) vstar = vlast;
@@ -770,10 +823,10 @@ void step_kernel(const StepArgs a)
                     for (int ii = 0; ii < F; ++ii) {
                         if (ii == i) {
                             hc = h[ii];
-                            if constexpr (!kCompact) dc = dg[ii];
+                            if constexpr (!kLdsDiag) dc = dg[ii];
                         }
                     }
-                    if constexpr (kCompact) dc = reinterpret_cast<const QW*>(own)[(gstar * BLOCK + tid) * 4 + vstar];
+                    if constexpr (kLdsDiag) dc = diag_of(i);
                     int64_t dEc;
                     if constexpr (kInt) dEc = (int64_t)delta_int(dc, hc, s, (xb >> i) & 1u);
                     else dEc = __double_as_longlong(delta_f64(dc, hc, s, (xb >> i) & 1u));
@@ -790,16 +843,10 @@ void step_kernel(const StepArgs a)
         __syncthreads();
         const bool stay = unbiased && stay_flag != 0;
 
-        int32_t action;
-        int64_t M;
         if (stay) {
             // Alg 6: not enough remaining original samples; stay L times and
             // switch to the next partial neighbor set.
-            M = L;
-            action = -1;
-            L = P.L0;
             ++sub;
-            ++c_stays;
             if constexpr (FLAV == FLAV_DRAWN) {
                 pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k + 1);
             } else if constexpr (kWin) {
@@ -808,7 +855,6 @@ void step_kernel(const StepArgs a)
             mem = compute_mem();
         } else {
             const int64_t sv0 = sel[0];
-            const int64_t dEc = sel[1];
             const int32_t c = (int32_t)(sv0 & 0xFFFFFFFFll);
             const bool xc = (sv0 >> 40) & 1;
             // field update from row c; the record and the next step's random
@@ -821,16 +867,6 @@ void step_kernel(const StepArgs a)
                 if (fb < pitch) r[g] = load_row4(row + fb);
                 else r[g] = {};
             }
-            action = c;
-            if (lead) {
-                if (!unbiased) multiplicity();
-                if (unbiased) L -= m;
-                c_sat += sat ? 1 : 0;
-                c_bad += (sv0 >> 41) & 1;
-                if constexpr (kInt) Ei += dEc;
-                else Ef += __longlong_as_double(dEc);
-            }
-            M = m;
             const int cl = (c >> 2) % BLOCK;
             const int cg = (c >> 2) / BLOCK;
             if (tid == cl) xb ^= 1u << (cg * 4 + (c & 3));
@@ -842,20 +878,40 @@ void step_kernel(const StepArgs a)
                     else h[g * 4 + v] += (HT)r[g].v[v];
                 }
             }
-            ++c_flips;
-        }
-
-        // record k = (state before the step, M), kept by the leader wave
-        if (lead) {
-            ++c_steps;
-            c_sumM += (double)M;
-            last_action = action;
-            last_M = M;
-            last_E = Erec;
         }
         if constexpr (INSTR) {
             if (snap) ++snap_n;
-            if (tid == lead_tid) {
+        }
+
+        // record k = (state before the step, M): the leader lane
+        if (tid == lead_tid) {
+            const int64_t Erec = lead_st[kLsE];
+            int32_t action;
+            int64_t M;
+            if (stay) {
+                M = lead_st[kLsL];
+                action = -1;
+                lead_st[kLsL] = P.L0;
+                lead_st[kLsStays] += 1;
+            } else {
+                const int64_t sv0 = sel[0];
+                const int64_t dEc = sel[1];
+                if (!unbiased) multiplicity();
+                if (unbiased) lead_st[kLsL] -= m;
+                lead_st[kLsSat] += sat ? 1 : 0;
+                lead_st[kLsBad] += (sv0 >> 41) & 1;
+                if constexpr (kInt) lead_st[kLsE] = Erec + dEc;
+                else lead_st[kLsE] = __double_as_longlong(__longlong_as_double(Erec) + __longlong_as_double(dEc));
+                lead_st[kLsFlips] += 1;
+                M = m;
+                action = (int32_t)(sv0 & 0xFFFFFFFFll);
+            }
+            lead_st[kLsSteps] += 1;
+            lead_st[kLsSumM] = __double_as_longlong(__longlong_as_double(lead_st[kLsSumM]) + (double)M);
+            lead_st[kLsLastA] = action;
+            lead_st[kLsLastM] = M;
+            lead_st[kLsLastE] = Erec;
+            if constexpr (INSTR) {
                 if (a.hist_w != nullptr) rec_idx = hist_idx;
                 if (a.log_cap > 0) {
                     const int64_t slot = (int64_t)chain * a.log_cap + (k % a.log_cap);
@@ -899,22 +955,22 @@ void step_kernel(const StepArgs a)
     }
     if (tid == lead_tid) {
         a.step[chain] = kend;
-        a.E[chain] = kInt ? Ei : __double_as_longlong(Ef);
-        a.L[chain] = L;
+        a.E[chain] = lead_st[kLsE];
+        a.L[chain] = lead_st[kLsL];
         a.sub[chain] = sub;
-        a.last_action[chain] = last_action;
-        a.last_M[chain] = last_M;
-        a.last_E[chain] = last_E;
+        a.last_action[chain] = (int32_t)lead_st[kLsLastA];
+        a.last_M[chain] = lead_st[kLsLastM];
+        a.last_E[chain] = lead_st[kLsLastE];
         if constexpr (INSTR) {
             if (a.snap_every > 0) a.snap_count[chain] = snap_n;
         }
         int64_t* cn = a.counters + (int64_t)chain * 6;
-        cn[0] += c_steps;
-        cn[1] += c_flips;
-        cn[2] += c_stays;
-        cn[3] += c_sat;
-        cn[4] = __double_as_longlong(__longlong_as_double(cn[4]) + c_sumM);
-        cn[5] += c_bad;
+        cn[0] += lead_st[kLsSteps];
+        cn[1] += lead_st[kLsFlips];
+        cn[2] += lead_st[kLsStays];
+        cn[3] += lead_st[kLsSat];
+        cn[4] = __double_as_longlong(__longlong_as_double(cn[4]) + __longlong_as_double(lead_st[kLsSumM]));
+        cn[5] += lead_st[kLsBad];
     }
 }
 
