@@ -289,16 +289,17 @@ __device__ uint32_t draw_subset(uint32_t* own, uint64_t* masks, int tid, int64_t
     }
 }
 
-// Occupancy asked of the compiler (waves per SIMD): compact-window kernels
-// of 512 or more lanes target two co-resident chains per compute unit.
 // Words of the leader lane's LDS state.
 constexpr int kLsE = 0, kLsL = 1, kLsLastA = 2, kLsLastM = 3, kLsLastE = 4, kLsSteps = 5, kLsFlips = 6,
               kLsStays = 7, kLsSat = 8, kLsBad = 9, kLsSumM = 10, kLeadWords = 11;
 
+// Occupancy asked of the compiler (waves per SIMD): compact-window kernels
+// of 512 lanes target two co-resident chains per compute unit (128 VGPRs);
+// 1024-lane kernels keep the register budget of one chain per unit.
 template <int BLOCK, int FLAV>
 constexpr int min_waves_per_eu()
 {
-    return (FLAV == FLAV_WINDOW_C && BLOCK >= 512) ? 2 * (BLOCK / 256) : 1;
+    return (FLAV == FLAV_WINDOW_C && BLOCK == 512) ? 4 : 1;
 }
 
 template <typename QT, typename HT, int BLOCK, int G, int FLAV, bool INSTR>
