@@ -29,6 +29,23 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def _measured_traffic(workload: str, chain_steps: int):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter runs (profiles/hbm_traffic.txt), or None when no run matches the
+    workload and launch length or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_2210_10513_amd", "csrc", "pns_step.h")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        f = line.split()
+        if len(f) == 6 and not line.startswith("#") and f[0] == workload and int(f[1]) == chain_steps and f[2] == sha:
+            return float(f[5])
+    return None
+
+
 def _workload(name: str):
     from paper_2210_10513_amd import inputs
     if name == "rf_n1024_int16":
@@ -265,6 +282,8 @@ def main():
     ap.add_argument("--tile", default="", help="workgroup size and 4-field groups per lane, e.g. 64,4")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB device buffer 3 times (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: chains are independent, so nothing here runs on more than one "
@@ -275,6 +294,16 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # 2^28 float32 = 1 GiB read and 1 GiB written per copy: the scale of
+        # the FETCH_SIZE / WRITE_SIZE counters for a kernel of known traffic
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "copies": 3}))
+        return
 
     wl = _workload(args.workload)
     if wl.get("fit"):
@@ -311,7 +340,8 @@ def main():
         "effective_mh_steps_per_s": summ / sec,
         "records_per_s": recs / sec,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _measured_traffic(args.workload, chain_steps) if args.steps >= 1 else None,
                      "bytes_per_flip": bytes_per_flip, "kernel": "step_kernel",
                      "kernel_avg_ms": sec * 1000.0},
     }
