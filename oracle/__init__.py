@@ -27,6 +27,7 @@ MODE_RF = 0
 MODE_BASIC = 1
 MODE_UNBIASED_SYS = 2
 MODE_UNBIASED_RAND = 3
+MODE_OPT = 4
 LAYOUT_SYMMETRIC = 0
 LAYOUT_UPPER = 1
 STAY = -1
@@ -89,6 +90,8 @@ class _RunArgs(ctypes.Structure):
         ("sub_final", ctypes.c_void_p),
         ("hist_w", ctypes.c_void_p), ("hist_v", ctypes.c_void_p), ("hist_from", ctypes.c_int64),
         ("n_flips", ctypes.c_void_p), ("n_stays", ctypes.c_void_p), ("n_saturated", ctypes.c_void_p),
+        ("temperature", ctypes.c_double), ("x_best", ctypes.c_void_p), ("Ei_best", ctypes.c_void_p),
+        ("Ef_best", ctypes.c_void_p),
     ]
 
 
@@ -210,16 +213,20 @@ class RunResult:
     flips: Optional[np.ndarray] = None
     stays: Optional[np.ndarray] = None
     saturated: Optional[np.ndarray] = None
+    x_best: Optional[np.ndarray] = None   # MODE_OPT: best state X_max
+    E_best: Optional[np.ndarray] = None
 
 
 def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, seed: int = 0,
         num_chains: int = 1, chain_ids=None, x0: Optional[np.ndarray] = None, init: str = "zero",
         layout: int = LAYOUT_SYMMETRIC, log: bool = True, hist: bool = False, hist_from: int = 0,
-        step0: int = 0, lib_handle: Optional[ctypes.CDLL] = None) -> RunResult:
+        step0: int = 0, lib_handle: Optional[ctypes.CDLL] = None, temperature: float = 1.0) -> RunResult:
     """Run ``num_chains`` independent chains for ``K`` steps each.
 
     ``beta`` is a scalar or one value per chain; ``init`` is ``"zero"``,
     ``"random"`` (the Bernoulli(1/2) stream) or ignored when ``x0`` is given.
+    ``MODE_OPT`` runs Alg 9 (n = N) / Alg 10 (n < N) at ``temperature`` and
+    fills ``x_best`` / ``E_best`` (the best state seen, X_max).
     """
     is_int, Qc = _as_q(Q)
     N = Qc.shape[0]
@@ -275,6 +282,13 @@ def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, se
     a.L_final, a.sub_final = _ptr(r.L), _ptr(r.sub)
     a.hist_w, a.hist_v, a.hist_from = _ptr(r.hist_w), _ptr(r.hist_v), hist_from
     a.n_flips, a.n_stays, a.n_saturated = _ptr(r.flips), _ptr(r.stays), _ptr(r.saturated)
+    a.temperature = temperature
+    r.x_best = np.zeros((C, N), dtype=np.uint8)
+    r.E_best = np.zeros(C, dtype=np.int64 if is_int else np.float64)
+    Eb_dummy = np.zeros(C, dtype=np.float64 if is_int else np.int64)
+    a.x_best = _ptr(r.x_best)
+    a.Ei_best = _ptr(r.E_best) if is_int else _ptr(Eb_dummy)
+    a.Ef_best = _ptr(Eb_dummy) if is_int else _ptr(r.E_best)
     rc = (lib_handle or lib()).orc_run(ctypes.byref(a))
     if rc != 0:
         raise ValueError(f"oracle run rejected its arguments (code {rc})")

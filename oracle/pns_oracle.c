@@ -43,6 +43,11 @@
 #define ORC_MODE_BASIC 1
 #define ORC_MODE_UNBIASED_SYS 2
 #define ORC_MODE_UNBIASED_RAND 3
+/* Optimization Rejection-Free (Alg 9, n = N) and Optimization PNS (Alg 10,
+ * a fresh uniformly random n-subset every step, the subset rule of Alg 3):
+ * the jump chain with acceptance min{1, [pi(y)/pi(x)]^(1/T)} at a constant
+ * temperature T, no multiplicity, and the best state X_max kept. */
+#define ORC_MODE_OPT 4
 
 #define ORC_LAYOUT_SYMMETRIC 0
 #define ORC_LAYOUT_UPPER 1
@@ -257,6 +262,12 @@ typedef struct {
     int64_t* n_flips;
     int64_t* n_stays;
     int64_t* n_saturated;
+    /* ORC_MODE_OPT: temperature T > 0 and the best state X_max of each chain
+     * (outputs may be NULL) */
+    double temperature;
+    uint8_t* x_best;            /* [num_chains][N] */
+    int64_t* Ei_best;           /* [num_chains] */
+    double* Ef_best;            /* [num_chains] */
 } orc_run_args;
 
 /* Local field of bit j: the part of dE_j that depends on the other bits,
@@ -326,10 +337,12 @@ int orc_run(const orc_run_args* a)
     const int32_t N = a->N;
     if (N <= 0) return -1;
     if (a->mode != ORC_MODE_RF && (a->n < 1 || a->n > N)) return -2;
+    if (a->mode == ORC_MODE_OPT && !(a->temperature > 0.0)) return -4;
     const int32_t n = a->mode == ORC_MODE_RF ? N : a->n;
     const int64_t I = orc_sys_count(N, n);
 
     uint8_t* x = (uint8_t*)malloc((size_t)N);
+    uint8_t* xbest = (uint8_t*)malloc((size_t)N);
     uint8_t* member = (uint8_t*)malloc((size_t)N);
     int64_t* hi = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
     double* hf = (double*)malloc(sizeof(double) * (size_t)N);
@@ -337,11 +350,12 @@ int orc_run(const orc_run_args* a)
     double* dEf = (double*)malloc(sizeof(double) * (size_t)N);
     double* lw = (double*)malloc(sizeof(double) * (size_t)N);
     double* w = (double*)malloc(sizeof(double) * (size_t)N);
-    if (!x || !member || !hi || !hf || !dEi || !dEf || !lw || !w) return -3;
+    if (!x || !xbest || !member || !hi || !hf || !dEi || !dEf || !lw || !w) return -3;
 
     for (int32_t ch = 0; ch < a->num_chains; ++ch) {
         const uint32_t cid = a->chain_ids[ch];
-        const double beta = a->betas[ch];
+        /* Alg 9/10 weigh by [pi(y)/pi(x)]^(1/T): the target at beta / T */
+        const double beta = a->mode == ORC_MODE_OPT ? a->betas[ch] / a->temperature : a->betas[ch];
         memcpy(x, a->x0 + (size_t)ch * N, (size_t)N);
         fields_init(a, x, hi, hf);
         int64_t Ei = a->is_int ? orc_energy_i(a->Qi, N, a->layout, x) : 0;
@@ -349,19 +363,24 @@ int orc_run(const orc_run_args* a)
         int64_t L = a->L0;
         int64_t sub = 0;
         int64_t flips = 0, stays = 0, saturated = 0;
+        /* X_max = J_0 */
+        memcpy(xbest, x, (size_t)N);
+        int64_t Ei_best = Ei;
+        double Ef_best = Ef;
 
         /* Alg 6: the first partial neighbor set is N_0 (systematic) or a
          * fresh random set drawn for the step where the block starts. */
         if (a->mode == ORC_MODE_UNBIASED_SYS) orc_sys_subset(N, n, sub, member);
         if (a->mode == ORC_MODE_UNBIASED_RAND) orc_random_subset(a->seed, cid, (uint64_t)a->step0, N, n, member);
-        if (a->mode == ORC_MODE_RF) memset(member, 1, (size_t)N);
+        if (a->mode == ORC_MODE_RF || (a->mode == ORC_MODE_OPT && n == N)) memset(member, 1, (size_t)N);
 
         for (int64_t kk = 0; kk < a->K; ++kk) {
             const int64_t k = a->step0 + kk;
             const size_t rec = (size_t)ch * (size_t)a->K + (size_t)kk;
 
             /* Alg 3: a fresh partial neighbor set every step. */
-            if (a->mode == ORC_MODE_BASIC) orc_random_subset(a->seed, cid, (uint64_t)k, N, n, member);
+            if (a->mode == ORC_MODE_BASIC || (a->mode == ORC_MODE_OPT && n < N))
+                orc_random_subset(a->seed, cid, (uint64_t)k, N, n, member);
 
             /* Acceptance probabilities min{1, pi(y)/pi(x)} of the subset's
              * neighbours (the uniform proposal cancels), kept as logs. */
@@ -413,7 +432,9 @@ int orc_run(const orc_run_args* a)
             else q = log(U1) / log1p(-p);
             int64_t m;
             int sat = 0;
-            if (!(q < 0x1p63)) {
+            if (a->mode == ORC_MODE_OPT) {
+                m = 1; /* no multiplicity: each jump counts once */
+            } else if (!(q < 0x1p63)) {
                 m = INT64_MAX;
                 sat = 1;
             } else {
@@ -475,6 +496,12 @@ int orc_run(const orc_run_args* a)
                 }
                 x[c] ^= 1u;
                 ++flips;
+                /* Alg 9/10: keep the state of largest pi seen so far */
+                if (a->mode == ORC_MODE_OPT && (a->is_int ? Ei < Ei_best : Ef < Ef_best)) {
+                    memcpy(xbest, x, (size_t)N);
+                    Ei_best = Ei;
+                    Ef_best = Ef;
+                }
             }
 
             /* Record k is (J_k-before, M_k) with its energy. */
@@ -509,9 +536,12 @@ int orc_run(const orc_run_args* a)
         if (a->n_flips) a->n_flips[ch] = flips;
         if (a->n_stays) a->n_stays[ch] = stays;
         if (a->n_saturated) a->n_saturated[ch] = saturated;
+        if (a->x_best) memcpy(a->x_best + (size_t)ch * N, xbest, (size_t)N);
+        if (a->Ei_best) a->Ei_best[ch] = Ei_best;
+        if (a->Ef_best) a->Ef_best[ch] = Ef_best;
     }
 
-    free(x); free(member); free(hi); free(hf); free(dEi); free(dEf); free(lw); free(w);
+    free(x); free(xbest); free(member); free(hi); free(hf); free(dEi); free(dEf); free(lw); free(w);
     return 0;
 }
 

@@ -400,3 +400,57 @@ def test_planted_mistake_is_caught(name, tmp_path):
         caught.append(exact.tv(exact.empirical(r.hist_w), pi) > 0.01)
     caught.append(_mean_multiplicity_error(L) > 0.05)
     assert any(caught), f"planted mistake {name} was not caught"
+
+
+# --------------------------------------------------------------------------
+# Optimization RF / PNS (Alg 9, Alg 10) used as burn-in (Sec 7)
+# --------------------------------------------------------------------------
+
+def test_optimization_at_unit_temperature_is_the_jump_chain_without_multiplicity():
+    """Sec 2 builds Basic PNS as Optimization PNS plus a multiplicity list,
+    and Optimization RF is RF's jump chain: at T = 1 the moves coincide
+    (same counter-based draws) and every jump counts once."""
+    Q = _small_int_q(10, 21)
+    for mode, n in ((oracle.MODE_RF, 10), (oracle.MODE_BASIC, 4)):
+        ref = oracle.run(Q, 0.2, mode, 300, n=n, seed=5, num_chains=3)
+        opt = oracle.run(Q, 0.2, oracle.MODE_OPT, 300, n=n, seed=5, num_chains=3, temperature=1.0)
+        assert np.array_equal(opt.action, ref.action)
+        assert np.array_equal(opt.E, ref.E)
+        assert (opt.M == 1).all()
+
+
+def test_optimization_temperature_tempers_the_target():
+    """Weights [pi(y)/pi(x)]^(1/T) of pi_beta are those of pi_{beta/T}."""
+    Q = _small_int_q(9, 22)
+    hot = oracle.run(Q, 0.3, oracle.MODE_OPT, 250, n=9, seed=2, num_chains=2, temperature=3.0)
+    ref = oracle.run(Q, 0.1, oracle.MODE_RF, 250, seed=2, num_chains=2)
+    assert np.array_equal(hot.action, ref.action)
+
+
+def test_optimization_keeps_the_best_state():
+    """X_max is the lowest-energy state of the trajectory (J_0 included), and
+    its energy is the brute-force x^T Q x of the stored bits."""
+    Q = _small_int_q(12, 23)
+    r = oracle.run(Q, 0.5, oracle.MODE_OPT, 400, n=5, seed=7, num_chains=4, temperature=0.7, init="random")
+    for c in range(4):
+        traj = np.concatenate([r.E[c], [r.E_final[c]]])
+        assert r.E_best[c] == traj.min()
+        xb = r.x_best[c].astype(np.int64)
+        assert r.E_best[c] == int(xb @ Q.astype(np.int64) @ xb)
+
+
+def test_cold_optimization_ends_in_a_local_minimum_and_finds_the_ground_state():
+    """At a low temperature Optimization RF descends: X_max is a local
+    minimum (no single flip lowers the energy), and over a few chains the
+    global minimum of a small problem (enumeration) is reached."""
+    Q = _small_int_q(8, 24)
+    r = oracle.run(Q, 1.0, oracle.MODE_OPT, 3000, n=8, seed=11, num_chains=16, temperature=0.5, init="random")
+    Qi = Q.astype(np.int64)
+    for c in range(16):
+        xb = r.x_best[c].astype(np.int64)
+        e0 = int(xb @ Qi @ xb)
+        for j in range(8):
+            y = xb.copy()
+            y[j] ^= 1
+            assert int(y @ Qi @ y) >= e0
+    assert r.E_best.min() == oracle.enumerate_energies(Q).min()
