@@ -328,6 +328,36 @@ int pns_set_q(pns_ctx* ctx, int32_t problem, const void* Q);
  * context's stream.  Errors: PNS_EINVAL (NULL ctx, snapshots off). */
 int pns_snapshots_clear(pns_ctx* ctx);
 
+/*
+ * Optimization Rejection-Free (Alg 9) / Optimization PNS (Alg 10) as burn-in
+ * (Sec 7): advance every chain by `steps` jumps of the jump chain whose
+ * acceptance is min{1, [pi(y)/pi(x)]^(1/T)} (the target at beta / T) with no
+ * multiplicity, keeping per chain the state of largest pi seen, X_max
+ * (initially the chain's state at the first call).  Problems whose subset
+ * size n is below N draw a fresh uniformly random n-subset every step (the
+ * subset rule of Alg 3: Basic PNS is Optimization PNS plus multiplicities,
+ * Sec 2); RF contexts and n = N consider every neighbour.  A cooling
+ * schedule T(k) is a sequence of calls with non-increasing T.  Draws come from
+ * the chains' counters like pns_run (step k uses the same Philox numbers), and
+ * the per-step log, histograms and snapshots record these jumps with M = 1.
+ * Budgets and set indices of Unbiased chains are left as they are; pns_run
+ * afterwards samples from the chains' current states (Sec 7.2), or from X_max
+ * after pns_adopt_best (Sec 7.1).  Queued on the context's stream.
+ * Errors: PNS_EINVAL (steps < 0, T not finite and > 0), PNS_ENOMEM,
+ * PNS_EDEVICE.
+ */
+int pns_optimize(pns_ctx* ctx, int64_t steps, double temperature);
+
+/* X_max of every chain (bits [C][N] concatenated as pns_read, energies [C]),
+ * host or device buffers, either may be NULL.  Synchronises.
+ * Errors: PNS_EINVAL (no pns_optimize yet). */
+int pns_read_best(pns_ctx* ctx, uint8_t* states, double* energies);
+
+/* Move every chain to its X_max: fields and energies recomputed, Unbiased
+ * budgets restarted at L0, last records reset.  Synchronises.
+ * Errors: PNS_EINVAL (no pns_optimize yet), PNS_EDEVICE. */
+int pns_adopt_best(pns_ctx* ctx);
+
 /* ---- differentiation path ----
  *
  * The target pi_beta(x) = exp(-beta x^T Q x) / Z(Q, beta) gives

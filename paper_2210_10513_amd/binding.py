@@ -39,7 +39,8 @@ EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_cu
            "pns_read_log", "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync",
            "pns_destroy", "pns_tile", "pns_last_error", "pns_version", "pns_create_batch", "pns_autotune",
            "pns_chain_offsets", "pns_num_problems", "pns_problem_info_get", "pns_moments", "pns_snapshot_moments",
-           "pns_log_partition", "pns_set_q", "pns_snapshots_clear"]
+           "pns_log_partition", "pns_set_q", "pns_snapshots_clear", "pns_optimize", "pns_read_best",
+           "pns_adopt_best"]
 
 
 class pns_opts(ctypes.Structure):
@@ -124,11 +125,14 @@ def _load() -> ctypes.CDLL:
     L.pns_log_partition.argtypes = [vp, i32, i32, i32, dbl, vp, vp]
     L.pns_set_q.argtypes = [vp, i32, vp]
     L.pns_snapshots_clear.argtypes = [vp]
+    L.pns_optimize.argtypes = [vp, i64, dbl]
+    L.pns_read_best.argtypes = [vp, vp, vp]
+    L.pns_adopt_best.argtypes = [vp]
     for name in ("pns_create", "pns_run", "pns_read", "pns_read_current", "pns_field_type", "pns_read_log",
                  "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync", "pns_destroy",
                  "pns_tile", "pns_create_batch", "pns_autotune", "pns_chain_offsets", "pns_num_problems",
                  "pns_problem_info_get", "pns_moments", "pns_snapshot_moments", "pns_log_partition", "pns_set_q",
-                 "pns_snapshots_clear"):
+                 "pns_snapshots_clear", "pns_optimize", "pns_read_best", "pns_adopt_best"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -314,6 +318,18 @@ def pns_snapshots_clear(ctx) -> None:
     _check(lib.pns_snapshots_clear(ctx))
 
 
+def pns_optimize(ctx, steps: int, temperature: float = 1.0) -> None:
+    _check(lib.pns_optimize(ctx, steps, float(temperature)))
+
+
+def pns_read_best(ctx, states=None, energies=None) -> None:
+    _check(lib.pns_read_best(ctx, _addr(states), _addr(energies)))
+
+
+def pns_adopt_best(ctx) -> None:
+    _check(lib.pns_adopt_best(ctx))
+
+
 def pns_last_error() -> str:
     return lib.pns_last_error().decode()
 
@@ -446,6 +462,21 @@ class Sampler:
             Qk = np.ascontiguousarray(Q)
         pns_set_q(self.ctx, 0, Qk)
         self._Q = Qk
+        return self
+
+    def optimize(self, steps: int, temperature: float = 1.0) -> "Sampler":
+        """Optimization RF / PNS burn-in (Alg 9, 10) at temperature T."""
+        pns_optimize(self.ctx, steps, temperature)
+        return self
+
+    def read_best(self):
+        s = np.zeros((self.num_chains, self.N), np.uint8)
+        e = np.zeros(self.num_chains, np.float64)
+        pns_read_best(self.ctx, s, e)
+        return s, e
+
+    def adopt_best(self) -> "Sampler":
+        pns_adopt_best(self.ctx)
         return self
 
     def snapshots_clear(self) -> "Sampler":

@@ -70,6 +70,10 @@ struct StepArgs {
     int64_t* snap_E;                // [C][snap_cap]
     int32_t* snap_count;            // [C]
     int64_t snap_pitch;
+    // optimization runs (mode 4, instrumented kernels only)
+    double inv_temp;                // 1 / T (1 for sampling)
+    uint8_t* xbest;                 // [fields] best state X_max, or NULL
+    int64_t* Ebest;                 // [C] its energy bits
 };
 
 struct InitArgs {

@@ -378,6 +378,11 @@ struct pns_ctx {
     int64_t* snap_M = nullptr;
     int64_t* snap_E = nullptr;
     int32_t* snap_count = nullptr;
+    // optimization runs: best states and their launch classes (built on first use)
+    uint8_t* xbest = nullptr;
+    int64_t* Ebest = nullptr;
+    bool best_valid = false;
+    std::vector<LaunchClass> opt_classes;
     // graph cache
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -423,6 +428,9 @@ struct pns_ctx {
         a.snap_E = snap_E;
         a.snap_count = snap_count;
         a.snap_pitch = max_pitch;
+        a.inv_temp = 1.0;
+        a.xbest = nullptr;
+        a.Ebest = nullptr;
         return a;
     }
 
@@ -476,6 +484,10 @@ struct pns_ctx {
         }
         for (auto& k : classes)
             if (k.d_list) (void)hipFree(k.d_list);
+        for (auto& k : opt_classes)
+            if (k.d_list) (void)hipFree(k.d_list);
+        if (xbest) (void)hipFree(xbest);
+        if (Ebest) (void)hipFree(Ebest);
         for (auto& sd : sides) {
             if (sd.stream) (void)hipStreamDestroy(sd.stream);
             if (sd.done) (void)hipEventDestroy(sd.done);
@@ -1723,6 +1735,132 @@ int pns_snapshots_clear(pns_ctx* ctx)
     // holds whole 64-bit words)
     if (e == hipSuccess) e = launch_fill64(ctx->snap_count, (C + 1) / 2, 0, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "clear snapshots");
+    return PNS_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int pns_optimize(pns_ctx* ctx, int64_t steps, double temperature)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    if (steps < 0) return fail(PNS_EINVAL, "steps must be >= 0");
+    if (!(temperature > 0.0) || !std::isfinite(temperature)) return fail(PNS_EINVAL, "temperature must be finite and > 0");
+    if (steps == 0) return PNS_OK;
+    const int64_t C = ctx->num_chains;
+    hipStream_t st = ctx->stream;
+    if (!ctx->xbest) {
+        int rc = dev_alloc(&ctx->xbest, (size_t)ctx->fields);
+        if (!rc) rc = dev_alloc(&ctx->Ebest, (size_t)C);
+        if (rc) return rc;
+    }
+    if (!ctx->best_valid) {
+        // X_max = J_0: the current states
+        HIP_TRY(hipMemcpyAsync(ctx->xbest, ctx->x, (size_t)ctx->fields, hipMemcpyDeviceToDevice, st), "best init");
+        HIP_TRY(hipMemcpyAsync(ctx->Ebest, ctx->E, (size_t)C * 8, hipMemcpyDeviceToDevice, st), "best init");
+        ctx->best_valid = true;
+    }
+    if (ctx->opt_classes.empty()) {
+        // every chain of a problem with n < N draws a fresh subset each step
+        // (flavour 2), the others consider all bits (flavour 0)
+        std::map<std::pair<std::pair<int32_t, int32_t>, int32_t>, size_t> class_of;
+        for (size_t p = 0; p < ctx->probs.size(); ++p) {
+            const ProblemRun& R = ctx->probs[p];
+            const int32_t flav = (ctx->mode != PNS_MODE_RF && R.n < R.N) ? 2 : 0;
+            const auto key = std::make_pair(std::make_pair(R.tile.block, R.tile.groups), flav);
+            if (!class_of.count(key)) {
+                class_of[key] = ctx->opt_classes.size();
+                LaunchClass k;
+                k.tile = R.tile;
+                k.flav = flav;
+                k.dyn = 0;
+                ctx->opt_classes.push_back(k);
+            }
+            LaunchClass& K = ctx->opt_classes[class_of[key]];
+            K.dyn = std::max(K.dyn, (size_t)R.pitch * 4 * (flav == 2 ? 2 : 1));
+            for (int32_t c = 0; c < R.chains; ++c) K.chains.push_back(R.chain_begin + c);
+        }
+        for (auto& k : ctx->opt_classes) {
+            int rc = dev_alloc(&k.d_list, k.chains.size());
+            if (rc) return rc;
+            HIP_TRY(hipMemcpy(k.d_list, k.chains.data(), k.chains.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+                    "upload chain list");
+        }
+    }
+    const int64_t chunk = ctx->chunk > 0 ? std::min<int64_t>(ctx->chunk, steps) : steps;
+    for (int64_t done = 0; done < steps; done += chunk) {
+        for (auto& k : ctx->opt_classes) {
+            StepArgs a = ctx->args(std::min(chunk, steps - done));
+            a.mode = 4;  // Alg 9 / Alg 10
+            a.inv_temp = 1.0 / temperature;
+            a.xbest = ctx->xbest;
+            a.Ebest = ctx->Ebest;
+            if (ctx->opt_classes.size() > 1 || (int64_t)k.chains.size() != C) a.chain_list = k.d_list;
+            hipError_t e = launch_steps(ctx->qtype, ctx->htype, k.flav, true, k.tile.block, k.tile.groups,
+                                        (int32_t)k.chains.size(), k.dyn, st, a);
+            if (e != hipSuccess) return hip_fail(e, "optimization kernel launch");
+        }
+    }
+    return PNS_OK;
+}
+
+int pns_read_best(pns_ctx* ctx, uint8_t* states, double* energies)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    if (!ctx->best_valid) return fail(PNS_EINVAL, "no optimization has run (pns_optimize)");
+    int rc = pns_sync(ctx);
+    if (rc) return rc;
+    const int64_t C = ctx->num_chains;
+    if (states) {
+        std::vector<uint8_t> xp;
+        if ((rc = d2h(xp, ctx->xbest, (size_t)ctx->fields))) return rc;
+        std::vector<uint8_t> xs((size_t)ctx->h_offsets.back());
+        for (int64_t c = 0; c < C; ++c)
+            std::memcpy(&xs[ctx->h_offsets[c]], &xp[ctx->h_foff[c]], ctx->probs[ctx->h_chain_problem[c]].N);
+        if ((rc = copy_out(states, xs.data(), xs.size()))) return rc;
+    }
+    if (energies) {
+        std::vector<int64_t> eb;
+        if ((rc = d2h(eb, ctx->Ebest, C))) return rc;
+        std::vector<double> e = energies_to_double(ctx, eb);
+        if ((rc = copy_out(energies, e.data(), C * 8))) return rc;
+    }
+    return PNS_OK;
+}
+
+int pns_adopt_best(pns_ctx* ctx)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    if (!ctx->best_valid) return fail(PNS_EINVAL, "no optimization has run (pns_optimize)");
+    hipStream_t st = ctx->stream;
+    const int64_t C = ctx->num_chains;
+    HIP_TRY(hipMemcpyAsync(ctx->x, ctx->xbest, (size_t)ctx->fields, hipMemcpyDeviceToDevice, st), "adopt best");
+    // fields and energies of the new states; budgets restart (a new block)
+    InitArgs ia{};
+    ia.problems = ctx->problems;
+    ia.chain_problem = ctx->chain_problem;
+    ia.foff = ctx->foff;
+    ia.num_chains = (int32_t)C;
+    ia.init = 2;
+    ia.seed = ctx->seed;
+    ia.chain_id = ctx->chain_id;
+    ia.x = ctx->x;
+    ia.h = ctx->h;
+    ia.E = ctx->E;
+    ia.last_E = ctx->last_E;
+    hipError_t e = launch_init_with_map(ctx->qtype, ctx->htype, (int32_t)ctx->max_pitch, st, ia,
+                                        ctx->h_chain_problem.data());
+    if (e != hipSuccess) return hip_fail(e, "recompute fields");
+    std::vector<int64_t> Lv((size_t)C);
+    for (int64_t c = 0; c < C; ++c) Lv[c] = ctx->probs[ctx->h_chain_problem[c]].L0;
+    std::vector<int32_t> la((size_t)C, PNS_STAY);
+    HIP_TRY(hipMemcpyAsync(ctx->L, Lv.data(), C * 8, hipMemcpyHostToDevice, st), "reset budgets");
+    HIP_TRY(hipMemcpyAsync(ctx->last_action, la.data(), C * 4, hipMemcpyHostToDevice, st), "reset records");
+    HIP_TRY(hipStreamSynchronize(st), "adopt best");
     return PNS_OK;
 }
 

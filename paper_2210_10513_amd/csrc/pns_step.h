@@ -42,6 +42,9 @@ namespace step {
 constexpr uint32_t kStreamStep = 0u;
 constexpr uint32_t kStreamSubset = 0x40000000u;
 constexpr int kModeRF = 0, kModeBasic = 1, kModeSys = 2, kModeRand = 3;
+// Optimization RF / PNS (Alg 9, 10): the jump chain at beta / T with no
+// multiplicity; a fresh random subset each step when n < N (as in Alg 3).
+constexpr int kModeOpt = 4;
 
 // Kernel flavours: how the subset of a step is formed.
 constexpr int FLAV_ALL = 0;     // every bit (RF, and Basic with n = N)
@@ -291,7 +294,7 @@ __device__ uint32_t draw_subset(uint32_t* own, uint64_t* masks, int tid, int64_t
 
 // Words of the leader lane's LDS state.
 constexpr int kLsE = 0, kLsL = 1, kLsLastA = 2, kLsLastM = 3, kLsLastE = 4, kLsSteps = 5, kLsFlips = 6,
-              kLsStays = 7, kLsSat = 8, kLsBad = 9, kLsSumM = 10, kLeadWords = 11;
+              kLsStays = 7, kLsSat = 8, kLsBad = 9, kLsSumM = 10, kLsBest = 11, kLeadWords = 12;
 
 // Occupancy asked of the compiler (waves per SIMD): compact-window kernels
 // of 512 lanes target two co-resident chains per compute unit (128 VGPRs);
@@ -352,7 +355,7 @@ void step_kernel(const StepArgs a)
     const int32_t n = FLAV == FLAV_ALL ? N : P.n;
     const int s = P.s;
     const int64_t off = a.foff[chain];
-    const double beta = a.beta[chain];
+    const double beta = a.beta[chain] * a.inv_temp;  // inv_temp = 1 except in kModeOpt
     const uint32_t cid = a.chain_id[chain];
     const uint64_t seed = a.seed;
 
@@ -400,18 +403,36 @@ void step_kernel(const StepArgs a)
 #pragma unroll
         for (int v = 0; v < 4; ++v) valid |= (uint32_t)((g * BLOCK + tid) * 4 + v < N) << (g * 4 + v);
 
+    // this lane's bits as bytes at dst[f] (the layout of x)
+    auto store_bits = [&](uint8_t* dst) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
+            if (fb < pitch) {
+                uint32_t xw = 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) xw |= ((xb >> (g * 4 + v)) & 1u) << (8 * v);
+                *reinterpret_cast<uint32_t*>(dst + fb) = xw;
+            }
+        }
+    };
     int64_t k = a.step[chain];
     const int64_t kend = k + a.steps;
     // Scalars only the leader lane uses (energy, budget, last record,
     // counters) live in LDS, not in every lane's registers.
     __shared__ int64_t lead_st[kLeadWords];
+    __shared__ int best_flag;  // the state after the last flip is a new X_max
     if (tid == lead_tid) {
         lead_st[kLsE] = a.E[chain];
+        if constexpr (INSTR) {
+            if (a.xbest != nullptr) lead_st[kLsBest] = a.Ebest[chain];
+        }
         lead_st[kLsL] = a.L[chain];
         lead_st[kLsLastA] = a.last_action[chain];
         lead_st[kLsLastM] = a.last_M[chain];
         lead_st[kLsLastE] = a.last_E[chain];
-        for (int q = kLsSteps; q < kLeadWords; ++q) lead_st[q] = 0;
+        for (int q = kLsSteps; q <= kLsSumM; ++q) lead_st[q] = 0;
+        best_flag = 0;
     }
     int64_t sub = a.sub[chain];
     int32_t snap_n = 0;
@@ -474,7 +495,8 @@ void step_kernel(const StepArgs a)
         }
         return m;
     };
-    uint32_t mem = (FLAV == FLAV_DRAWN && mode == kModeBasic) ? 0u : compute_mem();
+    const bool draw_each_step = mode == kModeBasic || mode == kModeOpt;
+    uint32_t mem = (FLAV == FLAV_DRAWN && draw_each_step) ? 0u : compute_mem();
 
     for (; k < kend; ++k) {
         if (k - ub_base >= 64) {
@@ -486,7 +508,7 @@ void step_kernel(const StepArgs a)
         U.U2 = read_lane(ubU2, uj);
         U.logU1 = lead ? read_lane(ubLog, uj) : 0.0;
         if constexpr (FLAV == FLAV_DRAWN) {
-            if (mode == kModeBasic) {
+            if (draw_each_step) {
                 pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k);
                 mem = compute_mem();
             }
@@ -652,6 +674,10 @@ void step_kernel(const StepArgs a)
         };
         scan_and_publish();
         __syncthreads();
+        if constexpr (INSTR) {
+            // X_max of Alg 9/10: the state reached by the previous step's flip
+            if (a.xbest != nullptr && best_flag) store_bits(a.xbest + off);
+        }
         double sv = lane < NSEG ? seg_sum[lane] : 0.0;
         double sinc = wave_scan(sv);
         double S = read_lane(sinc, NSEG - 1);
@@ -894,10 +920,15 @@ void step_kernel(const StepArgs a)
                 action = -1;
                 lead_st[kLsL] = P.L0;
                 lead_st[kLsStays] += 1;
+                if constexpr (INSTR) best_flag = 0;
             } else {
                 const int64_t sv0 = sel[0];
                 const int64_t dEc = sel[1];
                 if (!unbiased) multiplicity();
+                if (mode == kModeOpt) {
+                    m = 1;  // no multiplicity: each jump counts once
+                    sat = false;
+                }
                 if (unbiased) lead_st[kLsL] -= m;
                 lead_st[kLsSat] += sat ? 1 : 0;
                 lead_st[kLsBad] += (sv0 >> 41) & 1;
@@ -906,6 +937,14 @@ void step_kernel(const StepArgs a)
                 lead_st[kLsFlips] += 1;
                 M = m;
                 action = (int32_t)(sv0 & 0xFFFFFFFFll);
+                if constexpr (INSTR) {
+                    if (a.xbest != nullptr) {
+                        const int64_t En = lead_st[kLsE], Eb = lead_st[kLsBest];
+                        const bool better = kInt ? En < Eb : __longlong_as_double(En) < __longlong_as_double(Eb);
+                        if (better) lead_st[kLsBest] = En;
+                        best_flag = better ? 1 : 0;
+                    }
+                }
             }
             lead_st[kLsSteps] += 1;
             lead_st[kLsSumM] = __double_as_longlong(__longlong_as_double(lead_st[kLsSumM]) + (double)M);
@@ -932,6 +971,12 @@ void step_kernel(const StepArgs a)
                 }
             }
         }
+    }
+
+    if constexpr (INSTR) {
+        __syncthreads();
+        if (a.xbest != nullptr && best_flag) store_bits(a.xbest + off);
+        if (a.xbest != nullptr && tid == lead_tid) a.Ebest[chain] = lead_st[kLsBest];
     }
 
     // ---- chain state back to memory ----
