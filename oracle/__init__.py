@@ -92,6 +92,7 @@ class _RunArgs(ctypes.Structure):
         ("n_flips", ctypes.c_void_p), ("n_stays", ctypes.c_void_p), ("n_saturated", ctypes.c_void_p),
         ("temperature", ctypes.c_double), ("x_best", ctypes.c_void_p), ("Ei_best", ctypes.c_void_p),
         ("Ef_best", ctypes.c_void_p),
+        ("orig_time", ctypes.c_int64), ("n_records", ctypes.c_void_p), ("step0s", ctypes.c_void_p),
     ]
 
 
@@ -124,6 +125,9 @@ def _declare(L: ctypes.CDLL) -> None:
     L.orc_basic_onestep.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
     L.orc_basic_onestep.restype = ctypes.c_int
+    L.orc_pt_round.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
+    L.orc_pt_round.restype = ctypes.c_int
 
 
 def _ptr(a: Optional[np.ndarray]) -> Optional[int]:
@@ -215,18 +219,23 @@ class RunResult:
     saturated: Optional[np.ndarray] = None
     x_best: Optional[np.ndarray] = None   # MODE_OPT: best state X_max
     E_best: Optional[np.ndarray] = None
+    n_records: Optional[np.ndarray] = None  # records per chain
 
 
 def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, seed: int = 0,
         num_chains: int = 1, chain_ids=None, x0: Optional[np.ndarray] = None, init: str = "zero",
         layout: int = LAYOUT_SYMMETRIC, log: bool = True, hist: bool = False, hist_from: int = 0,
-        step0: int = 0, lib_handle: Optional[ctypes.CDLL] = None, temperature: float = 1.0) -> RunResult:
+        step0=0, lib_handle: Optional[ctypes.CDLL] = None, temperature: float = 1.0,
+        orig_time: int = 0) -> RunResult:
     """Run ``num_chains`` independent chains for ``K`` steps each.
 
     ``beta`` is a scalar or one value per chain; ``init`` is ``"zero"``,
     ``"random"`` (the Bernoulli(1/2) stream) or ignored when ``x0`` is given.
     ``MODE_OPT`` runs Alg 9 (n = N) / Alg 10 (n < N) at ``temperature`` and
-    fills ``x_best`` / ``E_best`` (the best state seen, X_max).
+    fills ``x_best`` / ``E_best`` (the best state seen, X_max).  With
+    ``orig_time`` > 0 (RF, Basic) each chain advances by exactly that many
+    original samples; ``K`` is then a cap and ``n_records`` the records made.
+    ``step0`` is a scalar or one first step index per chain.
     """
     is_int, Qc = _as_q(Q)
     N = Qc.shape[0]
@@ -268,7 +277,11 @@ def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, se
     a.Qi = Qc.ctypes.data if is_int else None
     a.Qf = None if is_int else Qc.ctypes.data
     a.mode, a.n, a.L0, a.seed = mode, (N if mode == MODE_RF else n), L0, seed
-    a.num_chains, a.chain_ids, a.betas, a.x0, a.K, a.step0 = C, cids.ctypes.data, betas.ctypes.data, x0.ctypes.data, K, step0
+    step0s = None
+    if np.ndim(step0) > 0:
+        step0s = np.ascontiguousarray(step0, dtype=np.int64)
+        step0 = 0
+    a.num_chains, a.chain_ids, a.betas, a.x0, a.K, a.step0 = C, cids.ctypes.data, betas.ctypes.data, x0.ctypes.data, K, int(step0)
     a.log_action = _ptr(r.action)
     a.log_M = _ptr(r.M)
     a.log_Ei = _ptr(r.E) if (log and is_int) else None
@@ -289,7 +302,34 @@ def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, se
     a.x_best = _ptr(r.x_best)
     a.Ei_best = _ptr(r.E_best) if is_int else _ptr(Eb_dummy)
     a.Ef_best = _ptr(Eb_dummy) if is_int else _ptr(r.E_best)
+    a.orig_time = orig_time
+    r.n_records = np.zeros(C, dtype=np.int64)
+    a.n_records = _ptr(r.n_records)
+    a.step0s = _ptr(step0s)
     rc = (lib_handle or lib()).orc_run(ctypes.byref(a))
     if rc != 0:
         raise ValueError(f"oracle run rejected its arguments (code {rc})")
     return r
+
+
+def pt_round(energies: np.ndarray, betas: np.ndarray, ladder: np.ndarray, T: int, seed: int, round_: int,
+             lib_handle: Optional[ctypes.CDLL] = None):
+    """One parallel-tempering swap round (see orc_pt_round); ``betas`` and
+    ``ladder`` (int32 [groups * T]) are updated in place.  Returns the
+    accepted flags [groups * T]."""
+    E = np.ascontiguousarray(energies)
+    is_int = np.issubdtype(E.dtype, np.integer)
+    Ei = E.astype(np.int64) if is_int else None
+    Ef = None if is_int else E.astype(np.float64)
+    assert betas.dtype == np.float64 and betas.flags["C_CONTIGUOUS"]
+    assert ladder.dtype == np.int32 and ladder.flags["C_CONTIGUOUS"]
+    groups = len(betas) // T
+    acc = np.zeros(groups * T, dtype=np.int32)
+    L = lib_handle or lib()
+    if lib_handle is not None:
+        _declare(L)
+    rc = L.orc_pt_round(groups, T, int(is_int), _ptr(Ei), _ptr(Ef), betas.ctypes.data, ladder.ctypes.data,
+                        seed, round_, acc.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad pt_round arguments")
+    return acc

@@ -268,6 +268,14 @@ typedef struct {
     uint8_t* x_best;            /* [num_chains][N] */
     int64_t* Ei_best;           /* [num_chains] */
     double* Ef_best;            /* [num_chains] */
+    /* RF / Basic: advance each chain by exactly orig_time original samples
+     * (0 = off): the records run until the multiplicities reach orig_time,
+     * the last one cut to the remaining time (the budget rule of Alg 6 used
+     * as a stopping time); n_records receives each chain's record count.
+     * step0s, if not NULL, gives each chain's first step index. */
+    int64_t orig_time;
+    int64_t* n_records;         /* [num_chains] */
+    const int64_t* step0s;      /* [num_chains] */
 } orc_run_args;
 
 /* Local field of bit j: the part of dE_j that depends on the other bits,
@@ -338,6 +346,8 @@ int orc_run(const orc_run_args* a)
     if (N <= 0) return -1;
     if (a->mode != ORC_MODE_RF && (a->n < 1 || a->n > N)) return -2;
     if (a->mode == ORC_MODE_OPT && !(a->temperature > 0.0)) return -4;
+    if (a->orig_time < 0 || (a->orig_time > 0 && a->mode != ORC_MODE_RF && a->mode != ORC_MODE_BASIC)) return -5;
+    const int timed = a->orig_time > 0;
     const int32_t n = a->mode == ORC_MODE_RF ? N : a->n;
     const int64_t I = orc_sys_count(N, n);
 
@@ -360,7 +370,9 @@ int orc_run(const orc_run_args* a)
         fields_init(a, x, hi, hf);
         int64_t Ei = a->is_int ? orc_energy_i(a->Qi, N, a->layout, x) : 0;
         double Ef = a->is_int ? (double)Ei : orc_energy_f(a->Qf, N, a->layout, x);
-        int64_t L = a->L0;
+        int64_t L = timed ? a->orig_time : a->L0;
+        const int64_t step0 = a->step0s ? a->step0s[ch] : a->step0;
+        int64_t nrec = 0;
         int64_t sub = 0;
         int64_t flips = 0, stays = 0, saturated = 0;
         /* X_max = J_0 */
@@ -371,11 +383,11 @@ int orc_run(const orc_run_args* a)
         /* Alg 6: the first partial neighbor set is N_0 (systematic) or a
          * fresh random set drawn for the step where the block starts. */
         if (a->mode == ORC_MODE_UNBIASED_SYS) orc_sys_subset(N, n, sub, member);
-        if (a->mode == ORC_MODE_UNBIASED_RAND) orc_random_subset(a->seed, cid, (uint64_t)a->step0, N, n, member);
+        if (a->mode == ORC_MODE_UNBIASED_RAND) orc_random_subset(a->seed, cid, (uint64_t)step0, N, n, member);
         if (a->mode == ORC_MODE_RF || (a->mode == ORC_MODE_OPT && n == N)) memset(member, 1, (size_t)N);
 
         for (int64_t kk = 0; kk < a->K; ++kk) {
-            const int64_t k = a->step0 + kk;
+            const int64_t k = step0 + kk;
             const size_t rec = (size_t)ch * (size_t)a->K + (size_t)kk;
 
             /* Alg 3: a fresh partial neighbor set every step. */
@@ -445,7 +457,14 @@ int orc_run(const orc_run_args* a)
             int32_t action;
             int64_t M;
             double tmargin = 0.0;
-            if (unbiased && q >= (double)L) {
+            if (timed && q >= (double)L) {
+                /* the original chain is still at J when the requested time
+                 * runs out: record the remaining time and stop */
+                M = L;
+                action = ORC_STAY;
+                L = 0;
+                ++stays;
+            } else if (unbiased && q >= (double)L) {
                 /* Alg 6 "else" branch: not enough remaining original
                  * samples; stay L times and move to the next set. */
                 M = L;
@@ -457,7 +476,7 @@ int orc_run(const orc_run_args* a)
                 ++stays;
             } else {
                 M = m;
-                if (unbiased) L -= m;
+                if (unbiased || timed) L -= m;
                 saturated += sat;
                 /* Proportional choice, App. C: the first index whose running
                  * sum exceeds U2 * S; rounding fallback: last positive one. */
@@ -524,7 +543,10 @@ int orc_run(const orc_run_args* a)
                 if (a->hist_w) a->hist_w[idx] = sat_add(a->hist_w[idx], (uint64_t)M);
                 if (a->hist_v) a->hist_v[idx] += 1u;
             }
+            ++nrec;
+            if (timed && action == ORC_STAY) break;
         }
+        if (a->n_records) a->n_records[ch] = nrec;
 
         if (a->x_final) memcpy(a->x_final + (size_t)ch * N, x, (size_t)N);
         if (a->hi_final && a->is_int) memcpy(a->hi_final + (size_t)ch * N, hi, sizeof(int64_t) * (size_t)N);
@@ -542,6 +564,51 @@ int orc_run(const orc_run_args* a)
     }
 
     free(x); free(xbest); free(member); free(hi); free(hf); free(dEi); free(dEf); free(lw); free(w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Parallel tempering (replica exchange between temperatures).               */
+/* ------------------------------------------------------------------------- */
+
+/* One swap round over `groups` groups of T chains (chains g*T .. g*T+T-1).
+ * ladder[g*T + t] is the chain of group g (0..T-1) holding the t-th
+ * temperature of the group's ladder.  Round r tries the pairs of positions
+ * (t, t+1) with t = r mod 2, r mod 2 + 2, ...: chains a (position t) and b
+ * (position t+1) exchange their inverse temperatures with probability
+ * min{1, exp[(beta_a - beta_b)(E_a - E_b)]}, the Metropolis ratio of
+ * pi_{beta_a}(x_b) pi_{beta_b}(x_a) / (pi_{beta_a}(x_a) pi_{beta_b}(x_b)).
+ * The uniform U in (0, 1] of a pair comes from Philox4x32-10 with key seed
+ * and counter (g, r low, r high, 0x60000000 | t), words 0 and 1 as for U1;
+ * the swap is accepted iff the exponent is >= 0 or log U < exponent.
+ * Energies are int64 (is_int) or double; accepted[g*T + t] = 1 if taken. */
+int orc_pt_round(int32_t groups, int32_t T, int32_t is_int, const int64_t* Ei, const double* Ef, double* betas,
+                 int32_t* ladder, uint64_t seed, uint64_t round, int32_t* accepted)
+{
+    if (groups < 0 || T < 1) return -1;
+    for (int32_t g = 0; g < groups; ++g) {
+        for (int32_t t = (int32_t)(round & 1u); t + 1 < T; t += 2) {
+            const int64_t ca = (int64_t)g * T + ladder[(int64_t)g * T + t];
+            const int64_t cb = (int64_t)g * T + ladder[(int64_t)g * T + t + 1];
+            const double dE = is_int ? (double)(Ei[ca] - Ei[cb]) : Ef[ca] - Ef[cb];
+            const double ex = (betas[ca] - betas[cb]) * dE;
+            uint32_t ctr[4] = {(uint32_t)g, (uint32_t)round, (uint32_t)(round >> 32), 0x60000000u | (uint32_t)t};
+            uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+            uint32_t o[4];
+            orc_philox4x32_10(ctr, key, o);
+            const double u = (double)(((((uint64_t)o[0] << 32) | o[1]) >> 11) + 1u) * 0x1p-53;
+            const int take = ex >= 0.0 || log(u) < ex;
+            if (accepted) accepted[(int64_t)g * T + t] = take;
+            if (take) {
+                const double tb = betas[ca];
+                betas[ca] = betas[cb];
+                betas[cb] = tb;
+                const int32_t tl = ladder[(int64_t)g * T + t];
+                ladder[(int64_t)g * T + t] = ladder[(int64_t)g * T + t + 1];
+                ladder[(int64_t)g * T + t + 1] = tl;
+            }
+        }
+    }
     return 0;
 }
 

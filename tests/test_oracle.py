@@ -454,3 +454,133 @@ def test_cold_optimization_ends_in_a_local_minimum_and_finds_the_ground_state():
             y[j] ^= 1
             assert int(y @ Qi @ y) >= e0
     assert r.E_best.min() == oracle.enumerate_energies(Q).min()
+
+
+# --------------------------------------------------------------------------
+# Original-time runs and parallel tempering
+# --------------------------------------------------------------------------
+
+def test_original_time_run_is_the_jump_chain_cut_at_time_t():
+    """The records of a run of T original samples are those of the untimed
+    run up to the record covering time T, whose multiplicity is cut to the
+    remaining time: the multiplicities sum to T exactly."""
+    Q = _small_int_q(10, 31)
+    T = 500
+    full = oracle.run(Q, 0.2, oracle.MODE_RF, 600, seed=4, num_chains=5)
+    cut = oracle.run(Q, 0.2, oracle.MODE_RF, T, seed=4, num_chains=5, orig_time=T)
+    for c in range(5):
+        k = int(cut.n_records[c])
+        assert cut.M[c, :k].sum() == T
+        assert cut.action[c, k - 1] == oracle.STAY
+        assert np.array_equal(cut.action[c, :k - 1], full.action[c, :k - 1])
+        assert np.array_equal(cut.M[c, :k - 1], full.M[c, :k - 1])
+        assert full.M[c, :k].sum() >= T > full.M[c, :k - 1].sum()
+
+
+def _pi_and_alpha(Q, beta):
+    N = Q.shape[0]
+    E = oracle.enumerate_energies(Q).astype(np.float64)
+    s = np.arange(1 << N)
+    alpha = np.mean([np.minimum(1.0, np.exp(-beta * (E[s ^ (1 << j)] - E))) for j in range(N)], axis=0)
+    pi = exact.target(Q, beta)
+    return pi, alpha
+
+
+def test_original_time_states_follow_pi_not_the_jump_law():
+    """From exact draws of pi, the original chain is still pi-distributed after
+    T original samples, while the jump chain's state law is alpha pi."""
+    Q = _small_int_q(8, 32, lo=-6, hi=6)
+    beta = 0.5
+    pi, alpha = _pi_and_alpha(Q, beta)
+    jump_law = alpha * pi / (alpha * pi).sum()
+    C = 40000
+    rng = np.random.default_rng(1)
+    idx0 = rng.choice(256, size=C, p=pi)
+    x0 = ((idx0[:, None] >> np.arange(8)) & 1).astype(np.uint8)
+    r = oracle.run(Q, beta, oracle.MODE_RF, 7, seed=9, num_chains=C, x0=x0, orig_time=7, log=False)
+    idx = (r.x.astype(np.int64) << np.arange(8)).sum(axis=1)
+    emp = np.bincount(idx, minlength=256) / C
+    floor = exact.tv(np.bincount(rng.choice(256, size=C, p=pi), minlength=256) / C, pi)
+    assert exact.tv(pi, jump_law) > 0.05
+    assert exact.tv(emp, pi) < floor + 0.015
+    assert exact.tv(emp, jump_law) > exact.tv(pi, jump_law) / 2
+
+
+def test_pt_swap_acceptance_rate_and_ladder():
+    """A pair of chains with fixed energies exchanges temperatures with
+    probability min{1, exp[(b_a - b_b)(E_a - E_b)]}; the ladder always lists
+    the chain holding each temperature."""
+    T = 2
+    groups = 20000
+    E = np.tile(np.array([5, 2], dtype=np.int64), groups)
+    ladder_betas = np.array([0.1, 0.5])
+    betas = np.tile(ladder_betas, groups).astype(np.float64)
+    ladder = np.tile(np.arange(T, dtype=np.int32), groups)
+    acc = oracle.pt_round(E, betas, ladder, T, seed=3, round_=0)
+    # chain 0 (beta 0.1, E 5) and chain 1 (beta 0.5, E 2): exponent (0.1-0.5)(5-2) = -1.2
+    rate = acc[0::2].mean()
+    assert abs(rate - np.exp(-1.2)) < 4 * np.sqrt(np.exp(-1.2) * (1 - np.exp(-1.2)) / groups)
+    for g in range(groups):
+        for t in range(T):
+            assert betas[g * T + ladder[g * T + t]] == ladder_betas[t]
+    # the reverse pair (higher energy at the colder temperature) always swaps
+    E2 = np.tile(np.array([2, 5], dtype=np.int64), groups)
+    betas2 = np.tile(ladder_betas, groups).astype(np.float64)
+    ladder2 = np.tile(np.arange(T, dtype=np.int32), groups)
+    assert oracle.pt_round(E2, betas2, ladder2, T, seed=3, round_=0)[0::2].all()
+
+
+def _pt_experiment(lib_handle=None):
+    """RF sweeps of 4 original samples alternated with swap rounds at two
+    temperatures; returns (TV of each temperature's states to its pi, the
+    sampling floor of each, swaps made)."""
+    Q = _small_int_q(6, 33, lo=-8, hi=8)
+    ladder_betas = np.array([0.15, 0.8])
+    T = 2
+    groups = 6000
+    C = groups * T
+    pis = [_pi_and_alpha(Q, b)[0] for b in ladder_betas]
+    rng = np.random.default_rng(2)
+    x = np.zeros((C, 6), np.uint8)
+    for t in range(T):
+        idx0 = rng.choice(64, size=groups, p=pis[t])
+        x[t::T] = ((idx0[:, None] >> np.arange(6)) & 1).astype(np.uint8)
+    betas = np.tile(ladder_betas, groups).astype(np.float64)
+    ladder = np.tile(np.arange(T, dtype=np.int32), groups)
+    steps = np.zeros(C, np.int64)
+    swaps = 0
+    for sweep in range(25):
+        r = oracle.run(Q, betas, oracle.MODE_RF, 4, seed=5, num_chains=C, x0=x, step0=steps, orig_time=4,
+                       lib_handle=lib_handle)
+        x = r.x
+        steps = steps + r.n_records
+        swaps += oracle.pt_round(r.E_final, betas, ladder, T, seed=5, round_=sweep, lib_handle=lib_handle).sum()
+    tvs, floors = [], []
+    for t in range(T):
+        chains = np.arange(groups) * T + ladder[t::T]
+        idx = (x[chains].astype(np.int64) << np.arange(6)).sum(axis=1)
+        tvs.append(exact.tv(np.bincount(idx, minlength=64) / groups, pis[t]))
+        floors.append(exact.tv(np.bincount(rng.choice(64, size=groups, p=pis[t]), minlength=64) / groups, pis[t]))
+    return tvs, floors, swaps
+
+
+def test_parallel_tempering_keeps_each_temperature_at_its_target():
+    """The state held at each temperature follows pi at that temperature
+    (enumeration) and swaps do happen."""
+    tvs, floors, swaps = _pt_experiment()
+    assert swaps > 0.05 * 6000 * 25 / 2
+    for tv, floor in zip(tvs, floors):
+        assert tv < floor + 0.02, (tvs, floors)
+
+
+@pytest.mark.parametrize("mutation", [
+    [("const double ex = (betas[ca] - betas[cb]) * dE;", "const double ex = (betas[cb] - betas[ca]) * dE;")],
+    [("                M = L;\n                action = ORC_STAY;\n                L = 0;",
+      "                M = L;\n                action = ORC_STAY;\n                L = 0;\n                x[0] ^= 1u;")],
+])
+def test_planted_tempering_mistakes_are_caught(mutation, tmp_path):
+    """A swap exponent of the wrong sign, or a chain that moves at the end of
+    its time budget, breaks the per-temperature laws."""
+    L = oracle.load_mutant(mutation, str(tmp_path))
+    tvs, floors, _ = _pt_experiment(L)
+    assert any(tv > floor + 0.02 for tv, floor in zip(tvs, floors)), (tvs, floors)
