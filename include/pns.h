@@ -358,6 +358,51 @@ int pns_read_best(pns_ctx* ctx, uint8_t* states, double* energies);
  * Errors: PNS_EINVAL (no pns_optimize yet), PNS_EDEVICE. */
 int pns_adopt_best(pns_ctx* ctx);
 
+/*
+ * Advance every chain of a Rejection-Free or Basic PNS context by exactly
+ * `original_steps` original samples (the time of the underlying Metropolis
+ * chain, Sec 1.2): records are made until their multiplicities reach
+ * original_steps, the record covering the end is cut to the remaining time
+ * (M = remaining, action PNS_STAY) and the chain stops on it without moving.
+ * This is the budget rule of Alg 6 used as a stopping time; by the
+ * memorylessness of the geometric holding time the next run continues the
+ * original chain exactly.  At a fixed original time the state follows the
+ * original chain's law (pi at stationarity), not the jump chain's alpha pi;
+ * parallel tempering (pns_pt_swap) compares chains at such times.  Chains
+ * end on different record counts (pns_read_current's step).  Queued on the
+ * context's stream.
+ * Errors: PNS_EINVAL (not an RF / Basic context, original_steps < 0),
+ * PNS_EDEVICE.
+ */
+int pns_run_original(pns_ctx* ctx, int64_t original_steps);
+
+/*
+ * One parallel-tempering swap round over groups of `temps` consecutive chains
+ * (chains g*temps .. g*temps+temps-1 hold one copy of each temperature of a
+ * ladder; Sec 5 combines replicas at different temperatures with PNS).  On
+ * the first call (or a new `temps`) each group's ladder is its chains ordered
+ * by their current beta.  Round r tries the adjacent ladder positions
+ * (t, t+1), t = r mod 2, r mod 2 + 2, ...: the two chains exchange their
+ * inverse temperatures with probability min{1, exp[(b_a - b_b)(E_a - E_b)]}
+ * (E the chains' current energies; U in (0, 1] from Philox with the
+ * context's seed, counter (group, r low, r high, 0x60000000 | t), accepted
+ * iff the exponent is >= 0 or log U is below it).  States stay with their
+ * chains; betas (pns_read_betas) and the ladder (pns_read_ladder) move.
+ * accepted [num_chains] int32 (host or device, or NULL) receives 1 at the
+ * position t of each accepted pair and 0 elsewhere.  Queued on the
+ * context's stream (synchronises for a host `accepted` and on the first
+ * call).  Errors: PNS_EINVAL (temps < 2 or not dividing the chains, a group
+ * across two problems, round < 0), PNS_EDEVICE.
+ */
+int pns_pt_swap(pns_ctx* ctx, int32_t temps, int64_t round, int32_t* accepted);
+
+/* Current inverse temperature of every chain [num_chains], host or device. */
+int pns_read_betas(pns_ctx* ctx, double* betas);
+
+/* Tempering ladder [num_chains]: entry g*temps + t is the chain of group g
+ * (0..temps-1) at temperature position t.  Errors: PNS_EINVAL (no swap yet). */
+int pns_read_ladder(pns_ctx* ctx, int32_t* ladder);
+
 /* ---- differentiation path ----
  *
  * The target pi_beta(x) = exp(-beta x^T Q x) / Z(Q, beta) gives

@@ -40,7 +40,7 @@ EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_cu
            "pns_destroy", "pns_tile", "pns_last_error", "pns_version", "pns_create_batch", "pns_autotune",
            "pns_chain_offsets", "pns_num_problems", "pns_problem_info_get", "pns_moments", "pns_snapshot_moments",
            "pns_log_partition", "pns_set_q", "pns_snapshots_clear", "pns_optimize", "pns_read_best",
-           "pns_adopt_best"]
+           "pns_adopt_best", "pns_run_original", "pns_pt_swap", "pns_read_betas", "pns_read_ladder"]
 
 
 class pns_opts(ctypes.Structure):
@@ -128,11 +128,16 @@ def _load() -> ctypes.CDLL:
     L.pns_optimize.argtypes = [vp, i64, dbl]
     L.pns_read_best.argtypes = [vp, vp, vp]
     L.pns_adopt_best.argtypes = [vp]
+    L.pns_run_original.argtypes = [vp, i64]
+    L.pns_pt_swap.argtypes = [vp, i32, i64, vp]
+    L.pns_read_betas.argtypes = [vp, vp]
+    L.pns_read_ladder.argtypes = [vp, vp]
     for name in ("pns_create", "pns_run", "pns_read", "pns_read_current", "pns_field_type", "pns_read_log",
                  "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync", "pns_destroy",
                  "pns_tile", "pns_create_batch", "pns_autotune", "pns_chain_offsets", "pns_num_problems",
                  "pns_problem_info_get", "pns_moments", "pns_snapshot_moments", "pns_log_partition", "pns_set_q",
-                 "pns_snapshots_clear", "pns_optimize", "pns_read_best", "pns_adopt_best"):
+                 "pns_snapshots_clear", "pns_optimize", "pns_read_best", "pns_adopt_best", "pns_run_original",
+                 "pns_pt_swap", "pns_read_betas", "pns_read_ladder"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -330,6 +335,22 @@ def pns_adopt_best(ctx) -> None:
     _check(lib.pns_adopt_best(ctx))
 
 
+def pns_run_original(ctx, original_steps: int) -> None:
+    _check(lib.pns_run_original(ctx, original_steps))
+
+
+def pns_pt_swap(ctx, temps: int, round_: int, accepted=None) -> None:
+    _check(lib.pns_pt_swap(ctx, temps, round_, _addr(accepted)))
+
+
+def pns_read_betas(ctx, betas) -> None:
+    _check(lib.pns_read_betas(ctx, _addr(betas)))
+
+
+def pns_read_ladder(ctx, ladder) -> None:
+    _check(lib.pns_read_ladder(ctx, _addr(ladder)))
+
+
 def pns_last_error() -> str:
     return lib.pns_last_error().decode()
 
@@ -478,6 +499,27 @@ class Sampler:
     def adopt_best(self) -> "Sampler":
         pns_adopt_best(self.ctx)
         return self
+
+    def run_original(self, original_steps: int) -> "Sampler":
+        """Advance every chain by exactly this many original samples."""
+        pns_run_original(self.ctx, original_steps)
+        return self
+
+    def pt_swap(self, temps: int, round_: int):
+        """One tempering swap round; returns the accepted flags."""
+        acc = np.zeros(self.num_chains, np.int32)
+        pns_pt_swap(self.ctx, temps, round_, acc)
+        return acc
+
+    def betas(self):
+        b = np.zeros(self.num_chains, np.float64)
+        pns_read_betas(self.ctx, b)
+        return b
+
+    def ladder(self):
+        l = np.zeros(self.num_chains, np.int32)
+        pns_read_ladder(self.ctx, l)
+        return l
 
     def snapshots_clear(self) -> "Sampler":
         pns_snapshots_clear(self.ctx)

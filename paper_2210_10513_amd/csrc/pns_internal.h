@@ -72,6 +72,7 @@ struct StepArgs {
     int64_t snap_pitch;
     // optimization runs (mode 4, instrumented kernels only)
     double inv_temp;                // 1 / T (1 for sampling)
+    int64_t orig_time;              // > 0: advance by this many original samples (RF, Basic)
     uint8_t* xbest;                 // [fields] best state X_max, or NULL
     int64_t* Ebest;                 // [C] its energy bits
 };
@@ -119,6 +120,12 @@ hipError_t launch_init_with_map(int32_t qtype, int32_t htype, int32_t max_pitch,
 // of |A| and max |diag| as FP64 bits), accumulated with atomics.
 hipError_t launch_prepare_rows(int32_t qtype, const void* Q, int32_t N, int32_t layout, int64_t pitch, void* A,
                                void* diag, unsigned long long* flags, hipStream_t st);
+
+// One parallel-tempering swap round over groups of T consecutive chains
+// (ladder [groups][T]: the chain of the group at each temperature position;
+// E as int64 or FP64 bits; accepted [C] or NULL).
+hipError_t launch_pt_swap(const int64_t* E, int32_t is_float, double* beta, int32_t* ladder, int32_t groups, int32_t T,
+                          uint64_t seed, uint64_t round, int32_t* accepted, hipStream_t st);
 
 // Fill `count` 64-bit words with a value (graph-safe alternative to memset).
 hipError_t launch_fill64(void* p, int64_t count, int64_t value, hipStream_t stream);

@@ -13,6 +13,7 @@ namespace {
 constexpr uint32_t kStreamStep = 0u;
 constexpr uint32_t kStreamInit = 0x20000000u;
 constexpr uint32_t kStreamSubset = 0x40000000u;
+constexpr uint32_t kStreamSwap = 0x60000000u;
 constexpr int kModeRF = 0, kModeBasic = 1, kModeSys = 2, kModeRand = 3;
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
@@ -314,6 +315,39 @@ __global__ __launch_bounds__(256) void prepare_row_kernel(const QT* __restrict__
     if (threadIdx.x == 0) atomicMax(&flags[2], (unsigned long long)__double_as_longlong(ssum[0]));
 }
 
+// Parallel tempering: one thread per pair of adjacent ladder positions
+// (pos, pos + 1), pos = round mod 2, round mod 2 + 2, ...  The chains exchange
+// inverse temperatures with probability min{1, exp[(b_a - b_b)(E_a - E_b)]};
+// U in (0, 1] from Philox (group, round, stream 0x60000000 | pos).
+__global__ void pt_swap_kernel(const int64_t* E, int32_t is_float, double* beta, int32_t* ladder, int32_t groups,
+                               int32_t T, uint64_t seed, uint64_t round, int32_t* accepted)
+{
+    const int32_t first = (int32_t)(round & 1u);
+    const int32_t pairs = (T - 1 - first + 1) / 2;
+    if (pairs <= 0) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t g = (int32_t)(t / pairs);
+    if (g >= groups) return;
+    const int32_t pos = first + 2 * (int32_t)(t % pairs);
+    int32_t* lad = ladder + (int64_t)g * T;
+    const int64_t ca = (int64_t)g * T + lad[pos];
+    const int64_t cb = (int64_t)g * T + lad[pos + 1];
+    const double dE = is_float ? __longlong_as_double(E[ca]) - __longlong_as_double(E[cb]) : (double)(E[ca] - E[cb]);
+    const double ex = (beta[ca] - beta[cb]) * dE;
+    const Words o = philox((uint32_t)g, (uint32_t)round, (uint32_t)(round >> 32), kStreamSwap | (uint32_t)pos, seed);
+    const double u = (double)(((((uint64_t)o.w0 << 32) | o.w1) >> 11) + 1u) * 0x1p-53;
+    const bool take = ex >= 0.0 || log(u) < ex;
+    if (accepted) accepted[(int64_t)g * T + pos] = take ? 1 : 0;
+    if (take) {
+        const double tb = beta[ca];
+        beta[ca] = beta[cb];
+        beta[cb] = tb;
+        const int32_t tl = lad[pos];
+        lad[pos] = lad[pos + 1];
+        lad[pos + 1] = tl;
+    }
+}
+
 __global__ void fill64_kernel(int64_t* p, int64_t count, int64_t value)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -391,6 +425,16 @@ hipError_t launch_prepare_rows(int32_t qtype, const void* Q, int32_t N, int32_t 
     else
         hipLaunchKernelGGL(prepare_row_kernel<float>, dim3(N), dim3(256), 0, st, reinterpret_cast<const float*>(Q), N,
                            layout, pitch, reinterpret_cast<float*>(A), reinterpret_cast<float*>(diag), flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_pt_swap(const int64_t* E, int32_t is_float, double* beta, int32_t* ladder, int32_t groups, int32_t T,
+                          uint64_t seed, uint64_t round, int32_t* accepted, hipStream_t st)
+{
+    const int64_t pairs = (int64_t)groups * ((T - (int32_t)(round & 1u)) / 2);
+    if (pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pt_swap_kernel, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, E, is_float, beta, ladder,
+                       groups, T, seed, round, accepted);
     return hipGetLastError();
 }
 

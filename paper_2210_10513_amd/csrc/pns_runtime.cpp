@@ -383,6 +383,10 @@ struct pns_ctx {
     int64_t* Ebest = nullptr;
     bool best_valid = false;
     std::vector<LaunchClass> opt_classes;
+    // parallel tempering: groups of pt_T consecutive chains, ladder [C]
+    int32_t pt_T = 0;
+    int32_t* pt_ladder = nullptr;
+    int32_t* pt_accepted = nullptr;
     // graph cache
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -431,10 +435,11 @@ struct pns_ctx {
         a.inv_temp = 1.0;
         a.xbest = nullptr;
         a.Ebest = nullptr;
+        a.orig_time = 0;
         return a;
     }
 
-    int launch_class(const LaunchClass& k, int64_t steps, hipStream_t st)
+    int launch_class(const LaunchClass& k, int64_t steps, hipStream_t st, int64_t orig_time = 0)
     {
         // host-side check that the launch matches what the kernels assume
         for (int32_t c : {k.chains.front(), k.chains.back()}) {
@@ -443,6 +448,7 @@ struct pns_ctx {
                 return fail(PNS_EINVAL, "tile %dx%d does not cover N=%d", k.tile.block, k.tile.groups, P.N);
         }
         StepArgs a = args(steps);
+        a.orig_time = orig_time;
         if (classes.size() > 1 || (int32_t)k.chains.size() != num_chains) a.chain_list = k.d_list;
         hipError_t e = launch_steps(qtype, htype, k.flav, instrumented(), k.tile.block, k.tile.groups,
                                     (int32_t)k.chains.size(), k.dyn, st, a);
@@ -452,14 +458,14 @@ struct pns_ctx {
 
     // One chunk of `steps` steps for every chain: one launch per class; with
     // several classes they run on their own streams between a fork and a join.
-    int launch_chunk(int64_t steps)
+    int launch_chunk(int64_t steps, int64_t orig_time = 0)
     {
-        if (classes.size() == 1) return launch_class(classes[0], steps, stream);
+        if (classes.size() == 1) return launch_class(classes[0], steps, stream, orig_time);
         HIP_TRY(hipEventRecord(fork, stream), "fork record");
         for (auto& sd : sides) {
             HIP_TRY(hipStreamWaitEvent(sd.stream, fork, 0), "fork wait");
             for (int32_t ki : sd.classes) {
-                int rc = launch_class(classes[ki], steps, sd.stream);
+                int rc = launch_class(classes[ki], steps, sd.stream, orig_time);
                 if (rc) return rc;
             }
             HIP_TRY(hipEventRecord(sd.done, sd.stream), "join record");
@@ -487,6 +493,8 @@ struct pns_ctx {
         for (auto& k : opt_classes)
             if (k.d_list) (void)hipFree(k.d_list);
         if (xbest) (void)hipFree(xbest);
+        if (pt_ladder) (void)hipFree(pt_ladder);
+        if (pt_accepted) (void)hipFree(pt_accepted);
         if (Ebest) (void)hipFree(Ebest);
         for (auto& sd : sides) {
             if (sd.stream) (void)hipStreamDestroy(sd.stream);
@@ -1862,6 +1870,91 @@ int pns_adopt_best(pns_ctx* ctx)
     HIP_TRY(hipMemcpyAsync(ctx->last_action, la.data(), C * 4, hipMemcpyHostToDevice, st), "reset records");
     HIP_TRY(hipStreamSynchronize(st), "adopt best");
     return PNS_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int pns_run_original(pns_ctx* ctx, int64_t original_steps)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    if (ctx->mode != PNS_MODE_RF && ctx->mode != PNS_MODE_BASIC)
+        return fail(PNS_EINVAL, "runs of original samples need a Rejection-Free or Basic PNS context");
+    if (original_steps < 0) return fail(PNS_EINVAL, "original_steps must be >= 0");
+    if (original_steps == 0) return PNS_OK;
+    // every record covers at least one original sample, so original_steps
+    // records always reach the end
+    return ctx->launch_chunk(original_steps, original_steps);
+}
+
+int pns_pt_swap(pns_ctx* ctx, int32_t temps, int64_t round, int32_t* accepted)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    const int64_t C = ctx->num_chains;
+    if (temps < 2 || C % temps != 0) return fail(PNS_EINVAL, "temps must be >= 2 and divide the number of chains");
+    if (round < 0) return fail(PNS_EINVAL, "round must be >= 0");
+    for (int64_t g0 = 0; g0 < C; g0 += temps)
+        if (ctx->h_chain_problem[g0] != ctx->h_chain_problem[g0 + temps - 1])
+            return fail(PNS_EINVAL, "a tempering group spans two problems");
+    hipStream_t st = ctx->stream;
+    if (ctx->pt_T != temps) {
+        // ladder: each group's chains ordered by their current beta
+        std::vector<double> b;
+        int rc = pns_sync(ctx);
+        if (!rc) rc = d2h(b, ctx->beta, (size_t)C);
+        if (rc) return rc;
+        std::vector<int32_t> lad((size_t)C);
+        for (int64_t g0 = 0; g0 < C; g0 += temps) {
+            for (int32_t t = 0; t < temps; ++t) lad[g0 + t] = t;
+            std::stable_sort(lad.begin() + g0, lad.begin() + g0 + temps,
+                             [&](int32_t x, int32_t y) { return b[g0 + x] < b[g0 + y]; });
+        }
+        if (!ctx->pt_ladder && (rc = dev_alloc(&ctx->pt_ladder, (size_t)C))) return rc;
+        if (!ctx->pt_accepted && (rc = dev_alloc(&ctx->pt_accepted, (size_t)C))) return rc;
+        HIP_TRY(hipMemcpy(ctx->pt_ladder, lad.data(), C * sizeof(int32_t), hipMemcpyHostToDevice), "upload ladder");
+        ctx->pt_T = temps;
+    }
+    const bool acc_dev = accepted && is_device_ptr(accepted);
+    int32_t* dacc = accepted ? (acc_dev ? accepted : ctx->pt_accepted) : nullptr;
+    if (dacc) {
+        hipError_t e = launch_fill64(dacc, C / 2, 0, st);
+        if (e != hipSuccess) return hip_fail(e, "clear accepted");
+        if (C % 2) HIP_TRY(hipMemsetAsync(dacc + C - 1, 0, 4, st), "clear accepted");
+    }
+    hipError_t e = launch_pt_swap(ctx->E, ctx->qtype == Q_F32 ? 1 : 0, ctx->beta, ctx->pt_ladder,
+                                  (int32_t)(C / temps), temps, ctx->seed, (uint64_t)round, dacc, st);
+    if (e != hipSuccess) return hip_fail(e, "swap kernel");
+    if (accepted && !acc_dev) {
+        HIP_TRY(hipMemcpyAsync(accepted, dacc, C * sizeof(int32_t), hipMemcpyDeviceToHost, st), "download accepted");
+        HIP_TRY(hipStreamSynchronize(st), "swap");
+    }
+    return PNS_OK;
+}
+
+int pns_read_betas(pns_ctx* ctx, double* betas)
+{
+    g_error.clear();
+    if (!ctx || !betas) return fail(PNS_EINVAL, "NULL argument");
+    int rc = pns_sync(ctx);
+    if (rc) return rc;
+    std::vector<double> b;
+    if ((rc = d2h(b, ctx->beta, (size_t)ctx->num_chains))) return rc;
+    return copy_out(betas, b.data(), b.size() * 8);
+}
+
+int pns_read_ladder(pns_ctx* ctx, int32_t* ladder)
+{
+    g_error.clear();
+    if (!ctx || !ladder) return fail(PNS_EINVAL, "NULL argument");
+    if (!ctx->pt_ladder) return fail(PNS_EINVAL, "no tempering ladder yet (pns_pt_swap)");
+    int rc = pns_sync(ctx);
+    if (rc) return rc;
+    std::vector<int32_t> l;
+    if ((rc = d2h(l, ctx->pt_ladder, (size_t)ctx->num_chains))) return rc;
+    return copy_out(ladder, l.data(), l.size() * 4);
 }
 
 }  // extern "C"

@@ -350,6 +350,10 @@ void step_kernel(const StepArgs a)
     QW* const dsh = reinterpret_cast<QW*>(own + (FLAV == FLAV_DRAWN ? pitch : 0));
     const int mode = a.mode;
     const bool unbiased = mode == kModeSys || mode == kModeRand;
+    // RF / Basic advancing by exactly a.orig_time original samples: the
+    // budget rule of Alg 6 used as a stopping time (the record covering the
+    // end is cut to the remaining time and the chain stops there)
+    const bool timed = a.orig_time > 0;
     constexpr bool kWin = FLAV == FLAV_WINDOW || FLAV == FLAV_WINDOW_C;
     constexpr bool kCompact = FLAV == FLAV_WINDOW_C;
     const int32_t n = FLAV == FLAV_ALL ? N : P.n;
@@ -427,7 +431,7 @@ void step_kernel(const StepArgs a)
         if constexpr (INSTR) {
             if (a.xbest != nullptr) lead_st[kLsBest] = a.Ebest[chain];
         }
-        lead_st[kLsL] = a.L[chain];
+        lead_st[kLsL] = timed ? a.orig_time : a.L[chain];
         lead_st[kLsLastA] = a.last_action[chain];
         lead_st[kLsLastM] = a.last_M[chain];
         lead_st[kLsLastE] = a.last_E[chain];
@@ -749,7 +753,7 @@ void step_kernel(const StepArgs a)
         };
         // Unbiased: wave 0 takes the budget decision of Alg 6 while the winner
         // wave resolves the (speculative) choice; both meet at the barrier.
-        if (unbiased && tid == lead_tid) {
+        if ((unbiased || timed) && tid == lead_tid) {
             multiplicity();
             stay_flag = q >= (double)lead_st[kLsL] ? 1 : 0;
         }
@@ -868,18 +872,20 @@ void step_kernel(const StepArgs a)
             }
         }
         __syncthreads();
-        const bool stay = unbiased && stay_flag != 0;
+        const bool stay = (unbiased || timed) && stay_flag != 0;
 
         if (stay) {
             // Alg 6: not enough remaining original samples; stay L times and
-            // switch to the next partial neighbor set.
-            ++sub;
-            if constexpr (FLAV == FLAV_DRAWN) {
-                pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k + 1);
-            } else if constexpr (kWin) {
-                sys_start = (int64_t)(((sub % P.num_sets) * (int64_t)n) % N);
+            // switch to the next partial neighbor set (a timed run just ends).
+            if (!timed) {
+                ++sub;
+                if constexpr (FLAV == FLAV_DRAWN) {
+                    pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k + 1);
+                } else if constexpr (kWin) {
+                    sys_start = (int64_t)(((sub % P.num_sets) * (int64_t)n) % N);
+                }
+                mem = compute_mem();
             }
-            mem = compute_mem();
         } else {
             const int64_t sv0 = sel[0];
             const int32_t c = (int32_t)(sv0 & 0xFFFFFFFFll);
@@ -918,18 +924,18 @@ void step_kernel(const StepArgs a)
             if (stay) {
                 M = lead_st[kLsL];
                 action = -1;
-                lead_st[kLsL] = P.L0;
+                lead_st[kLsL] = timed ? 0 : P.L0;
                 lead_st[kLsStays] += 1;
                 if constexpr (INSTR) best_flag = 0;
             } else {
                 const int64_t sv0 = sel[0];
                 const int64_t dEc = sel[1];
-                if (!unbiased) multiplicity();
+                if (!unbiased && !timed) multiplicity();
                 if (mode == kModeOpt) {
                     m = 1;  // no multiplicity: each jump counts once
                     sat = false;
                 }
-                if (unbiased) lead_st[kLsL] -= m;
+                if (unbiased || timed) lead_st[kLsL] -= m;
                 lead_st[kLsSat] += sat ? 1 : 0;
                 lead_st[kLsBad] += (sv0 >> 41) & 1;
                 if constexpr (kInt) lead_st[kLsE] = Erec + dEc;
@@ -971,6 +977,10 @@ void step_kernel(const StepArgs a)
                 }
             }
         }
+        if (timed && stay) {
+            ++k;  // the cut record was the run's last
+            break;
+        }
     }
 
     if constexpr (INSTR) {
@@ -1000,7 +1010,7 @@ void step_kernel(const StepArgs a)
         }
     }
     if (tid == lead_tid) {
-        a.step[chain] = kend;
+        a.step[chain] = k;
         a.E[chain] = lead_st[kLsE];
         a.L[chain] = lead_st[kLsL];
         a.sub[chain] = sub;
