@@ -93,6 +93,7 @@ class _RunArgs(ctypes.Structure):
         ("temperature", ctypes.c_double), ("x_best", ctypes.c_void_p), ("Ei_best", ctypes.c_void_p),
         ("Ef_best", ctypes.c_void_p),
         ("orig_time", ctypes.c_int64), ("n_records", ctypes.c_void_p), ("step0s", ctypes.c_void_p),
+        ("log_w", ctypes.c_void_p), ("hist_rb", ctypes.c_void_p),
     ]
 
 
@@ -128,6 +129,8 @@ def _declare(L: ctypes.CDLL) -> None:
     L.orc_pt_round.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
     L.orc_pt_round.restype = ctypes.c_int
+    L.orc_expected_multiplicity.argtypes = [ctypes.c_double, ctypes.c_int64]
+    L.orc_expected_multiplicity.restype = ctypes.c_double
 
 
 def _ptr(a: Optional[np.ndarray]) -> Optional[int]:
@@ -220,6 +223,8 @@ class RunResult:
     x_best: Optional[np.ndarray] = None   # MODE_OPT: best state X_max
     E_best: Optional[np.ndarray] = None
     n_records: Optional[np.ndarray] = None  # records per chain
+    w: Optional[np.ndarray] = None        # expected multiplicity of each record (Rao-Blackwell weight)
+    hist_rb: Optional[np.ndarray] = None  # sum of w per state
 
 
 def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, seed: int = 0,
@@ -258,6 +263,7 @@ def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, se
         r.p = np.zeros((C, K))
         r.q = np.zeros((C, K))
         r.tmargin = np.zeros((C, K))
+        r.w = np.zeros((C, K))
     r.x = np.zeros((C, N), dtype=np.uint8)
     r.h = np.zeros((C, N), dtype=np.int64 if is_int else np.float64)
     r.E_final = np.zeros(C, dtype=np.int64 if is_int else np.float64)
@@ -272,6 +278,7 @@ def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, se
             raise ValueError("histograms need N <= 24")
         r.hist_w = np.zeros(1 << N, dtype=np.uint64)
         r.hist_v = np.zeros(1 << N, dtype=np.uint64)
+        r.hist_rb = np.zeros(1 << N, dtype=np.float64)
     a = _RunArgs()
     a.N, a.is_int, a.layout = N, is_int, layout
     a.Qi = Qc.ctypes.data if is_int else None
@@ -306,10 +313,17 @@ def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, se
     r.n_records = np.zeros(C, dtype=np.int64)
     a.n_records = _ptr(r.n_records)
     a.step0s = _ptr(step0s)
+    a.log_w, a.hist_rb = _ptr(r.w), _ptr(r.hist_rb)
     rc = (lib_handle or lib()).orc_run(ctypes.byref(a))
     if rc != 0:
         raise ValueError(f"oracle run rejected its arguments (code {rc})")
     return r
+
+
+def expected_multiplicity(p: float, L: int = -1, lib_handle: Optional[ctypes.CDLL] = None) -> float:
+    """E[min(1 + G, L)] for G geometric (failures) with success probability
+    p, the mean multiplicity of a record (Thm 3 (2)); L < 0: no budget."""
+    return float((lib_handle or lib()).orc_expected_multiplicity(float(p), int(L)))
 
 
 def pt_round(energies: np.ndarray, betas: np.ndarray, ladder: np.ndarray, T: int, seed: int, round_: int,

@@ -276,7 +276,34 @@ typedef struct {
     int64_t orig_time;
     int64_t* n_records;         /* [num_chains] */
     const int64_t* step0s;      /* [num_chains] */
+    /* Rao-Blackwell weights (Thm 3 (2), (5)): the expected multiplicity of
+     * each record given its state, subset and budget, per step
+     * ([num_chains][K]) and summed per state ([2^N], N <= 24, from
+     * hist_from on); each may be NULL */
+    double* log_w;
+    double* hist_rb;
 } orc_run_args;
+
+/* Expected multiplicity of a record (Thm 3 (2)): M = 1 + G with G a
+ * geometric number of failures of success probability p, so
+ * P(M >= m) = (1 - p)^(m - 1), and for a record cut at a remaining budget L
+ * (Alg 6) the recorded value is min(M, L).  Its mean is the sum over m >= 1
+ * of P(min(M, L) >= m), added term by term up to m = L (L < 0: no budget;
+ * the infinite series then sums to 1 / p).  Terms below 2^-60 of the running
+ * sum are dropped. */
+double orc_expected_multiplicity(double p, int64_t L)
+{
+    if (p >= 1.0) return 1.0;
+    if (p <= 0.0) return L < 0 ? INFINITY : (double)L;
+    if (L < 0) return 1.0 / p;
+    double sum = 0.0, term = 1.0;
+    for (int64_t m = 1; m <= L; ++m) {
+        sum += term;
+        term *= 1.0 - p;
+        if (term < sum * 0x1p-60) break;
+    }
+    return sum;
+}
 
 /* Local field of bit j: the part of dE_j that depends on the other bits,
  * h_j = sum_{i != j} c(i, j) x_i / s where s = 2 for symmetric Q (so that
@@ -454,6 +481,10 @@ int orc_run(const orc_run_args* a)
             }
 
             const int unbiased = a->mode == ORC_MODE_UNBIASED_SYS || a->mode == ORC_MODE_UNBIASED_RAND;
+            /* Rao-Blackwell weight: the budget L at the start of the record
+             * cuts M for Unbiased PNS and exact-time runs */
+            const double wrb = a->mode == ORC_MODE_OPT ? 1.0
+                                                       : orc_expected_multiplicity(p, (unbiased || timed) ? L : -1);
             int32_t action;
             int64_t M;
             double tmargin = 0.0;
@@ -533,7 +564,8 @@ int orc_run(const orc_run_args* a)
             if (a->log_p) a->log_p[rec] = p;
             if (a->log_q) a->log_q[rec] = q;
             if (a->log_tmargin) a->log_tmargin[rec] = tmargin;
-            if ((a->hist_w || a->hist_v) && N <= 24 && k >= a->hist_from) {
+            if (a->log_w) a->log_w[rec] = wrb;
+            if ((a->hist_w || a->hist_v || a->hist_rb) && N <= 24 && k >= a->hist_from) {
                 uint32_t idx = 0;
                 for (int32_t j = 0; j < N; ++j) {
                     uint8_t bit = x[j];
@@ -542,6 +574,7 @@ int orc_run(const orc_run_args* a)
                 }
                 if (a->hist_w) a->hist_w[idx] = sat_add(a->hist_w[idx], (uint64_t)M);
                 if (a->hist_v) a->hist_v[idx] += 1u;
+                if (a->hist_rb) a->hist_rb[idx] += wrb;
             }
             ++nrec;
             if (timed && action == ORC_STAY) break;
