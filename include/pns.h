@@ -453,6 +453,60 @@ int pns_moments(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int3
 int pns_snapshot_moments(pns_ctx* ctx, int32_t problem, double* G, double* sum_m);
 
 /*
+ * G = X^T diag(w) X = sum_k w_k x_k x_k^T with real (FP64) weights, e.g. the
+ * expected multiplicities of pns_read_rb_weights (the Rao-Blackwellised
+ * ratio estimator of Thm 3 (5)).  Arguments as pns_moments, with
+ *   w      [K] FP64 weights of any sign, host or device; non-finite weights
+ *          count as 0 in G and in the sum.
+ *   sum_w  receives sum_k w_k (FP64 atomics: exact up to FP64 rounding in
+ *          an unspecified order), host or device, or NULL.
+ * The weights are scaled by the power of two 2^-e, e = ilogb(max_k |w_k|),
+ * rounded to FP32 (relative error <= 2^-24) and split exactly into three bf16
+ * pieces; the matrix cores then form exact products, which each wave sums in
+ * FP32 over R records before the FP64 reduction, R = 32 max(32,
+ * ceil(ceil(K / 32) T / 2048)) with T = t (t + 1) / 2, t = ceil(N / 64).
+ * Hence |G_ij - exact| <= (3 R + 2) 2^-24 sum_k |w_k| x_ki x_kj (a worst-case
+ * bound; typical errors are near sqrt(R) 2^-24) for weights within 2^100 of
+ * the largest; smaller ones fall below the bf16 normal range and may lose
+ * their low pieces.
+ * Errors: as pns_moments.
+ */
+int pns_moments_f64(const uint8_t* X, int64_t ldx, const double* w, int64_t K, int32_t N, double* G, double* sum_w,
+                    void* stream);
+
+/*
+ * Rao-Blackwell weights (Thm 3 (2), (5)): the expected multiplicity of a
+ * record given its state J_k, its subset and, for a budgeted record
+ * (Unbiased PNS, Alg 6, and runs of exact original time), the remaining
+ * budget L at the start of the record: with p the escape probability of the
+ * step and M = 1 + G, G ~ Geometric(p) counting failures,
+ *     w = E[min(M, L)] = (1 - (1 - p)^L) / p,   and w = 1 / p unbudgeted,
+ * (w = 1 for p >= 1; p <= 0, where every weight underflowed, gives L, or
+ * +inf unbudgeted; w = 1 in optimization runs, where M = 1).
+ * sum_k w_k h(J_k) / sum_k w_k estimates pi(h) like the multiplicity-weighted
+ * average, with the sampling noise of M removed.
+ *   log_w   [num_chains][log_capacity] weights of the per-step log ring
+ *           (slots as pns_read_log); PNS_EINVAL if the log is off.
+ *   snap_w  [num_chains][snapshot_capacity] weights of the snapshots (slots
+ *           as pns_read_snapshots, unwritten slots 0); PNS_EINVAL if
+ *           snapshots are off.
+ *   hist_rb [2^N] sum of the weights of the records per state (pooled over
+ *           chains, cleared by pns_hist_clear); PNS_EINVAL if histograms
+ *           are off.
+ * Any pointer may be NULL; each is host or device.  Synchronises.
+ */
+int pns_read_rb_weights(pns_ctx* ctx, double* log_w, double* snap_w, double* hist_rb);
+
+/*
+ * pns_snapshot_moments with the snapshots' expected multiplicities
+ * (pns_read_rb_weights) as weights, through pns_moments_f64 (same error
+ * bound); *sum_w receives their sum.  Queued on the context's stream;
+ * synchronises it only when G or sum_w is in host memory.
+ * Errors: as pns_snapshot_moments.
+ */
+int pns_snapshot_moments_rb(pns_ctx* ctx, int32_t problem, double* G, double* sum_w);
+
+/*
  * log Z(Q, beta) = log sum_x exp(-beta x^T Q x) by enumeration of all 2^N
  * states on the device (Gray-code order, incremental energies: exact int64
  * for integer Q, FP64 for float Q; FP64 log-sum-exp).  Q [N][N] of `dtype`

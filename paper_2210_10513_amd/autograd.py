@@ -10,6 +10,9 @@ the library's sampler on Q (Rejection-Free by default, or Unbiased PNS) and
 keeps snapshots (J_k, M_k) of its records; the backward pass calls the
 library's moment kernel, G = X^T diag(m) X on the bf16 matrix cores, and
 returns -beta G / sum(m) (the multiplicity-weighted average of Sec 1.2).
+With ``weights="rb"`` the multiplicities are replaced by their expected
+values given the records (1 / p, or the budget-cut mean for Unbiased PNS):
+the ratio estimator of Thm 3 (5) without the sampling noise of M.
 
 The forward value is log Z itself when N <= ``exact_max`` (enumeration on the
 device, ``pns_log_partition``).  Beyond that no exact value is available: the
@@ -36,7 +39,9 @@ from . import binding
 @dataclass
 class ChainOptions:
     """How LogZ samples: ``num_chains`` chains, ``burn_in`` steps, then
-    ``samples`` snapshots every ``every`` steps per chain.  ``state``, if a
+    ``samples`` snapshots every ``every`` steps per chain.  ``weights`` is
+    "M" (the sampled multiplicities) or "rb" (their expected values given
+    the records, the Rao-Blackwell weights of Thm 3 (5)).  ``state``, if a
     dict, keeps the sampler between calls (warm start, see LogZ)."""
     num_chains: int = 8192
     burn_in: int = 256
@@ -47,6 +52,7 @@ class ChainOptions:
     L0: int = 100
     seed: int = 0
     exact_max: int = 24
+    weights: str = "M"
     state: Optional[dict] = None
 
 
@@ -94,6 +100,7 @@ class LogZ(torch.autograd.Function):
         ctx.beta = float(beta)
         ctx.N = N
         ctx.qdtype = Q.dtype
+        ctx.rb = _rb(opts)
         return torch.tensor(value, dtype=Q.dtype, device=Q.device)
 
     @staticmethod
@@ -103,12 +110,18 @@ class LogZ(torch.autograd.Function):
         G = torch.empty((ctx.N, ctx.N), dtype=torch.float64, device=dev)
         sm = torch.empty(1, dtype=torch.float64, device=dev)
         # queued on the sampler's stream (the current stream): no host wait
-        binding.pns_snapshot_moments(s.ctx, 0, G, sum_m=sm)
+        binding.pns_snapshot_moments(s.ctx, 0, G, sum_m=sm, rb=ctx.rb)
         grad = (G * (-ctx.beta / sm)).to(ctx.qdtype)
         if ctx.owned:
             s.close()
         ctx.sampler = None
         return grad_out * grad, None, None
+
+
+def _rb(opts: ChainOptions) -> bool:
+    if opts.weights not in ("M", "rb"):
+        raise ValueError("weights must be 'M' or 'rb'")
+    return opts.weights == "rb"
 
 
 def release(state: Optional[dict]) -> None:
@@ -134,7 +147,7 @@ def moments_of_samples(Q_true: torch.Tensor, beta: float, opts: ChainOptions):
     s.run(opts.burn_in + opts.samples * opts.every)
     G = torch.empty((N, N), dtype=torch.float64, device=Q_true.device)
     sm = torch.empty(1, dtype=torch.float64, device=Q_true.device)
-    binding.pns_snapshot_moments(s.ctx, 0, G, sum_m=sm)
+    binding.pns_snapshot_moments(s.ctx, 0, G, sum_m=sm, rb=_rb(opts))
     out = G / sm
     s.close()
     return out, opts.num_chains * opts.samples

@@ -40,7 +40,8 @@ EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_cu
            "pns_destroy", "pns_tile", "pns_last_error", "pns_version", "pns_create_batch", "pns_autotune",
            "pns_chain_offsets", "pns_num_problems", "pns_problem_info_get", "pns_moments", "pns_snapshot_moments",
            "pns_log_partition", "pns_set_q", "pns_snapshots_clear", "pns_optimize", "pns_read_best",
-           "pns_adopt_best", "pns_run_original", "pns_pt_swap", "pns_read_betas", "pns_read_ladder"]
+           "pns_adopt_best", "pns_run_original", "pns_pt_swap", "pns_read_betas", "pns_read_ladder",
+           "pns_moments_f64", "pns_read_rb_weights", "pns_snapshot_moments_rb"]
 
 
 class pns_opts(ctypes.Structure):
@@ -132,12 +133,16 @@ def _load() -> ctypes.CDLL:
     L.pns_pt_swap.argtypes = [vp, i32, i64, vp]
     L.pns_read_betas.argtypes = [vp, vp]
     L.pns_read_ladder.argtypes = [vp, vp]
+    L.pns_moments_f64.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
+    L.pns_read_rb_weights.argtypes = [vp, vp, vp, vp]
+    L.pns_snapshot_moments_rb.argtypes = [vp, i32, vp, vp]
     for name in ("pns_create", "pns_run", "pns_read", "pns_read_current", "pns_field_type", "pns_read_log",
                  "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync", "pns_destroy",
                  "pns_tile", "pns_create_batch", "pns_autotune", "pns_chain_offsets", "pns_num_problems",
                  "pns_problem_info_get", "pns_moments", "pns_snapshot_moments", "pns_log_partition", "pns_set_q",
                  "pns_snapshots_clear", "pns_optimize", "pns_read_best", "pns_adopt_best", "pns_run_original",
-                 "pns_pt_swap", "pns_read_betas", "pns_read_ladder"):
+                 "pns_pt_swap", "pns_read_betas", "pns_read_ladder", "pns_moments_f64", "pns_read_rb_weights",
+                 "pns_snapshot_moments_rb"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -290,14 +295,33 @@ def pns_moments(X, m, G, *, N: Optional[int] = None, ldx: Optional[int] = None, 
     return float(sm[0])
 
 
-def pns_snapshot_moments(ctx, problem: int, G, sum_m=None):
-    """Moments of the snapshots of one problem; like pns_moments."""
-    if sum_m is not None:
-        _check(lib.pns_snapshot_moments(ctx, problem, _addr(G), _addr(sum_m)))
+def pns_moments_f64(X, w, G, *, N: Optional[int] = None, ldx: Optional[int] = None, stream=None, sum_w=None):
+    """G[:] = X^T diag(w) X with w [K] float64; otherwise like pns_moments."""
+    K = int(X.shape[0])
+    ld = int(X.shape[1]) if ldx is None else ldx
+    n = int(G.shape[0]) if N is None else N
+    if sum_w is not None:
+        _check(lib.pns_moments_f64(_addr(X), ld, _addr(w), K, n, _addr(G), _addr(sum_w), _stream_handle(stream)))
         return None
     sm = np.zeros(1, np.float64)
-    _check(lib.pns_snapshot_moments(ctx, problem, _addr(G), sm.ctypes.data))
+    _check(lib.pns_moments_f64(_addr(X), ld, _addr(w), K, n, _addr(G), sm.ctypes.data, _stream_handle(stream)))
     return float(sm[0])
+
+
+def pns_snapshot_moments(ctx, problem: int, G, sum_m=None, *, rb: bool = False):
+    """Moments of the snapshots of one problem; like pns_moments.  With
+    ``rb`` the weights are the expected multiplicities (pns_read_rb_weights)."""
+    fn = lib.pns_snapshot_moments_rb if rb else lib.pns_snapshot_moments
+    if sum_m is not None:
+        _check(fn(ctx, problem, _addr(G), _addr(sum_m)))
+        return None
+    sm = np.zeros(1, np.float64)
+    _check(fn(ctx, problem, _addr(G), sm.ctypes.data))
+    return float(sm[0])
+
+
+def pns_read_rb_weights(ctx, log_w=None, snap_w=None, hist_rb=None) -> None:
+    _check(lib.pns_read_rb_weights(ctx, _addr(log_w), _addr(snap_w), _addr(hist_rb)))
 
 
 def pns_log_partition(Q, beta: float, *, layout: int = PNS_SYMMETRIC, stream=None) -> float:
@@ -416,6 +440,8 @@ class Sampler:
         o.autotune = 1 if autotune else 0
         self.log_capacity = log_capacity
         self.snapshot_capacity = snapshot_capacity
+        self.snapshot_every = snapshot_every
+        self.hist = bool(hist)
         self.ctx = pns_create(self._Q, self.N, float(betas[0]), subset_size, self.mode, o)
 
     def run(self, steps: int) -> "Sampler":
@@ -525,12 +551,25 @@ class Sampler:
         pns_snapshots_clear(self.ctx)
         return self
 
-    def snapshot_moments(self, G=None):
-        """(G, sum_m): G = X^T diag(m) X over every stored snapshot."""
+    def snapshot_moments(self, G=None, *, rb: bool = False):
+        """(G, sum_w): G = X^T diag(w) X over every stored snapshot, w the
+        multiplicities M, or with ``rb`` their expected values given the
+        records (Rao-Blackwell weights)."""
         if G is None:
             G = np.zeros((self.N, self.N), np.float64)
-        sm = pns_snapshot_moments(self.ctx, 0, G)
+        sm = pns_snapshot_moments(self.ctx, 0, G, rb=rb)
         return G, sm
+
+    def rb_weights(self):
+        """Expected multiplicities of the records: {"log": [C, log_capacity]
+        or None, "snap": [C, snapshot_capacity] or None, "hist": [2^N] or
+        None}, whichever outputs the sampler keeps."""
+        C = self.num_chains
+        lw = np.zeros((C, self.log_capacity)) if self.log_capacity else None
+        sw = np.zeros((C, self.snapshot_capacity)) if self.snapshot_every else None
+        hw = np.zeros(1 << self.N) if self.hist else None
+        pns_read_rb_weights(self.ctx, lw, sw, hw)
+        return {"log": lw, "snap": sw, "hist": hw}
 
     def tile(self):
         return pns_tile(self.ctx)

@@ -60,14 +60,17 @@ struct StepArgs {
     int64_t* log_M;
     int64_t* log_E;                 // energy bits
     double* log_p;
+    double* log_w;                  // expected multiplicity of the record (Rao-Blackwell weight)
     int64_t log_cap;
     unsigned long long* hist_w;     // [2^N]
     unsigned long long* hist_v;
+    double* hist_rb;                // [2^N] sum of expected multiplicities
     int32_t snap_every;
     int32_t snap_cap;
     uint8_t* snap_x;                // [C][snap_cap][snap_pitch]
     int64_t* snap_M;                // [C][snap_cap]
     int64_t* snap_E;                // [C][snap_cap]
+    double* snap_w;                 // [C][snap_cap] expected multiplicity of the record
     int32_t* snap_count;            // [C]
     int64_t snap_pitch;
     // optimization runs (mode 4, instrumented kernels only)
@@ -148,6 +151,14 @@ hipError_t launch_pack_bits(const uint8_t* X, int64_t ldx, int64_t K, int32_t N,
 hipError_t launch_moments(const uint32_t* Xb, int32_t npad, int64_t words, int32_t N, const uint16_t* pieces,
                           int64_t kpad, int64_t chunk_words, const unsigned long long* max_m, float* part, double* G,
                           hipStream_t st);
+// Weight pieces of FP64 weights: *maxbits (zeroed by the caller) receives the
+// largest finite |w| (as bits), the weights are scaled by 2^-ilogb(max),
+// rounded to FP32 and split exactly into three bf16; *sum_w (zeroed) receives
+// their unscaled FP64 sum.  Non-finite weights count as 0.
+hipError_t launch_moments_prep_f64(const double* w, int64_t K, int64_t kpad, uint16_t* pieces, double* sum_w,
+                                   unsigned long long* maxbits, hipStream_t st);
+// G[0..n) *= 2^ilogb(max): undoes the weight scaling of launch_moments_prep_f64.
+hipError_t launch_moments_unscale(double* G, int64_t n, const unsigned long long* maxbits, hipStream_t st);
 // *out = (double)*sum_m on the device.
 hipError_t launch_moments_sum(const unsigned long long* sum_m, double* out, hipStream_t st);
 // log Z by enumeration: `blocks` x 256 threads, thread t covers the states

@@ -69,6 +69,62 @@ __global__ void moments_prep_kernel(const int64_t* m, int64_t K, int64_t kpad, u
     }
 }
 
+// Real (FP64) weights, e.g. the expected multiplicities 1 / p of Thm 3 (5).
+// First the largest |w_k| (finite ones; bit patterns of non-negative doubles
+// order like the numbers), so that the weights can be scaled by a power of
+// two into [-2, 2] before they are rounded to FP32 (relative 2^-24) and split
+// exactly into three bf16 pieces; G is scaled back at the end.  Non-finite
+// weights count as 0 in G and in the sum.
+__global__ void moments_absmax_kernel(const double* w, int64_t K, unsigned long long* maxbits)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (k < K && isfinite(w[k])) v = fabs(w[k]);
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const unsigned long long o = __shfl_xor(b, d, 64);
+        b = b > o ? b : o;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(maxbits, b);
+}
+
+__device__ __forceinline__ int weight_exponent(const unsigned long long* maxbits)
+{
+    const double mx = __longlong_as_double((long long)*maxbits);
+    return mx > 0.0 ? ilogb(mx) : 0;
+}
+
+__global__ void moments_prep_f64_kernel(const double* w, int64_t K, int64_t kpad, uint16_t* pieces, double* sum_w,
+                                        const unsigned long long* maxbits)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double wk = 0.0;
+    if (k < K && isfinite(w[k])) wk = w[k];
+    if (k < kpad) {
+        float r = (float)ldexp(wk, -weight_exponent(maxbits));
+        uint16_t b[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            b[s] = bf16_bits(r);
+            r = r - bf16_value(b[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < 3; ++s) pieces[s * kpad + k] = b[s];
+    }
+    double sv = wk;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) sv += __shfl_xor(sv, d, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(sum_w, sv);
+}
+
+// G *= 2^e, the scale the weights were divided by.
+__global__ void moments_unscale_kernel(double* G, int64_t n, const unsigned long long* maxbits)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) G[i] = ldexp(G[i], weight_exponent(maxbits));
+}
+
 constexpr int kTile = 64;  // output tile (rows and columns) per wave
 
 // Upper-triangle tile t (row-major over ti <= tj) -> (ti, tj).
@@ -386,6 +442,22 @@ hipError_t launch_moments_prep(const int64_t* m, int64_t K, int64_t kpad, uint16
     const int64_t n = kpad > K ? kpad : K;
     hipLaunchKernelGGL(moments_prep_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, m, K, kpad, pieces,
                        sum_m, max_m);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_prep_f64(const double* w, int64_t K, int64_t kpad, uint16_t* pieces, double* sum_w,
+                                   unsigned long long* maxbits, hipStream_t st)
+{
+    if (K > 0) hipLaunchKernelGGL(moments_absmax_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, w, K, maxbits);
+    const int64_t n = kpad > K ? kpad : K;
+    hipLaunchKernelGGL(moments_prep_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, K, kpad, pieces,
+                       sum_w, maxbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_unscale(double* G, int64_t n, const unsigned long long* maxbits, hipStream_t st)
+{
+    hipLaunchKernelGGL(moments_unscale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, G, n, maxbits);
     return hipGetLastError();
 }
 

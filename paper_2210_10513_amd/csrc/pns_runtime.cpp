@@ -371,12 +371,15 @@ struct pns_ctx {
     int64_t* log_M = nullptr;
     int64_t* log_E = nullptr;
     double* log_p = nullptr;
+    double* log_w = nullptr;
     unsigned long long* hist_w = nullptr;
     unsigned long long* hist_v = nullptr;
+    double* hist_rb = nullptr;
     int32_t snap_every = 0, snap_cap = 0;
     uint8_t* snap_x = nullptr;
     int64_t* snap_M = nullptr;
     int64_t* snap_E = nullptr;
+    double* snap_w = nullptr;
     int32_t* snap_count = nullptr;
     // optimization runs: best states and their launch classes (built on first use)
     uint8_t* xbest = nullptr;
@@ -422,14 +425,17 @@ struct pns_ctx {
         a.log_M = log_M;
         a.log_E = log_E;
         a.log_p = log_p;
+        a.log_w = log_w;
         a.log_cap = log_cap;
         a.hist_w = hist_w;
         a.hist_v = hist_v;
+        a.hist_rb = hist_rb;
         a.snap_every = snap_every;
         a.snap_cap = snap_cap;
         a.snap_x = snap_x;
         a.snap_M = snap_M;
         a.snap_E = snap_E;
+        a.snap_w = snap_w;
         a.snap_count = snap_count;
         a.snap_pitch = max_pitch;
         a.inv_temp = 1.0;
@@ -479,8 +485,8 @@ struct pns_ctx {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
         void* ptrs[] = {problems, chain_problem, foff, beta, chain_id, x, h, rmem, E, L, sub, step, last_action, last_M,
-                        last_E, counters, log_action, log_M, log_E, log_p, hist_w, hist_v, snap_x, snap_M, snap_E,
-                        snap_count};
+                        last_E, counters, log_action, log_M, log_E, log_p, log_w, hist_w, hist_v, hist_rb,
+                        snap_x, snap_M, snap_E, snap_w, snap_count};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         for (auto& P : probs) {
@@ -727,10 +733,12 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         ALLOC(ctx->log_M, int64_t, (size_t)C * o.log_capacity);
         ALLOC(ctx->log_E, int64_t, (size_t)C * o.log_capacity);
         ALLOC(ctx->log_p, double, (size_t)C * o.log_capacity);
+        ALLOC(ctx->log_w, double, (size_t)C * o.log_capacity);
     }
     if (o.hist) {
         ALLOC(ctx->hist_w, unsigned long long, (size_t)1 << specs[0].N);
         ALLOC(ctx->hist_v, unsigned long long, (size_t)1 << specs[0].N);
+        ALLOC(ctx->hist_rb, double, (size_t)1 << specs[0].N);
     }
     if (o.snapshot_every > 0) {
         ctx->snap_every = o.snapshot_every;
@@ -738,6 +746,7 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         ALLOC(ctx->snap_x, uint8_t, (size_t)C * o.snapshot_capacity * ctx->max_pitch);
         ALLOC(ctx->snap_M, int64_t, (size_t)C * o.snapshot_capacity);
         ALLOC(ctx->snap_E, int64_t, (size_t)C * o.snapshot_capacity);
+        ALLOC(ctx->snap_w, double, (size_t)C * o.snapshot_capacity);
         ALLOC(ctx->snap_count, int32_t, (C + 1) / 2 * 2);  // whole 64-bit words (cleared as such)
     }
     for (auto& k : ctx->classes) ALLOC(k.d_list, int32_t, k.chains.size());
@@ -770,6 +779,7 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
     if (ctx->hist_w) {
         e = hipMemset(ctx->hist_w, 0, sizeof(unsigned long long) << specs[0].N);
         if (e == hipSuccess) e = hipMemset(ctx->hist_v, 0, sizeof(unsigned long long) << specs[0].N);
+        if (e == hipSuccess) e = hipMemset(ctx->hist_rb, 0, sizeof(double) << specs[0].N);
         if (e != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
     }
     if (ctx->rmem && (e = hipMemset(ctx->rmem, 0, fields)) != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
@@ -778,6 +788,7 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         e = hipMemset(ctx->snap_x, 0, (size_t)C * ctx->snap_cap * ctx->max_pitch);
         if (e == hipSuccess) e = hipMemset(ctx->snap_M, 0, (size_t)C * ctx->snap_cap * 8);
         if (e == hipSuccess) e = hipMemset(ctx->snap_E, 0, (size_t)C * ctx->snap_cap * 8);
+        if (e == hipSuccess) e = hipMemset(ctx->snap_w, 0, (size_t)C * ctx->snap_cap * 8);
         if (e != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
     }
     if (ctx->classes.size() > 1) {
@@ -1407,6 +1418,7 @@ int pns_hist_clear(pns_ctx* ctx)
     const int64_t cnt = (int64_t)1 << ctx->probs[0].N;
     hipError_t e = launch_fill64(ctx->hist_w, cnt, 0, ctx->stream);
     if (e == hipSuccess) e = launch_fill64(ctx->hist_v, cnt, 0, ctx->stream);
+    if (e == hipSuccess) e = launch_fill64(ctx->hist_rb, cnt, 0, ctx->stream);  // +0.0 is all-zero bits
     if (e != hipSuccess) return hip_fail(e, "histogram clear");
     return PNS_OK;
 }
@@ -1477,13 +1489,14 @@ int pns_destroy(pns_ctx* ctx)
 
 namespace {
 
-// G (N x N, FP64, overwritten) = X^T diag(m) X, queued on `st` without a
-// host synchronisation; device pointers.  The exact sum of the weights goes
-// to *sum_host (synchronising) and/or *sum_dev (queued), either may be NULL.
+// G (N x N, FP64, overwritten) = X^T diag(w) X, queued on `st` without a
+// host synchronisation; device pointers.  The weights are integers m (exact
+// path) or, when m is NULL, FP64 weights wf.  The sum of the weights goes to
+// *sum_host (synchronising) and/or *sum_dev (queued), either may be NULL.
 // Workspace comes from the stream-ordered allocator and is released in
 // stream order.
-int moments_device(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int32_t N, double* G, hipStream_t st,
-                   double* sum_host, double* sum_dev)
+int moments_device(const uint8_t* X, int64_t ldx, const int64_t* m, const double* wf, int64_t K, int32_t N, double* G,
+                   hipStream_t st, double* sum_host, double* sum_dev)
 {
     const int64_t kpad = std::max<int64_t>(64, round_up(K, 64));
     const int32_t npad = (int32_t)round_up(N, 64);
@@ -1504,7 +1517,9 @@ int moments_device(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, i
         if (part) (void)hipFreeAsync(part, st);
     };
     hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&pieces), (size_t)3 * kpad * sizeof(uint16_t), st);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&cnt), 2 * sizeof(unsigned long long), st);
+    // cnt: [0] sum of the weights (uint64, or FP64 bits), [1] largest integer
+    // weight (0 on the FP64 path: no flushes), [2] largest |FP64 weight| bits
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&cnt), 3 * sizeof(unsigned long long), st);
     if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&Xb), (size_t)words * npad * sizeof(uint32_t), st);
     if (e == hipSuccess)
         e = hipMallocAsync(reinterpret_cast<void**>(&part), (size_t)chunks * tiles * 64 * 64 * sizeof(float), st);
@@ -1514,11 +1529,18 @@ int moments_device(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, i
         return fail(PNS_ENOMEM, "workspace allocation failed: %s", hipGetErrorString(e));
     }
     e = launch_fill64(G, (int64_t)N * N, 0, st);
-    if (e == hipSuccess) e = launch_fill64(cnt, 2, 0, st);
-    if (e == hipSuccess) e = launch_moments_prep(m, K, kpad, pieces, cnt, cnt + 1, st);
+    if (e == hipSuccess) e = launch_fill64(cnt, 3, 0, st);
+    if (e == hipSuccess) {
+        if (m) e = launch_moments_prep(m, K, kpad, pieces, cnt, cnt + 1, st);
+        else e = launch_moments_prep_f64(wf, K, kpad, pieces, reinterpret_cast<double*>(cnt), cnt + 2, st);
+    }
     if (e == hipSuccess) e = launch_pack_bits(X, ldx, K, N, npad, words, Xb, st);
     if (e == hipSuccess) e = launch_moments(Xb, npad, words, N, pieces, kpad, chunk_words, cnt + 1, part, G, st);
-    if (e == hipSuccess && sum_dev) e = launch_moments_sum(cnt, sum_dev, st);
+    if (e == hipSuccess && !m) e = launch_moments_unscale(G, (int64_t)N * N, cnt + 2, st);
+    if (e == hipSuccess && sum_dev) {
+        if (m) e = launch_moments_sum(cnt, sum_dev, st);
+        else e = hipMemcpyAsync(sum_dev, cnt, sizeof(double), hipMemcpyDeviceToDevice, st);
+    }
     unsigned long long hs = 0;
     if (e == hipSuccess && sum_host) {
         e = hipMemcpyAsync(&hs, cnt, sizeof(hs), hipMemcpyDeviceToHost, st);
@@ -1526,26 +1548,27 @@ int moments_device(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, i
     }
     release();
     if (e != hipSuccess) return hip_fail(e, "moments kernels");
-    if (sum_host) *sum_host = (double)hs;
+    if (sum_host) {
+        if (m) *sum_host = (double)hs;
+        else std::memcpy(sum_host, &hs, sizeof(double));
+    }
     return PNS_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int pns_moments(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int32_t N, double* G, double* sum_m,
-                void* stream)
+// pns_moments / pns_moments_f64: host or device inputs; exactly one of m, wf.
+int moments_entry(const uint8_t* X, int64_t ldx, const int64_t* m, const double* wf, int64_t K, int32_t N, double* G,
+                  double* sum_w, void* stream)
 {
     g_error.clear();
-    if (!X || !m || !G) return fail(PNS_EINVAL, "NULL argument");
+    if (!X || (!m && !wf) || !G) return fail(PNS_EINVAL, "NULL argument");
     if (N < 1 || N > 32768) return fail(PNS_EINVAL, "N must be in [1, 32768]");
     if (K < 0) return fail(PNS_EINVAL, "K must be >= 0");
     if (ldx < N) return fail(PNS_EINVAL, "ldx must be >= N");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const bool xd = is_device_ptr(X), md = is_device_ptr(m), gd = is_device_ptr(G);
+    const void* wv = m ? static_cast<const void*>(m) : static_cast<const void*>(wf);
+    const bool xd = is_device_ptr(X), md = is_device_ptr(wv), gd = is_device_ptr(G);
     uint8_t* dX = nullptr;
-    int64_t* dm = nullptr;
+    int64_t* dm = nullptr;  // 8-byte weights of either type
     double* dG = nullptr;
     auto done = [&](int r) {
         if (!xd && dX) (void)hipFree(dX);
@@ -1558,14 +1581,15 @@ int pns_moments(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int3
     else if (!(rc = dev_alloc(&dX, (size_t)K * ldx)) && K > 0)
         if (hipMemcpy(dX, X, (size_t)K * ldx, hipMemcpyHostToDevice) != hipSuccess) rc = fail(PNS_EDEVICE, "upload X");
     if (rc) return done(rc);
-    if (md) dm = const_cast<int64_t*>(m);
+    if (md) dm = static_cast<int64_t*>(const_cast<void*>(wv));
     else if (!(rc = dev_alloc(&dm, (size_t)K)) && K > 0)
-        if (hipMemcpy(dm, m, (size_t)K * 8, hipMemcpyHostToDevice) != hipSuccess) rc = fail(PNS_EDEVICE, "upload m");
+        if (hipMemcpy(dm, wv, (size_t)K * 8, hipMemcpyHostToDevice) != hipSuccess) rc = fail(PNS_EDEVICE, "upload weights");
     if (rc) return done(rc);
     if (gd) dG = G;
     else if ((rc = dev_alloc(&dG, (size_t)N * N))) return done(rc);
-    const bool sd = sum_m && is_device_ptr(sum_m);
-    rc = moments_device(dX, ldx, dm, K, N, dG, st, sum_m && !sd ? sum_m : nullptr, sd ? sum_m : nullptr);
+    const bool sd = sum_w && is_device_ptr(sum_w);
+    rc = moments_device(dX, ldx, m ? dm : nullptr, m ? nullptr : reinterpret_cast<const double*>(dm), K, N, dG, st,
+                        sum_w && !sd ? sum_w : nullptr, sd ? sum_w : nullptr);
     if (rc) return done(rc);
     if (!gd) {
         hipError_t e = hipMemcpyAsync(G, dG, (size_t)N * N * 8, hipMemcpyDeviceToHost, st);
@@ -1580,7 +1604,9 @@ int pns_moments(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int3
     return done(PNS_OK);
 }
 
-int pns_snapshot_moments(pns_ctx* ctx, int32_t problem, double* G, double* sum_m)
+// Snapshot moments of one problem with multiplicities (rb = false) or
+// expected multiplicities (rb = true) as weights.
+int snapshot_moments(pns_ctx* ctx, int32_t problem, bool rb, double* G, double* sum_w)
 {
     g_error.clear();
     if (!ctx || !G) return fail(PNS_EINVAL, "NULL argument");
@@ -1593,9 +1619,10 @@ int pns_snapshot_moments(pns_ctx* ctx, int32_t problem, double* G, double* sum_m
     double* dG = G;
     int rc = PNS_OK;
     if (!gd && (rc = dev_alloc(&dG, (size_t)R.N * R.N))) return rc;
-    const bool sd = sum_m && is_device_ptr(sum_m);
-    rc = moments_device(ctx->snap_x + row0 * ctx->max_pitch, ctx->max_pitch, ctx->snap_M + row0, K, R.N, dG,
-                        ctx->stream, sum_m && !sd ? sum_m : nullptr, sd ? sum_m : nullptr);
+    const bool sd = sum_w && is_device_ptr(sum_w);
+    rc = moments_device(ctx->snap_x + row0 * ctx->max_pitch, ctx->max_pitch, rb ? nullptr : ctx->snap_M + row0,
+                        rb ? ctx->snap_w + row0 : nullptr, K, R.N, dG, ctx->stream, sum_w && !sd ? sum_w : nullptr,
+                        sd ? sum_w : nullptr);
     if (!rc && !gd) {
         hipError_t e = hipMemcpyAsync(G, dG, (size_t)R.N * R.N * 8, hipMemcpyDeviceToHost, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -1603,6 +1630,61 @@ int pns_snapshot_moments(pns_ctx* ctx, int32_t problem, double* G, double* sum_m
     }
     if (!gd) (void)hipFree(dG);
     return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pns_moments(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int32_t N, double* G, double* sum_m,
+                void* stream)
+{
+    if (!m) {
+        g_error.clear();
+        return fail(PNS_EINVAL, "NULL argument");
+    }
+    return moments_entry(X, ldx, m, nullptr, K, N, G, sum_m, stream);
+}
+
+int pns_moments_f64(const uint8_t* X, int64_t ldx, const double* w, int64_t K, int32_t N, double* G, double* sum_w,
+                    void* stream)
+{
+    if (!w) {
+        g_error.clear();
+        return fail(PNS_EINVAL, "NULL argument");
+    }
+    return moments_entry(X, ldx, nullptr, w, K, N, G, sum_w, stream);
+}
+
+int pns_snapshot_moments(pns_ctx* ctx, int32_t problem, double* G, double* sum_m)
+{
+    return snapshot_moments(ctx, problem, false, G, sum_m);
+}
+
+int pns_snapshot_moments_rb(pns_ctx* ctx, int32_t problem, double* G, double* sum_w)
+{
+    return snapshot_moments(ctx, problem, true, G, sum_w);
+}
+
+int pns_read_rb_weights(pns_ctx* ctx, double* log_w, double* snap_w, double* hist_rb)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    if (log_w && ctx->log_cap == 0) return fail(PNS_EINVAL, "the per-step log is off (log_capacity = 0)");
+    if (snap_w && !ctx->snap_x) return fail(PNS_EINVAL, "snapshots are off (snapshot_every = 0)");
+    if (hist_rb && !ctx->hist_w) return fail(PNS_EINVAL, "histograms are off (opts.hist = 0)");
+    int rc = pns_sync(ctx);
+    if (rc) return rc;
+    const int64_t C = ctx->num_chains;
+    auto out = [&](double* dst, const double* src, size_t cnt) {
+        std::vector<double> v;
+        int r = d2h(v, src, cnt);
+        return r ? r : copy_out(dst, v.data(), cnt * 8);
+    };
+    if (log_w && (rc = out(log_w, ctx->log_w, (size_t)C * ctx->log_cap))) return rc;
+    if (snap_w && (rc = out(snap_w, ctx->snap_w, (size_t)C * ctx->snap_cap))) return rc;
+    if (hist_rb && (rc = out(hist_rb, ctx->hist_rb, (size_t)1 << ctx->probs[0].N))) return rc;
+    return PNS_OK;
 }
 
 int pns_log_partition(const void* Q, int32_t N, int32_t dtype, int32_t layout, double beta, double* out, void* stream)
@@ -1739,6 +1821,7 @@ int pns_snapshots_clear(pns_ctx* ctx)
     if (!ctx->snap_x) return fail(PNS_EINVAL, "snapshots are off (snapshot_every = 0)");
     const int64_t C = ctx->num_chains;
     hipError_t e = launch_fill64(ctx->snap_M, C * ctx->snap_cap, 0, ctx->stream);
+    if (e == hipSuccess) e = launch_fill64(ctx->snap_w, C * ctx->snap_cap, 0, ctx->stream);
     // counts are int32: clear them as 64-bit words, rounded up (the buffer
     // holds whole 64-bit words)
     if (e == hipSuccess) e = launch_fill64(ctx->snap_count, (C + 1) / 2, 0, ctx->stream);

@@ -237,6 +237,19 @@ __device__ __forceinline__ double delta_f64(float d, double h, int s, uint32_t x
     return xbit ? -e : e;
 }
 
+// Mean multiplicity of a record given its state, subset and remaining budget
+// L (Thm 3 (2): M = 1 + G, G ~ Geometric(p) counting failures, cut at L when
+// the record is budgeted): E[min(1 + G, L)] = (1 - (1 - p)^L) / p, and 1 / p
+// with no budget.  These are the Rao-Blackwell weights of the ratio estimator
+// of Thm 3 (5).  p <= 0 (every weight underflowed) gives L, or +inf unbudgeted.
+__device__ __noinline__ double expected_multiplicity(double p, int64_t L, bool budgeted)
+{
+    if (p >= 1.0) return 1.0;
+    if (p <= 0.0) return budgeted ? (double)L : INFINITY;
+    if (!budgeted) return 1.0 / p;
+    return -expm1((double)L * log1p(-p)) / p;
+}
+
 // Uniformly random n-subset of {0..N-1}: the first n distinct values of the
 // i.i.d. candidate stream, candidate s drawn from Philox stream
 // 0x40000000 | (s/2) of step `k` (words 0,1 for even s, 2,3 for odd s) and
@@ -919,6 +932,7 @@ void step_kernel(const StepArgs a)
         // record k = (state before the step, M): the leader lane
         if (tid == lead_tid) {
             const int64_t Erec = lead_st[kLsE];
+            const int64_t Lrec = lead_st[kLsL];  // budget at the start of the record
             int32_t action;
             int64_t M;
             if (stay) {
@@ -958,6 +972,10 @@ void step_kernel(const StepArgs a)
             lead_st[kLsLastM] = M;
             lead_st[kLsLastE] = Erec;
             if constexpr (INSTR) {
+                // Rao-Blackwell weight of the record: E[M | state, subset, budget]
+                double wrb = 1.0;
+                if (mode != kModeOpt && (snap || a.log_cap > 0 || a.hist_w != nullptr))
+                    wrb = expected_multiplicity(p, Lrec, unbiased || timed);
                 if (a.hist_w != nullptr) rec_idx = hist_idx;
                 if (a.log_cap > 0) {
                     const int64_t slot = (int64_t)chain * a.log_cap + (k % a.log_cap);
@@ -965,15 +983,18 @@ void step_kernel(const StepArgs a)
                     a.log_M[slot] = M;
                     a.log_E[slot] = Erec;
                     a.log_p[slot] = p;
+                    a.log_w[slot] = wrb;
                 }
                 if (a.hist_w != nullptr) {
                     atomicAdd(&a.hist_w[rec_idx], (unsigned long long)M);
                     atomicAdd(&a.hist_v[rec_idx], 1ull);
+                    atomicAdd(&a.hist_rb[rec_idx], wrb);
                 }
                 if (snap) {
                     const int32_t slot = (snap_n - 1) % a.snap_cap;
                     a.snap_M[(int64_t)chain * a.snap_cap + slot] = M;
                     a.snap_E[(int64_t)chain * a.snap_cap + slot] = Erec;
+                    a.snap_w[(int64_t)chain * a.snap_cap + slot] = wrb;
                 }
             }
         }

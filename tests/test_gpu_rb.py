@@ -1,0 +1,229 @@
+"""GPU parity of the Rao-Blackwell weights (Thm 3 (2), (5)): the expected
+multiplicity of every record (per-step log, snapshots, histogram) against the
+oracle's, the real-weight moment kernel against the oracle's FP64 moments
+within its stated bound, and the Rao-Blackwellised estimators (histogram,
+LogZ gradient) against enumeration."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact, moments
+from paper_2210_10513_amd import inputs
+
+from parity_util import compare_logs, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+W_RTOL = 1e-11  # p agrees to 1e-12 (compare_logs); the weight is a smooth function of it
+
+
+@pytest.mark.parametrize("mode,n,N,dtype,L0", [("rf", 0, 90, np.int32, 100), ("basic", 5, 150, np.int16, 100),
+                                               ("unbiased_sys", 40, 300, np.int16, 30),
+                                               ("unbiased_rand", 16, 200, np.float32, 50),
+                                               ("unbiased_sys", 3, 37, np.int32, 4)])
+def test_log_weights_match_oracle(mode, n, N, dtype, L0):
+    from paper_2210_10513_amd.binding import Sampler
+    if dtype == np.float32:
+        Q = inputs.symmetric_gauss(N, seed=N)
+        beta, is_int = 2.0, False
+    else:
+        Q = inputs.symmetric_int(N, -40, 40, dtype, seed=N)
+        beta, is_int = 0.05, True
+    C, K = 4, 300
+    s = Sampler(Q, beta, n, mode, num_chains=C, seed=21, init="random", L0=L0, log_capacity=K)
+    s.run(K)
+    log = s.read_log()
+    w = s.rb_weights()["log"]
+    s.close()
+    o = oracle_run(Q, beta, mode, K, n=n, L0=L0, seed=21, chains=list(range(C)), init="random")
+    assert compare_logs(log, o, chain_rows=list(range(C)), is_int=is_int) == C * K
+    assert np.allclose(w, o.w, rtol=W_RTOL, atol=0)
+    if mode == "rf":
+        assert np.allclose(w, 1.0 / log["p"], rtol=1e-15)
+    if mode.startswith("unbiased"):
+        # w = E[min(M, L)] lies in [0, L] and L <= L0
+        assert (w >= 0).all() and (w <= L0).all()
+        stays = log["action"] == oracle.STAY
+        assert stays.any()
+
+
+def test_exact_time_and_optimization_weights():
+    from paper_2210_10513_amd.binding import Sampler
+    N, C, T = 60, 5, 250
+    Q = inputs.symmetric_int(N, -30, 30, np.int32, seed=7)
+    s = Sampler(Q, 0.08, 0, "rf", num_chains=C, seed=4, init="random", log_capacity=T)
+    s.run_original(T)
+    w = s.rb_weights()["log"]
+    cur = s.read_current()
+    s.optimize(40, 0.5)
+    w_opt = s.rb_weights()["log"]
+    s.close()
+    o = oracle.run(Q.astype(np.int64), 0.08, oracle.MODE_RF, T, seed=4, num_chains=C, init="random", orig_time=T)
+    assert np.array_equal(cur["step"], o.n_records)
+    for c in range(C):
+        k = int(o.n_records[c])
+        assert np.allclose(w[c, :k], o.w[c, :k], rtol=W_RTOL, atol=0)
+    # the optimization steps overwrote the ring slots T .. T + 39 (mod T) with 1
+    steps = cur["step"]
+    for c in range(C):
+        slots = (steps[c] + np.arange(40)) % T
+        assert (w_opt[c, slots] == 1.0).all()
+
+
+def test_snapshot_weights_match_oracle_records():
+    """Snapshots every 3 records into a ring of 10: slot s % 10 holds the
+    weight of record 3 (s + 1) - 1."""
+    from paper_2210_10513_amd.binding import Sampler
+    N, C, every, cap, K = 70, 6, 3, 10, 40
+    Q = inputs.symmetric_int(N, -30, 30, np.int16, seed=3)
+    s = Sampler(Q, 0.06, 0, "rf", num_chains=C, seed=2, init="random", snapshot_every=every,
+                snapshot_capacity=cap)
+    s.run(K)
+    xs, ms, _, cnt = s.read_snapshots()
+    sw = s.rb_weights()["snap"]
+    s.close()
+    o = oracle_run(Q, 0.06, "rf", K, seed=2, chains=list(range(C)), init="random")
+    assert cnt == cap
+    for snap in range(K // every):
+        k = every * (snap + 1) - 1
+        slot = snap % cap
+        if snap >= K // every - cap:
+            assert np.allclose(sw[:, slot], o.w[:, k], rtol=W_RTOL, atol=0)
+            assert np.array_equal(ms[:, slot], o.M[:, k])
+
+
+@pytest.mark.parametrize("mode,n", [("rf", 0), ("unbiased_sys", 4), ("basic", 3)])
+def test_rb_histogram_matches_oracle(mode, n):
+    from paper_2210_10513_amd.binding import Sampler
+    N, C, K = 10, 64, 200
+    Q = inputs.symmetric_int(N, -12, 12, np.int32, seed=10)
+    s = Sampler(Q, 0.2, n, mode, num_chains=C, seed=6, init="random", L0=7, hist=True)
+    s.run(K)
+    hw, hv = s.read_hist()
+    hrb = s.rb_weights()["hist"]
+    s.close()
+    o = oracle.run(Q.astype(np.int64), 0.2, parity_mode(mode), K, n=n, L0=7, seed=6, num_chains=C, init="random",
+                   log=False, hist=True)
+    assert np.array_equal(hw, o.hist_w) and np.array_equal(hv, o.hist_v)
+    assert np.allclose(hrb, o.hist_rb, rtol=1e-11, atol=0)
+
+
+def parity_mode(mode):
+    return {"rf": oracle.MODE_RF, "basic": oracle.MODE_BASIC, "unbiased_sys": oracle.MODE_UNBIASED_SYS}[mode]
+
+
+def _records_per_partial(K, N):
+    """Records each wave sums in FP32 (the stated bound of pns_moments_f64)."""
+    t = -(-N // 64)
+    T = t * (t + 1) // 2
+    words = max(1, -(-K // 32))
+    return 32 * max(32, -(-words * T // 2048))
+
+
+@pytest.mark.parametrize("K,N", [(0, 5), (1, 1), (63, 7), (65, 65), (1000, 100), (5000, 130), (40000, 512)])
+@pytest.mark.parametrize("kind", ["lognormal", "signed", "huge", "tiny"])
+def test_real_weight_moments_within_stated_bound(K, N, kind):
+    from paper_2210_10513_amd import binding
+    rng = np.random.default_rng(K + N)
+    X = (rng.random((K, N)) < 0.5).astype(np.uint8)
+    w = np.exp(rng.normal(0.0, 2.0, size=K))
+    if kind == "signed":
+        w *= rng.choice([-1.0, 1.0], size=K)
+    elif kind == "huge":
+        w *= 1e290
+    elif kind == "tiny":
+        w *= 1e-290
+    G = np.full((N, N), -7.0)
+    sw = binding.pns_moments_f64(X, w, G)
+    want = moments.weighted_moments(X, w)
+    absw = moments.weighted_moments(X, np.abs(w))
+    R = _records_per_partial(K, N)
+    bound = (3 * R + 2) * 2.0 ** -24 * absw
+    assert np.all(np.abs(G - want) <= bound + 1e-300 * (K == 0)), np.max(np.abs(G - want) / np.maximum(absw, 1e-300))
+    assert sw == pytest.approx(float(w.sum()), rel=1e-12, abs=1e-300)
+
+
+def test_real_weight_moments_skip_non_finite_weights_and_use_device_buffers():
+    import torch
+    from paper_2210_10513_amd import binding
+    K, N, ld = 3000, 70, 96
+    rng = np.random.default_rng(1)
+    X = (rng.random((K, ld)) < 0.3).astype(np.uint8)
+    w = rng.random(K) * 5
+    w[[3, 500, 2999]] = [np.inf, np.nan, -np.inf]
+    Xt, wt = torch.from_numpy(X).cuda(), torch.from_numpy(w).cuda()
+    G = torch.zeros((N, N), dtype=torch.float64, device="cuda")
+    sm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    binding.pns_moments_f64(Xt, wt, G, N=N, ldx=ld, stream=torch.cuda.current_stream(), sum_w=sm)
+    torch.cuda.synchronize()
+    wf = np.where(np.isfinite(w), w, 0.0)
+    want = moments.weighted_moments(X[:, :N], wf)
+    R = _records_per_partial(K, N)
+    assert np.all(np.abs(G.cpu().numpy() - want) <= (3 * R + 2) * 2.0 ** -24 * want)
+    assert float(sm.item()) == pytest.approx(wf.sum(), rel=1e-12)
+
+
+def test_snapshot_moments_rb_equal_oracle_on_read_back_snapshots():
+    from paper_2210_10513_amd.binding import Sampler
+    N = 90
+    Q = inputs.symmetric_int(N, -30, 30, np.int32, seed=4)
+    s = Sampler(Q, 0.05, 30, "unbiased_sys", num_chains=37, seed=2, init="random", L0=20, snapshot_every=3,
+                snapshot_capacity=10)
+    s.run(40)
+    xs, _, _, cnt = s.read_snapshots()
+    sw = s.rb_weights()["snap"]
+    G, sm = s.snapshot_moments(rb=True)
+    s.close()
+    X = xs.reshape(-1, N)
+    w = sw.reshape(-1)
+    want = moments.weighted_moments(X, w)
+    R = _records_per_partial(X.shape[0], N)
+    assert np.all(np.abs(G - want) <= (3 * R + 2) * 2.0 ** -24 * want)
+    assert sm == pytest.approx(w.sum(), rel=1e-12)
+
+
+def test_rb_histogram_is_closer_to_pi_than_the_multiplicity_histogram():
+    """Thm 3 (5) at scale: 16 x 16 upper-triangular Q_ij ~ N(0, 1) (the
+    Sec 7.2 model), 20000 RF chains from exact draws of pi, 100 records each:
+    both weightings estimate pi, the expected multiplicities with the
+    sampling noise of M removed."""
+    from paper_2210_10513_amd.binding import Sampler
+    N = 16
+    Q = inputs.paper_upper_gauss(N, sigma=1.0, seed=72).astype(np.float32)
+    pi = exact.target(Q.astype(np.float64), 1.0, layout=oracle.LAYOUT_UPPER)
+    C = 20000
+    rng = np.random.default_rng(4)
+    idx0 = rng.choice(1 << N, size=C, p=pi)
+    x0 = ((idx0[:, None] >> np.arange(N)) & 1).astype(np.uint8)
+    s = Sampler(Q, 1.0, 0, "rf", num_chains=C, seed=8, x0=x0, layout="upper", hist=True)
+    s.run(100)
+    hw, _ = s.read_hist()
+    hrb = s.rb_weights()["hist"]
+    s.close()
+    tv_m = exact.tv(hw / hw.sum(), pi)
+    tv_rb = exact.tv(hrb / hrb.sum(), pi)
+    assert tv_rb < tv_m, (tv_rb, tv_m)
+    assert tv_rb < 0.05
+
+
+@pytest.mark.parametrize("mode,n", [("rf", 0), ("unbiased_sys", 6)])
+def test_logz_gradient_with_rb_weights_matches_enumeration(mode, n):
+    import torch
+    from paper_2210_10513_amd.autograd import ChainOptions, LogZ
+    N = 12
+    rng = np.random.default_rng(12)
+    U = rng.standard_normal((N, N))
+    Qn = ((U + U.T) / 2).astype(np.float32)
+    beta = 0.7
+    Q = torch.tensor(Qn, device="cuda", requires_grad=True)
+    opts = ChainOptions(num_chains=8192, burn_in=200, samples=32, every=5, mode=mode, subset_size=n, seed=3,
+                        weights="rb")
+    lz = LogZ.apply(Q, beta, opts)
+    lz.backward()
+    assert math.isclose(float(lz.item()), exact.log_partition(Qn.astype(np.float64), beta), rel_tol=1e-6)
+    want = moments.grad_log_partition(Qn.astype(np.float64), beta)
+    got = Q.grad.cpu().numpy().astype(np.float64)
+    assert np.abs(got - want).max() < 0.01 * beta, np.abs(got - want).max()
+    assert np.allclose(got, got.T, rtol=0, atol=1e-6 * beta)
