@@ -7,7 +7,8 @@ shares no code with it.
 ``pns_oracle.c`` holds the plain single-threaded FP64/int64 chain simulation
 (Rejection-Free Alg 2, Basic PNS Alg 3, Unbiased PNS Alg 6 on the QUBO target
 of Sec 4) and its own Philox4x32-10; this module loads it with ctypes and
-``exact.py`` holds the enumeration-based exact laws used as pins.
+``exact.py`` holds the enumeration-based exact laws used as pins;
+``donut.py`` the exact moments of the continuous (donut) target by quadrature.
 """
 from __future__ import annotations
 
@@ -131,6 +132,11 @@ def _declare(L: ctypes.CDLL) -> None:
     L.orc_pt_round.restype = ctypes.c_int
     L.orc_expected_multiplicity.argtypes = [ctypes.c_double, ctypes.c_int64]
     L.orc_expected_multiplicity.restype = ctypes.c_double
+    L.orc_cont_run.argtypes = [ctypes.POINTER(_ContArgs)]
+    L.orc_cont_run.restype = ctypes.c_int
+    L.orc_cont_offsets.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_void_p]
+    L.orc_cont_offsets.restype = None
 
 
 def _ptr(a: Optional[np.ndarray]) -> Optional[int]:
@@ -318,6 +324,82 @@ def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, se
     if rc != 0:
         raise ValueError(f"oracle run rejected its arguments (code {rc})")
     return r
+
+
+class _ContArgs(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("mu0", ctypes.c_double), ("sigma", ctypes.c_double), ("pairs", ctypes.c_int32),
+        ("L0", ctypes.c_int64), ("seed", ctypes.c_uint64), ("num_chains", ctypes.c_int32),
+        ("chain_ids", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("K", ctypes.c_int64),
+        ("log_action", ctypes.c_void_p), ("log_M", ctypes.c_void_p), ("log_lp", ctypes.c_void_p),
+        ("log_p", ctypes.c_void_p), ("log_q", ctypes.c_void_p), ("log_tmargin", ctypes.c_void_p),
+        ("log_w", ctypes.c_void_p), ("log_x", ctypes.c_void_p),
+        ("x_final", ctypes.c_void_p), ("L_final", ctypes.c_void_p), ("set_final", ctypes.c_void_p),
+        ("n_flips", ctypes.c_void_p), ("n_stays", ctypes.c_void_p), ("sums", ctypes.c_void_p),
+    ]
+
+
+@dataclass
+class ContResult:
+    action: Optional[np.ndarray] = None   # [C, K] neighbour index or STAY
+    M: Optional[np.ndarray] = None
+    E: Optional[np.ndarray] = None        # log pi of the record's state (named E for the shared comparisons)
+    p: Optional[np.ndarray] = None
+    q: Optional[np.ndarray] = None
+    tmargin: Optional[np.ndarray] = None
+    w: Optional[np.ndarray] = None
+    xs: Optional[np.ndarray] = None       # [C, K, dim] record states (log_states=True)
+    x: Optional[np.ndarray] = None        # [C, dim] final states
+    L: Optional[np.ndarray] = None
+    set: Optional[np.ndarray] = None
+    flips: Optional[np.ndarray] = None
+    stays: Optional[np.ndarray] = None
+    sums: Optional[np.ndarray] = None     # [C, 2, 4 dim + 1]
+
+
+def cont_run(x0: np.ndarray, K: int, *, mu0: float = 9.0, sigma: float = 0.1, pairs: int = 25, L0: int = 1000,
+             seed: int = 0, chain_ids=None, log: bool = True, log_states: bool = False,
+             lib_handle: Optional[ctypes.CDLL] = None) -> ContResult:
+    """Continuous Unbiased PNS (Alg 7) on the donut target from states x0
+    [C, dim] for K records per chain (see orc_cont_run)."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    C, d = x0.shape
+    cids = np.arange(C, dtype=np.uint32) if chain_ids is None else np.ascontiguousarray(chain_ids, dtype=np.uint32)
+    r = ContResult()
+    if log:
+        r.action = np.zeros((C, K), np.int32)
+        r.M = np.zeros((C, K), np.int64)
+        r.E = np.zeros((C, K))
+        r.p = np.zeros((C, K))
+        r.q = np.zeros((C, K))
+        r.tmargin = np.zeros((C, K))
+        r.w = np.zeros((C, K))
+    if log_states:
+        r.xs = np.zeros((C, K, d))
+    r.x = np.zeros((C, d))
+    r.L = np.zeros(C, np.int64)
+    r.set = np.zeros(C, np.int64)
+    r.flips = np.zeros(C, np.int64)
+    r.stays = np.zeros(C, np.int64)
+    r.sums = np.zeros((C, 2, 4 * d + 1))
+    a = _ContArgs()
+    a.dim, a.mu0, a.sigma, a.pairs, a.L0, a.seed = d, mu0, sigma, pairs, L0, seed
+    a.num_chains, a.chain_ids, a.x0, a.K = C, cids.ctypes.data, x0.ctypes.data, K
+    a.log_action, a.log_M, a.log_lp, a.log_p = _ptr(r.action), _ptr(r.M), _ptr(r.E), _ptr(r.p)
+    a.log_q, a.log_tmargin, a.log_w, a.log_x = _ptr(r.q), _ptr(r.tmargin), _ptr(r.w), _ptr(r.xs)
+    a.x_final, a.L_final, a.set_final = _ptr(r.x), _ptr(r.L), _ptr(r.set)
+    a.n_flips, a.n_stays, a.sums = _ptr(r.flips), _ptr(r.stays), _ptr(r.sums)
+    rc = (lib_handle or lib()).orc_cont_run(ctypes.byref(a))
+    if rc != 0:
+        raise ValueError(f"oracle continuous run rejected its arguments (code {rc})")
+    return r
+
+
+def cont_offsets(seed: int, chain: int, set_index: int, pairs: int, dim: int) -> np.ndarray:
+    """Offset vectors [pairs, dim] of partial neighbor set `set_index`."""
+    out = np.zeros((pairs, dim))
+    lib().orc_cont_offsets(seed, chain, set_index, pairs, dim, out.ctypes.data)
+    return out
 
 
 def expected_multiplicity(p: float, L: int = -1, lib_handle: Optional[ctypes.CDLL] = None) -> float:

@@ -17,6 +17,8 @@
  *     (Sec 5);
  *   - on the QUBO target of Sec 4 with single-bit-flip neighbours and a
  *     uniform proposal 1/N (so the proposal cancels in every ratio);
+ *   - Unbiased PNS for continuous states (Alg 7) on the donut target of
+ *     Sec 6 (orc_cont_run, at the end of this file);
  *   - proportional choice by the inverse-CDF rule of App. C (first index
  *     whose running sum exceeds U times the total).
  * Conventions (each one a reading of the paper where it is silent):
@@ -713,6 +715,203 @@ int orc_basic_onestep(int64_t num_states, int32_t D, const int64_t* nbr, const d
             for (int32_t t = r + 1; t < n; ++t) idx[t] = idx[t - 1] + 1;
         }
         EM[s] = em;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Continuous Unbiased PNS (Alg 7) on the donut target of Sec 6.             */
+/* ------------------------------------------------------------------------- */
+/*
+ * Target on R^d: log pi(x) = -(|x|^2 - mu0)^2 / (2 sigma^2) + const (the
+ * density of Sec 6 written for any dimension d; d = 2 in the paper).
+ * Proposal: standard normal increments, symmetric, so every acceptance ratio
+ * is pi(y) / pi(x).  Partial neighbor set i of a chain: P offset vectors
+ * delta_1..delta_P with i.i.d. N(0, 1) coordinates, each used with both signs
+ * (the pairs of Sec 6 keep the set reversible); the neighbours of x are
+ * x + delta_j (j = 0..P-1) then x - delta_j (j = P..2P-1), in that order,
+ * and the set is drawn anew after each block of L0 original samples.
+ * Reading: the proposal restricted to the finite set is uniform over its 2P
+ * points (the offsets are already draws of the proposal density), so
+ * p = (1 / 2P) sum_j min(1, pi(y_j) / pi(x)) and the next state is chosen
+ * proportionally to min(1, pi(y_j) / pi(x)), as in Alg 6.
+ * Normal draws: Box-Muller (Box and Muller, 1958) on two uniforms from one
+ * Philox block with counter (chain, set index low, set index high,
+ * 0x80000000 | pair << 8 | t): u1 in (0, 1] from words 0, 1 and u2 in [0, 1)
+ * from words 2, 3, z0 = sqrt(-2 log u1) cos(2 pi u2) for coordinate 2t and
+ * z1 = sqrt(-2 log u1) sin(2 pi u2) for coordinate 2t + 1.
+ * The two uniforms of step k are those of the discrete samplers.
+ */
+#define ORC_CONT_MAX_DIM 7
+#define ORC_CONT_MAX_PAIRS 32
+
+typedef struct {
+    int32_t dim;                /* 1 .. 7 */
+    double mu0, sigma;          /* donut radius^2 and width */
+    int32_t pairs;              /* P: 2P neighbours per set, 1 .. 32 */
+    int64_t L0;
+    uint64_t seed;
+    int32_t num_chains;
+    const uint32_t* chain_ids;  /* [num_chains] */
+    const double* x0;           /* [num_chains][dim] */
+    int64_t K;                  /* records per chain */
+    /* per-step outputs [num_chains][K], each may be NULL */
+    int32_t* log_action;        /* neighbour index 0 .. 2P-1, or ORC_STAY */
+    int64_t* log_M;
+    double* log_lp;             /* log pi of the record's state (without the constant) */
+    double* log_p;
+    double* log_q;
+    double* log_tmargin;
+    double* log_w;              /* expected multiplicity (Rao-Blackwell weight) */
+    double* log_x;              /* [num_chains][K][dim] the record's state */
+    /* final outputs, each may be NULL */
+    double* x_final;            /* [num_chains][dim] */
+    int64_t* L_final;
+    int64_t* set_final;         /* index of the current partial neighbor set */
+    int64_t* n_flips;           /* jumps */
+    int64_t* n_stays;
+    /* estimator sums [num_chains][2][4 dim + 1]: for weights M (row 0) and
+     * the expected multiplicities (row 1): sum w, then sum w x_i, sum w x_i^2,
+     * sum w x_i^4 and sum w 1(x_i > 0) for i = 0..dim-1 (each may be NULL) */
+    double* sums;
+} orc_cont_args;
+
+static double cont_logpi(const orc_cont_args* a, const double* x)
+{
+    double r2 = 0.0;
+    for (int32_t i = 0; i < a->dim; ++i) r2 += x[i] * x[i];
+    const double t = r2 - a->mu0;
+    return -(t * t) / (2.0 * a->sigma * a->sigma);
+}
+
+/* Offsets of set `set` of a chain: delta[j][i] for pair j, coordinate i. */
+void orc_cont_offsets(uint64_t seed, uint32_t chain, uint64_t set, int32_t pairs, int32_t dim, double* delta)
+{
+    for (int32_t j = 0; j < pairs; ++j) {
+        for (int32_t t = 0; 2 * t < dim; ++t) {
+            uint32_t w[4];
+            draw4(seed, chain, set, 0x80000000u | ((uint32_t)j << 8) | (uint32_t)t, w);
+            const double u1 = (double)(bits53(w[0], w[1]) + 1u) * 0x1p-53;
+            const double u2 = (double)bits53(w[2], w[3]) * 0x1p-53;
+            const double r = sqrt(-2.0 * log(u1));
+            const double ang = 6.283185307179586 * u2; /* 2 pi, rounded to double */
+            delta[j * dim + 2 * t] = r * cos(ang);
+            if (2 * t + 1 < dim) delta[j * dim + 2 * t + 1] = r * sin(ang);
+        }
+    }
+}
+
+int orc_cont_run(const orc_cont_args* a)
+{
+    const int32_t d = a->dim, P = a->pairs, n = 2 * a->pairs;
+    if (d < 1 || d > ORC_CONT_MAX_DIM) return -1;
+    if (P < 1 || P > ORC_CONT_MAX_PAIRS) return -2;
+    if (a->L0 < 1) return -3;
+    if (!(a->sigma > 0.0)) return -4;
+    const int32_t nsum = 4 * d + 1;
+    for (int32_t ch = 0; ch < a->num_chains; ++ch) {
+        const uint32_t cid = a->chain_ids[ch];
+        double x[ORC_CONT_MAX_DIM], delta[ORC_CONT_MAX_PAIRS * ORC_CONT_MAX_DIM];
+        double lpy[2 * ORC_CONT_MAX_PAIRS], w[2 * ORC_CONT_MAX_PAIRS];
+        double acc[2][4 * ORC_CONT_MAX_DIM + 1];
+        memset(acc, 0, sizeof(acc));
+        memcpy(x, a->x0 + (size_t)ch * d, sizeof(double) * (size_t)d);
+        int64_t L = a->L0, set = 0, flips = 0, stays = 0;
+        orc_cont_offsets(a->seed, cid, (uint64_t)set, P, d, delta);
+        double lpx = cont_logpi(a, x);
+        for (int64_t k = 0; k < a->K; ++k) {
+            const size_t rec = (size_t)ch * (size_t)a->K + (size_t)k;
+            /* weights of the 2P neighbours, summed in neighbour order */
+            double S = 0.0;
+            for (int32_t j = 0; j < n; ++j) {
+                double y[ORC_CONT_MAX_DIM];
+                const double sgn = j < P ? 1.0 : -1.0;
+                for (int32_t i = 0; i < d; ++i) y[i] = x[i] + sgn * delta[(j % P) * d + i];
+                lpy[j] = cont_logpi(a, y);
+                const double l = lpy[j] - lpx;
+                w[j] = l < 0.0 ? exp(l) : 1.0;
+                S += w[j];
+            }
+            const double p = S / (double)n;
+            double U1, U2;
+            orc_uniforms(a->seed, cid, (uint64_t)k, &U1, &U2);
+            double q;
+            if (p >= 1.0) q = 0.0;
+            else if (p <= 0.0) q = INFINITY;
+            else q = log(U1) / log1p(-p);
+            const double wrb = orc_expected_multiplicity(p, L);
+            int32_t action;
+            int64_t M;
+            double tmargin = 0.0;
+            /* the record's state, before the move */
+            double xr[ORC_CONT_MAX_DIM];
+            memcpy(xr, x, sizeof(double) * (size_t)d);
+            const double lpr = lpx;
+            if (q >= (double)L) {
+                /* not enough original samples left: stay L times, new set */
+                M = L;
+                action = ORC_STAY;
+                L = a->L0;
+                ++set;
+                ++stays;
+                orc_cont_offsets(a->seed, cid, (uint64_t)set, P, d, delta);
+            } else {
+                M = (int64_t)floor(q) + 1;
+                L -= M;
+                const double t = U2 * S;
+                double run = 0.0, prev = 0.0;
+                int32_t c = -1, last_pos = -1;
+                for (int32_t j = 0; j < n; ++j) {
+                    if (w[j] > 0.0) last_pos = j;
+                    prev = run;
+                    run += w[j];
+                    if (run > t && w[j] > 0.0) {
+                        c = j;
+                        break;
+                    }
+                }
+                if (c < 0) {
+                    c = last_pos;
+                    tmargin = 0.0;
+                } else {
+                    const double lo = t - prev, hi = run - t;
+                    tmargin = (lo < hi ? lo : hi) / S;
+                }
+                action = c;
+                const double sgn = c < P ? 1.0 : -1.0;
+                for (int32_t i = 0; i < d; ++i) x[i] = x[i] + sgn * delta[(c % P) * d + i];
+                lpx = lpy[c];
+                ++flips;
+            }
+            /* estimator sums over the record (J_k, M_k) */
+            const double wt[2] = {(double)M, wrb};
+            for (int32_t r = 0; r < 2; ++r) {
+                acc[r][0] += wt[r];
+                for (int32_t i = 0; i < d; ++i) {
+                    const double v = xr[i], v2 = v * v;
+                    acc[r][1 + i] += wt[r] * v;
+                    acc[r][1 + d + i] += wt[r] * v2;
+                    acc[r][1 + 2 * d + i] += wt[r] * (v2 * v2);
+                    acc[r][1 + 3 * d + i] += v > 0.0 ? wt[r] : 0.0;
+                }
+            }
+            if (a->log_action) a->log_action[rec] = action;
+            if (a->log_M) a->log_M[rec] = M;
+            if (a->log_lp) a->log_lp[rec] = lpr;
+            if (a->log_p) a->log_p[rec] = p;
+            if (a->log_q) a->log_q[rec] = q;
+            if (a->log_tmargin) a->log_tmargin[rec] = tmargin;
+            if (a->log_w) a->log_w[rec] = wrb;
+            if (a->log_x) memcpy(a->log_x + rec * (size_t)d, xr, sizeof(double) * (size_t)d);
+        }
+        if (a->x_final) memcpy(a->x_final + (size_t)ch * d, x, sizeof(double) * (size_t)d);
+        if (a->L_final) a->L_final[ch] = L;
+        if (a->set_final) a->set_final[ch] = set;
+        if (a->n_flips) a->n_flips[ch] = flips;
+        if (a->n_stays) a->n_stays[ch] = stays;
+        if (a->sums)
+            for (int32_t r = 0; r < 2; ++r)
+                memcpy(a->sums + ((size_t)ch * 2 + r) * nsum, acc[r], sizeof(double) * (size_t)nsum);
     }
     return 0;
 }

@@ -132,3 +132,36 @@ def c5_fit(N: int, seed: int | None = None, chains: int = 8192) -> Workload:
     {64, 512}, Q* = (A + A^T)/2, A ~ N(0,1)/sqrt(N), beta = 1."""
     Q = symmetric_gauss(N, seed, tag=50 + N)
     return Workload(f"fit_n{N}_f32", Q, np.ones(chains), "rf", N, 0)
+
+
+def donut_draws(C: int, dim: int = 2, mu0: float = 9.0, sigma: float = 0.1, seed: int | None = None,
+                tag: int = 200) -> np.ndarray:
+    """C exact draws [C, dim] from the donut density of Sec 6,
+    f(x) proportional to exp(-(|x|^2 - mu0)^2 / (2 sigma^2)) on R^dim: the
+    squared radius u = |x|^2 has density proportional to
+    exp(-(u - mu0)^2 / (2 sigma^2)) u^(dim/2 - 1) on u > 0 (drawn by rejection
+    from the normal N(mu0, sigma^2) restricted to mu0 +- 12 sigma, u > 0), and
+    the direction is uniform on the sphere (a normalised Gaussian vector)."""
+    rng = _rng(tag, seed)
+    lo, hi = max(mu0 - 12 * sigma, 1e-12), mu0 + 12 * sigma
+    g_max = max(lo ** (dim / 2 - 1), hi ** (dim / 2 - 1))
+    u = np.empty(0)
+    while u.size < C:
+        v = rng.normal(mu0, sigma, size=2 * C)
+        v = v[(v > lo) & (v < hi)]
+        keep = rng.random(v.size) * g_max < v ** (dim / 2 - 1)
+        u = np.concatenate([u, v[keep]])
+    g = rng.standard_normal((C, dim))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    return np.sqrt(u[:C])[:, None] * g
+
+
+def donut_ring(C: int, dim: int = 2, mu0: float = 9.0) -> np.ndarray:
+    """C states on the ring |x|^2 = mu0 at evenly spaced angles in the
+    (x_0, x_1) plane (a deterministic start away from equilibrium in angle)."""
+    x = np.zeros((C, dim))
+    ang = 2 * np.pi * np.arange(C) / max(C, 1)
+    x[:, 0] = np.sqrt(mu0) * np.cos(ang)
+    if dim > 1:
+        x[:, 1] = np.sqrt(mu0) * np.sin(ang)
+    return x
