@@ -518,6 +518,102 @@ int pns_snapshot_moments_rb(pns_ctx* ctx, int32_t problem, double* G, double* su
 int pns_log_partition(const void* Q, int32_t N, int32_t dtype, int32_t layout, double beta, double* out,
                       void* stream);
 
+/* ---- continuous states: Unbiased PNS for the continuous case (Alg 7) ----
+ *
+ * Target on R^dim (the donut of Sec 6, written for any dimension):
+ *     log pi(x) = -(|x|^2 - mu0)^2 / (2 sigma^2) + const.
+ * Proposal: increments with i.i.d. N(0, 1) coordinates (Sec 6), symmetric,
+ * so every acceptance ratio is pi(y) / pi(x).  A partial neighbor set is
+ * `pairs` offsets delta_1..delta_P drawn from the proposal, each used with
+ * both signs (Sec 6: 25 pairs, 50 neighbours; the pairs make the set
+ * reversible); neighbour j of x is x + delta_j (j < P) and x - delta_{j-P}
+ * (P <= j < 2P).  As in Alg 6, with M = 1 + Geometric(p) and
+ * p = (1 / 2P) sum_j min(1, pi(y_j) / pi(x)):  M <= L jumps to a neighbour
+ * chosen proportionally to min(1, pi(y_j) / pi(x)), L -= M;  otherwise the
+ * chain stays (record M = L), L = L0 and a new set is drawn (Alg 7).
+ * Reading: the proposal restricted to the finite set is uniform over its
+ * 2P points.
+ * Random numbers: Philox4x32-10 keyed by the seed; step k of a chain uses
+ * counter (chain id, k low, k high, 0) (U1 = (top 53 bits of words 0,1 + 1)
+ * 2^-53 for M, U2 = top 53 bits of words 2,3 2^-53 for the choice); the
+ * offsets of set s use counter (chain id, s low, s high, 0x80000000 |
+ * j << 8 | t) and Box-Muller (coordinates 2t, 2t + 1 of pair j).
+ * One wave of 64 lanes per chain on the device (2P <= 64).
+ */
+typedef struct pns_cont pns_cont;
+
+typedef struct pns_cont_opts {
+    int32_t dim;            /* 1 .. 7 (Sec 6: 2)                                */
+    int32_t pairs;          /* P, 1 .. 32: 2P neighbours per set (Sec 6: 25)    */
+    double mu0;             /* squared radius of the donut (Sec 6: 9)           */
+    double sigma;           /* width (Sec 6: 0.1), > 0                          */
+    int64_t L0;             /* original samples per set, 1 .. 2^53 (Sec 6: 1000) */
+    uint64_t seed;
+    int32_t num_chains;     /* >= 1                                             */
+    uint32_t chain_id_base; /* chain c uses counter word chain_id_base + c      */
+    const double* x0;       /* [num_chains][dim] initial states, host or device;
+                               NULL: the origin.  Copied on create.              */
+    int64_t log_capacity;   /* per-step log ring per chain (0 = off)            */
+    void* stream;           /* hipStream_t (NULL: the context creates its own)  */
+    int32_t reserved[8];    /* must be zero                                       */
+} pns_cont_opts;
+
+/* Sec 6 defaults: dim 2, 25 pairs, mu0 9, sigma 0.1, L0 1000, one chain. */
+void pns_cont_opts_default(pns_cont_opts* opts);
+
+/*
+ * Create a continuous sampler; the chains start at x0 with L = L0, set 0,
+ * step 0.  Errors: PNS_EINVAL (dim, pairs, sigma, mu0, L0, num_chains,
+ * log_capacity out of range, non-finite x0, nonzero reserved fields),
+ * PNS_ENOMEM, PNS_EDEVICE.  Synchronises.
+ */
+int pns_cont_create(pns_cont** ctx, const pns_cont_opts* opts);
+
+/* Queue `steps` records per chain (launches of at most 8192 records). */
+int pns_cont_run(pns_cont* ctx, int64_t steps);
+
+/*
+ * Chain state: states [num_chains][dim], log pi of each state (without the
+ * constant), remaining budgets L, set indices and record counters
+ * [num_chains].  Any pointer may be NULL; each is host or device.
+ * Synchronises.
+ */
+int pns_cont_read(pns_cont* ctx, double* states, double* log_density, int64_t* L, int64_t* set_index,
+                  int64_t* step);
+
+/*
+ * Per-step log ring [num_chains][log_capacity] (record k at slot k mod
+ * log_capacity): neighbour index 0 .. 2P-1 or PNS_STAY, multiplicity M,
+ * log pi of the record's state, p, and the expected multiplicity
+ * (1 - (1 - p)^L) / p of the record (the Rao-Blackwell weight of
+ * pns_read_rb_weights).  Any pointer may be NULL; each is host or device.
+ * Errors: PNS_EINVAL if the log is off.  Synchronises.
+ */
+int pns_cont_read_log(pns_cont* ctx, int32_t* actions, int64_t* multiplicities, double* log_density, double* p,
+                      double* weights);
+
+/*
+ * Estimator sums per chain [num_chains][2][4 dim + 1] (FP64), accumulated
+ * over every record since creation or the last pns_cont_clear_sums, with
+ * weights M (row 0) and the expected multiplicities (row 1): sum w, then
+ * sum w x_i, sum w x_i^2, sum w x_i^4 and sum w 1(x_i > 0) for
+ * i = 0 .. dim-1.  Their ratios are the estimators of Sec 6 (E[x_i],
+ * E[x_i^2], E[x_i^4], P(x_i > 0)).  Host or device.  Synchronises.
+ */
+int pns_cont_read_sums(pns_cont* ctx, double* sums);
+
+/* Zero the estimator sums (e.g. after burn-in), queued on the stream. */
+int pns_cont_clear_sums(pns_cont* ctx);
+
+/* Jumps and stays per chain [num_chains], host or device.  Synchronises. */
+int pns_cont_stats(pns_cont* ctx, int64_t* jumps, int64_t* stays);
+
+/* Wait for the queued work of the context. */
+int pns_cont_sync(pns_cont* ctx);
+
+/* Release the context (NULL is accepted). */
+int pns_cont_destroy(pns_cont* ctx);
+
 #ifdef __cplusplus
 }
 #endif

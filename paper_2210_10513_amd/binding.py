@@ -41,7 +41,9 @@ EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_cu
            "pns_chain_offsets", "pns_num_problems", "pns_problem_info_get", "pns_moments", "pns_snapshot_moments",
            "pns_log_partition", "pns_set_q", "pns_snapshots_clear", "pns_optimize", "pns_read_best",
            "pns_adopt_best", "pns_run_original", "pns_pt_swap", "pns_read_betas", "pns_read_ladder",
-           "pns_moments_f64", "pns_read_rb_weights", "pns_snapshot_moments_rb"]
+           "pns_moments_f64", "pns_read_rb_weights", "pns_snapshot_moments_rb", "pns_cont_opts_default",
+           "pns_cont_create", "pns_cont_run", "pns_cont_read", "pns_cont_read_log", "pns_cont_read_sums",
+           "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy"]
 
 
 class pns_opts(ctypes.Structure):
@@ -53,6 +55,15 @@ class pns_opts(ctypes.Structure):
         ("groups", ctypes.c_int32), ("stream", ctypes.c_void_p), ("log_capacity", ctypes.c_int64),
         ("hist", ctypes.c_int32), ("snapshot_every", ctypes.c_int32), ("snapshot_capacity", ctypes.c_int32),
         ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class pns_cont_opts(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("pairs", ctypes.c_int32), ("mu0", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("L0", ctypes.c_int64), ("seed", ctypes.c_uint64), ("num_chains", ctypes.c_int32),
+        ("chain_id_base", ctypes.c_uint32), ("x0", ctypes.c_void_p), ("log_capacity", ctypes.c_int64),
+        ("stream", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 8),
     ]
 
 
@@ -136,13 +147,25 @@ def _load() -> ctypes.CDLL:
     L.pns_moments_f64.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
     L.pns_read_rb_weights.argtypes = [vp, vp, vp, vp]
     L.pns_snapshot_moments_rb.argtypes = [vp, i32, vp, vp]
+    L.pns_cont_opts_default.argtypes = [ctypes.POINTER(pns_cont_opts)]
+    L.pns_cont_opts_default.restype = None
+    L.pns_cont_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(pns_cont_opts)]
+    L.pns_cont_run.argtypes = [vp, i64]
+    L.pns_cont_read.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pns_cont_read_log.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pns_cont_read_sums.argtypes = [vp, vp]
+    L.pns_cont_clear_sums.argtypes = [vp]
+    L.pns_cont_stats.argtypes = [vp, vp, vp]
+    L.pns_cont_sync.argtypes = [vp]
+    L.pns_cont_destroy.argtypes = [vp]
     for name in ("pns_create", "pns_run", "pns_read", "pns_read_current", "pns_field_type", "pns_read_log",
                  "pns_read_hist", "pns_hist_clear", "pns_read_snapshots", "pns_stats", "pns_sync", "pns_destroy",
                  "pns_tile", "pns_create_batch", "pns_autotune", "pns_chain_offsets", "pns_num_problems",
                  "pns_problem_info_get", "pns_moments", "pns_snapshot_moments", "pns_log_partition", "pns_set_q",
                  "pns_snapshots_clear", "pns_optimize", "pns_read_best", "pns_adopt_best", "pns_run_original",
                  "pns_pt_swap", "pns_read_betas", "pns_read_ladder", "pns_moments_f64", "pns_read_rb_weights",
-                 "pns_snapshot_moments_rb"):
+                 "pns_snapshot_moments_rb", "pns_cont_create", "pns_cont_run", "pns_cont_read", "pns_cont_read_log",
+                 "pns_cont_read_sums", "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -718,6 +741,84 @@ class BatchSampler:
     def close(self) -> None:
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             pns_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ContSampler:
+    """Unbiased PNS for continuous states (Alg 7) on the donut target of
+    Sec 6, ``num_chains`` chains on the device (pns_cont_*)."""
+
+    def __init__(self, num_chains: int = 1, *, dim: int = 2, pairs: int = 25, mu0: float = 9.0, sigma: float = 0.1,
+                 L0: int = 1000, seed: int = 0, x0=None, chain_id_base: int = 0, log_capacity: int = 0, stream=None):
+        o = pns_cont_opts()
+        lib.pns_cont_opts_default(ctypes.byref(o))
+        o.dim, o.pairs, o.mu0, o.sigma, o.L0, o.seed = dim, pairs, mu0, sigma, L0, seed
+        o.num_chains, o.chain_id_base, o.log_capacity = num_chains, chain_id_base, log_capacity
+        if x0 is not None:
+            if hasattr(x0, "data_ptr"):
+                self._x0 = x0.contiguous()
+            else:
+                self._x0 = np.ascontiguousarray(np.broadcast_to(np.asarray(x0, np.float64), (num_chains, dim)))
+            o.x0 = _addr(self._x0)
+        if stream is not None:
+            o.stream = stream if isinstance(stream, int) else stream.cuda_stream
+        self.num_chains, self.dim, self.pairs, self.log_capacity = num_chains, dim, pairs, log_capacity
+        self.ctx = ctypes.c_void_p()
+        _check(lib.pns_cont_create(ctypes.byref(self.ctx), ctypes.byref(o)))
+
+    def run(self, steps: int) -> "ContSampler":
+        _check(lib.pns_cont_run(self.ctx, steps))
+        return self
+
+    def sync(self) -> None:
+        _check(lib.pns_cont_sync(self.ctx))
+
+    def read(self):
+        C, d = self.num_chains, self.dim
+        x = np.zeros((C, d))
+        lp = np.zeros(C)
+        L = np.zeros(C, np.int64)
+        st = np.zeros(C, np.int64)
+        k = np.zeros(C, np.int64)
+        _check(lib.pns_cont_read(self.ctx, x.ctypes.data, lp.ctypes.data, L.ctypes.data, st.ctypes.data,
+                                 k.ctypes.data))
+        return {"x": x, "lp": lp, "L": L, "set": st, "step": k}
+
+    def read_log(self):
+        C, K = self.num_chains, self.log_capacity
+        a = np.zeros((C, K), np.int32)
+        m = np.zeros((C, K), np.int64)
+        lp = np.zeros((C, K))
+        p = np.zeros((C, K))
+        w = np.zeros((C, K))
+        _check(lib.pns_cont_read_log(self.ctx, a.ctypes.data, m.ctypes.data, lp.ctypes.data, p.ctypes.data,
+                                     w.ctypes.data))
+        return {"action": a, "M": m, "E": lp, "p": p, "w": w}
+
+    def read_sums(self):
+        out = np.zeros((self.num_chains, 2, 4 * self.dim + 1))
+        _check(lib.pns_cont_read_sums(self.ctx, out.ctypes.data))
+        return out
+
+    def clear_sums(self) -> "ContSampler":
+        _check(lib.pns_cont_clear_sums(self.ctx))
+        return self
+
+    def stats(self):
+        j = np.zeros(self.num_chains, np.int64)
+        s = np.zeros(self.num_chains, np.int64)
+        _check(lib.pns_cont_stats(self.ctx, j.ctypes.data, s.ctypes.data))
+        return {"jumps": j, "stays": s}
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            lib.pns_cont_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):

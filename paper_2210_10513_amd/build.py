@@ -21,7 +21,7 @@ LIB = os.path.join(LIBDIR, "libpns.so")
 ARCH = os.environ.get("PNS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["pns_step_i16.hip", "pns_step_i32.hip", "pns_step_i64.hip", "pns_step_f32.hip", "pns_kernels.hip",
-           "pns_moments.hip", "pns_runtime.cpp"]
+           "pns_moments.hip", "pns_cont.hip", "pns_runtime.cpp"]
 
 # Per-source additions: the moment kernel adds FP64 partial sums with the
 # hardware atomic add (device memory only).

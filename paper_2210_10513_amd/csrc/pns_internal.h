@@ -151,6 +151,34 @@ hipError_t launch_pack_bits(const uint8_t* X, int64_t ldx, int64_t K, int32_t N,
 hipError_t launch_moments(const uint32_t* Xb, int32_t npad, int64_t words, int32_t N, const uint16_t* pieces,
                           int64_t kpad, int64_t chunk_words, const unsigned long long* max_m, float* part, double* G,
                           hipStream_t st);
+// ---- continuous Unbiased PNS (Alg 7, donut target) ----
+struct ContArgs {
+    int32_t dim;                    // 1 .. 7
+    int32_t pairs;                  // P: 2P neighbours per set, 1 .. 32
+    double mu0;                     // donut: log pi = -(|x|^2 - mu0)^2 / den
+    double den;                     // 2 sigma^2
+    int64_t L0;
+    uint64_t seed;
+    int32_t num_chains;
+    const uint32_t* chain_id;       // [C]
+    double* x;                      // [C][dim]
+    double* lpx;                    // [C] log pi of the state
+    int64_t* L;                     // [C] remaining budget
+    int64_t* set;                   // [C] index of the current partial neighbor set
+    int64_t* step;                  // [C] records so far
+    int64_t* counters;              // [C][2] jumps, stays
+    double* sums;                   // [C][2][4 dim + 1] estimator sums (M, expected multiplicity)
+    int64_t steps;                  // records per chain in this launch
+    int64_t log_cap;                // per-step log ring (0: off)
+    int32_t* log_action;
+    int64_t* log_M;
+    double* log_lp;
+    double* log_p;
+    double* log_w;
+};
+// init = true: lpx from x; else `steps` records per chain.
+hipError_t launch_cont(const ContArgs& a, bool init, hipStream_t st);
+
 // Weight pieces of FP64 weights: *maxbits (zeroed by the caller) receives the
 // largest finite |w| (as bits), the weights are scaled by 2^-ilogb(max),
 // rounded to FP32 and split exactly into three bf16; *sum_w (zeroed) receives

@@ -2041,3 +2041,277 @@ int pns_read_ladder(pns_ctx* ctx, int32_t* ladder)
 }
 
 }  // extern "C"
+
+// ---- continuous Unbiased PNS (Alg 7, donut target) ----
+
+struct pns_cont {
+    pns_cont_opts o{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int32_t C = 0, dim = 0;
+    uint32_t* chain_id = nullptr;
+    double* x = nullptr;
+    double* lpx = nullptr;
+    int64_t* L = nullptr;
+    int64_t* set = nullptr;
+    int64_t* step = nullptr;
+    int64_t* counters = nullptr;
+    double* sums = nullptr;
+    int32_t* log_action = nullptr;
+    int64_t* log_M = nullptr;
+    double* log_lp = nullptr;
+    double* log_p = nullptr;
+    double* log_w = nullptr;
+
+    ContArgs args(int64_t steps) const
+    {
+        ContArgs a{};
+        a.dim = dim;
+        a.pairs = o.pairs;
+        a.mu0 = o.mu0;
+        a.den = 2.0 * o.sigma * o.sigma;
+        a.L0 = o.L0;
+        a.seed = o.seed;
+        a.num_chains = C;
+        a.chain_id = chain_id;
+        a.x = x;
+        a.lpx = lpx;
+        a.L = L;
+        a.set = set;
+        a.step = step;
+        a.counters = counters;
+        a.sums = sums;
+        a.steps = steps;
+        a.log_cap = o.log_capacity;
+        a.log_action = log_action;
+        a.log_M = log_M;
+        a.log_lp = log_lp;
+        a.log_p = log_p;
+        a.log_w = log_w;
+        return a;
+    }
+
+    void free_all()
+    {
+        void* ptrs[] = {chain_id, x, lpx, L, set, step, counters, sums, log_action, log_M, log_lp, log_p, log_w};
+        for (void* p : ptrs)
+            if (p) (void)hipFree(p);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+constexpr int64_t kContChunk = 8192;  // records per chain per launch
+
+int cont_sums_count(const pns_cont* ctx) { return 2 * (4 * ctx->dim + 1); }
+
+}  // namespace
+
+extern "C" {
+
+void pns_cont_opts_default(pns_cont_opts* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->dim = 2;
+    o->pairs = 25;
+    o->mu0 = 9.0;
+    o->sigma = 0.1;
+    o->L0 = 1000;
+    o->num_chains = 1;
+}
+
+int pns_cont_create(pns_cont** out, const pns_cont_opts* o)
+{
+    g_error.clear();
+    if (!out || !o) return fail(PNS_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (o->dim < 1 || o->dim > 7) return fail(PNS_EINVAL, "dim must be in [1, 7]");
+    if (o->pairs < 1 || o->pairs > 32) return fail(PNS_EINVAL, "pairs must be in [1, 32]");
+    if (!(o->sigma > 0.0) || !std::isfinite(o->sigma)) return fail(PNS_EINVAL, "sigma must be finite and > 0");
+    if (!std::isfinite(o->mu0)) return fail(PNS_EINVAL, "mu0 must be finite");
+    if (!std::isfinite(2.0 * o->sigma * o->sigma) || 2.0 * o->sigma * o->sigma == 0.0)
+        return fail(PNS_EINVAL, "2 sigma^2 must be a finite positive double");
+    if (o->L0 < 1 || o->L0 > ((int64_t)1 << 53)) return fail(PNS_EINVAL, "L0 must be in [1, 2^53]");
+    if (o->num_chains < 1) return fail(PNS_EINVAL, "num_chains must be >= 1");
+    if (o->log_capacity < 0) return fail(PNS_EINVAL, "log_capacity must be >= 0");
+    for (int r : o->reserved)
+        if (r != 0) return fail(PNS_EINVAL, "reserved fields must be zero");
+    const int64_t C = o->num_chains, d = o->dim;
+    std::vector<double> x0((size_t)(C * d), 0.0);
+    if (o->x0) {
+        int rc = copy_in(x0.data(), o->x0, x0.size() * sizeof(double));
+        if (rc) return rc;
+        for (double v : x0)
+            if (!std::isfinite(v)) return fail(PNS_EINVAL, "x0 must be finite");
+    }
+    pns_cont* ctx = new pns_cont();
+    ctx->o = *o;
+    ctx->o.x0 = nullptr;
+    ctx->C = o->num_chains;
+    ctx->dim = o->dim;
+    auto fail_free = [&](int rc) {
+        ctx->free_all();
+        delete ctx;
+        return rc;
+    };
+    if (o->stream) {
+        ctx->stream = reinterpret_cast<hipStream_t>(o->stream);
+    } else {
+        hipError_t e = hipStreamCreate(&ctx->stream);
+        if (e != hipSuccess) return fail_free(hip_fail(e, "hipStreamCreate"));
+        ctx->own_stream = true;
+    }
+    const int ns = cont_sums_count(ctx);
+    int rc = PNS_OK;
+    if (!rc) rc = dev_alloc(&ctx->chain_id, (size_t)C);
+    if (!rc) rc = dev_alloc(&ctx->x, (size_t)(C * d));
+    if (!rc) rc = dev_alloc(&ctx->lpx, (size_t)C);
+    if (!rc) rc = dev_alloc(&ctx->L, (size_t)C);
+    if (!rc) rc = dev_alloc(&ctx->set, (size_t)C);
+    if (!rc) rc = dev_alloc(&ctx->step, (size_t)C);
+    if (!rc) rc = dev_alloc(&ctx->counters, (size_t)C * 2);
+    if (!rc) rc = dev_alloc(&ctx->sums, (size_t)C * ns);
+    if (!rc && o->log_capacity > 0) {
+        const size_t n = (size_t)C * (size_t)o->log_capacity;
+        if (!rc) rc = dev_alloc(&ctx->log_action, n);
+        if (!rc) rc = dev_alloc(&ctx->log_M, n);
+        if (!rc) rc = dev_alloc(&ctx->log_lp, n);
+        if (!rc) rc = dev_alloc(&ctx->log_p, n);
+        if (!rc) rc = dev_alloc(&ctx->log_w, n);
+    }
+    if (rc) return fail_free(rc);
+    std::vector<uint32_t> cid((size_t)C);
+    for (int64_t c = 0; c < C; ++c) cid[c] = o->chain_id_base + (uint32_t)c;
+    std::vector<int64_t> Lv((size_t)C, o->L0), zeros((size_t)C * 2, 0);
+    hipError_t e = hipMemcpy(ctx->chain_id, cid.data(), C * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->x, x0.data(), x0.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->L, Lv.data(), C * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->set, zeros.data(), C * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->step, zeros.data(), C * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->counters, zeros.data(), C * 2 * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(ctx->sums, 0, (size_t)C * ns * sizeof(double));
+    if (e == hipSuccess) e = launch_cont(ctx->args(0), true, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail_free(hip_fail(e, "continuous sampler set-up"));
+    *out = ctx;
+    return PNS_OK;
+}
+
+int pns_cont_run(pns_cont* ctx, int64_t steps)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    if (steps < 0) return fail(PNS_EINVAL, "steps must be >= 0");
+    for (int64_t done = 0; done < steps;) {
+        const int64_t n = std::min(kContChunk, steps - done);
+        hipError_t e = launch_cont(ctx->args(n), false, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "continuous step kernel launch");
+        done += n;
+    }
+    return PNS_OK;
+}
+
+int pns_cont_read(pns_cont* ctx, double* states, double* log_density, int64_t* L, int64_t* set_index, int64_t* step)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "stream synchronize");
+    const size_t C = (size_t)ctx->C;
+    int rc = PNS_OK;
+    auto out64 = [&](void* dst, const void* src, size_t count) {
+        std::vector<int64_t> v;
+        int r = d2h(v, src, count);
+        return r ? r : copy_out(dst, v.data(), count * 8);
+    };
+    if (states && (rc = out64(states, ctx->x, C * ctx->dim))) return rc;
+    if (log_density && (rc = out64(log_density, ctx->lpx, C))) return rc;
+    if (L && (rc = out64(L, ctx->L, C))) return rc;
+    if (set_index && (rc = out64(set_index, ctx->set, C))) return rc;
+    if (step && (rc = out64(step, ctx->step, C))) return rc;
+    return PNS_OK;
+}
+
+int pns_cont_read_log(pns_cont* ctx, int32_t* actions, int64_t* multiplicities, double* log_density, double* p,
+                      double* weights)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    if (ctx->o.log_capacity == 0) return fail(PNS_EINVAL, "the per-step log is off (log_capacity = 0)");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "stream synchronize");
+    const size_t n = (size_t)ctx->C * (size_t)ctx->o.log_capacity;
+    int rc = PNS_OK;
+    if (actions) {
+        std::vector<int32_t> v;
+        if ((rc = d2h(v, ctx->log_action, n)) || (rc = copy_out(actions, v.data(), n * 4))) return rc;
+    }
+    auto out64 = [&](void* dst, const void* src) {
+        std::vector<int64_t> v;
+        int r = d2h(v, src, n);
+        return r ? r : copy_out(dst, v.data(), n * 8);
+    };
+    if (multiplicities && (rc = out64(multiplicities, ctx->log_M))) return rc;
+    if (log_density && (rc = out64(log_density, ctx->log_lp))) return rc;
+    if (p && (rc = out64(p, ctx->log_p))) return rc;
+    if (weights && (rc = out64(weights, ctx->log_w))) return rc;
+    return PNS_OK;
+}
+
+int pns_cont_read_sums(pns_cont* ctx, double* sums)
+{
+    g_error.clear();
+    if (!ctx || !sums) return fail(PNS_EINVAL, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "stream synchronize");
+    const size_t n = (size_t)ctx->C * cont_sums_count(ctx);
+    std::vector<double> v;
+    int rc = d2h(v, ctx->sums, n);
+    return rc ? rc : copy_out(sums, v.data(), n * 8);
+}
+
+int pns_cont_clear_sums(pns_cont* ctx)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    hipError_t e = launch_fill64(ctx->sums, (int64_t)ctx->C * cont_sums_count(ctx), 0, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "clear sums");
+    return PNS_OK;
+}
+
+int pns_cont_stats(pns_cont* ctx, int64_t* jumps, int64_t* stays)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "stream synchronize");
+    std::vector<int64_t> v;
+    int rc = d2h(v, ctx->counters, (size_t)ctx->C * 2);
+    if (rc) return rc;
+    std::vector<int64_t> j((size_t)ctx->C), s((size_t)ctx->C);
+    for (int32_t c = 0; c < ctx->C; ++c) {
+        j[c] = v[(size_t)c * 2];
+        s[c] = v[(size_t)c * 2 + 1];
+    }
+    if (jumps && (rc = copy_out(jumps, j.data(), j.size() * 8))) return rc;
+    if (stays && (rc = copy_out(stays, s.data(), s.size() * 8))) return rc;
+    return PNS_OK;
+}
+
+int pns_cont_sync(pns_cont* ctx)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "stream synchronize");
+    HIP_TRY(hipGetLastError(), "queued work");
+    return PNS_OK;
+}
+
+int pns_cont_destroy(pns_cont* ctx)
+{
+    if (!ctx) return PNS_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->free_all();
+    delete ctx;
+    return PNS_OK;
+}
+
+}  // extern "C"

@@ -119,13 +119,40 @@ def test_autotune_rejects_bad_arguments():
         assert ei.value.code == b.PNS_EINVAL and expect in str(ei.value)
 
 
+@pytest.mark.parametrize("field,value,expect", [
+    ("dim", 0, "dim"), ("dim", 8, "dim"), ("pairs", 0, "pairs"), ("pairs", 33, "pairs"),
+    ("sigma", 0.0, "sigma"), ("sigma", float("nan"), "sigma"), ("mu0", float("inf"), "mu0"),
+    ("L0", 0, "L0"), ("num_chains", 0, "num_chains"), ("log_capacity", -1, "log_capacity"),
+    ("sigma", 1e-200, "2 sigma^2"),
+])
+def test_continuous_create_rejects_bad_options(field, value, expect):
+    from paper_2210_10513_amd import binding as b
+    o = b.pns_cont_opts()
+    b.lib.pns_cont_opts_default(ctypes.byref(o))
+    assert (o.dim, o.pairs, o.mu0, o.sigma, o.L0, o.num_chains) == (2, 25, 9.0, 0.1, 1000, 1)
+    setattr(o, field, value)
+    ctx = ctypes.c_void_p()
+    rc = b.lib.pns_cont_create(ctypes.byref(ctx), ctypes.byref(o))
+    assert rc == b.PNS_EINVAL and expect in b.pns_last_error() and not ctx.value
+
+
+def test_continuous_create_rejects_reserved_fields():
+    from paper_2210_10513_amd import binding as b
+    o = b.pns_cont_opts()
+    b.lib.pns_cont_opts_default(ctypes.byref(o))
+    o.reserved[3] = 1
+    ctx = ctypes.c_void_p()
+    assert b.lib.pns_cont_create(ctypes.byref(ctx), ctypes.byref(o)) == b.PNS_EINVAL
+    assert "reserved" in b.pns_last_error()
+
+
 def test_structs_match_header_layout(tmp_path):
     """Every struct of the binding has the size and field offsets that a C
     compiler gives the header's declaration."""
     import subprocess
     from paper_2210_10513_amd import binding as b
     structs = {"pns_opts": b.pns_opts, "pns_problem": b.pns_problem, "pns_problem_info": b.pns_problem_info,
-               "pns_tune": b.pns_tune, "pns_chain_stats": b.pns_chain_stats}
+               "pns_tune": b.pns_tune, "pns_chain_stats": b.pns_chain_stats, "pns_cont_opts": b.pns_cont_opts}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pns.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
