@@ -12,6 +12,12 @@ The JSON line reports flips/s (value) and effective Metropolis steps/s
 (bytes of Q read per flip = N * sizeof(int16)), the same workload with Basic
 PNS subset 64 and in the plain one-launch-per-step form, and the CPU oracle
 timed on a bounded sample on this host.
+
+Other workloads (--workload): basic64_n1024_int16, unbiased_n8192_f32
+(Unbiased PNS, N = 8192 float32, 4096 chains), batched64_uneven_int16 (64
+problems of uneven N in one context), fit_n64_f32 / fit_n512_f32
+(maximum-likelihood fit through the MFMA moment kernel), donut_cont_f64
+(continuous Unbiased PNS, Alg 7, on the donut target of Sec 6).
 """
 from __future__ import annotations
 
@@ -64,6 +70,9 @@ def _workload(name: str):
                  for i, Q in enumerate(w.Q)]
         return dict(problems=probs, betas=w.betas, mode="unbiased_sys", n=0, L0=100, qbytes=2, steps=20_000,
                     desc=w.name, Ns=np.asarray(w.extra["Ns"]))
+    if name == "donut_cont_f64":
+        return dict(cont=True, dim=2, pairs=25, mu0=9.0, sigma=0.1, L0=1000, chains=65536, steps=4000,
+                    desc="donut_d2_mu9_sigma0.1_pairs25_L1000_65536chains")
     if name in ("fit_n64_f32", "fit_n512_f32"):
         N = 64 if name == "fit_n64_f32" else 512
         w = inputs.c5_fit(N)
@@ -153,6 +162,87 @@ def _bench_fit(args, wl):
                              "kernel": "moments (fill + prep + pack + moments_kernel + reduce + sum)",
                              "kernel_avg_ms": mom_ms},
     }
+    print(json.dumps(out))
+
+
+# FP64 operations per neighbour evaluation of the continuous sampler: y = x + s
+# (D adds), |y|^2 (D multiplies, D adds), (|y|^2 - mu0)^2 / (2 sigma^2) (3),
+# the log-density difference (1), min(0, .) (1), and exp counted as 20 (range
+# reduction, a degree-11 polynomial, scaling).
+def _cont_flops_per_neighbour(D: int) -> int:
+    return 4 * D + 5 + 20
+
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def _bench_cont(args, wl):
+    """Continuous Unbiased PNS (Alg 7) on the donut target of Sec 6: d = 2,
+    mu0 = 9, sigma = 0.1, 25 pairs (50 neighbours), L0 = 1000; 65536 chains
+    from exact draws of the target.  One bench step runs every chain for
+    --chain-steps records (default 4000).  Value: original (Metropolis-
+    equivalent) samples per second, the unit of the Sec 6 comparison."""
+    import torch
+    from paper_2210_10513_amd import inputs
+    from paper_2210_10513_amd.binding import ContSampler
+    chain_steps = args.chain_steps or wl["steps"]
+    C, d = wl["chains"], wl["dim"]
+    x0 = inputs.donut_draws(C, d, wl["mu0"], wl["sigma"], seed=1)
+    stream = torch.cuda.current_stream()
+    s = ContSampler(C, dim=d, pairs=wl["pairs"], mu0=wl["mu0"], sigma=wl["sigma"], L0=wl["L0"], seed=2, x0=x0,
+                    stream=stream)
+    for _ in range(args.warmup):
+        s.run(chain_steps)
+    s.sync()
+    S0 = s.read_sums()[:, 0, 0].sum()
+    st0 = s.stats()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        s.run(chain_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1000.0 / args.steps
+    S1 = s.read_sums()[:, 0, 0].sum()
+    st1 = s.stats()
+    s.close()
+    orig = (S1 - S0) / args.steps
+    recs = float(C) * chain_steps
+    jumps = float((st1["jumps"] - st0["jumps"]).sum()) / args.steps
+    nbr = recs * 2 * wl["pairs"]
+    flops = nbr * _cont_flops_per_neighbour(d)
+    launches = -(-chain_steps // 8192)
+    achieved = flops / sec / 1e12
+    out = {
+        "metric": "original_samples/s", "value": orig / sec, "unit": "original samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1000.0, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["desc"], "dim": d, "pairs": wl["pairs"], "mu0": wl["mu0"], "sigma": wl["sigma"],
+                   "L0": wl["L0"], "chains": C, "records_per_chain_per_step": chain_steps},
+        "records_per_s": recs / sec, "jumps_per_s": jumps / sec, "neighbour_evaluations_per_s": nbr / sec,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_neighbour": _cont_flops_per_neighbour(d), "kernel": "cont_kernel",
+                     "kernel_avg_ms": sec * 1000.0 / launches},
+    }
+    if not args.no_cpu:
+        import oracle
+        K = 200
+        t0 = time.perf_counter()
+        oracle.cont_run(x0[:8], K, mu0=wl["mu0"], sigma=wl["sigma"], pairs=wl["pairs"], L0=wl["L0"], seed=2,
+                        log=False)
+        dt = time.perf_counter() - t0
+        K = max(200, int(K * 12.0 / max(dt, 1e-6)))
+        t0 = time.perf_counter()
+        r = oracle.cont_run(x0[:8], K, mu0=wl["mu0"], sigma=wl["sigma"], pairs=wl["pairs"], L0=wl["L0"], seed=2,
+                            log=False)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": float(r.sums[:, 0, 0].sum()) / dt, "unit": "original samples/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"8 chains x {K} records of the same workload, single-threaded FP64 oracle "
+                                         f"({dt:.1f} s)"}
     print(json.dumps(out))
 
 
@@ -306,6 +396,9 @@ def main():
         return
 
     wl = _workload(args.workload)
+    if wl.get("cont"):
+        _bench_cont(args, wl)
+        return
     if wl.get("fit"):
         _bench_fit(args, wl)
         return
