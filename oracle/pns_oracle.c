@@ -776,12 +776,15 @@ typedef struct {
     double* sums;
 } orc_cont_args;
 
+/* log pi(x) = -(|x|^2 - mu0)^2 / (2 sigma^2), evaluated as -(t t) c with
+ * c = 1 / (2 sigma^2) rounded once. */
 static double cont_logpi(const orc_cont_args* a, const double* x)
 {
     double r2 = 0.0;
     for (int32_t i = 0; i < a->dim; ++i) r2 += x[i] * x[i];
     const double t = r2 - a->mu0;
-    return -(t * t) / (2.0 * a->sigma * a->sigma);
+    const double c = 1.0 / (2.0 * a->sigma * a->sigma);
+    return -(t * t) * c;
 }
 
 /* Offsets of set `set` of a chain: delta[j][i] for pair j, coordinate i. */
