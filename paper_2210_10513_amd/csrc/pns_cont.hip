@@ -11,14 +11,20 @@
 // pi(x)) and the next state is chosen proportionally to min(1, pi(y_j) /
 // pi(x)).
 //
-// Layout: one wave per chain (four chains per 256-thread block); lane j keeps
-// neighbour j's signed offset in registers and evaluates its weight; a wave
-// prefix sum gives p and the inverse-CDF choice (App. C); the state, its
-// log-density, the budget and the estimator sums stay in registers for the
-// whole launch.  Normal offsets: Box-Muller on two uniforms of one Philox
-// block, counter (chain, set index low, set index high, 0x80000000 | j << 8 |
-// t) for coordinates 2t, 2t + 1.  Step uniforms: those of the discrete
-// samplers (stream 0, counter (chain, step low, step high, 0)).
+// Layout: a group of 8 lanes per chain, 8 chains per wave, 32 per 256-thread
+// workgroup.  Lane r of a group holds the signed offsets of neighbours
+// j = r m .. r m + m - 1 (m = ceil(2P / 8) <= 8) in registers and evaluates
+// their weights one after the other; a segmented DPP scan over the group gives
+// S, p and the inverse-CDF choice (App. C: the first neighbour whose running
+// sum exceeds U2 S).  The per-record scalar work (the multiplicity, the
+// budget, the expected multiplicity) is then shared by 8 chains per wave
+// instruction instead of being repeated by a whole wave for one chain.  The
+// state, its log-density, the budget and the estimator sums stay in registers
+// for the whole launch.  Normal offsets: Box-Muller on two uniforms of one
+// Philox block, counter (chain, set index low, set index high, 0x80000000 |
+// j << 8 | t) for coordinates 2t, 2t + 1.  Step uniforms: those of the
+// discrete samplers (counter (chain, step low, step high, 0)), drawn 8 steps at
+// a time (lane r of a group holds step k + r).
 //
 // Floating-point contraction is off in this file so that the density and the
 // estimator sums round like their plain definitions.
@@ -29,13 +35,13 @@
 namespace pns {
 namespace cont {
 
-using step::batch_uniforms;
+using step::dpp_f64;
 using step::philox;
-using step::read_lane;
-using step::wave_scan;
 using step::Words;
 
 constexpr uint32_t kStreamOffsets = 0x80000000u;
+constexpr int kGroup = 8;                  // lanes per chain
+constexpr int kChainsPerBlock = 256 / kGroup;
 
 // Coordinates of offset pair `pj` of set `set`: Box-Muller, z0 = sqrt(-2 log
 // u1) cos(2 pi u2) for coordinate 2t and z1 = sqrt(-2 log u1) sin(2 pi u2) for
@@ -80,6 +86,15 @@ __device__ __noinline__ Geo geometric(double p, double logU1, int64_t L)
     return {logU1 / lg, -expm1((double)L * lg) / p};
 }
 
+// Uniforms of step k of chain cid: log U1 (U1 in (0, 1], words 0, 1) and U2
+// in [0, 1) (words 2, 3), returned as (q, wrb) = (log U1, U2).
+__device__ __noinline__ Geo step_uniforms(uint32_t cid, int64_t k, uint64_t seed)
+{
+    const Words o = philox(cid, (uint32_t)k, (uint32_t)((uint64_t)k >> 32), 0u, seed);
+    const double u1 = (double)(((((uint64_t)o.w0 << 32) | o.w1) >> 11) + 1u) * 0x1p-53;
+    return {log(u1), (double)((((uint64_t)o.w2 << 32) | o.w3) >> 11) * 0x1p-53};
+}
+
 template <int D>
 __device__ __forceinline__ double pick(const double* v, int i)
 {
@@ -90,90 +105,145 @@ __device__ __forceinline__ double pick(const double* v, int i)
     return r;
 }
 
+// log pi(x) = -(|x|^2 - mu0)^2 c with c = 1 / (2 sigma^2) rounded once (on the
+// host).
 template <int D>
+__device__ __forceinline__ double log_density(const double* x, double mu0, double c)
+{
+    double r2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) r2 += x[i] * x[i];
+    const double tt = r2 - mu0;
+    return -(tt * tt) * c;
+}
+
+// Inclusive prefix sum within each group of 8 lanes (rows of 16 hold two
+// groups; row_shr by 1, 2, 4 with the lanes below the shift masked off).
+__device__ __forceinline__ double group_scan(double v, int r)
+{
+    double t = dpp_f64<0x111, 0xF>(v);
+    if (r >= 1) v += t;
+    t = dpp_f64<0x112, 0xF>(v);
+    if (r >= 2) v += t;
+    t = dpp_f64<0x114, 0xF>(v);
+    if (r >= 4) v += t;
+    return v;
+}
+
+// MP: neighbours per lane the kernel is built for (m <= MP; the launcher
+// picks the smallest of 2, 4, 7, 8 that holds m), so that the weights of a
+// lane are straight-line code without branches and their exponentials
+// interleave.
+template <int D, int MP>
 __global__ __launch_bounds__(256) void cont_kernel(const ContArgs a)
 {
     const int lane = threadIdx.x & 63;
-    const int32_t chain = (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6);
-    if (chain >= a.num_chains) return;  // wave-uniform
+    const int r = lane & (kGroup - 1);            // lane within the chain's group
+    const int gbase = lane & ~(kGroup - 1);       // first lane of the group
+    const int32_t chain = (int32_t)blockIdx.x * kChainsPerBlock + (int32_t)(threadIdx.x / kGroup);
+    // groups past the last chain run along on chain 0's data and write nothing,
+    // so that every lane takes part in the wave-wide exchanges
+    const bool live = chain < a.num_chains;
+    const int32_t ch = live ? chain : 0;
     const int P = a.pairs, n = 2 * a.pairs;
-    const bool active = lane < n;
-    const int pj = lane < P ? lane : lane - P;
-    const double sgn = lane < P ? 1.0 : -1.0;
-    const uint32_t cid = a.chain_id[chain];
-    constexpr int NS = 4 * D + 1;  // estimator sums per weighting
+    const int m = (n + kGroup - 1) / kGroup;      // neighbours per lane
+    const uint32_t cid = a.chain_id[ch];
+    constexpr int NS = 4 * D + 1;                 // estimator sums per weighting
+    constexpr int NA = (2 * NS + kGroup - 1) / kGroup;  // sums per lane
 
-    double x[D], s[D];
+    double x[D], s[MP][D], w[MP];
 #pragma unroll
-    for (int i = 0; i < D; ++i) x[i] = a.x[(int64_t)chain * D + i];
-    double lpx = a.lpx[chain];
-    int64_t L = a.L[chain], set = a.set[chain];
-    const int64_t k0 = a.step[chain];
+    for (int i = 0; i < D; ++i) x[i] = a.x[(int64_t)ch * D + i];
+    double lpx = a.lpx[ch];
+    int64_t L = a.L[ch], set = a.set[ch];
+    const int64_t k0 = a.step[ch];
     int64_t flips = 0, stays = 0;
 
     auto load_set = [&]() {
-        const Offset<D> dl = draw_offset<D>(a.seed, cid, set, pj);
 #pragma unroll
-        for (int i = 0; i < D; ++i) s[i] = active ? sgn * dl.v[i] : 0.0;
+        for (int t = 0; t < MP; ++t) {
+            const int j = r * m + t;
+            if (t < m && j < n) {
+                const int pj = j < P ? j : j - P;
+                const Offset<D> dl = draw_offset<D>(a.seed, cid, set, pj);
+#pragma unroll
+                for (int i = 0; i < D; ++i) s[t][i] = j < P ? dl.v[i] : -dl.v[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < D; ++i) s[t][i] = 0.0;
+            }
+        }
     };
     load_set();
 
-    // lane t < 2 NS keeps estimator sum t: weighting t / NS (M, then the
-    // expected multiplicity), component t % NS (sum w, then w x_i, w x_i^2,
-    // w x_i^4, w 1(x_i > 0))
-    const bool has_acc = lane < 2 * NS;
-    const int kind = lane < NS ? 0 : 1;
-    const int comp = lane - kind * NS;
-    const int grp = comp == 0 ? -1 : (comp - 1) / D;
-    const int ci = comp == 0 ? 0 : (comp - 1) % D;
-    double acc = has_acc ? a.sums[(int64_t)chain * 2 * NS + lane] : 0.0;
+    // lane r keeps estimator sums r, r + 8, ...: weighting idx / NS (M, then
+    // the expected multiplicity), component idx % NS (sum w, then w x_i,
+    // w x_i^2, w x_i^4, w 1(x_i > 0))
+    double acc[NA];
+    int akind[NA], agrp[NA], aci[NA];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+        const int idx = r + kGroup * u;
+        akind[u] = idx < 2 * NS ? idx / NS : -1;
+        const int comp = idx % NS;
+        agrp[u] = comp == 0 ? -1 : (comp - 1) / D;
+        aci[u] = comp == 0 ? 0 : (comp - 1) % D;
+        acc[u] = akind[u] >= 0 ? a.sums[(int64_t)ch * 2 * NS + idx] : 0.0;
+    }
 
     double logU1b = 0.0, U2b = 0.0;
     for (int64_t it = 0; it < a.steps; ++it) {
         const int64_t k = k0 + it;
-        const int bl = (int)(it & 63);
-        if (bl == 0) batch_uniforms(cid, k, a.seed, lane, true, &logU1b, &U2b);
-        // weight of this lane's neighbour
-        double y[D], r2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            y[i] = x[i] + s[i];
-            r2 += y[i] * y[i];
+        const int bl = (int)(it & (kGroup - 1));
+        if (bl == 0) {
+            const Geo u = step_uniforms(cid, k + r, a.seed);
+            logU1b = u.q;
+            U2b = u.wrb;
         }
-        const double tt = r2 - a.mu0;
-        const double lpy = -(tt * tt) / a.den;
-        const double l = lpy - lpx;
-        const double w = active ? (l < 0.0 ? exp(l) : 1.0) : 0.0;
-        const double incl = wave_scan(w);
-        const double S = read_lane(incl, 63);
+        // weights of this lane's neighbours, min(1, pi(y)/pi(x)) = exp(min(l, 0))
+        // (exp(0) = 1 exactly), summed in neighbour order
+        double ls = 0.0;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) {
+            double y[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) y[i] = x[i] + s[t][i];
+            const double l = fmin(log_density<D>(y, a.mu0, a.c) - lpx, 0.0);
+            const bool on = t < m && r * m + t < n;
+            w[t] = on ? exp(l) : 0.0;
+            ls += w[t];
+        }
+        const double incl = group_scan(ls, r);
+        const double S = __shfl(incl, gbase + kGroup - 1, 64);
         const double p = S / (double)n;
-        const double logU1 = read_lane(logU1b, bl), U2 = read_lane(U2b, bl);
+        const double logU1 = __shfl(logU1b, gbase + bl, 64), U2 = __shfl(U2b, gbase + bl, 64);
         const Geo g = geometric(p, logU1, L);
-        const double q = g.q, wrb = g.wrb;
-        const bool stay = q >= (double)L;
-        const int64_t M = stay ? L : (int64_t)floor(q) + 1;
+        const bool stay = g.q >= (double)L;
+        const int64_t M = stay ? L : (int64_t)floor(g.q) + 1;
 
         // the record (J_k, M_k): estimator sums over the state before the move
-        if (has_acc) {
-            const double wt = kind == 0 ? (double)M : wrb;
-            if (grp < 0) {
-                acc += wt;
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            if (akind[u] < 0) continue;
+            const double wt = akind[u] == 0 ? (double)M : g.wrb;
+            if (agrp[u] < 0) {
+                acc[u] += wt;
             } else {
-                const double v = pick<D>(x, ci), v2 = v * v;
-                if (grp == 0) acc += wt * v;
-                else if (grp == 1) acc += wt * v2;
-                else if (grp == 2) acc += wt * (v2 * v2);
-                else acc += v > 0.0 ? wt : 0.0;
+                const double v = pick<D>(x, aci[u]), v2 = v * v;
+                if (agrp[u] == 0) acc[u] += wt * v;
+                else if (agrp[u] == 1) acc[u] += wt * v2;
+                else if (agrp[u] == 2) acc[u] += wt * (v2 * v2);
+                else acc[u] += v > 0.0 ? wt : 0.0;
             }
         }
-        int32_t action;
-        if (a.log_cap > 0 && lane == 0) {
-            const int64_t slot = (int64_t)chain * a.log_cap + (k % a.log_cap);
+        const int64_t slot = (int64_t)ch * a.log_cap + (a.log_cap > 0 ? k % a.log_cap : 0);
+        if (a.log_cap > 0 && live && r == 0) {
             a.log_M[slot] = M;
             a.log_lp[slot] = lpx;
             a.log_p[slot] = p;
-            a.log_w[slot] = wrb;
+            a.log_w[slot] = g.wrb;
         }
+        int32_t action;
         if (stay) {
             // Alg 7 "else": stay for the remaining L samples, next set
             action = -1;
@@ -186,27 +256,47 @@ __global__ __launch_bounds__(256) void cont_kernel(const ContArgs a)
             // first neighbour whose running sum exceeds U2 * S (weights > 0);
             // rounding fallback: the last positive one
             const double t2 = U2 * S;
-            const uint64_t hit = __ballot(active && incl > t2 && w > 0.0);
-            int sel;
-            if (hit != 0) {
-                sel = __builtin_ctzll(hit);
-            } else {
-                const uint64_t pos = __ballot(w > 0.0);
-                sel = 63 - __builtin_clzll(pos);
-            }
+            double run = incl - ls;
+            int found = -1, lastpos = -1;
 #pragma unroll
-            for (int i = 0; i < D; ++i) x[i] = x[i] + __shfl(s[i], sel, 64);
-            lpx = __shfl(lpy, sel, 64);
-            action = sel;
+            for (int t = 0; t < MP; ++t) {
+                if (w[t] > 0.0) lastpos = t;
+                run += w[t];
+                if (found < 0 && run > t2 && w[t] > 0.0) found = t;
+            }
+            const uint32_t hit = (uint32_t)(__ballot(found >= 0) >> gbase) & 0xFFu;
+            int src, tsel;
+            if (hit != 0) {
+                src = __builtin_ctz(hit);
+                tsel = __shfl(found, gbase + src, 64);
+            } else {
+                const uint32_t pos = (uint32_t)(__ballot(lastpos >= 0) >> gbase) & 0xFFu;
+                src = 31 - __builtin_clz(pos);
+                tsel = __shfl(lastpos, gbase + src, 64);
+            }
+            // the chosen offset, from lane src of the group
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double v = s[0][i];
+#pragma unroll
+                for (int t = 1; t < MP; ++t)
+                    if (tsel == t) v = s[t][i];
+                x[i] = x[i] + __shfl(v, gbase + src, 64);
+            }
+            lpx = log_density<D>(x, a.mu0, a.c);
+            action = src * m + tsel;
             ++flips;
         }
-        if (a.log_cap > 0 && lane == 0) a.log_action[(int64_t)chain * a.log_cap + (k % a.log_cap)] = action;
+        if (a.log_cap > 0 && live && r == 0) a.log_action[slot] = action;
     }
 
     // chain state back to memory
-    if (lane < D) a.x[(int64_t)chain * D + lane] = pick<D>(x, lane);
-    if (has_acc) a.sums[(int64_t)chain * 2 * NS + lane] = acc;
-    if (lane == 0) {
+    if (!live) return;
+    if (r < D) a.x[(int64_t)chain * D + r] = pick<D>(x, r);
+#pragma unroll
+    for (int u = 0; u < NA; ++u)
+        if (akind[u] >= 0) a.sums[(int64_t)chain * 2 * NS + r + kGroup * u] = acc[u];
+    if (r == 0) {
         a.lpx[chain] = lpx;
         a.L[chain] = L;
         a.set[chain] = set;
@@ -222,14 +312,10 @@ __global__ void cont_init_kernel(const ContArgs a)
 {
     const int32_t c = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     if (c >= a.num_chains) return;
-    double r2 = 0.0;
+    double x[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-        const double v = a.x[(int64_t)c * D + i];
-        r2 += v * v;
-    }
-    const double tt = r2 - a.mu0;
-    a.lpx[c] = -(tt * tt) / a.den;
+    for (int i = 0; i < D; ++i) x[i] = a.x[(int64_t)c * D + i];
+    a.lpx[c] = log_density<D>(x, a.mu0, a.c);
 }
 
 }  // namespace cont
@@ -237,11 +323,16 @@ __global__ void cont_init_kernel(const ContArgs a)
 hipError_t launch_cont(const ContArgs& a, bool init, hipStream_t st)
 {
     if (a.num_chains <= 0) return hipSuccess;
-    const dim3 grid_run((unsigned)((a.num_chains + 3) / 4)), grid_init((unsigned)((a.num_chains + 255) / 256));
-#define PNS_CONT_CASE(DD)                                                                              \
-    case DD:                                                                                           \
-        if (init) hipLaunchKernelGGL(cont::cont_init_kernel<DD>, grid_init, dim3(256), 0, st, a);      \
-        else hipLaunchKernelGGL(cont::cont_kernel<DD>, grid_run, dim3(256), 0, st, a);                 \
+    const dim3 grid_run((unsigned)((a.num_chains + cont::kChainsPerBlock - 1) / cont::kChainsPerBlock));
+    const dim3 grid_init((unsigned)((a.num_chains + 255) / 256));
+    const int m = (2 * a.pairs + cont::kGroup - 1) / cont::kGroup;
+#define PNS_CONT_CASE(DD)                                                                                \
+    case DD:                                                                                             \
+        if (init) hipLaunchKernelGGL(cont::cont_init_kernel<DD>, grid_init, dim3(256), 0, st, a);        \
+        else if (m <= 2) hipLaunchKernelGGL((cont::cont_kernel<DD, 2>), grid_run, dim3(256), 0, st, a);  \
+        else if (m <= 4) hipLaunchKernelGGL((cont::cont_kernel<DD, 4>), grid_run, dim3(256), 0, st, a);  \
+        else if (m <= 7) hipLaunchKernelGGL((cont::cont_kernel<DD, 7>), grid_run, dim3(256), 0, st, a);  \
+        else hipLaunchKernelGGL((cont::cont_kernel<DD, 8>), grid_run, dim3(256), 0, st, a);              \
         break;
     switch (a.dim) {
         PNS_CONT_CASE(1)

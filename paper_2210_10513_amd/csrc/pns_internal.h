@@ -155,8 +155,8 @@ hipError_t launch_moments(const uint32_t* Xb, int32_t npad, int64_t words, int32
 struct ContArgs {
     int32_t dim;                    // 1 .. 7
     int32_t pairs;                  // P: 2P neighbours per set, 1 .. 32
-    double mu0;                     // donut: log pi = -(|x|^2 - mu0)^2 / den
-    double den;                     // 2 sigma^2
+    double mu0;                     // donut: log pi = -(|x|^2 - mu0)^2 c
+    double c;                       // 1 / (2 sigma^2), rounded once
     int64_t L0;
     uint64_t seed;
     int32_t num_chains;

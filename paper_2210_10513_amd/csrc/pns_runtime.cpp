@@ -2069,7 +2069,7 @@ struct pns_cont {
         a.dim = dim;
         a.pairs = o.pairs;
         a.mu0 = o.mu0;
-        a.den = 2.0 * o.sigma * o.sigma;
+        a.c = 1.0 / (2.0 * o.sigma * o.sigma);
         a.L0 = o.L0;
         a.seed = o.seed;
         a.num_chains = C;
@@ -2131,8 +2131,9 @@ int pns_cont_create(pns_cont** out, const pns_cont_opts* o)
     if (o->pairs < 1 || o->pairs > 32) return fail(PNS_EINVAL, "pairs must be in [1, 32]");
     if (!(o->sigma > 0.0) || !std::isfinite(o->sigma)) return fail(PNS_EINVAL, "sigma must be finite and > 0");
     if (!std::isfinite(o->mu0)) return fail(PNS_EINVAL, "mu0 must be finite");
-    if (!std::isfinite(2.0 * o->sigma * o->sigma) || 2.0 * o->sigma * o->sigma == 0.0)
-        return fail(PNS_EINVAL, "2 sigma^2 must be a finite positive double");
+    if (!std::isfinite(1.0 / (2.0 * o->sigma * o->sigma)) || 2.0 * o->sigma * o->sigma == 0.0 ||
+        !std::isfinite(2.0 * o->sigma * o->sigma))
+        return fail(PNS_EINVAL, "2 sigma^2 and its reciprocal must be finite positive doubles");
     if (o->L0 < 1 || o->L0 > ((int64_t)1 << 53)) return fail(PNS_EINVAL, "L0 must be in [1, 2^53]");
     if (o->num_chains < 1) return fail(PNS_EINVAL, "num_chains must be >= 1");
     if (o->log_capacity < 0) return fail(PNS_EINVAL, "log_capacity must be >= 0");
