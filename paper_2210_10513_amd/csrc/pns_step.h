@@ -161,9 +161,13 @@ struct Four {
     T v[4];
 };
 
-__device__ __forceinline__ Four<int32_t> load_row4(const int16_t* p)
+// Raw loads of four consecutive coefficients and their widening, split so
+// that the wait for the load can sit at the first use of the values.
+__device__ __forceinline__ uint2 load_raw4(const int16_t* p) { return *reinterpret_cast<const uint2*>(p); }
+__device__ __forceinline__ int4 load_raw4(const int32_t* p) { return *reinterpret_cast<const int4*>(p); }
+__device__ __forceinline__ float4 load_raw4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ Four<int32_t> widen4(uint2 r)
 {
-    const uint2 r = *reinterpret_cast<const uint2*>(p);
     Four<int32_t> o;
     o.v[0] = (int32_t)(int16_t)(r.x & 0xFFFFu);
     o.v[1] = (int32_t)(int16_t)(r.x >> 16);
@@ -171,16 +175,8 @@ __device__ __forceinline__ Four<int32_t> load_row4(const int16_t* p)
     o.v[3] = (int32_t)(int16_t)(r.y >> 16);
     return o;
 }
-__device__ __forceinline__ Four<int32_t> load_row4(const int32_t* p)
-{
-    const int4 r = *reinterpret_cast<const int4*>(p);
-    return {{r.x, r.y, r.z, r.w}};
-}
-__device__ __forceinline__ Four<float> load_row4(const float* p)
-{
-    const float4 r = *reinterpret_cast<const float4*>(p);
-    return {{r.x, r.y, r.z, r.w}};
-}
+__device__ __forceinline__ Four<int32_t> widen4(int4 r) { return {{r.x, r.y, r.z, r.w}}; }
+__device__ __forceinline__ Four<float> widen4(float4 r) { return {{r.x, r.y, r.z, r.w}}; }
 
 template <typename T>
 __device__ __forceinline__ Four<T> load4(const T* p)
@@ -359,6 +355,10 @@ void step_kernel(const StepArgs a)
     // kept (the chosen lane recomputes its weights); one group keeps both in
     // registers.  The compact window always reads the diagonal from LDS.
     constexpr bool kLdsDiag = FLAV == FLAV_WINDOW_C || G >= 2;
+    // One field group per lane: the record bookkeeping (and an unbudgeted
+    // multiplicity) runs while the row of the flip is loading (the registers
+    // allow it); wider tiles keep the shorter live ranges.
+    constexpr bool kEarly = G == 1 && FLAV != FLAV_WINDOW_C;
     constexpr bool kKeepW = FLAV == FLAV_WINDOW_C || G == 1;
     QW* const dsh = reinterpret_cast<QW*>(own + (FLAV == FLAV_DRAWN ? pitch : 0));
     const int mode = a.mode;
@@ -515,8 +515,36 @@ void step_kernel(const StepArgs a)
     const bool draw_each_step = mode == kModeBasic || mode == kModeOpt;
     uint32_t mem = (FLAV == FLAV_DRAWN && draw_each_step) ? 0u : compute_mem();
 
+    // RF / Basic sampling without per-step outputs: M steers nothing, so the
+    // multiplicities of up to 64 steps are computed together by the leader
+    // wave, lane j for step ub_base + j (the step uniforms are laid out the
+    // same way); lane j of pbuf keeps that step's escape probability p.
+    const bool lazy_m = !INSTR && !unbiased && !timed && mode != kModeOpt;
+    double pbuf = 0.0;
+    auto flush_m = [&](int cnt) {  // leader wave only
+        const double pj = pbuf;
+        double qj;
+        if (pj >= 1.0) qj = 0.0;
+        else if (pj <= 0.0) qj = INFINITY;
+        else qj = ubLog / log1p(-pj);
+        const bool act = lane < cnt;
+        const bool satj = act && !(qj < 0x1p63);
+        const int64_t mj = satj ? INT64_MAX : (act ? (int64_t)floor(qj) + 1 : 0);
+        double tot = act ? (double)mj : 0.0;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, 64);
+        const uint64_t nsat = __ballot(satj);
+        const int lo = __shfl((int)(uint32_t)mj, cnt - 1, 64), hi = __shfl((int)(mj >> 32), cnt - 1, 64);
+        if (tid == lead_tid) {
+            lead_st[kLsSumM] = __double_as_longlong(__longlong_as_double(lead_st[kLsSumM]) + tot);
+            lead_st[kLsSat] += __builtin_popcountll(nsat);
+            lead_st[kLsLastM] = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+        }
+    };
+
     for (; k < kend; ++k) {
         if (k - ub_base >= 64) {
+            if (lazy_m && lead) flush_m(64);
             ub_base = k;
             batch_uniforms(cid, ub_base, seed, lane, lead, &ubLog, &ubU2);
         }
@@ -745,6 +773,12 @@ void step_kernel(const StepArgs a)
             S = read_lane(sinc, NSEG - 1);
         }
 
+        if (lazy_m && lead) {
+            const double Ss = scaled ? exp(mx) * S : S;
+            const double pv = n_pow2 ? Ss * inv_n : Ss / (double)n;
+            pbuf = lane == uj ? pv : pbuf;
+        }
+
         // Escape probability and multiplicity M = 1 + G, G ~ Geometric(p)
         // counting failures; uniform FP64 work done by wave 0 only.
         double p = 0.0, q = 0.0;
@@ -764,8 +798,10 @@ void step_kernel(const StepArgs a)
                 sat = false;
             }
         };
-        // Unbiased: wave 0 takes the budget decision of Alg 6 while the winner
-        // wave resolves the (speculative) choice; both meet at the barrier.
+        // Budgeted runs: the leader takes the budget decision of Alg 6 while
+        // the winner wave resolves the (speculative) choice; both meet at the
+        // barrier.  Otherwise M does not steer the chain and is computed with
+        // the record, off the path to the next step.
         if ((unbiased || timed) && tid == lead_tid) {
             multiplicity();
             stay_flag = q >= (double)lead_st[kLsL] ? 1 : 0;
@@ -887,6 +923,38 @@ void step_kernel(const StepArgs a)
         __syncthreads();
         const bool stay = (unbiased || timed) && stay_flag != 0;
 
+        // row c of the flip: with one field group per lane it is loaded before
+        // the record bookkeeping below, which then runs while the loads are in
+        // flight, and the fields are updated after it
+        decltype(load_raw4(static_cast<const QT*>(nullptr))) raw[G];
+        bool xc = false;
+        auto update_fields = [&]() {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const auto r = widen4(raw[g]);
+                if (((int64_t)g * BLOCK + tid) * 4 < pitch) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        if (xc) h[g * 4 + v] -= (HT)r.v[v];
+                        else h[g * 4 + v] += (HT)r.v[v];
+                    }
+                }
+            }
+        };
+        const int64_t sv0 = sel[0];
+        const int32_t csel = (int32_t)(sv0 & 0xFFFFFFFFll);  // in [0, N) on every step
+        // Row csel: every lane loads (lanes past the pitch read the row's start
+        // and drop it), so no branch forces an early wait.  One group per
+        // lane: loaded whether or not the chain stays (a stay drops it), so
+        // that the loaded registers are not joined from two branches.
+        const QT* row = reinterpret_cast<const QT*>(P.A) + (int64_t)csel * pitch;
+        if constexpr (kEarly) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
+                raw[g] = load_raw4(row + (fb < pitch ? fb : 0));
+            }
+        }
         if (stay) {
             // Alg 6: not enough remaining original samples; stay L times and
             // switch to the next partial neighbor set (a timed run just ends).
@@ -900,30 +968,19 @@ void step_kernel(const StepArgs a)
                 mem = compute_mem();
             }
         } else {
-            const int64_t sv0 = sel[0];
-            const int32_t c = (int32_t)(sv0 & 0xFFFFFFFFll);
-            const bool xc = (sv0 >> 40) & 1;
-            // field update from row c; the record and the next step's random
-            // numbers are computed while the row is in flight
-            const QT* row = reinterpret_cast<const QT*>(P.A) + (int64_t)c * pitch;
-            decltype(load_row4(row)) r[G];
+            const int32_t c = csel;
+            xc = (sv0 >> 40) & 1;
+            if constexpr (!kEarly) {
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
-                if (fb < pitch) r[g] = load_row4(row + fb);
-                else r[g] = {};
+                for (int g = 0; g < G; ++g) {
+                    const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
+                    raw[g] = load_raw4(row + (fb < pitch ? fb : 0));
+                }
             }
             const int cl = (c >> 2) % BLOCK;
             const int cg = (c >> 2) / BLOCK;
             if (tid == cl) xb ^= 1u << (cg * 4 + (c & 3));
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    if (xc) h[g * 4 + v] -= (HT)r[g].v[v];
-                    else h[g * 4 + v] += (HT)r[g].v[v];
-                }
-            }
+            if constexpr (!kEarly) update_fields();
         }
         if constexpr (INSTR) {
             if (snap) ++snap_n;
@@ -944,7 +1001,7 @@ void step_kernel(const StepArgs a)
             } else {
                 const int64_t sv0 = sel[0];
                 const int64_t dEc = sel[1];
-                if (!unbiased && !timed) multiplicity();
+                if (!unbiased && !timed && !lazy_m) multiplicity();
                 if (mode == kModeOpt) {
                     m = 1;  // no multiplicity: each jump counts once
                     sat = false;
@@ -967,9 +1024,9 @@ void step_kernel(const StepArgs a)
                 }
             }
             lead_st[kLsSteps] += 1;
-            lead_st[kLsSumM] = __double_as_longlong(__longlong_as_double(lead_st[kLsSumM]) + (double)M);
+            if (!lazy_m) lead_st[kLsSumM] = __double_as_longlong(__longlong_as_double(lead_st[kLsSumM]) + (double)M);
             lead_st[kLsLastA] = action;
-            lead_st[kLsLastM] = M;
+            if (!lazy_m) lead_st[kLsLastM] = M;
             lead_st[kLsLastE] = Erec;
             if constexpr (INSTR) {
                 // Rao-Blackwell weight of the record: E[M | state, subset, budget]
@@ -998,11 +1055,15 @@ void step_kernel(const StepArgs a)
                 }
             }
         }
+        if constexpr (kEarly) {
+            if (!stay) update_fields();
+        }
         if (timed && stay) {
             ++k;  // the cut record was the run's last
             break;
         }
     }
+    if (lazy_m && lead && k > ub_base) flush_m((int)(k - ub_base));
 
     if constexpr (INSTR) {
         __syncthreads();

@@ -216,3 +216,45 @@ def test_unbiased_n8192_f32_sampled_chains():
     o = oracle_run(Q64, betas[rows], "unbiased_sys", 150, chains=rows, n=512, L0=100, seed=2210105133)
     assert compare_logs(g["log"], o, chain_rows=rows, is_int=False) == len(rows) * 150
     compare_final(g["cur"], o, chain_rows=rows, is_int=False)
+
+
+@pytest.mark.parametrize("mode,n,launch,chunk,K", [("rf", 0, "persistent", 0, 130), ("rf", 0, "persistent", 50, 177),
+                                                   ("basic", 7, "persistent", 64, 128), ("rf", 0, "plain", 0, 70),
+                                                   ("basic", 5, "graph", 33, 99)])
+def test_uninstrumented_runs_keep_the_multiplicity_counters(mode, n, launch, chunk, K):
+    """Without per-step outputs the RF / Basic kernels compute the
+    multiplicities of up to 64 steps together: the last record's M
+    (pns_read), the sum of M and the saturation count equal the oracle's
+    records, across launch forms, chunk boundaries and two runs."""
+    from paper_2210_10513_amd.binding import Sampler
+    N, C = 120, 5
+    Q = inputs.symmetric_int(N, -40, 40, np.int32, seed=21)
+    s = Sampler(Q, 0.06, n, mode, num_chains=C, seed=5, init="random", launch=launch, chunk=chunk)
+    s.run(K)
+    s.run(K // 2)
+    _, m, e = s.read()  # the last record (J, M, E(J))
+    x = s.read_current()["x"]
+    st = s.stats()
+    s.close()
+    o = oracle_run(Q, 0.06, mode, K + K // 2, n=n, seed=5, chains=list(range(C)), init="random")
+    assert np.array_equal(x, o.x)
+    assert np.array_equal(e, o.E[:, -1].astype(np.float64))
+    # M = 1 + floor(log U / log1p(-p)) grows like 1/p: p agrees to 1e-12
+    # relative (summation order), so a multiplicity of 1e16 (p ~ 1e-16, which
+    # this seed reaches) agrees to about that relative precision, not exactly
+    assert np.allclose(m, o.M[:, -1], rtol=1e-12, atol=0)
+    assert np.allclose(st["sum_M"], o.M.astype(np.float64).sum(axis=1), rtol=1e-12, atol=0)
+    assert (st["saturated"] == 0).all() and (st["steps"] == K + K // 2).all()
+
+
+def test_uninstrumented_frozen_chain_saturates():
+    from paper_2210_10513_amd.binding import Sampler
+    Q = (np.diag(np.arange(1, 7)) * 1000).astype(np.int32)
+    s = Sampler(Q, 10.0, 0, "rf", num_chains=2, seed=1)
+    s.run(3)
+    _, m, _ = s.read()
+    st = s.stats()
+    s.close()
+    o = oracle_run(Q, 10.0, "rf", 3, chains=[0, 1], seed=1)
+    assert np.array_equal(m, o.M[:, -1])
+    assert np.array_equal(st["saturated"], (o.M == np.iinfo(np.int64).max).sum(axis=1))
