@@ -128,6 +128,21 @@ __device__ __forceinline__ double wave_scan(double v)
     return v;
 }
 
+// The same inclusive prefix sum restricted to lanes 0 .. NS-1 (the other
+// lanes' values are not used): the shifts and broadcasts that cannot reach
+// those lanes from below are skipped, which leaves their sums unchanged.
+template <int NS>
+__device__ __forceinline__ double small_scan(double v)
+{
+    v += dpp_f64<0x111, 0xF>(v);
+    if constexpr (NS > 2) v += dpp_f64<0x112, 0xF>(v);
+    if constexpr (NS > 4) v += dpp_f64<0x114, 0xF>(v);
+    if constexpr (NS > 8) v += dpp_f64<0x118, 0xF>(v);
+    if constexpr (NS > 16) v += dpp_f64<0x142, 0xA>(v);
+    if constexpr (NS > 32) v += dpp_f64<0x143, 0xC>(v);
+    return v;
+}
+
 __device__ __forceinline__ double read_lane(double v, int lane)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -724,7 +739,7 @@ void step_kernel(const StepArgs a)
             if (a.xbest != nullptr && best_flag) store_bits(a.xbest + off);
         }
         double sv = lane < NSEG ? seg_sum[lane] : 0.0;
-        double sinc = wave_scan(sv);
+        double sinc = small_scan<NSEG>(sv);
         double S = read_lane(sinc, NSEG - 1);
         double mx = 0.0;
         bool scaled = false;
@@ -769,7 +784,7 @@ void step_kernel(const StepArgs a)
             scan_and_publish();
             __syncthreads();
             sv = lane < NSEG ? seg_sum[lane] : 0.0;
-            sinc = wave_scan(sv);
+            sinc = small_scan<NSEG>(sv);
             S = read_lane(sinc, NSEG - 1);
         }
 
