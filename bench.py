@@ -339,7 +339,7 @@ def _time_sampler(wl, chain_steps: int, steps: int, warmup: int, launch: str, se
     return ms / 1000.0 / steps, flips, recs, summ, wall, tile
 
 
-def _cpu_baseline(wl, budget_s: float = 12.0):
+def _cpu_baseline(wl, budget_s: float = 15.0):
     import oracle
     Q = wl["Q"].astype(np.int64) if np.issubdtype(wl["Q"].dtype, np.integer) else wl["Q"].astype(np.float64)
     modes = {"rf": oracle.MODE_RF, "basic": oracle.MODE_BASIC, "unbiased_sys": oracle.MODE_UNBIASED_SYS}

@@ -860,7 +860,7 @@ void step_kernel(const StepArgs a)
             jstar = jstar < NSEG ? jstar : NSEG - 1;
             const int gstar = jstar / W, wstar = jstar % W;
             if (wave == wstar) {
-                const double base = jstar > 0 ? __shfl(sinc, jstar - 1, 64) : 0.0;
+                const double base = jstar > 0 ? read_lane(sinc, jstar - 1) : 0.0;  // jstar is wave-uniform
                 double my_inc = 0.0, my_ls = 0.0;
                 if constexpr (kCompact) {
                     my_inc = inc[0];
@@ -878,7 +878,7 @@ void step_kernel(const StepArgs a)
                 const uint64_t bl = __ballot(my_ls > 0.0 && Gl > t);
                 const uint64_t blp = __ballot(my_ls > 0.0);
                 const int lstar = bl ? __builtin_ctzll(bl) : (blp ? 63 - __builtin_clzll(blp) : 0);
-                const double prev_l = __shfl(my_inc, lstar > 0 ? lstar - 1 : 0, 64);
+                const double prev_l = read_lane(my_inc, lstar > 0 ? lstar - 1 : 0);  // lstar is wave-uniform
                 if (lane == lstar) {
                     double run = lstar > 0 ? base + prev_l : base;
                     int vstar = -1, vlast = -1;
