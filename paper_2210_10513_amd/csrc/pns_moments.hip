@@ -15,6 +15,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "pns_internal.h"
@@ -37,26 +38,31 @@ __device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float
 
 // Pieces of each weight (m = p0 + p1 + p2, each a bf16) and the exact sum
 // and maximum of the weights.  Pieces are stored [3][kpad], zero past K.
-__global__ void moments_prep_kernel(const int64_t* m, int64_t K, int64_t kpad, uint16_t* pieces,
-                                    unsigned long long* sum_m, unsigned long long* max_m)
+// Grid-stride loop; one atomic per workgroup for the sum and the maximum.
+__global__ __launch_bounds__(256) void moments_prep_kernel(const int64_t* m, int64_t K, int64_t kpad, uint16_t* pieces,
+                                                           unsigned long long* sum_m, unsigned long long* max_m)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t mk = 0;
-    if (k < K) mk = m[k] > 0 ? m[k] : 0;
-    if (k < kpad) {
-        // m < 2^24 is exact in float; the pieces then sum to it exactly
-        float r = (float)mk;
-        uint16_t b[3];
+    __shared__ unsigned long long red[2][4];
+    const int64_t n = kpad > K ? kpad : K;
+    unsigned long long sv = 0, mv = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t mk = 0;
+        if (k < K) mk = m[k] > 0 ? m[k] : 0;
+        if (k < kpad) {
+            // m < 2^24 is exact in float; the pieces then sum to it exactly
+            float r = (float)mk;
+            uint16_t b[3];
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            b[s] = bf16_bits(r);
-            r = r - bf16_value(b[s]);
+            for (int s = 0; s < 3; ++s) {
+                b[s] = bf16_bits(r);
+                r = r - bf16_value(b[s]);
+            }
+#pragma unroll
+            for (int s = 0; s < 3; ++s) pieces[s * kpad + k] = b[s];
         }
-#pragma unroll
-        for (int s = 0; s < 3; ++s) pieces[s * kpad + k] = b[s];
+        sv += (unsigned long long)mk;
+        mv = mv > (unsigned long long)mk ? mv : (unsigned long long)mk;
     }
-    // wave reductions, then one atomic per wave
-    unsigned long long sv = (unsigned long long)mk, mv = (unsigned long long)mk;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         sv += __shfl_xor(sv, d, 64);
@@ -64,8 +70,18 @@ __global__ void moments_prep_kernel(const int64_t* m, int64_t K, int64_t kpad, u
         mv = mv > o ? mv : o;
     }
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(sum_m, sv);
-        atomicMax(max_m, mv);
+        red[0][threadIdx.x >> 6] = sv;
+        red[1][threadIdx.x >> 6] = mv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long ts = 0, tm = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            ts += red[0][w];
+            tm = tm > red[1][w] ? tm : red[1][w];
+        }
+        atomicAdd(sum_m, ts);
+        atomicMax(max_m, tm);
     }
 }
 
@@ -75,18 +91,27 @@ __global__ void moments_prep_kernel(const int64_t* m, int64_t K, int64_t kpad, u
 // two into [-2, 2] before they are rounded to FP32 (relative 2^-24) and split
 // exactly into three bf16 pieces; G is scaled back at the end.  Non-finite
 // weights count as 0 in G and in the sum.
-__global__ void moments_absmax_kernel(const double* w, int64_t K, unsigned long long* maxbits)
+__global__ __launch_bounds__(256) void moments_absmax_kernel(const double* w, int64_t K, unsigned long long* maxbits)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double v = 0.0;
-    if (k < K && isfinite(w[k])) v = fabs(w[k]);
-    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    __shared__ unsigned long long red[4];
+    unsigned long long b = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x) {
+        const double v = isfinite(w[k]) ? fabs(w[k]) : 0.0;
+        const unsigned long long vb = (unsigned long long)__double_as_longlong(v);
+        b = b > vb ? b : vb;
+    }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         const unsigned long long o = __shfl_xor(b, d, 64);
         b = b > o ? b : o;
     }
-    if ((threadIdx.x & 63) == 0) atomicMax(maxbits, b);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = t > red[i] ? t : red[i];
+        atomicMax(maxbits, t);
+    }
 }
 
 __device__ __forceinline__ int weight_exponent(const unsigned long long* maxbits)
@@ -95,27 +120,39 @@ __device__ __forceinline__ int weight_exponent(const unsigned long long* maxbits
     return mx > 0.0 ? ilogb(mx) : 0;
 }
 
-__global__ void moments_prep_f64_kernel(const double* w, int64_t K, int64_t kpad, uint16_t* pieces, double* sum_w,
-                                        const unsigned long long* maxbits)
+__global__ __launch_bounds__(256) void moments_prep_f64_kernel(const double* w, int64_t K, int64_t kpad,
+                                                               uint16_t* pieces, double* sum_w,
+                                                               const unsigned long long* maxbits)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double wk = 0.0;
-    if (k < K && isfinite(w[k])) wk = w[k];
-    if (k < kpad) {
-        float r = (float)ldexp(wk, -weight_exponent(maxbits));
-        uint16_t b[3];
+    __shared__ double red[4];
+    const int64_t n = kpad > K ? kpad : K;
+    const int e = weight_exponent(maxbits);
+    double sv = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        double wk = 0.0;
+        if (k < K && isfinite(w[k])) wk = w[k];
+        if (k < kpad) {
+            float r = (float)ldexp(wk, -e);
+            uint16_t b[3];
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            b[s] = bf16_bits(r);
-            r = r - bf16_value(b[s]);
+            for (int s = 0; s < 3; ++s) {
+                b[s] = bf16_bits(r);
+                r = r - bf16_value(b[s]);
+            }
+#pragma unroll
+            for (int s = 0; s < 3; ++s) pieces[s * kpad + k] = b[s];
         }
-#pragma unroll
-        for (int s = 0; s < 3; ++s) pieces[s * kpad + k] = b[s];
+        sv += wk;
     }
-    double sv = wk;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) sv += __shfl_xor(sv, d, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(sum_w, sv);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sv;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+        atomicAdd(sum_w, t);
+    }
 }
 
 // G *= 2^e, the scale the weights were divided by.
@@ -156,6 +193,45 @@ __global__ void pack_bits_kernel(const uint8_t* __restrict__ X, int64_t ldx, int
         for (int r = 0; r < rmax; ++r) v |= (uint32_t)(X[(k0 + r) * ldx + i] != 0) << r;
     }
     Xb[w * npad + i] = v;
+}
+
+// The same packing four columns per thread: one 32-bit load per record
+// (rows 4-byte aligned: ldx % 4 == 0 and X aligned), npad % 4 == 0.
+__global__ void pack_bits4_kernel(const uint8_t* __restrict__ X, int64_t ldx, int64_t K, int32_t N, int32_t npad,
+                                  int64_t words, uint32_t* __restrict__ Xb)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t q = npad / 4;
+    const int64_t w = t / q;
+    const int32_t i0 = (int32_t)(t % q) * 4;
+    if (w >= words) return;
+    uint32_t v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+    if (i0 < N) {
+        const int64_t k0 = w * 32;
+        const int rmax = K - k0 < 32 ? (int)(K - k0) : 32;
+        // columns at or past N (inside the row's pitch, or past it when
+        // N = ldx) are masked below; a load never starts past the row
+        const bool full = i0 + 4 <= ldx;
+        for (int r = 0; r < rmax; ++r) {
+            const uint8_t* row = X + (k0 + r) * ldx;
+            uint32_t b;
+            if (full) {
+                b = *reinterpret_cast<const uint32_t*>(row + i0);
+            } else {
+                b = 0;
+                for (int c = 0; c < 4 && i0 + c < ldx; ++c) b |= (uint32_t)row[i0 + c] << (8 * c);
+            }
+            v0 |= (uint32_t)((b & 0xFFu) != 0) << r;
+            v1 |= (uint32_t)((b & 0xFF00u) != 0) << r;
+            v2 |= (uint32_t)((b & 0xFF0000u) != 0) << r;
+            v3 |= (uint32_t)((b & 0xFF000000u) != 0) << r;
+        }
+        if (i0 + 1 >= N) v1 = 0;
+        if (i0 + 2 >= N) v2 = 0;
+        if (i0 + 3 >= N) v3 = 0;
+    }
+    uint4 out = make_uint4(v0, v1, v2, v3);
+    *reinterpret_cast<uint4*>(Xb + w * npad + i0) = out;
 }
 
 // 0xFFFF per set bit of a 2-bit field, in the matching half word.
@@ -286,24 +362,25 @@ __global__ __launch_bounds__(256) void moments_kernel(const uint32_t* __restrict
             for (int e = 0; e < 4; ++e) dst[(a * 16 + lg * 4 + e) * kTile + b * 16 + l16] = acc[a][b][e];
 }
 
-// G[i][j] += sum over chunks of the partial tiles (FP64; the partials are
-// exact integers), both triangles.  One thread per element of G.
+// G[i][j] += sum over chunks of the partial tiles (FP64, in chunk order).
+// One thread per element of an upper-triangle tile (reads coalesced along the
+// tile row); an off-diagonal tile's element also gives G[j][i].
 __global__ void moments_reduce_kernel(const float* __restrict__ part, int64_t chunks, int32_t tiles, int32_t N,
                                       double* __restrict__ G)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)N * N) return;
-    const int i = (int)(e / N), j = (int)(e % N);
-    const int a = i < j ? i : j, b = i < j ? j : i;  // upper-triangle element (a, b)
+    if (e >= (int64_t)tiles * (kTile * kTile)) return;
+    const int t = (int)(e / (kTile * kTile));
+    const int off = (int)(e % (kTile * kTile));
     const int nt = (N + kTile - 1) / kTile;
-    const int ti = a / kTile, tj = b / kTile;
-    const int t = ti * nt - ti * (ti - 1) / 2 + (tj - ti);
-    const int r = a - ti * kTile, q = b - tj * kTile;
-    const int64_t off = (int64_t)t * kTile * kTile + (ti == tj ? (i - ti * kTile) * kTile + (j - tj * kTile)
-                                                                 : r * kTile + q);
+    int ti, tj;
+    upper_tile(t, nt, &ti, &tj);
+    const int i = ti * kTile + off / kTile, j = tj * kTile + off % kTile;
+    if (i >= N || j >= N) return;
     double s = 0.0;
-    for (int64_t c = 0; c < chunks; ++c) s += (double)part[c * tiles * (int64_t)(kTile * kTile) + off];
-    G[e] += s;
+    for (int64_t c = 0; c < chunks; ++c) s += (double)part[c * tiles * (int64_t)(kTile * kTile) + e];
+    G[(int64_t)i * N + j] += s;
+    if (ti != tj) G[(int64_t)j * N + i] += s;
 }
 
 // sum of the weights as FP64 into a device word.
@@ -440,18 +517,19 @@ hipError_t launch_moments_prep(const int64_t* m, int64_t K, int64_t kpad, uint16
                                unsigned long long* max_m, hipStream_t st)
 {
     const int64_t n = kpad > K ? kpad : K;
-    hipLaunchKernelGGL(moments_prep_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, m, K, kpad, pieces,
-                       sum_m, max_m);
+    const int64_t blocks = std::min<int64_t>(256, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(moments_prep_kernel, dim3((unsigned)blocks), dim3(256), 0, st, m, K, kpad, pieces, sum_m, max_m);
     return hipGetLastError();
 }
 
 hipError_t launch_moments_prep_f64(const double* w, int64_t K, int64_t kpad, uint16_t* pieces, double* sum_w,
                                    unsigned long long* maxbits, hipStream_t st)
 {
-    if (K > 0) hipLaunchKernelGGL(moments_absmax_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, w, K, maxbits);
     const int64_t n = kpad > K ? kpad : K;
-    hipLaunchKernelGGL(moments_prep_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, K, kpad, pieces,
-                       sum_w, maxbits);
+    const int64_t blocks = std::min<int64_t>(256, std::max<int64_t>(1, (n + 255) / 256));
+    if (K > 0) hipLaunchKernelGGL(moments_absmax_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w, K, maxbits);
+    hipLaunchKernelGGL(moments_prep_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w, K, kpad, pieces, sum_w,
+                       maxbits);
     return hipGetLastError();
 }
 
@@ -464,9 +542,15 @@ hipError_t launch_moments_unscale(double* G, int64_t n, const unsigned long long
 hipError_t launch_pack_bits(const uint8_t* X, int64_t ldx, int64_t K, int32_t N, int32_t npad, int64_t words,
                             uint32_t* Xb, hipStream_t st)
 {
-    const int64_t n = words * npad;
-    hipLaunchKernelGGL(pack_bits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, ldx, K, N, npad, words,
-                       Xb);
+    if (ldx % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 3u) == 0 && npad % 4 == 0) {
+        const int64_t n = words * (npad / 4);
+        hipLaunchKernelGGL(pack_bits4_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, ldx, K, N, npad,
+                           words, Xb);
+    } else {
+        const int64_t n = words * npad;
+        hipLaunchKernelGGL(pack_bits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, ldx, K, N, npad,
+                           words, Xb);
+    }
     return hipGetLastError();
 }
 
@@ -482,7 +566,7 @@ hipError_t launch_moments(const uint32_t* Xb, int32_t npad, int64_t words, int32
                        kpad, chunk_words, tiles, max_m, part, G);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t n = (int64_t)N * N;
+    const int64_t n = (int64_t)tiles * kTile * kTile;
     hipLaunchKernelGGL(moments_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, chunks, tiles,
                        N, G);
     return hipGetLastError();
