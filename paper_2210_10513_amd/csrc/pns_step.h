@@ -323,14 +323,14 @@ constexpr int kLsE = 0, kLsL = 1, kLsLastA = 2, kLsLastM = 3, kLsLastE = 4, kLsS
 // Occupancy asked of the compiler (waves per SIMD): compact-window kernels
 // of 512 lanes target two co-resident chains per compute unit (128 VGPRs);
 // 1024-lane kernels keep the register budget of one chain per unit.
-template <int BLOCK, int FLAV>
+template <int BLOCK, int G, int FLAV>
 constexpr int min_waves_per_eu()
 {
-    return (FLAV == FLAV_WINDOW_C && BLOCK == 512) ? 4 : 1;
+    return ((FLAV == FLAV_WINDOW_C && BLOCK == 512) || (G == 1 && BLOCK <= 512)) ? 4 : 1;
 }
 
 template <typename QT, typename HT, int BLOCK, int G, int FLAV, bool INSTR>
-__global__ __attribute__((amdgpu_flat_work_group_size(1, BLOCK), amdgpu_waves_per_eu(min_waves_per_eu<BLOCK, FLAV>())))
+__global__ __attribute__((amdgpu_flat_work_group_size(1, BLOCK), amdgpu_waves_per_eu(min_waves_per_eu<BLOCK, G, FLAV>())))
 void step_kernel(const StepArgs a)
 {
     using QW = typename Wide<QT>::T;
