@@ -349,7 +349,7 @@ void step_kernel(const StepArgs a)
     __shared__ int64_t sel[2];
     __shared__ int32_t stay_flag;
     __shared__ uint32_t hist_idx;
-    __shared__ double tab_lo[kInt ? kTabLo + 1 : 1];
+    __shared__ double tab_lo[kInt ? 2 * kTabLo : 1];
     __shared__ double tab_hi[kInt ? kTabHi : 1];
 
     const int tid = threadIdx.x;
@@ -392,11 +392,11 @@ void step_kernel(const StepArgs a)
     const uint64_t seed = a.seed;
 
     if constexpr (kInt) {
-        // tab_lo[kTabLo] = 0 is the weight of a bit outside the subset
-        for (int i = tid; i < kTabLo + 1 + kTabHi; i += BLOCK) {
+        // tab_lo[kTabLo .. 2 kTabLo) = 0 are the weights of bits outside the subset
+        for (int i = tid; i < 2 * kTabLo + kTabHi; i += BLOCK) {
             if (i < kTabLo) tab_lo[i] = exp(-beta * (double)i);
-            else if (i == kTabLo) tab_lo[i] = 0.0;
-            else tab_hi[i - kTabLo - 1] = exp(-beta * (double)(kTabLo * (i - kTabLo - 1)));
+            else if (i < 2 * kTabLo) tab_lo[i] = 0.0;
+            else tab_hi[i - 2 * kTabLo] = exp(-beta * (double)(kTabLo * (i - 2 * kTabLo)));
         }
     }
 
@@ -507,13 +507,15 @@ void step_kernel(const StepArgs a)
         if constexpr (kWin) {
             if (!full) {
                 // bit f is in the window iff (f - start) mod N < n
+                // (built by shifts from the top bit down: no per-bit mask
+                // constants, which would sit in registers for the whole loop)
                 m = 0;
                 const int32_t d0 = tid * 4 - (int32_t)sys_start;
 #pragma unroll
-                for (int i = 0; i < F; ++i) {
+                for (int i = F - 1; i >= 0; --i) {
                     int32_t d = d0 + (i >> 2) * (BLOCK * 4) + (i & 3);
                     d += d < 0 ? N : 0;
-                    m |= (uint32_t)(d < n) << i;
+                    m = (m << 1) | (uint32_t)(d < n);
                 }
                 m &= valid;
             }
@@ -529,6 +531,18 @@ void step_kernel(const StepArgs a)
     };
     const bool draw_each_step = mode == kModeBasic || mode == kModeOpt;
     uint32_t mem = (FLAV == FLAV_DRAWN && draw_each_step) ? 0u : compute_mem();
+    // one group per lane, 32-bit integer fields: the table reads of the
+    // weights by byte offset (below), with the offset of the zero slots of
+    // tab_lo for each bit outside the subset kept with the membership
+    constexpr bool kByteTab = kInt && sizeof(HT) == 4 && G == 1 && !kCompact;
+    uint32_t zo[kByteTab ? 4 : 1] = {};
+    auto set_zo = [&]() {
+        if constexpr (kByteTab) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) zo[v] = ((mem >> v) & 1u) ? 0u : (uint32_t)(8 * kTabLo);
+        }
+    };
+    set_zo();
 
     // RF / Basic sampling without per-step outputs: M steers nothing, so the
     // multiplicities of up to 64 steps are computed together by the leader
@@ -571,6 +585,7 @@ void step_kernel(const StepArgs a)
             if (draw_each_step) {
                 pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k);
                 mem = compute_mem();
+                set_zo();
             }
         }
 
@@ -674,22 +689,62 @@ void step_kernel(const StepArgs a)
                 }
                 double w4[4];
                 HT emax = 0;
+                HT ep4[kByteTab ? 4 : 1];
+                if constexpr (kByteTab) {
+                    // The tables are read by byte offset and the eight reads
+                    // go out together (one LDS round trip); wider tiles and
+                    // 64-bit fields keep the per-bit form below, which holds
+                    // fewer registers.  tab_hi[ep >> 6] sits at
+                    // (ep >> 3) & ~7 (an ep past the table wraps inside it and
+                    // its weight is recomputed by exp below), tab_lo[ep & 63]
+                    // at 8 (ep & 63), moved into the zero slots for a bit
+                    // outside the subset.
+                    const char* thb = reinterpret_cast<const char*>(tab_hi);
+                    const char* tlb = reinterpret_cast<const char*>(tab_lo);
+                    uint32_t ho[4], lo[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = g * 4 + v;
-                    const HT e = delta_int(d4.v[v], h[i], s, (xb >> i) & 1u);
-                    const HT ep = e > 0 ? e : 0;
-                    emax = emax > ep ? emax : ep;
-                    const uint32_t hi =
-                        (uint32_t)(ep >> 6) < (uint32_t)kTabHi ? (uint32_t)(ep >> 6) : (uint32_t)(kTabHi - 1);
-                    const uint32_t lo = ((mem >> i) & 1u) ? (uint32_t)ep & 63u : (uint32_t)kTabLo;
-                    w4[v] = tab_hi[hi] * tab_lo[lo];
+                    for (int v = 0; v < 4; ++v) {
+                        // dE with the sign of the bit as (t ^ m) - m, m = 0 or -1
+                        const HT m = -(HT)((xb >> v) & 1u);
+                        const HT t = (HT)d4.v[v] + (s == 2 ? (HT)(h[v] + h[v]) : h[v]);
+                        const HT e = (t ^ m) - m;
+                        const HT ep = e > 0 ? e : 0;
+                        ep4[v] = ep;
+                        emax = emax > ep ? emax : ep;
+                        const uint32_t u = (uint32_t)ep;
+                        ho[v] = (u >> 3) & (uint32_t)(8 * (kTabHi - 1));
+                        lo[v] = ((u << 3) & (uint32_t)(8 * (kTabLo - 1))) | zo[v];
+                    }
+                    double th[4], tl[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        th[v] = *reinterpret_cast<const double*>(thb + ho[v]);
+                        tl[v] = *reinterpret_cast<const double*>(tlb + lo[v]);
+                    }
+                    __builtin_amdgcn_sched_group_barrier(0x0100, 8, 0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) w4[v] = th[v] * tl[v];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = g * 4 + v;
+                        const HT e = delta_int(d4.v[v], h[i], s, (xb >> i) & 1u);
+                        const HT ep = e > 0 ? e : 0;
+                        emax = emax > ep ? emax : ep;
+                        const uint32_t hi =
+                            (uint32_t)(ep >> 6) < (uint32_t)kTabHi ? (uint32_t)(ep >> 6) : (uint32_t)(kTabHi - 1);
+                        const uint32_t lo = ((mem >> i) & 1u) ? (uint32_t)ep & 63u : (uint32_t)kTabLo;
+                        w4[v] = tab_hi[hi] * tab_lo[lo];
+                    }
                 }
                 if (__ballot(emax >= (HT)kTabMax)) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int i = g * 4 + v;
-                        const HT e = delta_int(d4.v[v], h[i], s, (xb >> i) & 1u);
+                        // (e = ep when e reaches the tables' end)
+                        HT e;
+                        if constexpr (kByteTab) e = ep4[v];
+                        else e = delta_int(d4.v[v], h[i], s, (xb >> i) & 1u);
                         if (((mem >> i) & 1u) && e >= (HT)kTabMax) w4[v] = exp(-beta * (double)e);
                     }
                 }
@@ -981,6 +1036,7 @@ void step_kernel(const StepArgs a)
                     sys_start = (int64_t)(((sub % P.num_sets) * (int64_t)n) % N);
                 }
                 mem = compute_mem();
+                set_zo();
             }
         } else {
             const int32_t c = csel;
