@@ -117,6 +117,19 @@ def test_graph_replays_continue_the_chain():
 # Edge cases
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("mode,n,N,tile", [("rf", 0, 60, (64, 1)), ("basic", 7, 60, (64, 1)),
+                                             ("unbiased_sys", 13, 60, (64, 1)), ("rf", 0, 700, (256, 1)),
+                                             ("unbiased_sys", 96, 700, (256, 1)), ("rf", 0, 700, (128, 2))])
+def test_energy_differences_past_the_weight_tables(mode, n, N, tile):
+    """int16 entries up to 30000 in magnitude: most dE exceed the 2^16 range of
+    the two weight tables, so their weights come from exp; beta = 2e-6 keeps
+    those weights between 1e-3 and 1 so that they steer the choices.  Every
+    record is bit-exact, for one-group tiles (byte-offset table reads) and a
+    two-group tile."""
+    Q = inputs.symmetric_int(N, -30000, 30000, np.int16, seed=N + n)
+    _both(Q, 2e-6, mode, 300, chains=3, n=n, L0=40, seed=9, init="random", block=tile[0], groups=tile[1])
+
+
 def test_infinite_temperature_unbiased_schedule():
     Q = inputs.symmetric_int(8, -5, 5, np.int32, seed=1)
     g = gpu_run(Q, 0.0, "unbiased_sys", 40, chains=1, n=2, L0=3, seed=1)
