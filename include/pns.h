@@ -146,7 +146,8 @@ typedef struct pns_problem_info {
     int32_t chain_begin;    /* first chain of the problem                        */
     int32_t num_chains;
     int32_t flavour;        /* 0 all bits, 1 window, 2 drawn subset, 3 compact
-                               window                                            */
+                               window (one 4-bit group per wave), 4 two-group
+                               window (at most two groups per wave)             */
     int32_t reserved;
 } pns_problem_info;
 

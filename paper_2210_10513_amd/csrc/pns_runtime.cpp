@@ -167,13 +167,42 @@ bool window_compact_ok(int32_t N, int32_t n, int32_t block, int32_t groups)
     return true;
 }
 
+// True if every window the run uses -- the systematic sets S_i = {(i n + t)
+// mod N : t < n}, i < N / gcd(N, n), or all bits when n >= N -- holds bits of
+// at most two different 4-bit groups within any one wave.
+bool window_two_groups_ok(int32_t N, int32_t n, int32_t block, int32_t groups)
+{
+    if (groups <= 2) return true;
+    const int64_t sets = n >= N ? 1 : N / gcd64(N, n);
+    for (int64_t i = 0; i < sets; ++i) {
+        const int64_t s0 = n >= N ? 0 : (i * n) % N;
+        for (int32_t w = 0; w < block / 64; ++w) {
+            int hit = 0;
+            for (int32_t g = 0; g < groups; ++g) {
+                const int64_t a0 = ((int64_t)g * block + 64 * w) * 4;
+                if (a0 >= N) continue;
+                const int64_t a1 = std::min<int64_t>(a0 + 255, N - 1);
+                // the window [s0, s0 + n) (cyclic) meets [a0, a1]
+                const bool meets = n >= N || ((a0 - s0) % N + N) % N < n || ((s0 - a0) % N + N) % N <= a1 - a0;
+                hit += meets ? 1 : 0;
+            }
+            if (hit > 2) return false;
+        }
+    }
+    return true;
+}
+
 // How the step kernel forms the subset: 0 every bit, 1 systematic window,
-// 2 random subset drawn in LDS, 3 compact systematic window.
+// 2 random subset drawn in LDS, 3 compact systematic window, 4 two-group
+// systematic window.
 int32_t flavour_of(int32_t mode, int32_t N, int32_t n, int32_t block, int32_t groups)
 {
     if (mode == PNS_MODE_RF) return 0;
     if (mode == PNS_MODE_BASIC) return n < N ? 2 : 0;
-    if (mode == PNS_MODE_UNBIASED_SYS || n >= N) return window_compact_ok(N, n, block, groups) ? 3 : 1;
+    if (mode == PNS_MODE_UNBIASED_SYS || n >= N) {
+        if (window_compact_ok(N, n, block, groups)) return 3;
+        return groups >= 2 && window_two_groups_ok(N, n, block, groups) ? 4 : 1;
+    }
     return 2;
 }
 

@@ -53,6 +53,9 @@ constexpr int FLAV_DRAWN = 2;   // random n-subset drawn in LDS (Basic, Unbiased
 constexpr int FLAV_WINDOW_C = 3; // systematic window touching at most one 4-bit group in any
                                  // wave (checked on the host): one scan per wave, four weights
                                  // per lane, diagonal read from LDS
+constexpr int FLAV_WINDOW_C2 = 4; // the same with at most two 4-bit groups in any wave (windows
+                                  // that span two groups or wrap from the last group to bit 0):
+                                  // two scans in the waves that hold both, eight weights per lane
 
 // Weight tables for integer energy differences: dE = 64 a + b, b < 64, a < 1024.
 constexpr int kTabLo = 64;
@@ -326,7 +329,7 @@ constexpr int kLsE = 0, kLsL = 1, kLsLastA = 2, kLsLastM = 3, kLsLastE = 4, kLsS
 template <int BLOCK, int G, int FLAV>
 constexpr int min_waves_per_eu()
 {
-    return ((FLAV == FLAV_WINDOW_C && BLOCK == 512) || (G == 1 && BLOCK <= 512)) ? 4 : 1;
+    return (((FLAV == FLAV_WINDOW_C || FLAV == FLAV_WINDOW_C2) && BLOCK == 512) || (G == 1 && BLOCK <= 512)) ? 4 : 1;
 }
 
 template <typename QT, typename HT, int BLOCK, int G, int FLAV, bool INSTR>
@@ -369,7 +372,7 @@ void step_kernel(const StepArgs a)
     // (G >= 2) the diagonal lives in LDS and only four-bit weight sums are
     // kept (the chosen lane recomputes its weights); one group keeps both in
     // registers.  The compact window always reads the diagonal from LDS.
-    constexpr bool kLdsDiag = FLAV == FLAV_WINDOW_C || G >= 2;
+    constexpr bool kLdsDiag = FLAV == FLAV_WINDOW_C || FLAV == FLAV_WINDOW_C2 || G >= 2;
     // One field group per lane: the record bookkeeping (and an unbudgeted
     // multiplicity) runs while the row of the flip is loading (the registers
     // allow it); wider tiles keep the shorter live ranges.
@@ -382,8 +385,10 @@ void step_kernel(const StepArgs a)
     // budget rule of Alg 6 used as a stopping time (the record covering the
     // end is cut to the remaining time and the chain stops there)
     const bool timed = a.orig_time > 0;
-    constexpr bool kWin = FLAV == FLAV_WINDOW || FLAV == FLAV_WINDOW_C;
+    constexpr bool kWin = FLAV == FLAV_WINDOW || FLAV == FLAV_WINDOW_C || FLAV == FLAV_WINDOW_C2;
     constexpr bool kCompact = FLAV == FLAV_WINDOW_C;
+    constexpr bool kTwo = FLAV == FLAV_WINDOW_C2;
+    static_assert(!kTwo || G >= 2, "the two-group window needs two groups");
     const int32_t n = FLAV == FLAV_ALL ? N : P.n;
     const int s = P.s;
     const int64_t off = a.foff[chain];
@@ -534,7 +539,7 @@ void step_kernel(const StepArgs a)
     // one group per lane, 32-bit integer fields: the table reads of the
     // weights by byte offset (below), with the offset of the zero slots of
     // tab_lo for each bit outside the subset kept with the membership
-    constexpr bool kByteTab = kInt && sizeof(HT) == 4 && G == 1 && !kCompact;
+    constexpr bool kByteTab = kInt && sizeof(HT) == 4 && G == 1 && !kCompact && !kTwo;
     uint32_t zo[kByteTab ? 4 : 1] = {};
     auto set_zo = [&]() {
         if constexpr (kByteTab) {
@@ -618,8 +623,9 @@ void step_kernel(const StepArgs a)
                 return shift == 0.0 ? exp(l) : exp(l - shift);
             }
         };
-        double w[kKeepW ? 4 : 1];  // weights of the lane's four bits (compact: in group gw)
-        double ls[kCompact ? 1 : G];
+        double w[kKeepW || kTwo ? 4 : 1];  // weights of the lane's four bits (compact: in group gw)
+        double w2[kTwo ? 4 : 1];            // two-group window: the four bits in group gb
+        double ls[kCompact || kTwo ? 1 : G];
         // Compact window: a wave's subset bits lie in one 4-bit group (gw) and
         // each lane's in its four bits of that group.
         double lsum = 0.0;
@@ -672,8 +678,69 @@ void step_kernel(const StepArgs a)
 #pragma unroll
             for (int v = 0; v < 4; ++v) w[v] = w4[v];
         };
+        // Two-group window: a wave's subset bits lie in groups ga <= gb (the
+        // lowest and highest it holds), so each lane weighs at most its four
+        // bits of ga and its four bits of gb.
+        double lsum2 = 0.0;
+        int ga = 0, gb = 0;
+        auto group_weights = [&](int gsel, double shift, double* w4) {
+            const uint32_t mg = (mem >> (4 * gsel)) & 0xFu;
+            HT h4[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) h4[v] = h[v];
+#pragma unroll
+            for (int g = 1; g < G; ++g) {
+                if (gsel == g) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) h4[v] = h[g * 4 + v];
+                }
+            }
+            const int32_t fb = (gsel * BLOCK + tid) * 4;
+            const Four<QW> d4 = load4(dsh + (fb < pitch ? fb : 0));
+            const uint32_t x4 = (xb >> (4 * gsel)) & 0xFu;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double wv;
+                if constexpr (kInt) {
+                    const HT e = delta_int(d4.v[v], h4[v], s, (x4 >> v) & 1u);
+                    if (shift == 0.0) {
+                        const HT ep = e > 0 ? e : 0;
+                        wv = ep < (HT)kTabMax ? tab_hi[(uint32_t)(ep >> 6)] * tab_lo[(uint32_t)ep & 63u]
+                                              : exp(-beta * (double)e);
+                    } else {
+                        double l = -beta * (double)e;
+                        l = l < 0.0 ? l : 0.0;
+                        wv = exp(l - shift);
+                    }
+                } else {
+                    double l = -beta * delta_f64(d4.v[v], h4[v], s, (x4 >> v) & 1u);
+                    l = l < 0.0 ? l : 0.0;
+                    wv = shift == 0.0 ? exp(l) : exp(l - shift);
+                }
+                w4[v] = ((mg >> v) & 1u) ? wv : 0.0;
+            }
+        };
+        auto two_group_weights = [&](double shift) {
+            uint32_t wg = 0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) wg |= __ballot(((mem >> (4 * g)) & 0xFu) != 0) ? (1u << g) : 0u;
+            ga = wg ? __builtin_ctz(wg) : 0;
+            gb = wg ? 31 - __builtin_clz(wg) : 0;
+            double wa[4] = {0.0, 0.0, 0.0, 0.0}, wb[4] = {0.0, 0.0, 0.0, 0.0};
+            if (wg) group_weights(ga, shift, wa);
+            if (gb != ga) group_weights(gb, shift, wb);
+            lsum = ((wa[0] + wa[1]) + wa[2]) + wa[3];
+            lsum2 = ((wb[0] + wb[1]) + wb[2]) + wb[3];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                w[v] = wa[v];
+                w2[v] = wb[v];
+            }
+        };
         if constexpr (kCompact) {
             compact_weights(0.0);
+        } else if constexpr (kTwo) {
+            two_group_weights(0.0);
         } else if constexpr (kInt) {
             // exp(-beta * max(e, 0)) = tab_hi[e >> 6] * tab_lo[e & 63]; exp(-0) = 1
             // covers e <= 0, and a bit outside the subset reads the zero slot.
@@ -770,13 +837,21 @@ void step_kernel(const StepArgs a)
                 }
             }
         }
-        double inc[kCompact ? 1 : G];
+        double inc[kCompact || kTwo ? 1 : G];
+        double inc2 = 0.0;
         auto scan_and_publish = [&]() {
             if constexpr (kCompact) {
                 inc[0] = wave_scan(lsum);
                 if (lane == 63) {
 #pragma unroll
                     for (int g = 0; g < G; ++g) seg_sum[g * W + wave] = g == gw ? inc[0] : 0.0;
+                }
+            } else if constexpr (kTwo) {
+                inc[0] = wave_scan(lsum);
+                inc2 = gb != ga ? wave_scan(lsum2) : 0.0;  // ga, gb are wave-uniform
+                if (lane == 63) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) seg_sum[g * W + wave] = g == ga ? inc[0] : (g == gb ? inc2 : 0.0);
                 }
             } else {
 #pragma unroll
@@ -820,6 +895,8 @@ void step_kernel(const StepArgs a)
             scaled = true;
             if constexpr (kCompact) {
                 compact_weights(mx);
+            } else if constexpr (kTwo) {
+                two_group_weights(mx);
             } else {
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
@@ -920,6 +997,10 @@ void step_kernel(const StepArgs a)
                 if constexpr (kCompact) {
                     my_inc = inc[0];
                     my_ls = lsum;
+                } else if constexpr (kTwo) {
+                    const bool second = gstar == gb && gb != ga;
+                    my_inc = second ? inc2 : inc[0];
+                    my_ls = second ? lsum2 : lsum;
                 } else {
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
@@ -940,7 +1021,11 @@ void step_kernel(const StepArgs a)
                     // the chosen lane's four weights in group gstar: kept, or
                     // recomputed (the same values as summed above)
                     double wsel[4];
-                    if constexpr (kKeepW) {
+                    if constexpr (kTwo) {
+                        const bool second = gstar == gb && gb != ga;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) wsel[v] = second ? w2[v] : w[v];
+                    } else if constexpr (kKeepW) {
 #pragma unroll
                         for (int v = 0; v < 4; ++v) wsel[v] = w[v];
                     } else {
@@ -1221,6 +1306,11 @@ hipError_t launch_one(int32_t grid, size_t dyn, hipStream_t st, const StepArgs& 
         if (flav == FLAV_WINDOW_C)                                                                          \
             return instr ? launch_one<QT, HT, B, GG, FLAV_WINDOW_C, true>(grid, dyn, st, a)                 \
                          : launch_one<QT, HT, B, GG, FLAV_WINDOW_C, false>(grid, dyn, st, a);               \
+        if (flav == FLAV_WINDOW_C2) {                                                                       \
+            if constexpr (GG >= 2)                                                                          \
+                return instr ? launch_one<QT, HT, B, GG, FLAV_WINDOW_C2, true>(grid, dyn, st, a)            \
+                             : launch_one<QT, HT, B, GG, FLAV_WINDOW_C2, false>(grid, dyn, st, a);          \
+        }                                                                                                   \
         return hipErrorInvalidConfiguration;                                                                \
     }
 

@@ -26,8 +26,9 @@ def gpu_run(Q, beta, mode, K, *, n=0, L0=100, seed=0, chains=1, init="zero", lay
                 launch=launch, chunk=chunk, block=block, groups=groups, log_capacity=K if log else 0,
                 chain_id_base=chain_id_base)
     s.run(K)
+    from paper_2210_10513_amd.binding import pns_problem_info_get
     out = {"log": s.read_log() if log else None, "cur": s.read_current(), "rec": s.read(), "stats": s.stats(),
-           "tile": s.tile()}
+           "tile": s.tile(), "flavour": pns_problem_info_get(s.ctx, 0).flavour}
     s.close()
     return out
 

@@ -87,6 +87,31 @@ def test_tile_shape_does_not_change_results(tile):
         assert np.array_equal(ref["log"][key], got["log"][key])
 
 
+@pytest.mark.parametrize("mode,N,n,tile,dtype,log", [
+    ("unbiased_sys", 2400, 1024, (512, 2), np.int16, True),    # windows that wrap to bit 0
+    ("unbiased_sys", 4398, 256, (1024, 2), np.int16, True),
+    ("unbiased_sys", 700, 100, (64, 4), np.int32, True),       # one wave holding four groups
+    ("unbiased_sys", 7659, 2048, (512, 4), np.float32, True),
+    ("unbiased_rand", 700, 700, (128, 2), np.int16, True),     # every bit, two groups per wave
+    ("unbiased_sys", 2400, 1024, (512, 2), np.int16, False),   # uninstrumented kernel
+])
+def test_two_group_window_kernel(mode, N, n, tile, dtype, log):
+    """Windows whose bits fall in two 4-bit groups of some wave run the
+    two-group window kernel (flavour 4): records and final state equal the
+    oracle's (integer Q bit-exact)."""
+    is_int = dtype != np.float32
+    Q = inputs.symmetric_int(N, -100, 100, dtype, seed=N + n) if is_int else inputs.symmetric_gauss(N, seed=N + n)
+    beta = 0.01 if is_int else 0.5
+    kw = dict(n=n, L0=40, seed=13, init="random", block=tile[0], groups=tile[1])
+    g = gpu_run(Q, beta, mode, 300, chains=3, log=log, **kw)
+    assert g["flavour"] == 4 and g["tile"] == tile
+    o = oracle_run(Q, beta, mode, 300, chains=[0, 1, 2], n=n, L0=40, seed=13, init="random")
+    if log:
+        assert compare_logs(g["log"], o, chain_rows=[0, 1, 2], is_int=is_int) == 3 * 300
+    compare_final(g["cur"], o, chain_rows=[0, 1, 2], is_int=is_int)
+    assert (g["stats"]["anomalies"] == 0).all()
+
+
 @pytest.mark.parametrize("launch,chunk", [("plain", 0), ("persistent", 37), ("graph", 50), ("graph", 0)])
 def test_launch_forms_agree(launch, chunk):
     Q = inputs.symmetric_int(300, -100, 100, np.int16, seed=32)
