@@ -371,7 +371,7 @@ void step_kernel(const StepArgs a)
     // Register budget: with four or more bits per lane beyond one group
     // (G >= 2) the diagonal lives in LDS and only four-bit weight sums are
     // kept (the chosen lane recomputes its weights); one group keeps both in
-    // registers.  The compact window always reads the diagonal from LDS.
+    // registers.  The compact and two-group windows read the diagonal from LDS.
     constexpr bool kLdsDiag = FLAV == FLAV_WINDOW_C || FLAV == FLAV_WINDOW_C2 || G >= 2;
     // One field group per lane: the record bookkeeping (and an unbudgeted
     // multiplicity) runs while the row of the flip is loading (the registers
@@ -623,7 +623,7 @@ void step_kernel(const StepArgs a)
                 return shift == 0.0 ? exp(l) : exp(l - shift);
             }
         };
-        double w[kKeepW || kTwo ? 4 : 1];  // weights of the lane's four bits (compact: in group gw)
+        double w[kKeepW || kTwo ? 4 : 1];  // weights of the lane's four bits (compact: in group gw; two-group: ga)
         double w2[kTwo ? 4 : 1];            // two-group window: the four bits in group gb
         double ls[kCompact || kTwo ? 1 : G];
         // Compact window: a wave's subset bits lie in one 4-bit group (gw) and
