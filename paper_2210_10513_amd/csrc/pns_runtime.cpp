@@ -132,6 +132,7 @@ struct Tile {
 Tile default_tile(int32_t N)
 {
     if (N <= 256) return {64, 1};
+    if (N <= 512) return {128, 1};
     if (N <= 1024) return {256, 1};
     if (N <= 2048) return {256, 2};
     if (N <= 4096) return {512, 2};
@@ -140,7 +141,7 @@ Tile default_tile(int32_t N)
 }
 
 // Every tile the step kernels are compiled for.
-const Tile kTiles[] = {{64, 1},  {64, 2},  {64, 4},  {128, 2}, {128, 4},  {256, 1},
+const Tile kTiles[] = {{64, 1},  {64, 2},  {64, 4},  {128, 1}, {128, 2}, {128, 4},  {256, 1},
                        {256, 2}, {256, 4}, {512, 2}, {512, 4}, {1024, 2}, {1024, 4}};
 
 // True if no window of n cyclically consecutive bits holds bits of two

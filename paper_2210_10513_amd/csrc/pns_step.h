@@ -1280,6 +1280,7 @@ hipError_t launch_one(int32_t grid, size_t dyn, hipStream_t st, const StepArgs& 
     X(QT, HT, 64, 1)             \
     X(QT, HT, 64, 2)             \
     X(QT, HT, 64, 4)             \
+    X(QT, HT, 128, 1)            \
     X(QT, HT, 128, 2)            \
     X(QT, HT, 128, 4)            \
     X(QT, HT, 256, 1)            \

@@ -87,6 +87,24 @@ def test_tile_shape_does_not_change_results(tile):
         assert np.array_equal(ref["log"][key], got["log"][key])
 
 
+@pytest.mark.parametrize("tile", [(64, 2), (128, 1), (128, 2), (256, 1)])
+def test_tile_shape_does_not_change_results_at_n500(tile):
+    """N = 500 (the default tile is 128x1, four bits per lane, no idle lanes):
+    every tile that holds N gives the same records, and the default equals the
+    oracle."""
+    Q = inputs.symmetric_int(500, -100, 100, np.int16, seed=35)
+    ref = gpu_run(Q, 0.01, "rf", 300, chains=2, seed=2)
+    assert ref["tile"] == (128, 1)
+    got = gpu_run(Q, 0.01, "rf", 300, chains=2, seed=2, block=tile[0], groups=tile[1])
+    assert got["tile"] == tile
+    for key in ("action", "M", "E", "p"):
+        assert np.array_equal(ref["log"][key], got["log"][key])
+    if tile == (128, 1):
+        _both(Q, 0.01, "rf", 300, chains=2, seed=2, block=128, groups=1)
+        Qf = inputs.symmetric_gauss(300, seed=36)
+        _both(Qf, 1.0, "unbiased_sys", 300, chains=2, n=60, L0=20, seed=3, is_int=False, block=128, groups=1)
+
+
 @pytest.mark.parametrize("mode,N,n,tile,dtype,log", [
     ("unbiased_sys", 2400, 1024, (512, 2), np.int16, True),    # windows that wrap to bit 0
     ("unbiased_sys", 4398, 256, (1024, 2), np.int16, True),
