@@ -251,6 +251,35 @@ __device__ __forceinline__ double delta_f64(float d, double h, int s, uint32_t x
     return xbit ? -e : e;
 }
 
+// q = log U1 / log1p(-p) for 0 < p < 1: M = 1 + floor(q) (Thm 3 (2): the
+// failures before the first success of a Bernoulli(p) sequence), and a
+// budgeted record stays when q >= L (Alg 6).  The FP64 log1p and division
+// are about 1400 cycles of one lane, so a cheap estimate decides first:
+// log1p(-p) from its series (p <= 2^-6, relative error < 1e-8) or from the
+// float logarithm of 1 - p (relative error < 5e-6 there), divided in FP64.
+// Its relative error is below 1e-5, so when the interval q_est (1 -+ 1e-4)
+// holds neither L nor an integer, the estimate has the same floor and the
+// same order against L as the exact quotient and is returned; otherwise (a
+// few percent of the calls) the exact quotient is.  L < 0: no budget.
+__device__ __forceinline__ double geometric_quotient(double logU1, double p, double L)
+{
+    double l1p = 0.0;
+    bool est = true;
+    if (p <= 0x1p-6) {
+        l1p = -p * (1.0 + p * (0.5 + p * (1.0 / 3.0 + p * 0.25)));
+    } else {
+        const double x = 1.0 - p;
+        est = x >= 0x1p-100;
+        l1p = est ? (double)logf((float)x) : -1.0;
+    }
+    if (est) {
+        const double qe = logU1 / l1p;
+        const double lo = qe * (1.0 - 1e-4), hi = qe * (1.0 + 1e-4);
+        if (qe < 0x1p52 && floor(lo) == floor(hi) && !(lo < L && hi >= L)) return qe;
+    }
+    return logU1 / log1p(-p);
+}
+
 // Mean multiplicity of a record given its state, subset and remaining budget
 // L (Thm 3 (2): M = 1 + G, G ~ Geometric(p) counting failures, cut at L when
 // the record is budgeted): E[min(1 + G, L)] = (1 - (1 - p)^L) / p, and 1 / p
@@ -931,12 +960,14 @@ void step_kernel(const StepArgs a)
         double p = 0.0, q = 0.0;
         int64_t m = 0;
         bool sat = false;
-        auto multiplicity = [&]() {
+        // (Lq: the budget the quotient is compared with, or -1 without one)
+        auto multiplicity = [&](double Lq) {
             const double Ss = scaled ? exp(mx) * S : S;
             p = n_pow2 ? Ss * inv_n : Ss / (double)n;
             if (p >= 1.0) q = 0.0;
             else if (p <= 0.0) q = INFINITY;
-            else q = U.logU1 / log1p(-p);
+            else if constexpr (FLAV == FLAV_ALL) q = U.logU1 / log1p(-p);  // budgets only in timed runs
+            else q = geometric_quotient(U.logU1, p, Lq);
             if (!(q < 0x1p63)) {
                 m = INT64_MAX;
                 sat = true;
@@ -950,8 +981,9 @@ void step_kernel(const StepArgs a)
         // barrier.  Otherwise M does not steer the chain and is computed with
         // the record, off the path to the next step.
         if ((unbiased || timed) && tid == lead_tid) {
-            multiplicity();
-            stay_flag = q >= (double)lead_st[kLsL] ? 1 : 0;
+            const double Lb = (double)lead_st[kLsL];
+            multiplicity(Lb);
+            stay_flag = q >= Lb ? 1 : 0;
         }
         uint32_t rec_idx = 0;
         bool snap = false;
@@ -1157,7 +1189,7 @@ void step_kernel(const StepArgs a)
             } else {
                 const int64_t sv0 = sel[0];
                 const int64_t dEc = sel[1];
-                if (!unbiased && !timed && !lazy_m) multiplicity();
+                if (!unbiased && !timed && !lazy_m) multiplicity(-1.0);
                 if (mode == kModeOpt) {
                     m = 1;  // no multiplicity: each jump counts once
                     sat = false;
