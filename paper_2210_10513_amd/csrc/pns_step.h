@@ -255,15 +255,16 @@ __device__ __forceinline__ double delta_f64(float d, double h, int s, uint32_t x
 // failures before the first success of a Bernoulli(p) sequence), and a
 // budgeted record stays when q >= L (Alg 6).  The FP64 log1p and division
 // are about 1400 cycles of one lane, so a cheap estimate decides first:
-// log1p(-p) from its series (p <= 2^-6, relative error < 1e-8) or from the
+// log1p(-p) from its series (p <= 2^-6, relative error < 1.3e-8) or from the
 // float logarithm of 1 - p (relative error < 5e-6 there), divided in FP64.
-// Its relative error is below 1e-5, so when the interval q_est (1 -+ 1e-4)
-// holds neither L nor an integer, the estimate has the same floor and the
-// same order against L as the exact quotient and is returned; otherwise (a
-// few percent of the calls) the exact quotient is.  L < 0: no budget.
+// When the interval q_est (1 -+ d) -- d = 1e-7 after the series, 1e-4 after
+// the float logarithm, at least 7 times the estimate's error -- holds neither
+// L nor an integer, the estimate has the same floor and the same order
+// against L as the exact quotient and is returned; otherwise the exact
+// quotient is.  L < 0: no budget.
 __device__ __forceinline__ double geometric_quotient(double logU1, double p, double L)
 {
-    double l1p = 0.0;
+    double l1p = 0.0, d = 1e-7;
     bool est = true;
     if (p <= 0x1p-6) {
         l1p = -p * (1.0 + p * (0.5 + p * (1.0 / 3.0 + p * 0.25)));
@@ -271,10 +272,11 @@ __device__ __forceinline__ double geometric_quotient(double logU1, double p, dou
         const double x = 1.0 - p;
         est = x >= 0x1p-100;
         l1p = est ? (double)logf((float)x) : -1.0;
+        d = 1e-4;
     }
     if (est) {
         const double qe = logU1 / l1p;
-        const double lo = qe * (1.0 - 1e-4), hi = qe * (1.0 + 1e-4);
+        const double lo = qe * (1.0 - d), hi = qe * (1.0 + d);
         if (qe < 0x1p52 && floor(lo) == floor(hi) && !(lo < L && hi >= L)) return qe;
     }
     return logU1 / log1p(-p);
