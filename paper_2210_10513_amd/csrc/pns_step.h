@@ -396,6 +396,13 @@ void step_kernel(const StepArgs a)
     const int leader = (int)(blockIdx.x % (unsigned)W);
     const bool lead = wave == leader;
     const int lead_tid = leader * 64;
+    // Uninstrumented window and drawn-subset kernels split the per-step record
+    // between the leader lane (budget, multiplicity) and lane 0 of the next
+    // wave (energy, action, counters), so that the two halves run on
+    // different SIMDs after the choice; the leader's half is what the next
+    // budget decision waits for.
+    constexpr bool kSplitRec = !INSTR && FLAV != FLAV_ALL;
+    const int rec_tid = W > 1 ? ((leader + 1) % W) * 64 : lead_tid + 1;
     const Problem P = a.problems[a.chain_problem[chain]];
     const int32_t N = P.N;
     const int64_t pitch = P.pitch;
@@ -1176,8 +1183,43 @@ void step_kernel(const StepArgs a)
             if (snap) ++snap_n;
         }
 
-        // record k = (state before the step, M): the leader lane
-        if (tid == lead_tid) {
+        // record k = (state before the step, M)
+        if constexpr (kSplitRec) {
+            if (tid == lead_tid) {
+                int64_t M;
+                if (stay) {
+                    M = lead_st[kLsL];
+                    lead_st[kLsL] = timed ? 0 : P.L0;
+                } else {
+                    if (mode == kModeOpt) {
+                        m = 1;  // no multiplicity: each jump counts once
+                        sat = false;
+                    }
+                    if (unbiased || timed) lead_st[kLsL] -= m;
+                    lead_st[kLsSat] += sat ? 1 : 0;
+                    M = m;
+                }
+                if (!lazy_m) lead_st[kLsSumM] = __double_as_longlong(__longlong_as_double(lead_st[kLsSumM]) + (double)M);
+                if (!lazy_m) lead_st[kLsLastM] = M;
+            }
+            if (tid == rec_tid) {
+                const int64_t Erec = lead_st[kLsE];
+                int32_t action = -1;
+                if (stay) {
+                    lead_st[kLsStays] += 1;
+                } else {
+                    const int64_t dEc = sel[1];
+                    lead_st[kLsBad] += (sv0 >> 41) & 1;
+                    if constexpr (kInt) lead_st[kLsE] = Erec + dEc;
+                    else lead_st[kLsE] = __double_as_longlong(__longlong_as_double(Erec) + __longlong_as_double(dEc));
+                    lead_st[kLsFlips] += 1;
+                    action = (int32_t)(sv0 & 0xFFFFFFFFll);
+                }
+                lead_st[kLsSteps] += 1;
+                lead_st[kLsLastA] = action;
+                lead_st[kLsLastE] = Erec;
+            }
+        } else if (tid == lead_tid) {
             const int64_t Erec = lead_st[kLsE];
             const int64_t Lrec = lead_st[kLsL];  // budget at the start of the record
             int32_t action;
@@ -1254,6 +1296,7 @@ void step_kernel(const StepArgs a)
         }
     }
     if (lazy_m && lead && k > ub_base) flush_m((int)(k - ub_base));
+    if constexpr (kSplitRec) __syncthreads();  // the record lane's words, for the write-out below
 
     if constexpr (INSTR) {
         __syncthreads();
