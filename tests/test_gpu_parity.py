@@ -303,6 +303,41 @@ def test_uninstrumented_runs_keep_the_multiplicity_counters(mode, n, launch, chu
     assert (st["saturated"] == 0).all() and (st["steps"] == K + K // 2).all()
 
 
+@pytest.mark.parametrize("mode,n,N,tile,dtype", [("unbiased_sys", 40, 300, (0, 0), np.int16),
+                                                ("unbiased_sys", 512, 2400, (512, 2), np.int16),
+                                                ("unbiased_rand", 24, 200, (0, 0), np.int32),
+                                                ("unbiased_sys", 60, 700, (128, 2), np.float32)])
+def test_uninstrumented_unbiased_records_and_counters(mode, n, N, tile, dtype):
+    """Uninstrumented window and drawn-subset kernels split the per-step record
+    between two lanes (budget and multiplicity; energy, action and counters):
+    the last record (pns_read), every counter and the final state equal the
+    oracle's, across two launches."""
+    from paper_2210_10513_amd.binding import Sampler
+    is_int = dtype != np.float32
+    Q = inputs.symmetric_int(N, -40, 40, dtype, seed=N + n) if is_int else inputs.symmetric_gauss(N, seed=N + n)
+    beta = 0.05 if is_int else 1.0
+    C, K = 5, 150
+    s = Sampler(Q, beta, n, mode, num_chains=C, seed=8, init="random", L0=30, block=tile[0], groups=tile[1])
+    s.run(K)
+    s.run(K)
+    _, m, e = s.read()
+    cur = s.read_current()
+    st = s.stats()
+    s.close()
+    o = oracle_run(Q, beta, mode, 2 * K, n=n, L0=30, seed=8, chains=list(range(C)), init="random")
+    compare_final(cur, o, chain_rows=list(range(C)), is_int=is_int)
+    assert np.array_equal(m, o.M[:, -1])
+    if is_int:
+        assert np.array_equal(e, o.E[:, -1].astype(np.float64))
+    else:
+        assert np.allclose(e, o.E[:, -1], rtol=1e-9, atol=1e-9)
+    assert (st["steps"] == 2 * K).all()
+    assert np.array_equal(st["flips"], (o.action >= 0).sum(axis=1))
+    assert np.array_equal(st["stays"], (o.action < 0).sum(axis=1))
+    assert np.array_equal(st["sum_M"], o.M.astype(np.float64).sum(axis=1))
+    assert (st["stays"] > 0).all() and (st["anomalies"] == 0).all()
+
+
 def test_uninstrumented_frozen_chain_saturates():
     from paper_2210_10513_amd.binding import Sampler
     Q = (np.diag(np.arange(1, 7)) * 1000).astype(np.int32)
