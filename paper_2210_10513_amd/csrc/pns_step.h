@@ -411,10 +411,12 @@ void step_kernel(const StepArgs a)
     // kept (the chosen lane recomputes its weights); one group keeps both in
     // registers.  The compact and two-group windows read the diagonal from LDS.
     constexpr bool kLdsDiag = FLAV == FLAV_WINDOW_C || FLAV == FLAV_WINDOW_C2 || G >= 2;
-    // One field group per lane: the record bookkeeping (and an unbudgeted
-    // multiplicity) runs while the row of the flip is loading (the registers
-    // allow it); wider tiles keep the shorter live ranges.
-    constexpr bool kEarly = G == 1 && FLAV != FLAV_WINDOW_C;
+    // The row of the flip is loaded before the record bookkeeping, which then
+    // runs while the loads are in flight: with one field group per lane (the
+    // registers allow it) and in the kernels whose record is split over two
+    // lanes (each half is short); the other wide tiles keep the shorter live
+    // ranges of loading after the record.
+    constexpr bool kEarly = (G == 1 && FLAV != FLAV_WINDOW_C) || kSplitRec;
     constexpr bool kKeepW = FLAV == FLAV_WINDOW_C || G == 1;
     QW* const dsh = reinterpret_cast<QW*>(own + (FLAV == FLAV_DRAWN ? pitch : 0));
     const int mode = a.mode;
@@ -1119,8 +1121,8 @@ void step_kernel(const StepArgs a)
         __syncthreads();
         const bool stay = (unbiased || timed) && stay_flag != 0;
 
-        // row c of the flip: with one field group per lane it is loaded before
-        // the record bookkeeping below, which then runs while the loads are in
+        // row c of the flip: in the early-load kernels it is loaded before the
+        // record bookkeeping below, which then runs while the loads are in
         // flight, and the fields are updated after it
         decltype(load_raw4(static_cast<const QT*>(nullptr))) raw[G];
         bool xc = false;
