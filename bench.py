@@ -9,7 +9,9 @@ beta = 0.01, int32 local fields.  One benchmark step runs every chain for
 the workload) in the persistent launch form, with all inputs resident in HBM.
 The JSON line reports flips/s (value) and effective Metropolis steps/s
 (sum of multiplicities per second), the HBM roofline of the dominant kernel
-(bytes of Q read per flip = N * sizeof(int16)), the same workload with Basic
+(bytes of Q read per flip = N * sizeof(int16)), the VALU issue roofline of
+the same kernel (wave64 VALU instructions per chain step from its counter
+run), the same workload with Basic
 PNS subset 64 and in the plain one-launch-per-step form, and the CPU oracle
 timed on a bounded sample on this host.
 
@@ -49,6 +51,28 @@ def _measured_traffic(workload: str, chain_steps: int):
         f = line.split()
         if len(f) == 6 and not line.startswith("#") and f[0] == workload and int(f[1]) == chain_steps and f[2] == sha:
             return float(f[5])
+    return None
+
+
+# Wave64 VALU issue peak: 256 CUs x 4 SIMDs, each SIMD16 issuing one wave64
+# instruction per 4 cycles, at 2.4 GHz.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def _valu_per_chain_step(workload: str):
+    """VALU instructions (wave64) per chain step of the step kernel from the
+    committed SQ counter runs (profiles/valu_issue.txt), or None when no run
+    matches the workload or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "valu_issue.txt")
+    src = os.path.join(ROOT, "paper_2210_10513_amd", "csrc", "pns_step.h")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        f = line.split()
+        if len(f) == 5 and not line.startswith("#") and f[0] == workload and f[1] == sha:
+            return float(f[2]) / float(f[3])
     return None
 
 
@@ -438,6 +462,12 @@ def main():
                      "bytes_per_flip": bytes_per_flip, "kernel": "step_kernel",
                      "kernel_avg_ms": sec * 1000.0},
     }
+    vps = _valu_per_chain_step(args.workload)
+    if vps is not None:
+        # the bound of an L2-resident step: wave64 VALU issue (records = loop iterations)
+        out["issue_roofline"] = {"bound": "alu", "achieved": vps * recs / sec, "peak": VALU_ISSUE_PEAK,
+                                 "unit": "wave64 VALU instr/s", "frac": vps * recs / sec / VALU_ISSUE_PEAK,
+                                 "valu_per_chain_step": vps}
     if not args.no_extras and args.workload == "rf_n1024_int16":
         extras = {}
         wb = _workload("basic64_n1024_int16")

@@ -1,0 +1,55 @@
+"""Host-side checks of bench.py: the one-GPU guard and the committed counter
+tables it reads (HBM bytes per launch, VALU instructions per chain step).
+CPU only: nothing here launches a kernel."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _rows(name, width):
+    for line in open(os.path.join(ROOT, "profiles", name)):
+        f = line.split()
+        if line.startswith("#") or not f:
+            continue
+        assert len(f) == width, line
+        yield f
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_hbm_traffic_rows_add_up():
+    # traffic_bytes = FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, both in KiB
+    rows = list(_rows("hbm_traffic.txt", 6))
+    assert {r[0] for r in rows} >= {"rf_n1024_int16", "unbiased_n8192_f32"}
+    for r in rows:
+        assert int(r[5]) == int(float(r[3]) * 2048 + float(r[4]) * 1024)
+
+
+def test_valu_rows_divide_out_and_gate_on_the_kernel_source():
+    rows = list(_rows("valu_issue.txt", 5))
+    assert {r[0] for r in rows} >= {"rf_n1024_int16", "unbiased_n8192_f32"}
+    for r in rows:
+        assert abs(float(r[2]) / float(r[3]) - float(r[4])) < 0.1
+        got = bench._valu_per_chain_step(r[0])
+        # reported exactly when the row was counted on the current kernel source
+        assert (got is not None) == any(q[0] == r[0] and q[1] == _current_sha() for q in rows)
+
+
+def test_issue_peak():
+    # 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD every 4 cycles
+    assert bench.VALU_ISSUE_PEAK == 6.144e11
+
+
+def _current_sha():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2210_10513_amd", "csrc", "pns_step.h")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
