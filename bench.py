@@ -59,10 +59,11 @@ def _measured_traffic(workload: str, chain_steps: int):
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
-def _valu_per_chain_step(workload: str):
+def _valu_per_chain_step(workload: str, tile):
     """VALU instructions (wave64) per chain step of the step kernel from the
     committed SQ counter runs (profiles/valu_issue.txt), or None when no run
-    matches the workload or the kernel source changed since."""
+    matches the workload and tile (block, groups) or the kernel source changed
+    since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "valu_issue.txt")
     src = os.path.join(ROOT, "paper_2210_10513_amd", "csrc", "pns_step.h")
@@ -71,8 +72,9 @@ def _valu_per_chain_step(workload: str):
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     for line in open(path):
         f = line.split()
-        if len(f) == 5 and not line.startswith("#") and f[0] == workload and f[1] == sha:
-            return float(f[2]) / float(f[3])
+        if (len(f) == 6 and not line.startswith("#") and f[0] == workload and f[1] == "%dx%d" % tuple(tile)
+                and f[2] == sha):
+            return float(f[3]) / float(f[4])
     return None
 
 
@@ -462,7 +464,7 @@ def main():
                      "bytes_per_flip": bytes_per_flip, "kernel": "step_kernel",
                      "kernel_avg_ms": sec * 1000.0},
     }
-    vps = _valu_per_chain_step(args.workload)
+    vps = _valu_per_chain_step(args.workload, tile)
     if vps is not None:
         # the bound of an L2-resident step: wave64 VALU issue (records = loop iterations)
         out["issue_roofline"] = {"bound": "alu", "achieved": vps * recs / sec, "peak": VALU_ISSUE_PEAK,

@@ -35,13 +35,16 @@ def test_hbm_traffic_rows_add_up():
 
 
 def test_valu_rows_divide_out_and_gate_on_the_kernel_source():
-    rows = list(_rows("valu_issue.txt", 5))
+    rows = list(_rows("valu_issue.txt", 6))
     assert {r[0] for r in rows} >= {"rf_n1024_int16", "unbiased_n8192_f32"}
     for r in rows:
-        assert abs(float(r[2]) / float(r[3]) - float(r[4])) < 0.1
-        got = bench._valu_per_chain_step(r[0])
+        assert abs(float(r[3]) / float(r[4]) - float(r[5])) < 0.1
+        tile = tuple(int(v) for v in r[1].split("x"))
+        got = bench._valu_per_chain_step(r[0], tile)
         # reported exactly when the row was counted on the current kernel source
-        assert (got is not None) == any(q[0] == r[0] and q[1] == _current_sha() for q in rows)
+        assert (got is not None) == any(q[0] == r[0] and q[1] == r[1] and q[2] == _current_sha() for q in rows)
+        # another tile runs other code
+        assert bench._valu_per_chain_step(r[0], (tile[0] * 2, tile[1])) is None
 
 
 def test_issue_peak():
