@@ -617,6 +617,7 @@ void step_kernel(const StepArgs a)
     };
 
     for (; k < kend; ++k) {
+        __builtin_amdgcn_s_setprio(0);
         if (k - ub_base >= 64) {
             if (lazy_m && lead) flush_m(64);
             ub_base = k;
@@ -902,6 +903,11 @@ void step_kernel(const StepArgs a)
                 }
             }
         };
+        // From the wave scans to the issue of the row load every wave of the
+        // chain waits at a barrier for the slowest one, so these phases take
+        // issue priority over the weights and field updates of the other
+        // chains on the SIMD.
+        __builtin_amdgcn_s_setprio(1);
         scan_and_publish();
         __syncthreads();
         if constexpr (INSTR) {
@@ -1152,6 +1158,12 @@ void step_kernel(const StepArgs a)
                 const int64_t fb = ((int64_t)g * BLOCK + tid) * 4;
                 raw[g] = load_raw4(row + (fb < pitch ? fb : 0));
             }
+        }
+        // (the leader wave keeps the priority through the record when it
+        // writes all of it: the next step's first barrier waits for it)
+        __builtin_amdgcn_s_setprio(0);
+        if constexpr (!kSplitRec) {
+            if (lead) __builtin_amdgcn_s_setprio(1);
         }
         if (stay) {
             // Alg 6: not enough remaining original samples; stay L times and
