@@ -1159,11 +1159,11 @@ void step_kernel(const StepArgs a)
                 raw[g] = load_raw4(row + (fb < pitch ? fb : 0));
             }
         }
-        // (the leader wave keeps the priority through the record when it
+        // (the leader wave takes a higher one through the record when it
         // writes all of it: the next step's first barrier waits for it)
         __builtin_amdgcn_s_setprio(0);
         if constexpr (!kSplitRec) {
-            if (lead) __builtin_amdgcn_s_setprio(1);
+            if (lead) __builtin_amdgcn_s_setprio(2);
         }
         if (stay) {
             // Alg 6: not enough remaining original samples; stay L times and
