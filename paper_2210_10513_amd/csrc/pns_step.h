@@ -629,9 +629,12 @@ void step_kernel(const StepArgs a)
         U.logU1 = lead ? read_lane(ubLog, uj) : 0.0;
         if constexpr (FLAV == FLAV_DRAWN) {
             if (draw_each_step) {
+                // the draw is barrier-gated too (its rounds meet in LDS)
+                __builtin_amdgcn_s_setprio(1);
                 pos_n = draw_subset<BLOCK, G>(own, masks, tid, pitch, N, n, seed, cid, k);
                 mem = compute_mem();
                 set_zo();
+                __builtin_amdgcn_s_setprio(0);
             }
         }
 
