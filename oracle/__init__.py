@@ -33,6 +33,17 @@ LAYOUT_SYMMETRIC = 0
 LAYOUT_UPPER = 1
 STAY = -1
 
+# Replay classes (orc_replay_class): how a followed record relates to the
+# oracle's own decision at the same state and draws.
+RP_SAME = 0        # same action and multiplicity
+RP_BUDGET = 1      # stay vs move differs, q within the window of the budget L
+RP_MULT = 2        # multiplicity differs, q within the window of the interval [M-1, M) the given M needs
+RP_CHOICE = 3      # chosen neighbour differs, U2*S within the window of its interval
+RP_MISMATCH = -1   # differs off every decision window
+RP_INVALID = -2    # the given action is impossible at that step
+RP_NAMES = {RP_SAME: "same", RP_BUDGET: "budget boundary", RP_MULT: "multiplicity boundary",
+            RP_CHOICE: "choice boundary", RP_MISMATCH: "mismatch", RP_INVALID: "invalid action"}
+
 
 def load_mutant(replacements, workdir: str) -> ctypes.CDLL:
     """Compile a copy of the oracle with textual replacements applied (used by
@@ -95,6 +106,8 @@ class _RunArgs(ctypes.Structure):
         ("Ef_best", ctypes.c_void_p),
         ("orig_time", ctypes.c_int64), ("n_records", ctypes.c_void_p), ("step0s", ctypes.c_void_p),
         ("log_w", ctypes.c_void_p), ("hist_rb", ctypes.c_void_p),
+        ("rp_action", ctypes.c_void_p), ("rp_M", ctypes.c_void_p), ("rp_class", ctypes.c_void_p),
+        ("rp_tol", ctypes.c_double),
     ]
 
 
@@ -231,13 +244,14 @@ class RunResult:
     n_records: Optional[np.ndarray] = None  # records per chain
     w: Optional[np.ndarray] = None        # expected multiplicity of each record (Rao-Blackwell weight)
     hist_rb: Optional[np.ndarray] = None  # sum of w per state
+    cls: Optional[np.ndarray] = None      # replay: RP_* class of each followed record
 
 
 def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, seed: int = 0,
         num_chains: int = 1, chain_ids=None, x0: Optional[np.ndarray] = None, init: str = "zero",
         layout: int = LAYOUT_SYMMETRIC, log: bool = True, hist: bool = False, hist_from: int = 0,
         step0=0, lib_handle: Optional[ctypes.CDLL] = None, temperature: float = 1.0,
-        orig_time: int = 0) -> RunResult:
+        orig_time: int = 0, follow=None, follow_tol: float = 0.0) -> RunResult:
     """Run ``num_chains`` independent chains for ``K`` steps each.
 
     ``beta`` is a scalar or one value per chain; ``init`` is ``"zero"``,
@@ -247,6 +261,10 @@ def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, se
     ``orig_time`` > 0 (RF, Basic) each chain advances by exactly that many
     original samples; ``K`` is then a cap and ``n_records`` the records made.
     ``step0`` is a scalar or one first step index per chain.
+    ``follow = (actions, multiplicities)`` ([C, K] each) replays given
+    records: ``action`` / ``M`` then hold the oracle's own decisions, ``cls``
+    the RP_* class of each given record, and every other output is derived
+    along the given trajectory (see ``replay``).
     """
     is_int, Qc = _as_q(Q)
     N = Qc.shape[0]
@@ -320,10 +338,38 @@ def run(Q: np.ndarray, beta, mode: int, K: int, *, n: int = 0, L0: int = 100, se
     a.n_records = _ptr(r.n_records)
     a.step0s = _ptr(step0s)
     a.log_w, a.hist_rb = _ptr(r.w), _ptr(r.hist_rb)
+    if follow is not None:
+        fa = np.ascontiguousarray(follow[0], dtype=np.int32)
+        fm = np.ascontiguousarray(follow[1], dtype=np.int64)
+        if fa.shape != (C, K) or fm.shape != (C, K):
+            raise ValueError(f"follow arrays must be [{C}, {K}]")
+        r.cls = np.zeros((C, K), dtype=np.int32)
+        a.rp_action, a.rp_M, a.rp_class, a.rp_tol = fa.ctypes.data, fm.ctypes.data, r.cls.ctypes.data, follow_tol
     rc = (lib_handle or lib()).orc_run(ctypes.byref(a))
     if rc != 0:
         raise ValueError(f"oracle run rejected its arguments (code {rc})")
     return r
+
+
+def replay(Q: np.ndarray, beta, mode: int, actions: np.ndarray, multiplicities: np.ndarray, *, tol: float,
+           **kw) -> RunResult:
+    """Replay mode: follow another implementation's records.
+
+    For each given record (action, M) of each chain the oracle derives, from
+    its own state and its own Philox draws, dE, the weights, p, q and its own
+    decision, classifies the given record against that decision (``cls``,
+    RP_*) and continues from the given decision, so that every later record
+    is derived along the given trajectory and nothing stops at a difference.
+    A differing decision counts as a decision-boundary case only where the
+    oracle's quotient q (against the budget L or an integer) or U2*S (against
+    a running-sum end of the given choice) lies within the band that a
+    relative difference ``tol`` in p can move it across; anything else is
+    RP_MISMATCH.  ``E`` and ``p`` are the oracle's values along the
+    trajectory, ``x``/``h``/``E_final`` its final state.  Other keywords as
+    in ``run``."""
+    actions = np.asarray(actions)
+    K = actions.shape[1]
+    return run(Q, beta, mode, K, follow=(actions, multiplicities), follow_tol=tol, **kw)
 
 
 class _ContArgs(ctypes.Structure):
@@ -336,6 +382,8 @@ class _ContArgs(ctypes.Structure):
         ("log_w", ctypes.c_void_p), ("log_x", ctypes.c_void_p),
         ("x_final", ctypes.c_void_p), ("L_final", ctypes.c_void_p), ("set_final", ctypes.c_void_p),
         ("n_flips", ctypes.c_void_p), ("n_stays", ctypes.c_void_p), ("sums", ctypes.c_void_p),
+        ("rp_action", ctypes.c_void_p), ("rp_M", ctypes.c_void_p), ("rp_class", ctypes.c_void_p),
+        ("rp_tol", ctypes.c_double),
     ]
 
 
@@ -355,13 +403,15 @@ class ContResult:
     flips: Optional[np.ndarray] = None
     stays: Optional[np.ndarray] = None
     sums: Optional[np.ndarray] = None     # [C, 2, 4 dim + 1]
+    cls: Optional[np.ndarray] = None      # replay: RP_* class of each followed record
 
 
 def cont_run(x0: np.ndarray, K: int, *, mu0: float = 9.0, sigma: float = 0.1, pairs: int = 25, L0: int = 1000,
              seed: int = 0, chain_ids=None, log: bool = True, log_states: bool = False,
-             lib_handle: Optional[ctypes.CDLL] = None) -> ContResult:
+             lib_handle: Optional[ctypes.CDLL] = None, follow=None, follow_tol: float = 0.0) -> ContResult:
     """Continuous Unbiased PNS (Alg 7) on the donut target from states x0
-    [C, dim] for K records per chain (see orc_cont_run)."""
+    [C, dim] for K records per chain (see orc_cont_run).  ``follow`` and
+    ``follow_tol`` replay given records as in ``run`` / ``replay``."""
     x0 = np.ascontiguousarray(x0, dtype=np.float64)
     C, d = x0.shape
     cids = np.arange(C, dtype=np.uint32) if chain_ids is None else np.ascontiguousarray(chain_ids, dtype=np.uint32)
@@ -389,6 +439,13 @@ def cont_run(x0: np.ndarray, K: int, *, mu0: float = 9.0, sigma: float = 0.1, pa
     a.log_q, a.log_tmargin, a.log_w, a.log_x = _ptr(r.q), _ptr(r.tmargin), _ptr(r.w), _ptr(r.xs)
     a.x_final, a.L_final, a.set_final = _ptr(r.x), _ptr(r.L), _ptr(r.set)
     a.n_flips, a.n_stays, a.sums = _ptr(r.flips), _ptr(r.stays), _ptr(r.sums)
+    if follow is not None:
+        fa = np.ascontiguousarray(follow[0], dtype=np.int32)
+        fm = np.ascontiguousarray(follow[1], dtype=np.int64)
+        if fa.shape != (C, K) or fm.shape != (C, K):
+            raise ValueError(f"follow arrays must be [{C}, {K}]")
+        r.cls = np.zeros((C, K), dtype=np.int32)
+        a.rp_action, a.rp_M, a.rp_class, a.rp_tol = fa.ctypes.data, fm.ctypes.data, r.cls.ctypes.data, follow_tol
     rc = (lib_handle or lib()).orc_cont_run(ctypes.byref(a))
     if rc != 0:
         raise ValueError(f"oracle continuous run rejected its arguments (code {rc})")

@@ -284,6 +284,19 @@ typedef struct {
      * hist_from on); each may be NULL */
     double* log_w;
     double* hist_rb;
+    /* Replay: follow another implementation's records (rp_action, rp_M
+     * [num_chains][K], or NULL for a plain run).  Every step still derives
+     * the oracle's own decision from its own state and draws (logged in
+     * log_action / log_M), classifies the given record against it into
+     * rp_class [num_chains][K] (see orc_replay_class), and then continues
+     * from the given record's decision, so that every later record, the
+     * energies, p and the final state are derived along the given
+     * trajectory.  rp_tol is the relative tolerance on p between the two
+     * implementations that sets the width of the decision windows. */
+    const int32_t* rp_action;
+    const int64_t* rp_M;
+    int32_t* rp_class;
+    double rp_tol;
 } orc_run_args;
 
 /* Expected multiplicity of a record (Thm 3 (2)): M = 1 + G with G a
@@ -367,6 +380,109 @@ static uint64_t sat_add(uint64_t a, uint64_t b)
 {
     uint64_t r = a + b;
     return r < a ? UINT64_MAX : r;
+}
+
+/* Proportional choice (the paper's appendix "How to Sample Proportionally",
+ * first method): the first candidate, in scan order, whose running sum of
+ * weights exceeds t = U2 * S; if rounding leaves none, the last candidate of
+ * positive weight.  Candidates are the j < n with use[j] != 0 (use == NULL:
+ * all).  *tmargin receives the distance of t to the ends of the chosen
+ * interval over S (0 for the fallback). */
+static int32_t choose_proportional(const uint8_t* use, const double* w, int32_t n, double t, double S,
+                                   double* tmargin)
+{
+    double run = 0.0, prev = 0.0;
+    int32_t last_pos = -1;
+    for (int32_t j = 0; j < n; ++j) {
+        if (use && !use[j]) continue;
+        if (w[j] > 0.0) last_pos = j;
+        prev = run;
+        run += w[j];
+        if (run > t && w[j] > 0.0) {
+            const double lo = t - prev, hi = run - t;
+            *tmargin = (lo < hi ? lo : hi) / S;
+            return j;
+        }
+    }
+    *tmargin = 0.0;
+    return last_pos;
+}
+
+/* Replay classes (rp_class): how a given record relates to the oracle's own
+ * decision at the same state and draws. */
+#define ORC_RP_SAME 0         /* same action and multiplicity                 */
+#define ORC_RP_BUDGET 1       /* stay vs move differs, q within the window of L */
+#define ORC_RP_MULT 2         /* multiplicity differs, q within the window of
+                                 the interval [M - 1, M) the given M needs    */
+#define ORC_RP_CHOICE 3       /* chosen neighbour differs, U2 S within the
+                                 window of a running-sum end of the given one  */
+#define ORC_RP_MISMATCH (-1)  /* differs off every decision window            */
+#define ORC_RP_INVALID (-2)   /* the given action is impossible here           */
+
+/* Half-width of the band around a boundary b of q = log U1 / log1p(-p) in
+ * which two computations of p that agree to a relative `tol` may fall on
+ * different sides: dq / q = kappa(p) dp / p with
+ * kappa(p) = p / ((1 - p) |log1p(-p)|), plus 8 ulp of each side's
+ * rounding. */
+static double q_window(double p, double q, double tol)
+{
+    double kappa = 1.0;
+    if (p > 0.0 && p < 1.0) kappa = p / ((1.0 - p) * fabs(log1p(-p)));
+    return (kappa * tol + 8.0 * 0x1p-52) * fabs(q);
+}
+
+/* Is t = U2 S within the window of the interval of candidate g, i.e. could
+ * a running sum computed in another order, agreeing to tol * S, choose g?
+ * Running sums and t each move by at most tol * S (plus 8 ulp of S). */
+static int choice_in_window(const uint8_t* use, const double* w, int32_t g, double t, double S, double tol)
+{
+    double before = 0.0;
+    for (int32_t j = 0; j < g; ++j)
+        if (!use || use[j]) before += w[j];
+    const double win = (2.0 * tol + 8.0 * 0x1p-52) * S;
+    return t >= before - win && t < before + w[g] + win;
+}
+
+/* Classify the given record (g_action, g_M) against the oracle's own
+ * decision (own_stay, own_c, own_m) of a step with escape probability p,
+ * quotient q, remaining budget L (budgeted: Unbiased PNS or an exact-time
+ * run), candidates use[0..n) with weights w, their sum S and t = U2 S. */
+static int32_t orc_replay_class(int budgeted, int own_stay, int32_t own_c, int64_t own_m, int32_t g_action,
+                                int64_t g_M, int64_t L, double p, double q, double tol, const uint8_t* use,
+                                const double* w, int32_t n, double t, double S)
+{
+    const int32_t own_action = own_stay ? ORC_STAY : own_c;
+    const int64_t own_M = own_stay ? L : own_m;
+    if (g_action == own_action && g_M == own_M) return ORC_RP_SAME;
+    if (g_action == ORC_STAY) {
+        if (!budgeted) return ORC_RP_INVALID;
+    } else if (g_action < 0 || g_action >= n || (use && !use[g_action]) || !(w[g_action] > 0.0)) {
+        return ORC_RP_INVALID;
+    }
+    const int g_stay = g_action == ORC_STAY;
+    if (g_stay != own_stay) {
+        /* at the budget boundary q = L both sides record M = L */
+        if (g_M != L || !(fabs(q - (double)L) <= q_window(p, q, tol))) return ORC_RP_MISMATCH;
+        if (!g_stay && g_action != own_c && !choice_in_window(use, w, g_action, t, S, tol)) return ORC_RP_MISMATCH;
+        return ORC_RP_BUDGET;
+    }
+    if (g_stay) return ORC_RP_MISMATCH; /* both stay, so both must record L */
+    int32_t cls = ORC_RP_SAME;
+    if (g_M != own_m) {
+        /* the given M = 1 + floor(q') needs q' in [M - 1, M): q must lie
+         * within the window of that interval (for q near 2^53 and beyond the
+         * window spans several integers) */
+        if (g_M < 1) return ORC_RP_MISMATCH;
+        const double lo = (double)(g_M - 1), hi = (double)g_M;
+        const double dist = q < lo ? lo - q : (q >= hi ? q - hi : 0.0);
+        if (!(dist <= q_window(p, q, tol))) return ORC_RP_MISMATCH;
+        cls = ORC_RP_MULT;
+    }
+    if (g_action != own_c) {
+        if (!choice_in_window(use, w, g_action, t, S, tol)) return ORC_RP_MISMATCH;
+        cls = ORC_RP_CHOICE;
+    }
+    return cls;
 }
 
 int orc_run(const orc_run_args* a)
@@ -487,53 +603,47 @@ int orc_run(const orc_run_args* a)
              * cuts M for Unbiased PNS and exact-time runs */
             const double wrb = a->mode == ORC_MODE_OPT ? 1.0
                                                        : orc_expected_multiplicity(p, (unbiased || timed) ? L : -1);
-            int32_t action;
-            int64_t M;
+            /* The record's state is the state before this step. */
+            const int64_t Ei_rec = Ei;
+            const double Ef_rec = Ef;
+            /* Alg 6 "else" branch (and the end of an exact-time run): not
+             * enough original samples left in the budget, stay with M = L. */
+            const int own_stay = (unbiased || timed) && q >= (double)L;
+            /* Proportional choice over the subset in bit order. */
+            const double t = U2 * S;
             double tmargin = 0.0;
-            if (timed && q >= (double)L) {
+            const int32_t own_c = choose_proportional(member, w, N, t, S, &tmargin);
+            if (own_stay) tmargin = 0.0;
+            int32_t action = own_stay ? ORC_STAY : own_c;
+            int64_t M = own_stay ? L : m;
+            if (a->log_action) a->log_action[rec] = action;
+            if (a->log_M) a->log_M[rec] = M;
+            if (a->rp_action) {
+                const int32_t cls = orc_replay_class(unbiased || timed, own_stay, own_c, m, a->rp_action[rec],
+                                                     a->rp_M[rec], L, p, q, a->rp_tol, member, w, N, t, S);
+                if (a->rp_class) a->rp_class[rec] = cls;
+                if (cls != ORC_RP_INVALID) {
+                    action = a->rp_action[rec];
+                    M = a->rp_M[rec];
+                    sat = M == INT64_MAX;
+                }
+            }
+            if (action == ORC_STAY && timed) {
                 /* the original chain is still at J when the requested time
                  * runs out: record the remaining time and stop */
-                M = L;
-                action = ORC_STAY;
                 L = 0;
                 ++stays;
-            } else if (unbiased && q >= (double)L) {
-                /* Alg 6 "else" branch: not enough remaining original
-                 * samples; stay L times and move to the next set. */
-                M = L;
-                action = ORC_STAY;
+            } else if (action == ORC_STAY) {
+                /* stay L times and move to the next set */
                 L = a->L0;
                 ++sub;
                 if (a->mode == ORC_MODE_UNBIASED_SYS) orc_sys_subset(N, n, sub % I, member);
                 else orc_random_subset(a->seed, cid, (uint64_t)(k + 1), N, n, member);
                 ++stays;
             } else {
-                M = m;
-                if (unbiased || timed) L -= m;
+                if (unbiased || timed) L -= M;
                 saturated += sat;
-                /* Proportional choice, App. C: the first index whose running
-                 * sum exceeds U2 * S; rounding fallback: last positive one. */
-                double t = U2 * S;
-                double run = 0.0, prev = 0.0;
-                int32_t c = -1, last_pos = -1;
-                for (int32_t j = 0; j < N; ++j) {
-                    if (!member[j]) continue;
-                    if (w[j] > 0.0) last_pos = j;
-                    prev = run;
-                    run += w[j];
-                    if (run > t && w[j] > 0.0) {
-                        c = j;
-                        break;
-                    }
-                }
-                if (c < 0) {
-                    c = last_pos;
-                    tmargin = 0.0;
-                } else {
-                    double lo = t - prev, hi2 = run - t;
-                    tmargin = (lo < hi2 ? lo : hi2) / S;
-                }
-                action = c;
+                const int32_t c = action;
                 /* Move: flip bit c and update energy and every other field. */
                 if (a->is_int) {
                     int64_t delta = x[c] ? -1 : 1;
@@ -557,12 +667,8 @@ int orc_run(const orc_run_args* a)
             }
 
             /* Record k is (J_k-before, M_k) with its energy. */
-            double Erec = a->is_int ? (double)(Ei - (action >= 0 ? dEi[action] : 0))
-                                    : (action >= 0 ? Ef - dEf[action] : Ef);
-            if (a->log_action) a->log_action[rec] = action;
-            if (a->log_M) a->log_M[rec] = M;
-            if (a->log_Ei) a->log_Ei[rec] = a->is_int ? Ei - (action >= 0 ? dEi[action] : 0) : 0;
-            if (a->log_Ef) a->log_Ef[rec] = Erec;
+            if (a->log_Ei) a->log_Ei[rec] = a->is_int ? Ei_rec : 0;
+            if (a->log_Ef) a->log_Ef[rec] = a->is_int ? (double)Ei_rec : Ef_rec;
             if (a->log_p) a->log_p[rec] = p;
             if (a->log_q) a->log_q[rec] = q;
             if (a->log_tmargin) a->log_tmargin[rec] = tmargin;
@@ -774,17 +880,22 @@ typedef struct {
      * the expected multiplicities (row 1): sum w, then sum w x_i, sum w x_i^2,
      * sum w x_i^4 and sum w 1(x_i > 0) for i = 0..dim-1 (each may be NULL) */
     double* sums;
+    /* Replay of given records, as for the discrete chains (orc_run_args):
+     * rp_action, rp_M [num_chains][K] or NULL, classes into rp_class. */
+    const int32_t* rp_action;
+    const int64_t* rp_M;
+    int32_t* rp_class;
+    double rp_tol;
 } orc_cont_args;
 
-/* log pi(x) = -(|x|^2 - mu0)^2 / (2 sigma^2), evaluated as -(t t) c with
- * c = 1 / (2 sigma^2) rounded once. */
+/* log pi(x) = -(|x|^2 - mu0)^2 / (2 sigma^2), the donut density of Sec 7
+ * (without its normalising constant). */
 static double cont_logpi(const orc_cont_args* a, const double* x)
 {
     double r2 = 0.0;
     for (int32_t i = 0; i < a->dim; ++i) r2 += x[i] * x[i];
     const double t = r2 - a->mu0;
-    const double c = 1.0 / (2.0 * a->sigma * a->sigma);
-    return -(t * t) * c;
+    return -(t * t) / (2.0 * a->sigma * a->sigma);
 }
 
 /* Offsets of set `set` of a chain: delta[j][i] for pair j, coordinate i. */
@@ -843,44 +954,38 @@ int orc_cont_run(const orc_cont_args* a)
             else if (p <= 0.0) q = INFINITY;
             else q = log(U1) / log1p(-p);
             const double wrb = orc_expected_multiplicity(p, L);
-            int32_t action;
-            int64_t M;
-            double tmargin = 0.0;
             /* the record's state, before the move */
             double xr[ORC_CONT_MAX_DIM];
             memcpy(xr, x, sizeof(double) * (size_t)d);
             const double lpr = lpx;
-            if (q >= (double)L) {
-                /* not enough original samples left: stay L times, new set */
-                M = L;
-                action = ORC_STAY;
+            /* not enough original samples left: stay L times, new set */
+            const int own_stay = q >= (double)L;
+            const int64_t own_m = !(q < 0x1p63) ? INT64_MAX : (int64_t)floor(q) + 1;
+            const double t = U2 * S;
+            double tmargin = 0.0;
+            const int32_t own_c = choose_proportional(NULL, w, n, t, S, &tmargin);
+            if (own_stay) tmargin = 0.0;
+            int32_t action = own_stay ? ORC_STAY : own_c;
+            int64_t M = own_stay ? L : own_m;
+            if (a->log_action) a->log_action[rec] = action;
+            if (a->log_M) a->log_M[rec] = M;
+            if (a->rp_action) {
+                const int32_t cls = orc_replay_class(1, own_stay, own_c, own_m, a->rp_action[rec], a->rp_M[rec], L,
+                                                     p, q, a->rp_tol, NULL, w, n, t, S);
+                if (a->rp_class) a->rp_class[rec] = cls;
+                if (cls != ORC_RP_INVALID) {
+                    action = a->rp_action[rec];
+                    M = a->rp_M[rec];
+                }
+            }
+            if (action == ORC_STAY) {
                 L = a->L0;
                 ++set;
                 ++stays;
                 orc_cont_offsets(a->seed, cid, (uint64_t)set, P, d, delta);
             } else {
-                M = (int64_t)floor(q) + 1;
                 L -= M;
-                const double t = U2 * S;
-                double run = 0.0, prev = 0.0;
-                int32_t c = -1, last_pos = -1;
-                for (int32_t j = 0; j < n; ++j) {
-                    if (w[j] > 0.0) last_pos = j;
-                    prev = run;
-                    run += w[j];
-                    if (run > t && w[j] > 0.0) {
-                        c = j;
-                        break;
-                    }
-                }
-                if (c < 0) {
-                    c = last_pos;
-                    tmargin = 0.0;
-                } else {
-                    const double lo = t - prev, hi = run - t;
-                    tmargin = (lo < hi ? lo : hi) / S;
-                }
-                action = c;
+                const int32_t c = action;
                 const double sgn = c < P ? 1.0 : -1.0;
                 for (int32_t i = 0; i < d; ++i) x[i] = x[i] + sgn * delta[(c % P) * d + i];
                 lpx = lpy[c];
@@ -898,8 +1003,6 @@ int orc_cont_run(const orc_cont_args* a)
                     acc[r][1 + 3 * d + i] += v > 0.0 ? wt[r] : 0.0;
                 }
             }
-            if (a->log_action) a->log_action[rec] = action;
-            if (a->log_M) a->log_M[rec] = M;
             if (a->log_lp) a->log_lp[rec] = lpr;
             if (a->log_p) a->log_p[rec] = p;
             if (a->log_q) a->log_q[rec] = q;

@@ -575,8 +575,8 @@ def test_parallel_tempering_keeps_each_temperature_at_its_target():
 
 @pytest.mark.parametrize("mutation", [
     [("const double ex = (betas[ca] - betas[cb]) * dE;", "const double ex = (betas[cb] - betas[ca]) * dE;")],
-    [("                M = L;\n                action = ORC_STAY;\n                L = 0;",
-      "                M = L;\n                action = ORC_STAY;\n                L = 0;\n                x[0] ^= 1u;")],
+    [("                L = 0;\n                ++stays;",
+      "                L = 0;\n                x[0] ^= 1u;\n                ++stays;")],
 ])
 def test_planted_tempering_mistakes_are_caught(mutation, tmp_path):
     """A swap exponent of the wrong sign, or a chain that moves at the end of
