@@ -8,7 +8,7 @@ import pytest
 
 from paper_2210_10513_amd import inputs
 
-from parity_util import compare_final, compare_logs, oracle_run
+from parity_util import replay_check
 
 pytestmark = pytest.mark.gpu
 
@@ -24,18 +24,19 @@ def _batch(problems, mode, K, **kw):
 
 
 def _check_problem(g, p, pr, mode, K, *, seed, L0, rows=None, is_int=True, init="zero", x0=None):
+    """Replay every record of the chosen chains of problem p through the
+    oracle run of that chain alone (same seed, chain id = its global index)
+    and compare the final states: every record is compared."""
     info = g["info"][p]
     c0 = info.chain_begin
     rows = list(range(info.num_chains)) if rows is None else list(rows)
     betas = np.broadcast_to(np.asarray(pr.get("beta", 1.0), np.float64), (info.num_chains,))
-    o = oracle_run(pr["Q"], betas[rows], mode, K, n=info.subset_size, L0=pr.get("L0") or L0, seed=seed,
-                   chains=[c0 + r for r in rows], init=init, layout=pr.get("layout", "symmetric"),
-                   x0=None if x0 is None else x0[rows])
     log = {k: v[p] for k, v in g["log"].items()}
     cur = {k: v[p] for k, v in g["cur"].items()}
-    n = compare_logs(log, o, chain_rows=rows, is_int=is_int)
-    if n == len(rows) * K:
-        compare_final(cur, o, chain_rows=rows, is_int=is_int)
+    _, cov = replay_check(log, pr["Q"], betas[rows], mode, rows=rows, chain_ids=[c0 + r for r in rows],
+                          is_int=is_int, gcur=cur, n=info.subset_size, L0=pr.get("L0") or L0, seed=seed, init=init,
+                          layout=pr.get("layout", "symmetric"), x0=None if x0 is None else x0[rows])
+    assert cov.compared == len(rows) * K and cov.finals == len(rows)
     assert (g["stats"]["anomalies"][c0:c0 + info.num_chains] == 0).all()
     return info
 

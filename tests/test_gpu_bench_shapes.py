@@ -1,0 +1,109 @@
+"""GPU parity of the kernels the benchmark times, at the benchmark's shapes.
+
+The timed runs are uninstrumented (no per-step log): the Rejection-Free
+N = 1024 int16 workload runs the all-bits kernel on a 256x1 tile with the
+multiplicities of up to 64 steps computed together, and the Unbiased PNS
+N = 8192 float32 workload runs the compact window kernel (flavour 3) on a
+512x4 tile with the split record.  Each is run over 2000 steps in two
+launches, and
+  - every chain's last record (pns_read), counters and final x, h, E equal
+    those of the instrumented kernel on the same inputs, whose full log
+  - is replayed record by record through the oracle on sampled chains, with
+    the last multiplicity of the timed kernel equal to the oracle's own
+    (exact below 2^53);
+and float32 fields after 10^5 steps of the N = 8192 workload stay within a
+relative 1e-5 of an FP64 recomputation offdiag(Q) x (FP32 Q accuracy over a
+long run: the fields are accumulated in FP64, so no refresh is needed).
+"""
+import numpy as np
+import pytest
+
+from paper_2210_10513_amd import inputs
+
+from parity_util import replay_check
+
+pytestmark = pytest.mark.gpu
+
+TWO53 = 2 ** 53
+
+
+def _run(Q, betas, n, mode, K, *, log, seed, L0=100, launches=2):
+    from paper_2210_10513_amd.binding import Sampler, pns_problem_info_get
+    s = Sampler(Q, betas, n, mode, num_chains=len(betas), L0=L0, seed=seed, log_capacity=K if log else 0)
+    for _ in range(launches):
+        s.run(K // launches)
+    out = {"rec": s.read(), "cur": s.read_current(), "stats": s.stats(), "tile": s.tile(),
+           "flavour": pns_problem_info_get(s.ctx, 0).flavour, "log": s.read_log() if log else None}
+    s.close()
+    return out
+
+
+def _timed_vs_instrumented(Q, betas, n, mode, K, seed, rows, is_int, tile, flavour):
+    u = _run(Q, betas, n, mode, K, log=False, seed=seed)
+    i = _run(Q, betas, n, mode, K, log=True, seed=seed)
+    assert u["tile"] == tile and u["flavour"] == flavour
+    # every chain: the timed kernel's record, counters and state equal the
+    # instrumented kernel's
+    xs, ms, es = u["rec"]
+    log = i["log"]
+    assert np.array_equal(ms, log["M"][:, -1]) and np.array_equal(es, log["E"][:, -1])
+    for key in ("x", "h", "E", "L", "sub", "step"):
+        assert np.array_equal(u["cur"][key], i["cur"][key]), key
+    for key in ("steps", "flips", "stays", "saturated", "anomalies"):
+        assert np.array_equal(u["stats"][key], i["stats"][key]), key
+    assert (u["stats"]["steps"] == K).all() and (u["stats"]["anomalies"] == 0).all()
+    assert np.array_equal(u["stats"]["flips"], (log["action"] >= 0).sum(axis=1))
+    # sum of M in step order, as the kernel adds it
+    assert np.array_equal(u["stats"]["sum_M"], np.cumsum(log["M"].astype(np.float64), axis=1)[:, -1])
+    # sampled chains: every record of the instrumented run through the oracle
+    o, cov = replay_check(log, Q, np.asarray(betas)[rows], mode, rows=rows, is_int=is_int, gcur=u["cur"], n=n,
+                          seed=seed)
+    assert cov.compared == len(rows) * K and cov.finals == len(rows)
+    # the timed kernel's last multiplicity is the oracle's own where it is
+    # below 2^53 and off every decision boundary
+    last_same = o.cls[:, -1] == 0
+    small = o.M[:, -1] < TWO53
+    sel = last_same & small
+    assert sel.sum() >= len(rows) - 1
+    assert np.array_equal(ms[rows][sel], o.M[sel, -1])
+    return u
+
+
+def test_rf_n1024_int16_timed_kernel():
+    w = inputs.c2_rf_n1024()
+    rows = [0, 1, 257, 511, 777, 1023]
+    _timed_vs_instrumented(w.Q, w.betas, 0, "rf", 2000, 2210105130, rows, True, (256, 1), 0)
+
+
+def test_basic64_n1024_int16_timed_kernel():
+    w = inputs.c2_rf_n1024(mode="basic")
+    rows = [0, 500, 1023]
+    _timed_vs_instrumented(w.Q, w.betas, 64, "basic", 2000, 2210105131, rows, True, (256, 1), 2)
+
+
+def test_unbiased_n8192_f32_timed_kernel():
+    w = inputs.c3_unbiased_n8192()
+    rows = [0, 5, 15, 1000, 2047, 4095]
+    _timed_vs_instrumented(w.Q, w.betas, 512, "unbiased_sys", 2000, 2210105133, rows, False, (512, 4), 3)
+
+
+def test_float32_fields_after_1e5_steps_match_fp64_recomputation():
+    """Float32 Q over the full per-chain length (10^5 steps, all 4096 chains
+    of the N = 8192 workload, timed kernel): sampled chains' local fields and
+    energies against offdiag(Q) x and x^T Q x recomputed in FP64."""
+    import torch
+    w = inputs.c3_unbiased_n8192()
+    u = _run(w.Q, w.betas, 512, "unbiased_sys", 100_000, log=False, seed=2210105133, launches=4)
+    assert (u["stats"]["steps"] == 100_000).all()
+    rows = np.arange(0, 4096, 256)
+    x = u["cur"]["x"][rows]
+    assert (u["stats"]["flips"][rows] > 50_000).all()
+    Qd = torch.from_numpy(w.Q).cuda().double()
+    X = torch.from_numpy(x.astype(np.float64)).cuda()
+    H = (X @ Qd - X * torch.diagonal(Qd)).cpu().numpy()   # offdiag(Q) x, FP64
+    E = ((X @ Qd) * X).sum(1).cpu().numpy()                 # x^T Q x, FP64
+    h = u["cur"]["h"][rows]
+    herr = np.abs(h - H).max(axis=1) / np.maximum(1.0, np.abs(H).max(axis=1))
+    eerr = np.abs(u["cur"]["E"][rows] - E) / np.maximum(1.0, np.abs(E))
+    assert herr.max() <= 1e-5 and eerr.max() <= 1e-5, (herr.max(), eerr.max())
+    print(f"fields after 1e5 steps: max relative error {herr.max():.3e}, energies {eerr.max():.3e}")

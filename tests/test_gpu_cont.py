@@ -1,4 +1,4 @@
-"""GPU parity of continuous Unbiased PNS (Alg 7, donut target of Sec 6)
+"""GPU parity of continuous Unbiased PNS (Alg 7, donut target of Sec 7)
 against the oracle: every record (neighbour choice, multiplicity, log
 density, p, expected multiplicity), final states, budgets, set indices and
 estimator sums, across launches, ragged chain counts and the option edges;
@@ -11,7 +11,7 @@ import oracle
 from oracle import donut
 from paper_2210_10513_amd import inputs
 
-from parity_util import compare_logs
+from parity_util import cont_replay_check
 
 pytestmark = pytest.mark.gpu
 
@@ -38,8 +38,13 @@ def _gpu(x0, K, runs=1, **kw):
     return out
 
 
-def _compare(g, o, C, K, L0):
-    assert compare_logs(g["log"], o, chain_rows=list(range(C)), is_int=False, p_rtol=P_RTOL) == C * K
+def _compare(g, x0, K, L0, chain_ids=None, **kw):
+    """Replay every GPU record through the oracle (the donut log density by
+    its definition, the oracle's own normal offsets) and compare records,
+    final states, budgets, set indices, sums and counters."""
+    C = x0.shape[0]
+    o, cov = cont_replay_check(g["log"], x0, p_rtol=P_RTOL, rtol=X_RTOL, chain_ids=chain_ids, L0=L0, **kw)
+    assert cov.compared == C * K
     assert np.allclose(g["log"]["w"], o.w, rtol=P_RTOL, atol=0)
     cur = g["cur"]
     assert np.allclose(cur["x"], o.x, rtol=X_RTOL, atol=X_RTOL)
@@ -57,8 +62,7 @@ def test_records_match_oracle(d, sigma, pairs, L0, C):
     x0 = inputs.donut_draws(C, d, mu0, sigma, seed=C + d)
     kw = dict(mu0=mu0, sigma=sigma, pairs=pairs, L0=L0, seed=31)
     g = _gpu(x0, K, **kw)
-    o = _oracle(x0, K, **kw)
-    _compare(g, o, C, K, L0)
+    _compare(g, x0, K, **kw)
     stays = (g["log"]["action"] == oracle.STAY).sum()
     assert stays > 0 and stays < C * K
 
@@ -78,8 +82,7 @@ def test_launches_continue_where_they_stopped_and_start_far_from_the_ring():
         s.run(K)
     g = {"log": s.read_log(), "cur": s.read(), "sums": s.read_sums(), "stats": s.stats()}
     s.close()
-    o = _oracle(x0, 3 * K, chain_ids=np.arange(1000, 1000 + C), **kw)
-    _compare(g, o, C, 3 * K, 200)
+    _compare(g, x0, 3 * K, chain_ids=np.arange(1000, 1000 + C), **kw)
 
 
 def test_clear_sums_and_zero_steps():
@@ -99,7 +102,7 @@ def test_clear_sums_and_zero_steps():
 
 
 def test_large_run_sampled_chains_match_oracle():
-    """65536 chains x 2000 records (the Sec 6 workload, 25 pairs, L0 = 1000,
+    """65536 chains x 2000 records (the Sec 7 workload, 25 pairs, L0 = 1000,
     sigma = 0.1): eight sampled chains equal the oracle's run of the same
     chain ids."""
     from paper_2210_10513_amd.binding import ContSampler
@@ -119,7 +122,7 @@ def test_large_run_sampled_chains_match_oracle():
 
 @pytest.mark.parametrize("d,sigma", [(2, 0.1), (3, 1.0)])
 def test_estimators_match_the_donut_moments(d, sigma):
-    """Ratio estimators of Sec 6 (weights M and the expected multiplicities)
+    """Ratio estimators of Sec 7 (weights M and the expected multiplicities)
     from 8192 chains started at exact draws, 4000 records each: E[x_i^2],
     E[|x|^2] and P(x_i > 0) within 5 standard errors of the per-chain
     estimates, and E[x_i^4] likewise."""

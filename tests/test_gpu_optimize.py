@@ -9,7 +9,7 @@ import oracle
 from oracle import exact
 from paper_2210_10513_amd import inputs
 
-from parity_util import compare_final, compare_logs
+from parity_util import compare_final, replay_check
 
 pytestmark = pytest.mark.gpu
 
@@ -38,11 +38,11 @@ def test_optimization_matches_oracle(mode, n, N, dtype, T):
     xb, eb = s.read_best()
     s.close()
     nn = N if mode == "rf" else n
-    o = _opt_oracle(Q, beta, K, nn, T, C, 17, init="random")
     rows = list(range(C))
-    assert compare_logs(g["log"], o, chain_rows=rows, is_int=is_int) == C * K
+    o, cov = replay_check(g["log"], Q, beta, "opt", rows=rows, is_int=is_int, gcur=g["cur"], n=nn, seed=17,
+                          init="random", temperature=T)
+    assert cov.compared == C * K and cov.finals == C
     assert (g["log"]["M"] == 1).all()
-    compare_final(g["cur"], o, chain_rows=rows, is_int=is_int)
     assert np.array_equal(xb, o.x_best)
     if is_int:
         assert np.array_equal(eb, o.E_best.astype(np.float64))
@@ -71,9 +71,9 @@ def test_cooling_schedule_and_sampling_after_burn_in():
     assert np.array_equal(eb, best.astype(np.float64))
     assert np.array_equal(x_burn, o2.x)
     rows = list(range(C))
-    o3 = oracle.run(Q.astype(np.int64), 0.1, oracle.MODE_RF, 100, seed=3, num_chains=C, x0=x_burn, step0=200)
-    assert compare_logs(g["log"], o3, chain_rows=rows, is_int=True) == C * 100
-    compare_final(g["cur"], o3, chain_rows=rows, is_int=True)
+    _, cov = replay_check(g["log"], Q, 0.1, "rf", rows=rows, is_int=True, gcur=g["cur"], seed=3, x0=x_burn,
+                          step0=200)
+    assert cov.compared == C * 100 and cov.finals == C
 
 
 def test_adopt_best_moves_chains_to_x_max():

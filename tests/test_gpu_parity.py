@@ -8,19 +8,24 @@ import oracle
 from oracle import exact
 from paper_2210_10513_amd import inputs
 
-from parity_util import compare_final, compare_logs, gpu_run, oracle_run
+from parity_util import compare_final, gpu_run, oracle_run, replay_check
 
 pytestmark = pytest.mark.gpu
 
 
 def _both(Q, beta, mode, K, *, chains, rows=None, is_int=True, **kw):
+    """Run the GPU with a full per-step log, replay every record of `rows`
+    through the oracle and compare the final states; every record of every
+    row is compared."""
     g = gpu_run(Q, beta, mode, K, chains=chains, **kw)
     rows = list(range(chains)) if rows is None else list(rows)
     okw = {k: v for k, v in kw.items() if k in ("n", "L0", "seed", "init", "layout")}
-    o = oracle_run(Q, beta, mode, K, chains=[kw.get("chain_id_base", 0) + r for r in rows], **okw)
-    n = compare_logs(g["log"], o, chain_rows=rows, is_int=is_int)
-    if n == len(rows) * K:
-        compare_final(g["cur"], o, chain_rows=rows, is_int=is_int)
+    if kw.get("x0") is not None:
+        okw["x0"] = np.asarray(kw["x0"])[rows]
+    b = np.asarray(beta)[rows] if np.ndim(beta) else beta
+    o, cov = replay_check(g["log"], Q, b, mode, rows=rows, chain_ids=[kw.get("chain_id_base", 0) + r for r in rows],
+                          is_int=is_int, gcur=g["cur"], **okw)
+    assert cov.compared == len(rows) * K and cov.finals == len(rows)
     assert (g["stats"]["anomalies"] == 0).all()
     return g, o
 
@@ -123,10 +128,13 @@ def test_two_group_window_kernel(mode, N, n, tile, dtype, log):
     kw = dict(n=n, L0=40, seed=13, init="random", block=tile[0], groups=tile[1])
     g = gpu_run(Q, beta, mode, 300, chains=3, log=log, **kw)
     assert g["flavour"] == 4 and g["tile"] == tile
-    o = oracle_run(Q, beta, mode, 300, chains=[0, 1, 2], n=n, L0=40, seed=13, init="random")
     if log:
-        assert compare_logs(g["log"], o, chain_rows=[0, 1, 2], is_int=is_int) == 3 * 300
-    compare_final(g["cur"], o, chain_rows=[0, 1, 2], is_int=is_int)
+        _, cov = replay_check(g["log"], Q, beta, mode, rows=[0, 1, 2], is_int=is_int, gcur=g["cur"], n=n, L0=40,
+                              seed=13, init="random")
+        assert cov.compared == 3 * 300 and cov.finals == 3
+    else:
+        o = oracle_run(Q, beta, mode, 300, chains=[0, 1, 2], n=n, L0=40, seed=13, init="random")
+        compare_final(g["cur"], o, chain_rows=[0, 1, 2], is_int=is_int)
     assert (g["stats"]["anomalies"] == 0).all()
 
 
@@ -258,9 +266,8 @@ def test_rf_n1024_int16_full_batch_sampled_chains():
     w = inputs.c2_rf_n1024()
     g = gpu_run(w.Q, 0.01, "rf", 300, chains=1024, seed=2210105130)
     rows = [0, 1, 511, 1023]
-    o = oracle_run(w.Q, 0.01, "rf", 300, chains=rows, seed=2210105130)
-    assert compare_logs(g["log"], o, chain_rows=rows, is_int=True) == len(rows) * 300
-    compare_final(g["cur"], o, chain_rows=rows, is_int=True)
+    _, cov = replay_check(g["log"], w.Q, 0.01, "rf", rows=rows, is_int=True, gcur=g["cur"], seed=2210105130)
+    assert cov.compared == len(rows) * 300 and cov.finals == len(rows)
 
 
 def test_unbiased_n8192_f32_sampled_chains():
@@ -268,10 +275,9 @@ def test_unbiased_n8192_f32_sampled_chains():
     betas = w.betas
     g = gpu_run(w.Q, betas, "unbiased_sys", 150, chains=len(betas), n=512, L0=100, seed=2210105133)
     rows = [0, 7, 15, 200, 255]
-    Q64 = w.Q
-    o = oracle_run(Q64, betas[rows], "unbiased_sys", 150, chains=rows, n=512, L0=100, seed=2210105133)
-    assert compare_logs(g["log"], o, chain_rows=rows, is_int=False) == len(rows) * 150
-    compare_final(g["cur"], o, chain_rows=rows, is_int=False)
+    _, cov = replay_check(g["log"], w.Q, betas[rows], "unbiased_sys", rows=rows, is_int=False, gcur=g["cur"], n=512,
+                          L0=100, seed=2210105133)
+    assert cov.compared == len(rows) * 150 and cov.finals == len(rows)
 
 
 @pytest.mark.parametrize("mode,n,launch,chunk,K", [("rf", 0, "persistent", 0, 130), ("rf", 0, "persistent", 50, 177),

@@ -12,11 +12,11 @@ import oracle
 from oracle import exact, moments
 from paper_2210_10513_amd import inputs
 
-from parity_util import compare_logs, oracle_run
+from parity_util import oracle_run, replay_check
 
 pytestmark = pytest.mark.gpu
 
-W_RTOL = 1e-11  # p agrees to 1e-12 (compare_logs); the weight is a smooth function of it
+W_RTOL = 1e-11  # p agrees to 1e-12 (replay_check); the weight is a smooth function of it
 
 
 @pytest.mark.parametrize("mode,n,N,dtype,L0", [("rf", 0, 90, np.int32, 100), ("basic", 5, 150, np.int16, 100),
@@ -35,10 +35,12 @@ def test_log_weights_match_oracle(mode, n, N, dtype, L0):
     s = Sampler(Q, beta, n, mode, num_chains=C, seed=21, init="random", L0=L0, log_capacity=K)
     s.run(K)
     log = s.read_log()
+    cur = s.read_current()
     w = s.rb_weights()["log"]
     s.close()
-    o = oracle_run(Q, beta, mode, K, n=n, L0=L0, seed=21, chains=list(range(C)), init="random")
-    assert compare_logs(log, o, chain_rows=list(range(C)), is_int=is_int) == C * K
+    o, cov = replay_check(log, Q, beta, mode, rows=list(range(C)), is_int=is_int, gcur=cur, n=n, L0=L0, seed=21,
+                          init="random")
+    assert cov.compared == C * K and cov.finals == C
     assert np.allclose(w, o.w, rtol=W_RTOL, atol=0)
     if mode == "rf":
         assert np.allclose(w, 1.0 / log["p"], rtol=1e-15)

@@ -7,7 +7,7 @@ import pytest
 
 from paper_2210_10513_amd import inputs
 
-from parity_util import compare_final, compare_logs, oracle_run
+from parity_util import oracle_run, replay_check
 
 pytestmark = pytest.mark.gpu
 
@@ -36,15 +36,12 @@ def test_set_q_continues_like_a_restart_on_the_new_q(mode, n, dtype):
     rows = list(range(C))
     o1 = oracle_run(Q1, beta, mode, K1, n=n, seed=9, chains=rows, init="random")
     assert np.array_equal(o1.x, x_mid)
-    import oracle
-    Qo = Q2.astype(np.int64) if is_int else Q2.astype(np.float64)
-    o2 = oracle.run(Qo, beta, {"rf": oracle.MODE_RF, "basic": oracle.MODE_BASIC}[mode], K2, n=n, seed=9,
-                    num_chains=C, chain_ids=np.arange(C, dtype=np.uint32), x0=x_mid, step0=K1)
     # fields and energies right after the swap are those of x_mid under Q2
     E_mid = np.einsum("ci,ij,cj->c", x_mid.astype(np.float64), Q2.astype(np.float64), x_mid.astype(np.float64))
     assert np.allclose(cur["E"], E_mid, rtol=1e-12, atol=1e-9)
-    assert compare_logs(g["log"], o2, chain_rows=rows, is_int=is_int) == C * K2
-    compare_final(g["cur"], o2, chain_rows=rows, is_int=is_int)
+    _, cov = replay_check(g["log"], Q2, beta, mode, rows=rows, is_int=is_int, gcur=g["cur"], n=n, seed=9, x0=x_mid,
+                          step0=K1)
+    assert cov.compared == C * K2 and cov.finals == C
 
 
 def test_set_q_rejects_bad_matrices_and_keeps_the_old_one():

@@ -8,7 +8,7 @@ import oracle
 from oracle import exact
 from paper_2210_10513_amd import inputs
 
-from parity_util import compare_final, compare_logs
+from parity_util import compare_final, replay_check
 
 pytestmark = pytest.mark.gpu
 
@@ -32,18 +32,11 @@ def test_original_time_run_matches_oracle(mode, n, dtype):
     o = oracle.run(Qo, beta, oracle.MODE_RF if mode == "rf" else oracle.MODE_BASIC, T, n=n, seed=8, num_chains=C,
                    init="random", orig_time=T)
     assert np.array_equal(cur["step"], o.n_records)
+    _, cov = replay_check(log, Q, beta, mode, rows=list(range(C)), is_int=is_int, lengths=cur["step"], gcur=cur,
+                          n=n, seed=8, init="random", orig_time=T)
+    assert cov.compared == int(o.n_records.sum()) and cov.finals == C
     for c in range(C):
-        k = int(o.n_records[c])
-        g = {key: v[c:c + 1, :k] for key, v in log.items()}
-
-        class O:
-            pass
-        oc = O()
-        for f in ("action", "M", "E", "p", "q", "tmargin"):
-            setattr(oc, f, getattr(o, f)[c:c + 1, :k])
-        assert compare_logs(g, oc, chain_rows=[0], is_int=is_int) == k
-        assert g["M"].sum() == T
-    compare_final(cur, o, chain_rows=list(range(C)), is_int=is_int)
+        assert log["M"][c, :int(o.n_records[c])].sum() == T
 
 
 def test_tempering_sweeps_match_oracle():
