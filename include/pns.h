@@ -408,6 +408,37 @@ int pns_read_betas(pns_ctx* ctx, double* betas);
  * (0..temps-1) at temperature position t.  Errors: PNS_EINVAL (no swap yet). */
 int pns_read_ladder(pns_ctx* ctx, int32_t* ladder);
 
+/* ---- checkpoints (resume) ----
+ *
+ * Every draw of a step is keyed by (seed, chain id, step), so a chain
+ * continues exactly where it stopped once its state and step counter are
+ * restored: K steps, pns_save, pns_load into a new context, K more steps give
+ * the records, states and counters of 2K steps in one run.
+ *
+ * pns_save writes the state of every chain into buf (host or device, caller
+ * owned, `capacity` bytes): current bits x, local fields h, energy E,
+ * remaining budget L and partial-neighbor-set index of Alg 6, step counter,
+ * last record, counters, inverse temperatures (tempering permutes them), the
+ * chain ids, and where present the random sets of UNBIASED_RAND, the
+ * tempering ladder and the best states of pns_optimize; then a checksum.
+ * *size receives the byte count; with buf == NULL only *size is set.
+ * Logs, histograms and snapshots are outputs, not state, and are not saved;
+ * Q is not saved either (the caller recreates the context from it).
+ * Synchronises the context's stream.  Errors: PNS_EINVAL (NULL ctx or size,
+ * capacity below the size), PNS_EDEVICE.
+ */
+int pns_save(pns_ctx* ctx, void* buf, int64_t capacity, int64_t* size);
+
+/* Restore a checkpoint of pns_save into ctx (buf host or device, `size`
+ * bytes).  ctx must have been created like the saved context: same mode,
+ * element and field type, seed, chain ids, and the same problems in the same
+ * order (N, layout, subset size, L0, chains; pass explicit subset sizes when
+ * the autotuner could choose differently).  The tile and launch form may
+ * differ.  Errors: PNS_EINVAL (not a checkpoint, wrong size or checksum, a
+ * context that differs in any of the above; nothing is changed then),
+ * PNS_ENOMEM, PNS_EDEVICE. */
+int pns_load(pns_ctx* ctx, const void* buf, int64_t size);
+
 /* ---- differentiation path ----
  *
  * The target pi_beta(x) = exp(-beta x^T Q x) / Z(Q, beta) gives

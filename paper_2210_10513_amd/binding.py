@@ -43,7 +43,7 @@ EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_cu
            "pns_adopt_best", "pns_run_original", "pns_pt_swap", "pns_read_betas", "pns_read_ladder",
            "pns_moments_f64", "pns_read_rb_weights", "pns_snapshot_moments_rb", "pns_cont_opts_default",
            "pns_cont_create", "pns_cont_run", "pns_cont_read", "pns_cont_read_log", "pns_cont_read_sums",
-           "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy"]
+           "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy", "pns_save", "pns_load"]
 
 
 class pns_opts(ctypes.Structure):
@@ -144,6 +144,8 @@ def _load() -> ctypes.CDLL:
     L.pns_pt_swap.argtypes = [vp, i32, i64, vp]
     L.pns_read_betas.argtypes = [vp, vp]
     L.pns_read_ladder.argtypes = [vp, vp]
+    L.pns_save.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
+    L.pns_load.argtypes = [vp, vp, i64]
     L.pns_moments_f64.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
     L.pns_read_rb_weights.argtypes = [vp, vp, vp, vp]
     L.pns_snapshot_moments_rb.argtypes = [vp, i32, vp, vp]
@@ -165,7 +167,8 @@ def _load() -> ctypes.CDLL:
                  "pns_snapshots_clear", "pns_optimize", "pns_read_best", "pns_adopt_best", "pns_run_original",
                  "pns_pt_swap", "pns_read_betas", "pns_read_ladder", "pns_moments_f64", "pns_read_rb_weights",
                  "pns_snapshot_moments_rb", "pns_cont_create", "pns_cont_run", "pns_cont_read", "pns_cont_read_log",
-                 "pns_cont_read_sums", "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy"):
+                 "pns_cont_read_sums", "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy",
+                 "pns_save", "pns_load"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -398,6 +401,19 @@ def pns_read_ladder(ctx, ladder) -> None:
     _check(lib.pns_read_ladder(ctx, _addr(ladder)))
 
 
+def pns_save(ctx, buf=None) -> int:
+    """Checkpoint size in bytes (buf None), or write the checkpoint into buf
+    (a host or device buffer of at least that size) and return its size."""
+    size = ctypes.c_int64(0)
+    cap = 0 if buf is None else (buf.nbytes if hasattr(buf, "nbytes") else buf.numel() * buf.element_size())
+    _check(lib.pns_save(ctx, _addr(buf), cap, ctypes.byref(size)))
+    return size.value
+
+
+def pns_load(ctx, buf, size: int) -> None:
+    _check(lib.pns_load(ctx, _addr(buf), size))
+
+
 def pns_last_error() -> str:
     return lib.pns_last_error().decode()
 
@@ -570,6 +586,18 @@ class Sampler:
         pns_read_ladder(self.ctx, l)
         return l
 
+    def save(self) -> np.ndarray:
+        """Checkpoint of every chain's state (pns_save) as a byte array."""
+        buf = np.zeros(pns_save(self.ctx), np.uint8)
+        pns_save(self.ctx, buf)
+        return buf
+
+    def load(self, buf) -> "Sampler":
+        """Restore a checkpoint of an identically created sampler (pns_load)."""
+        b = np.ascontiguousarray(buf, dtype=np.uint8)
+        pns_load(self.ctx, b, b.nbytes)
+        return self
+
     def snapshots_clear(self) -> "Sampler":
         pns_snapshots_clear(self.ctx)
         return self
@@ -684,6 +712,18 @@ class BatchSampler:
 
     def sync(self) -> None:
         pns_sync(self.ctx)
+
+    def save(self) -> np.ndarray:
+        """Checkpoint of every chain's state (pns_save) as a byte array."""
+        buf = np.zeros(pns_save(self.ctx), np.uint8)
+        pns_save(self.ctx, buf)
+        return buf
+
+    def load(self, buf) -> "BatchSampler":
+        """Restore a checkpoint of an identically created batch (pns_load)."""
+        b = np.ascontiguousarray(buf, dtype=np.uint8)
+        pns_load(self.ctx, b, b.nbytes)
+        return self
 
     def _split_bits(self, flat, rows: Optional[int] = None):
         out = []

@@ -2072,6 +2072,197 @@ int pns_read_ladder(pns_ctx* ctx, int32_t* ladder)
 
 }  // extern "C"
 
+// ---- checkpoints (pns_save / pns_load) ----
+
+namespace {
+
+constexpr char kCkptMagic[8] = {'P', 'N', 'S', 'C', 'K', 'P', 'T', '1'};
+constexpr uint32_t kCkptVersion = 1;
+
+enum : uint32_t { kCkptRandSets = 1u, kCkptLadder = 2u, kCkptBest = 4u };
+
+// Fixed-size header of a checkpoint; the problem descriptors, the state
+// arrays and an FNV-1a checksum of everything before it follow.
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t flags;
+    int32_t mode, qtype, htype, num_chains;
+    int32_t num_problems, pt_T;
+    uint64_t seed;
+    int64_t fields;
+    int64_t total_bytes;
+};
+
+struct CkptProblem {
+    int32_t N, n, layout, chains;
+    int64_t L0, pitch;
+};
+
+uint64_t fnv1a(const uint8_t* p, size_t n)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// One device array of the chain state: address and byte count.
+struct CkptArray {
+    void* dev;
+    size_t bytes;
+};
+
+// The arrays a checkpoint holds, in their order in the blob.
+std::vector<CkptArray> ckpt_arrays(pns_ctx* ctx, uint32_t flags)
+{
+    const size_t C = (size_t)ctx->num_chains, F = (size_t)ctx->fields;
+    const size_t hb = ctx->htype == H_I32 ? 4 : 8;
+    std::vector<CkptArray> a = {
+        {ctx->x, F},          {ctx->h, F * hb},          {ctx->E, C * 8},          {ctx->L, C * 8},
+        {ctx->sub, C * 8},    {ctx->step, C * 8},        {ctx->last_action, C * 4}, {ctx->last_M, C * 8},
+        {ctx->last_E, C * 8}, {ctx->counters, C * 6 * 8}, {ctx->beta, C * 8},       {ctx->chain_id, C * 4},
+    };
+    if (flags & kCkptRandSets) a.push_back({ctx->rmem, F});
+    if (flags & kCkptLadder) a.push_back({ctx->pt_ladder, C * 4});
+    if (flags & kCkptBest) {
+        a.push_back({ctx->xbest, F});
+        a.push_back({ctx->Ebest, C * 8});
+    }
+    return a;
+}
+
+uint32_t ckpt_flags(const pns_ctx* ctx)
+{
+    return (ctx->rmem ? kCkptRandSets : 0u) | (ctx->pt_ladder ? kCkptLadder : 0u) |
+           (ctx->best_valid ? kCkptBest : 0u);
+}
+
+size_t ckpt_size(pns_ctx* ctx, uint32_t flags)
+{
+    size_t n = sizeof(CkptHeader) + ctx->probs.size() * sizeof(CkptProblem) + 8;
+    for (const CkptArray& a : ckpt_arrays(ctx, flags)) n += a.bytes;
+    return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pns_save(pns_ctx* ctx, void* buf, int64_t capacity, int64_t* size)
+{
+    g_error.clear();
+    if (!ctx || !size) return fail(PNS_EINVAL, "NULL argument");
+    const uint32_t flags = ckpt_flags(ctx);
+    const size_t total = ckpt_size(ctx, flags);
+    *size = (int64_t)total;
+    if (!buf) return PNS_OK;
+    if (capacity < (int64_t)total) return fail(PNS_EINVAL, "checkpoint needs %zu bytes, buffer holds %lld", total,
+                                               (long long)capacity);
+    int rc = pns_sync(ctx);
+    if (rc) return rc;
+    std::vector<uint8_t> blob(total);
+    CkptHeader h{};
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.version = kCkptVersion;
+    h.flags = flags;
+    h.mode = ctx->mode;
+    h.qtype = ctx->qtype;
+    h.htype = ctx->htype;
+    h.num_chains = ctx->num_chains;
+    h.num_problems = (int32_t)ctx->probs.size();
+    h.pt_T = ctx->pt_T;
+    h.seed = ctx->seed;
+    h.fields = ctx->fields;
+    h.total_bytes = (int64_t)total;
+    size_t off = 0;
+    std::memcpy(&blob[off], &h, sizeof(h));
+    off += sizeof(h);
+    for (const ProblemRun& P : ctx->probs) {
+        CkptProblem cp{P.N, P.n, P.layout, P.chains, P.L0, P.pitch};
+        std::memcpy(&blob[off], &cp, sizeof(cp));
+        off += sizeof(cp);
+    }
+    for (const CkptArray& a : ckpt_arrays(ctx, flags)) {
+        HIP_TRY(hipMemcpy(&blob[off], a.dev, a.bytes, hipMemcpyDeviceToHost), "checkpoint download");
+        off += a.bytes;
+    }
+    const uint64_t sum = fnv1a(blob.data(), off);
+    std::memcpy(&blob[off], &sum, 8);
+    return copy_out(buf, blob.data(), total);
+}
+
+int pns_load(pns_ctx* ctx, const void* buf, int64_t size)
+{
+    g_error.clear();
+    if (!ctx || !buf) return fail(PNS_EINVAL, "NULL argument");
+    if (size < (int64_t)sizeof(CkptHeader)) return fail(PNS_EINVAL, "checkpoint of %lld bytes is too short",
+                                                         (long long)size);
+    std::vector<uint8_t> blob((size_t)size);
+    int rc = copy_in(blob.data(), buf, blob.size());
+    if (rc) return rc;
+    CkptHeader h;
+    std::memcpy(&h, blob.data(), sizeof(h));
+    if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != kCkptVersion)
+        return fail(PNS_EINVAL, "not a checkpoint of this library version");
+    if (h.total_bytes != size) return fail(PNS_EINVAL, "checkpoint size %lld, header says %lld", (long long)size,
+                                           (long long)h.total_bytes);
+    uint64_t sum;
+    std::memcpy(&sum, &blob[(size_t)size - 8], 8);
+    if (sum != fnv1a(blob.data(), (size_t)size - 8)) return fail(PNS_EINVAL, "checkpoint checksum mismatch");
+    if (h.mode != ctx->mode || h.qtype != ctx->qtype || h.htype != ctx->htype || h.num_chains != ctx->num_chains ||
+        h.num_problems != (int32_t)ctx->probs.size() || h.seed != ctx->seed || h.fields != ctx->fields)
+        return fail(PNS_EINVAL, "checkpoint is of a context with another mode, element type, chain count, "
+                                "problem count or seed");
+    size_t off = sizeof(h);
+    for (const ProblemRun& P : ctx->probs) {
+        CkptProblem cp;
+        std::memcpy(&cp, &blob[off], sizeof(cp));
+        off += sizeof(cp);
+        if (cp.N != P.N || cp.n != P.n || cp.layout != P.layout || cp.chains != P.chains || cp.L0 != P.L0 ||
+            cp.pitch != P.pitch)
+            return fail(PNS_EINVAL, "checkpoint problem (N=%d, n=%d, L0=%lld, %d chains) differs from the "
+                                    "context's (N=%d, n=%d, L0=%lld, %d chains)",
+                        cp.N, cp.n, (long long)cp.L0, cp.chains, P.N, P.n, (long long)P.L0, P.chains);
+    }
+    if ((rc = pns_sync(ctx))) return rc;
+    // the chain ids must be those of this context
+    std::vector<uint32_t> cid;
+    if ((rc = d2h(cid, ctx->chain_id, (size_t)ctx->num_chains))) return rc;
+    {
+        size_t o2 = off;
+        for (const CkptArray& a : ckpt_arrays(ctx, 0)) {
+            if (a.dev == ctx->chain_id) {
+                if (std::memcmp(&blob[o2], cid.data(), a.bytes) != 0)
+                    return fail(PNS_EINVAL, "checkpoint chain ids differ (another chain_id_base)");
+                break;
+            }
+            o2 += a.bytes;
+        }
+    }
+    // optional parts the context may not have yet
+    if ((h.flags & kCkptLadder) && !ctx->pt_ladder) {
+        if ((rc = dev_alloc(&ctx->pt_ladder, (size_t)ctx->num_chains))) return rc;
+        if (!ctx->pt_accepted && (rc = dev_alloc(&ctx->pt_accepted, (size_t)ctx->num_chains))) return rc;
+    }
+    if ((h.flags & kCkptBest) && !ctx->xbest) {
+        if ((rc = dev_alloc(&ctx->xbest, (size_t)ctx->fields))) return rc;
+        if ((rc = dev_alloc(&ctx->Ebest, (size_t)ctx->num_chains))) return rc;
+    }
+    if ((h.flags & kCkptRandSets) && !ctx->rmem) return fail(PNS_EINVAL, "checkpoint holds random sets");
+    for (const CkptArray& a : ckpt_arrays(ctx, h.flags)) {
+        HIP_TRY(hipMemcpy(a.dev, &blob[off], a.bytes, hipMemcpyHostToDevice), "checkpoint upload");
+        off += a.bytes;
+    }
+    ctx->pt_T = h.pt_T;
+    ctx->best_valid = (h.flags & kCkptBest) != 0;
+    return PNS_OK;
+}
+
+}  // extern "C"
+
 // ---- continuous Unbiased PNS (Alg 7, donut target) ----
 
 struct pns_cont {

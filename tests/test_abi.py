@@ -168,3 +168,11 @@ def test_structs_match_header_layout(tmp_path):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for fname, _ in cls._fields_:
             assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, f"{name}.{fname}"
+
+
+def test_checkpoint_calls_reject_null_arguments():
+    from paper_2210_10513_amd import binding as b
+    size = ctypes.c_int64(-1)
+    assert b.lib.pns_save(None, None, 0, ctypes.byref(size)) == b.PNS_EINVAL
+    assert b.lib.pns_load(None, None, 0) == b.PNS_EINVAL
+    assert "NULL" in b.pns_last_error()
