@@ -2,24 +2,27 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-Workload (default ``rf_n1024_int16``): Rejection-Free on a dense symmetric
-int16 QUBO, N = 1024, entries uniform on {-100..100}, 1024 chains,
-beta = 0.01, int32 local fields.  One benchmark step runs every chain for
-``--chain-steps`` sampler steps (default 100000, the full per-chain length of
-the workload) in the persistent launch form, with all inputs resident in HBM.
-The JSON line reports flips/s (value) and effective Metropolis steps/s
-(sum of multiplicities per second), the HBM roofline of the dominant kernel
-(bytes of Q read per flip = N * sizeof(int16)), the VALU issue roofline of
-the same kernel (wave64 VALU instructions per chain step from its counter
-run), the same workload with Basic
-PNS subset 64 and in the plain one-launch-per-step form, and the CPU oracle
-timed on a bounded sample on this host.
+Default workload (``batched64_uneven_int16``): Unbiased PNS with systematic
+partial neighbor sets over 64 dense-stored int16 QUBOs of uneven size (N
+log-uniform in [256, 16384], half the entries zero, entries uniform on
+{-100..100}), 64 chains each (4096 chains), beta = 0.01 sqrt(2048 / N),
+subset sizes and tiles from the autotuner, in one context whose launch
+classes run concurrently, captured in a HIP graph.  One benchmark step runs
+every chain for ``--chain-steps`` sampler steps (default 100000, the full
+per-chain length), with all inputs resident in HBM.  The JSON line reports
+aggregate flips/s (value), effective Metropolis steps/s (sum of
+multiplicities per second), the HBM roofline of the dominant kernel (the
+launch class on the critical path: bytes of Q read per flip = N * 2 over its
+kernel time, from HIP events on that class's stream), the same for the
+problems with N >= 8192, every class's figures, the batched form against
+the plain one-launch-per-step form, the Unbiased PNS N = 8192 float32 and
+Rejection-Free N = 1024 int16 workloads as extra keys, and the CPU oracle
+timed on a bounded sample of the workload on one core and on every core.
 
-Other workloads (--workload): basic64_n1024_int16, unbiased_n8192_f32
-(Unbiased PNS, N = 8192 float32, 4096 chains), batched64_uneven_int16 (64
-problems of uneven N in one context), fit_n64_f32 / fit_n512_f32
+Other workloads (--workload): rf_n1024_int16, basic64_n1024_int16,
+unbiased_n8192_f32 (single-problem contexts), fit_n64_f32 / fit_n512_f32
 (maximum-likelihood fit through the MFMA moment kernel), donut_cont_f64
-(continuous Unbiased PNS, Alg 7, on the donut target of Sec 6).
+(continuous Unbiased PNS, Alg 7, on the donut target of Sec 7).
 """
 from __future__ import annotations
 
@@ -94,7 +97,7 @@ def _workload(name: str):
         cp = int(w.extra["chains_per"])
         probs = [{"Q": Q, "num_chains": cp, "beta": w.betas[i * cp:(i + 1) * cp], "subset_size": 0}
                  for i, Q in enumerate(w.Q)]
-        return dict(problems=probs, betas=w.betas, mode="unbiased_sys", n=0, L0=100, qbytes=2, steps=20_000,
+        return dict(problems=probs, betas=w.betas, mode="unbiased_sys", n=0, L0=100, qbytes=2, steps=w.steps,
                     desc=w.name, Ns=np.asarray(w.extra["Ns"]))
     if name == "donut_cont_f64":
         return dict(cont=True, dim=2, pairs=25, mu0=9.0, sigma=0.1, L0=1000, chains=65536, steps=4000,
@@ -203,11 +206,11 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
 def _bench_cont(args, wl):
-    """Continuous Unbiased PNS (Alg 7) on the donut target of Sec 6: d = 2,
+    """Continuous Unbiased PNS (Alg 7) on the donut target of Sec 7: d = 2,
     mu0 = 9, sigma = 0.1, 25 pairs (50 neighbours), L0 = 1000; 65536 chains
     from exact draws of the target.  One bench step runs every chain for
     --chain-steps records (default 4000).  Value: original (Metropolis-
-    equivalent) samples per second, the unit of the Sec 6 comparison."""
+    equivalent) samples per second, the unit of the Sec 7 comparison."""
     import torch
     from paper_2210_10513_amd import inputs
     from paper_2210_10513_amd.binding import ContSampler
@@ -272,46 +275,90 @@ def _bench_cont(args, wl):
     print(json.dumps(out))
 
 
-def _time_batch(wl, chain_steps: int, steps: int, warmup: int, launch: str, seed: int):
+def _class_rows(prof, sec_scale: float):
+    """Per-class figures from pns_profile_read: kernel time per launch, flips/s
+    and GB/s of algorithmic row bytes over that kernel time."""
+    rows = []
+    for k in prof:
+        ms = k["kernel_ms"] / max(1, k["launches"])
+        gbs = k["row_bytes"] / max(k["kernel_ms"], 1e-12) / 1e6
+        rows.append({"tile": f"{k['block']}x{k['groups']}", "flavour": k["flavour"], "chains": k["chains"],
+                     "N_min": k["N_min"], "N_max": k["N_max"], "launches": k["launches"],
+                     "kernel_avg_ms": ms, "flips_per_launch": k["flips"] / max(1, k["launches"]),
+                     "bytes_per_launch": k["row_bytes"] / max(1, k["launches"]),
+                     "flips_per_s": k["flips"] / max(k["kernel_ms"] * 1e-3, 1e-12), "GB_per_s": gbs,
+                     "hbm_frac": gbs / HBM_PEAK_GBS})
+    return rows
+
+
+def _time_batch(wl, chain_steps: int, steps: int, warmup: int, launch: str, seed: int, profile: bool = True):
     """Batched context over every problem of the workload (subset sizes and
-    tiles from the autotuner).  Returns (seconds per bench step, flips, Q
-    bytes streamed, records, sum M per bench step, problem infos)."""
+    tiles from the autotuner).  The K timed steps in the requested launch
+    form are bracketed by HIP events on the context's stream.  With
+    `profile`, K further steps run with per-class timing (pns_profile: HIP
+    events on each launch class's own stream; a graph context queues the
+    same launches directly while profiling).  Returns a dict of figures."""
     import torch
+    from paper_2210_10513_amd import binding as bd
     from paper_2210_10513_amd.binding import BatchSampler
     stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
     s = BatchSampler(wl["problems"], wl["mode"], L0=wl["L0"], seed=seed, launch=launch, stream=stream)
+    setup = time.perf_counter() - t0
+    C = s.num_chains
     nbits = np.concatenate([np.full(i.num_chains, i.N) for i in s.info]).astype(np.float64)
+
+    def timed():
+        st0 = s.stats()
+        torch.cuda.synchronize()
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        t_start.record(stream)
+        for _ in range(steps):
+            s.run(chain_steps)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        st1 = s.stats()
+        d = {k: (st1[k] - st0[k]).astype(np.float64) / steps for k in ("flips", "steps", "sum_M")}
+        return t_start.elapsed_time(t_end) / 1000.0 / steps, d
+
     for _ in range(warmup):
         s.run(chain_steps)
     s.sync()
-    st0 = s.stats()
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    t_start.record(stream)
-    for _ in range(steps):
-        s.run(chain_steps)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    ms = t_start.elapsed_time(t_end)
-    st1 = s.stats()
-    info = [(i.N, i.subset_size, i.block, i.groups, i.flavour) for i in s.info]
+    sec, d = timed()
+    out = {"sec": sec, "flips": float(d["flips"].sum()), "qbytes": float((d["flips"] * nbits).sum()) * wl["qbytes"],
+           "records": float(d["steps"].sum()), "sum_M": float(d["sum_M"].sum()), "setup_s": setup,
+           "info": [(i.N, i.subset_size, i.block, i.groups, i.flavour) for i in s.info], "chain_N": nbits,
+           "chain_class": bd.pns_class_of_chain(s.ctx, C), "prof": None}
+    if profile:
+        bd.pns_profile(s.ctx, True)
+        psec, pd = timed()
+        out["prof"] = bd.pns_profile_read(s.ctx)
+        bd.pns_profile(s.ctx, False)
+        out["prof_sec"] = psec
+        out["prof_dflips"] = pd["flips"]
     s.close()
-    dflips = (st1["flips"] - st0["flips"]).astype(np.float64)
-    flips = float(dflips.sum()) / steps
-    qbytes = float((dflips * nbits).sum()) * wl["qbytes"] / steps
-    recs = float((st1["steps"] - st0["steps"]).sum()) / steps
-    summ = float((st1["sum_M"] - st0["sum_M"]).sum()) / steps
-    return ms / 1000.0 / steps, flips, qbytes, recs, summ, info
+    return out
 
 
-def _bench_batch(args, wl):
+def _bench_batch(args, wl, cpu_spec=None):
     chain_steps = args.chain_steps or wl["steps"]
     launch = args.launch if args.launch != "persistent" else "graph"
-    t0 = time.perf_counter()
-    sec, flips, qb, recs, summ, info = _time_batch(wl, chain_steps, args.steps, args.warmup, launch, seed=1)
-    setup = time.perf_counter() - t0
-    achieved = qb / sec / 1e9
+    r = _time_batch(wl, chain_steps, args.steps, args.warmup, launch, seed=1)
+    sec, flips, info = r["sec"], r["flips"], r["info"]
+    achieved_all = r["qbytes"] / sec / 1e9
+    classes = _class_rows(r["prof"], 1.0)
+    # the dominant kernel: the launch class with the longest kernel time (the
+    # critical path of the concurrently running classes)
+    dom = max(range(len(classes)), key=lambda i: classes[i]["kernel_avg_ms"])
+    dk = classes[dom]
+    # problems with N >= 8192: their flips' row bytes over the longest kernel
+    # time among the classes that hold them (a lower bound on their own rate)
+    big = r["chain_N"] >= 8192
+    big_cls = sorted({int(c) for c in r["chain_class"][big]})
+    big_ms = max(classes[i]["kernel_avg_ms"] for i in big_cls) if big_cls else 0.0
+    big_bytes = float((r["prof_dflips"][big] * r["chain_N"][big]).sum()) * wl["qbytes"]
+    big_gbs = big_bytes / (big_ms * 1e-3) / 1e9 if big_ms else 0.0
     out = {
         "metric": "flips/s", "value": flips / sec, "unit": "flips/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": sec * 1000.0, "higher_is_better": True, "scaling": "weak",
@@ -320,23 +367,63 @@ def _bench_batch(args, wl):
                    "N_min": int(min(i[0] for i in info)), "N_max": int(max(i[0] for i in info)),
                    "mode": wl["mode"], "subset": "autotuned", "chain_steps_per_step": chain_steps, "launch": launch,
                    "subset_sizes": [int(i[1]) for i in info], "tiles": sorted({f"{i[2]}x{i[3]}" for i in info})},
-        "effective_mh_steps_per_s": summ / sec,
-        "records_per_s": recs / sec,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_flip": "N_p * 2 for the flipping chain's problem", "kernel": "step_kernel (all classes)",
-                     "kernel_avg_ms": sec * 1000.0},
-        "setup_s": setup,
+        "effective_mh_steps_per_s": r["sum_M"] / sec,
+        "records_per_s": r["records"] / sec,
+        "roofline": {"bound": "hbm", "achieved": dk["GB_per_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dk["hbm_frac"],
+                     "traffic": _measured_traffic(f"batched64_class_{dk['tile']}_f{dk['flavour']}", chain_steps),
+                     "bytes_per_flip": "N * 2 of the flipping chain's problem",
+                     "kernel": f"step_kernel<short, int, {dk['tile'].replace('x', ', ')}, {dk['flavour']}, false> "
+                               f"(launch class N {dk['N_min']}..{dk['N_max']}, {dk['chains']} chains)",
+                     "kernel_avg_ms": dk["kernel_avg_ms"], "bytes_per_launch": dk["bytes_per_launch"],
+                     "timing": f"HIP events on the class's stream over {args.steps} further timed steps with the "
+                               f"graph's launches queued directly (step {r['prof_sec'] * 1e3:.1f} ms vs "
+                               f"{sec * 1e3:.1f} ms in the graph form)"},
+        "n_ge_8192": {"problems": int(sum(1 for i in info if i[0] >= 8192)), "chains": int(big.sum()),
+                      "flips_per_s": float(r["prof_dflips"][big].sum()) / (big_ms * 1e-3) if big_ms else 0.0,
+                      "GB_per_s": big_gbs, "hbm_frac": big_gbs / HBM_PEAK_GBS, "kernel_ms": big_ms,
+                      "classes": [classes[i]["tile"] + "/f" + str(classes[i]["flavour"]) for i in big_cls]},
+        "whole_batch": {"GB_per_s": achieved_all, "hbm_frac": achieved_all / HBM_PEAK_GBS,
+                        "note": "all classes' row bytes over the step time (classes overlap)"},
+        "classes": classes,
+        "setup_s": r["setup_s"],
     }
     if not args.no_extras:
-        sp, fp, qp, _, _, _ = _time_batch(wl, 100, 1, 1, "plain", seed=3)
-        out["variants"] = {"plain_launch_flips_per_s": fp / sp, "batched_over_plain": (flips / sec) / (fp / sp)}
+        p = _time_batch(wl, 100, 1, 1, "plain", seed=3, profile=False)
+        out["variants"] = {"plain_launch_flips_per_s": p["flips"] / p["sec"],
+                           "batched_over_plain": (flips / sec) / (p["flips"] / p["sec"])}
+        out["extra_workloads"] = {name: _single_summary(name, args) for name in
+                                  ("unbiased_n8192_f32", "rf_n1024_int16")}
+    if cpu_spec is not None:
+        out["cpu_baseline"] = _cpu_baseline(dict(cpu_spec, subsets=[int(i[1]) for i in info]))
     print(json.dumps(out))
 
 
-def _time_sampler(wl, chain_steps: int, steps: int, warmup: int, launch: str, seed: int, tile=(0, 0)):
-    """Returns (seconds per bench step, flips per bench step, sum M per bench step)."""
+def _single_summary(name, args):
+    """One single-problem workload at its full per-chain length: flips/s,
+    effective MH steps/s and the HBM roofline of its step kernel (kernel time
+    from HIP events on the context's stream)."""
+    wl = _workload(name)
+    r = _time_sampler(wl, wl["steps"], 2, 1, "persistent", seed=1, profile=True)
+    sec, flips, recs, summ, _, tile, prof = r
+    k = _class_rows(prof, 1.0)[0]
+    out = {"config": {"workload": wl["desc"], "N": int(wl["Q"].shape[0]), "chains": int(len(wl["betas"])),
+                      "mode": wl["mode"], "subset": int(wl["n"] or wl["Q"].shape[0]),
+                      "chain_steps_per_step": wl["steps"], "tile": list(tile)},
+           "flips_per_s": flips / sec, "effective_mh_steps_per_s": summ / sec, "records_per_s": recs / sec,
+           "roofline": {"bound": "hbm", "achieved": k["GB_per_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": k["hbm_frac"], "traffic": _measured_traffic(name, wl["steps"]),
+                        "bytes_per_flip": int(wl["Q"].shape[0] * wl["qbytes"]), "kernel_avg_ms": k["kernel_avg_ms"],
+                        "bytes_per_launch": k["bytes_per_launch"]}}
+    return out
+
+
+def _time_sampler(wl, chain_steps: int, steps: int, warmup: int, launch: str, seed: int, tile=(0, 0),
+                  profile: bool = False):
+    """Returns (seconds per bench step, flips, records and sum M per bench
+    step, wall seconds, tile, per-class kernel timing or None)."""
     import torch
+    from paper_2210_10513_amd import binding as bd
     from paper_2210_10513_amd.binding import Sampler
     stream = torch.cuda.current_stream()
     s = Sampler(wl["Q"], wl["betas"], wl["n"], wl["mode"], num_chains=len(wl["betas"]), L0=wl["L0"], seed=seed,
@@ -344,6 +431,8 @@ def _time_sampler(wl, chain_steps: int, steps: int, warmup: int, launch: str, se
     for _ in range(warmup):
         s.run(chain_steps)
     s.sync()
+    if profile:
+        bd.pns_profile(s.ctx, True)
     st0 = s.stats()
     torch.cuda.synchronize()
     t_start = torch.cuda.Event(enable_timing=True)
@@ -358,41 +447,148 @@ def _time_sampler(wl, chain_steps: int, steps: int, warmup: int, launch: str, se
     ms = t_start.elapsed_time(t_end)
     st1 = s.stats()
     tile = s.tile()
+    prof = bd.pns_profile_read(s.ctx) if profile else None
     s.close()
     flips = float((st1["flips"] - st0["flips"]).sum()) / steps
     recs = float((st1["steps"] - st0["steps"]).sum()) / steps
     summ = float((st1["sum_M"] - st0["sum_M"]).sum()) / steps
-    return ms / 1000.0 / steps, flips, recs, summ, wall, tile
+    return ms / 1000.0 / steps, flips, recs, summ, wall, tile, prof
 
 
-def _cpu_baseline(wl, budget_s: float = 15.0):
+def _cpu_model() -> str:
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_cores() -> int:
+    """Cores this process may use, at most 16 (a one-GPU machine's CPU share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _cpu_tasks(spec):
+    """The oracle sample of a workload: (Q as int64/float64, beta, mode, n,
+    L0, chain id) per chain.  Batched: one chain of each of 8 problems spread
+    evenly over the sizes (smallest and largest included), with the subset
+    size the GPU context ran; single problems: 4 chains."""
     import oracle
-    Q = wl["Q"].astype(np.int64) if np.issubdtype(wl["Q"].dtype, np.integer) else wl["Q"].astype(np.float64)
     modes = {"rf": oracle.MODE_RF, "basic": oracle.MODE_BASIC, "unbiased_sys": oracle.MODE_UNBIASED_SYS}
-    chains = 4
-    # calibrate on a short run, then size the sample to the budget
-    K = 200
+    tasks = []
+    if spec["workload"] == "batched64_uneven_int16":
+        from paper_2210_10513_amd import inputs
+        Ns = inputs.c4_batched(only=()).extra["Ns"]
+        order = np.argsort(Ns, kind="stable")
+        pick = [int(order[j]) for j in np.linspace(0, len(order) - 1, 8).round().astype(int)]
+        w = inputs.c4_batched(only=pick)
+        cp = int(w.extra["chains_per"])
+        for i in pick:
+            cid = i * cp
+            tasks.append((w.Q[i].astype(np.int64), float(w.betas[cid]), modes[w.mode], int(spec["subsets"][i]), w.L0,
+                          cid))
+    else:
+        wl = _workload(spec["workload"])
+        Q = wl["Q"].astype(np.int64) if np.issubdtype(wl["Q"].dtype, np.integer) else wl["Q"].astype(np.float64)
+        for c in range(4):
+            tasks.append((Q, float(wl["betas"][c]), modes[wl["mode"]], int(wl["n"]), wl["L0"], c))
+    return tasks
+
+
+def _cpu_run(tasks, K, offset=0):
+    import oracle
+    flips = 0
+    for Q, beta, mode, n, L0, cid in tasks:
+        r = oracle.run(Q, beta, mode, K, n=n, L0=L0, seed=1, num_chains=1,
+                       chain_ids=np.array([cid + offset], np.uint32), log=False)
+        flips += int(r.flips.sum())
+    return flips
+
+
+_CPU_TASKS = None  # the sample, inherited by the forked workers (not pickled)
+
+
+def _cpu_worker(args):
+    K, offset = args
+    return _cpu_run(_CPU_TASKS, K, offset)
+
+
+def _cpu_baseline_child(spec) -> dict:
+    """The single-threaded FP64/int64 oracle on a bounded sample of the
+    workload: one core, then one process per core with the chains split
+    between them (each process runs the same sample with its own chain ids).
+    Runs in a process that never touches the GPU."""
+    import multiprocessing as mp
+    global _CPU_TASKS
+    tasks = _cpu_tasks(spec)
+    _CPU_TASKS = tasks
+    budget = float(spec.get("budget_s", 12.0))
+    # a run costs a fixed part (fields of the initial state, O(N^2)) plus a
+    # part per step: time two lengths and size the sample to the budget
+    _cpu_run(tasks, 10)  # first call: library load and page faults
     t0 = time.perf_counter()
-    oracle.run(Q, wl["betas"][:chains], modes[wl["mode"]], K, n=wl["n"], L0=wl["L0"], seed=1, num_chains=chains,
-               log=False)
-    dt = time.perf_counter() - t0
-    K = max(200, int(K * budget_s / max(dt, 1e-6)))
+    _cpu_run(tasks, 20)
+    t1 = time.perf_counter()
+    _cpu_run(tasks, 60)
+    t2 = time.perf_counter()
+    per_step = max((t2 - t1) - (t1 - t0), 1e-9) / 40
+    fixed = max(0.0, (t1 - t0) - 20 * per_step)
+    K = max(20, int((budget - fixed) / per_step))
     t0 = time.perf_counter()
-    r = oracle.run(Q, wl["betas"][:chains], modes[wl["mode"]], K, n=wl["n"], L0=wl["L0"], seed=1,
-                   num_chains=chains, log=False)
+    flips = _cpu_run(tasks, K)
     dt = time.perf_counter() - t0
-    flips = float(r.flips.sum())
-    return {"value": flips / dt, "unit": "flips/s", "cores": 1, "kind": "oracle",
-            "sample": f"{chains} chains x {K} steps of the same workload, single-threaded FP64/int64 oracle "
-                      f"({dt:.1f} s)"}
+    cores = _cpu_cores()
+    Ns = sorted({int(t[0].shape[0]) for t in tasks})
+    sample = (f"{len(tasks)} chains (N = {', '.join(map(str, Ns))}) x {K} steps of the workload, single-threaded "
+              f"FP64/int64 oracle ({dt:.1f} s)")
+    out = {"value": flips / dt, "unit": "flips/s", "cores": 1, "kind": "oracle", "sample": sample,
+           "cpu_model": _cpu_model()}
+    if cores > 1:
+        ctx = mp.get_context("fork")
+        t0 = time.perf_counter()
+        with ctx.Pool(cores) as pool:
+            res = pool.map(_cpu_worker, [(K, 1_000_000 * (w + 1)) for w in range(cores)], chunksize=1)
+        wall = time.perf_counter() - t0
+        out["all_cores"] = {"value": float(sum(res)) / wall, "unit": "flips/s", "cores": cores, "kind": "oracle",
+                            "sample": f"{cores} processes, each the sample above with its own chain ids "
+                                      f"({wall:.1f} s wall)"}
+    return out
+
+
+def _cpu_baseline(spec) -> dict:
+    """Run _cpu_baseline_child in a child process (this process holds the GPU)."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline", json.dumps(spec)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-2000:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--cpu-baseline":
+        # child process of _cpu_baseline: CPU only, never touches the GPU
+        print(json.dumps(_cpu_baseline_child(json.loads(sys.argv[2]))))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rf_n1024_int16")
+    ap.add_argument("--workload", default="batched64_uneven_int16")
     ap.add_argument("--chain-steps", type=int, default=0, help="sampler steps per chain per bench step (0 = workload)")
     ap.add_argument("--launch", default="persistent")
     ap.add_argument("--tile", default="", help="workgroup size and 4-field groups per lane, e.g. 64,4")
@@ -429,17 +625,17 @@ def main():
         _bench_fit(args, wl)
         return
     if "problems" in wl:
-        _bench_batch(args, wl)
+        _bench_batch(args, wl, cpu_spec=None if args.no_cpu else {"workload": args.workload})
         return
     chain_steps = args.chain_steps or wl["steps"]
     C = len(wl["betas"])
     N = wl["Q"].shape[0]
     tile_req = tuple(int(v) for v in args.tile.split(",")) if args.tile else (0, 0)
-    sec, flips, recs, summ, wall, tile = _time_sampler(wl, chain_steps, args.steps, args.warmup, args.launch, seed=1,
-                                                       tile=tile_req)
+    sec, flips, recs, summ, wall, tile, prof = _time_sampler(wl, chain_steps, args.steps, args.warmup, args.launch,
+                                                             seed=1, tile=tile_req, profile=True)
+    k = _class_rows(prof, 1.0)[0]
     value = flips / sec
     bytes_per_flip = N * wl["qbytes"]
-    achieved = flips * bytes_per_flip / sec / 1e9
     out = {
         "metric": "flips/s",
         "value": value,
@@ -458,11 +654,12 @@ def main():
                    "tile": list(tile)},
         "effective_mh_steps_per_s": summ / sec,
         "records_per_s": recs / sec,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "achieved": k["GB_per_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": k["hbm_frac"],
                      "traffic": _measured_traffic(args.workload, chain_steps) if args.steps >= 1 else None,
                      "bytes_per_flip": bytes_per_flip, "kernel": "step_kernel",
-                     "kernel_avg_ms": sec * 1000.0},
+                     "kernel_avg_ms": k["kernel_avg_ms"], "bytes_per_launch": k["bytes_per_launch"],
+                     "timing": "HIP events on the context's stream, every timed step"},
     }
     vps = _valu_per_chain_step(args.workload, tile)
     if vps is not None:
@@ -473,15 +670,15 @@ def main():
     if not args.no_extras and args.workload == "rf_n1024_int16":
         extras = {}
         wb = _workload("basic64_n1024_int16")
-        s2, f2, r2, m2, _, t2 = _time_sampler(wb, chain_steps // 4, 1, 1, "persistent", seed=2)
+        s2, f2, r2, m2, _, t2, _ = _time_sampler(wb, chain_steps // 4, 1, 1, "persistent", seed=2)
         extras["basic64_flips_per_s"] = f2 / s2
         extras["basic64_effective_mh_steps_per_s"] = m2 / s2
-        sp, fp, rp, mp, _, _ = _time_sampler(wl, 200, 1, 1, "plain", seed=3)
+        sp, fp, rp, mp, _, _, _ = _time_sampler(wl, 200, 1, 1, "plain", seed=3)
         extras["plain_launch_flips_per_s"] = fp / sp
         extras["persistent_over_plain"] = value / (fp / sp)
         out["variants"] = extras
     if not args.no_cpu:
-        out["cpu_baseline"] = _cpu_baseline(wl)
+        out["cpu_baseline"] = _cpu_baseline({"workload": args.workload})
     print(json.dumps(out))
 
 

@@ -408,6 +408,43 @@ int pns_read_betas(pns_ctx* ctx, double* betas);
  * (0..temps-1) at temperature position t.  Errors: PNS_EINVAL (no swap yet). */
 int pns_read_ladder(pns_ctx* ctx, int32_t* ladder);
 
+/* ---- kernel timing per launch class ----
+ *
+ * The chains of a context are grouped into launch classes (same tile and
+ * kernel flavour); a batch's classes run concurrently on their own streams.
+ * With profiling on, every pns_run records a HIP event before the first and
+ * after the last launch of each class on that class's stream and adds their
+ * elapsed time.  Events inside a replayed graph cannot be timed, so a
+ * context of the graph form queues the same launches directly while
+ * profiling is on.  Profiling waits at the start of each pns_run for the
+ * previous run's events (one host synchronisation per run). */
+typedef struct pns_class_profile {
+    int32_t block, groups;  /* tile of the class                               */
+    int32_t flavour;        /* as pns_problem_info.flavour                     */
+    int32_t chains;         /* chains of the class                             */
+    int32_t N_min, N_max;   /* smallest and largest problem of the class       */
+    int64_t launches;       /* kernel launches timed                           */
+    double kernel_ms;       /* summed event time of the class's launches       */
+    int64_t flips;          /* flips of the class's chains while profiling     */
+    int64_t records;        /* records (steps) of the class's chains           */
+    double row_bytes;       /* algorithmic bytes: one row of the flipped bit's
+                               problem per flip, N * sizeof(Q element)         */
+} pns_class_profile;
+
+/* enable = 1 starts (and resets) per-class timing and counting, 0 stops it.
+ * Synchronises the context's stream.  Errors: PNS_EINVAL (NULL ctx),
+ * PNS_EDEVICE. */
+int pns_profile(pns_ctx* ctx, int32_t enable);
+
+/* *count = number of launch classes; with out != NULL (capacity entries)
+ * fills one pns_class_profile per class, in class order.  Synchronises.
+ * Errors: PNS_EINVAL (NULL ctx or count, capacity too small, profiling never
+ * started), PNS_EDEVICE. */
+int pns_profile_read(pns_ctx* ctx, pns_class_profile* out, int32_t capacity, int32_t* count);
+
+/* Launch class of every chain: cls [num_chains] (host). */
+int pns_class_of_chain(const pns_ctx* ctx, int32_t* cls);
+
 /* ---- checkpoints (resume) ----
  *
  * Every draw of a step is keyed by (seed, chain id, step), so a chain

@@ -43,7 +43,17 @@ EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_cu
            "pns_adopt_best", "pns_run_original", "pns_pt_swap", "pns_read_betas", "pns_read_ladder",
            "pns_moments_f64", "pns_read_rb_weights", "pns_snapshot_moments_rb", "pns_cont_opts_default",
            "pns_cont_create", "pns_cont_run", "pns_cont_read", "pns_cont_read_log", "pns_cont_read_sums",
-           "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy", "pns_save", "pns_load"]
+           "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy", "pns_save", "pns_load", "pns_profile",
+           "pns_profile_read", "pns_class_of_chain"]
+
+
+class pns_class_profile(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_int32), ("groups", ctypes.c_int32), ("flavour", ctypes.c_int32),
+        ("chains", ctypes.c_int32), ("N_min", ctypes.c_int32), ("N_max", ctypes.c_int32),
+        ("launches", ctypes.c_int64), ("kernel_ms", ctypes.c_double), ("flips", ctypes.c_int64),
+        ("records", ctypes.c_int64), ("row_bytes", ctypes.c_double),
+    ]
 
 
 class pns_opts(ctypes.Structure):
@@ -144,6 +154,9 @@ def _load() -> ctypes.CDLL:
     L.pns_pt_swap.argtypes = [vp, i32, i64, vp]
     L.pns_read_betas.argtypes = [vp, vp]
     L.pns_read_ladder.argtypes = [vp, vp]
+    L.pns_profile.argtypes = [vp, i32]
+    L.pns_profile_read.argtypes = [vp, ctypes.POINTER(pns_class_profile), i32, ctypes.POINTER(i32)]
+    L.pns_class_of_chain.argtypes = [vp, vp]
     L.pns_save.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
     L.pns_load.argtypes = [vp, vp, i64]
     L.pns_moments_f64.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
@@ -168,7 +181,7 @@ def _load() -> ctypes.CDLL:
                  "pns_pt_swap", "pns_read_betas", "pns_read_ladder", "pns_moments_f64", "pns_read_rb_weights",
                  "pns_snapshot_moments_rb", "pns_cont_create", "pns_cont_run", "pns_cont_read", "pns_cont_read_log",
                  "pns_cont_read_sums", "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy",
-                 "pns_save", "pns_load"):
+                 "pns_save", "pns_load", "pns_profile", "pns_profile_read", "pns_class_of_chain"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -399,6 +412,27 @@ def pns_read_betas(ctx, betas) -> None:
 
 def pns_read_ladder(ctx, ladder) -> None:
     _check(lib.pns_read_ladder(ctx, _addr(ladder)))
+
+
+def pns_profile(ctx, enable: bool = True) -> None:
+    _check(lib.pns_profile(ctx, 1 if enable else 0))
+
+
+def pns_profile_read(ctx):
+    """Per launch class: tile, flavour, chains, N range, launches, summed
+    kernel time (HIP events on the class's stream), flips, records and
+    algorithmic row bytes since pns_profile."""
+    n = ctypes.c_int32(0)
+    _check(lib.pns_profile_read(ctx, None, 0, ctypes.byref(n)))
+    arr = (pns_class_profile * max(1, n.value))()
+    _check(lib.pns_profile_read(ctx, arr, n.value, ctypes.byref(n)))
+    return [{f: getattr(arr[i], f) for f, _ in pns_class_profile._fields_} for i in range(n.value)]
+
+
+def pns_class_of_chain(ctx, num_chains: int) -> np.ndarray:
+    out = np.zeros(num_chains, np.int32)
+    _check(lib.pns_class_of_chain(ctx, out.ctypes.data))
+    return out
 
 
 def pns_save(ctx, buf=None) -> int:

@@ -424,6 +424,16 @@ struct pns_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int64_t graph_steps = -1;
+    // kernel timing per launch class (pns_profile): a start and a stop event
+    // per class bracket its launches of one pns_run on the class's stream
+    bool prof_on = false;
+    bool prof_active = false;               // inside pns_run: its launches are timed
+    bool prof_pending = false;
+    std::vector<hipEvent_t> prof_ev;       // [2 * classes]
+    std::vector<double> prof_ms;           // [classes] summed kernel time
+    std::vector<int64_t> prof_launches;    // [classes]
+    std::vector<int64_t> prof_runs_now;    // [classes] launches queued in the pending run
+    std::vector<int64_t> prof_base;        // counters [C][6] when profiling started
 
     bool instrumented() const { return log_cap > 0 || hist_w != nullptr || snap_every > 0; }
 
@@ -475,7 +485,34 @@ struct pns_ctx {
         return a;
     }
 
-    int launch_class(const LaunchClass& k, int64_t steps, hipStream_t st, int64_t orig_time = 0)
+    // Index of k in `classes`, or -1 (optimization classes are not profiled).
+    int class_index(const LaunchClass& k) const
+    {
+        if (classes.empty() || &k < &classes.front() || &k > &classes.back()) return -1;
+        return (int)(&k - &classes.front());
+    }
+
+    hipError_t prof_record(int ki, int which, hipStream_t st) { return hipEventRecord(prof_ev[2 * ki + which], st); }
+
+    // Add the kernel time of the pending run (waits for it).
+    int prof_collect()
+    {
+        if (!prof_pending) return PNS_OK;
+        for (size_t ki = 0; ki < classes.size(); ++ki) {
+            if (prof_runs_now[ki] == 0) continue;
+            HIP_TRY(hipEventSynchronize(prof_ev[2 * ki + 1]), "profile event wait");
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, prof_ev[2 * ki], prof_ev[2 * ki + 1]), "profile event time");
+            prof_ms[ki] += ms;
+            prof_launches[ki] += prof_runs_now[ki];
+            prof_runs_now[ki] = 0;
+        }
+        prof_pending = false;
+        return PNS_OK;
+    }
+
+    int launch_class(const LaunchClass& k, int64_t steps, hipStream_t st, int64_t orig_time = 0, bool first = true,
+                     bool last = true)
     {
         // host-side check that the launch matches what the kernels assume
         for (int32_t c : {k.chains.front(), k.chains.back()}) {
@@ -486,22 +523,28 @@ struct pns_ctx {
         StepArgs a = args(steps);
         a.orig_time = orig_time;
         if (classes.size() > 1 || (int32_t)k.chains.size() != num_chains) a.chain_list = k.d_list;
+        const int ki = prof_on && prof_active ? class_index(k) : -1;
+        if (ki >= 0 && first) HIP_TRY(prof_record(ki, 0, st), "profile start event");
         hipError_t e = launch_steps(qtype, htype, k.flav, instrumented(), k.tile.block, k.tile.groups,
                                     (int32_t)k.chains.size(), k.dyn, st, a);
         if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+        if (ki >= 0) {
+            ++prof_runs_now[ki];
+            if (last) HIP_TRY(prof_record(ki, 1, st), "profile stop event");
+        }
         return PNS_OK;
     }
 
     // One chunk of `steps` steps for every chain: one launch per class; with
     // several classes they run on their own streams between a fork and a join.
-    int launch_chunk(int64_t steps, int64_t orig_time = 0)
+    int launch_chunk(int64_t steps, int64_t orig_time = 0, bool first = true, bool last = true)
     {
-        if (classes.size() == 1) return launch_class(classes[0], steps, stream, orig_time);
+        if (classes.size() == 1) return launch_class(classes[0], steps, stream, orig_time, first, last);
         HIP_TRY(hipEventRecord(fork, stream), "fork record");
         for (auto& sd : sides) {
             HIP_TRY(hipStreamWaitEvent(sd.stream, fork, 0), "fork wait");
             for (int32_t ki : sd.classes) {
-                int rc = launch_class(classes[ki], steps, sd.stream, orig_time);
+                int rc = launch_class(classes[ki], steps, sd.stream, orig_time, first, last);
                 if (rc) return rc;
             }
             HIP_TRY(hipEventRecord(sd.done, sd.stream), "join record");
@@ -514,6 +557,8 @@ struct pns_ctx {
     {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t ev : prof_ev)
+            if (ev) (void)hipEventDestroy(ev);
         void* ptrs[] = {problems, chain_problem, foff, beta, chain_id, x, h, rmem, E, L, sub, step, last_action, last_M,
                         last_E, counters, log_action, log_M, log_E, log_p, log_w, hist_w, hist_v, hist_rb,
                         snap_x, snap_M, snap_E, snap_w, snap_count};
@@ -1231,23 +1276,52 @@ int pns_autotune(const void* Q, int32_t N, double beta, int32_t subset_size, int
     return autotune_impl(S, mode, o, trial_steps, out);
 }
 
+}  // extern "C"
+
+namespace {
+
+int run_impl(pns_ctx* ctx, int64_t steps);
+
+}  // namespace
+
+extern "C" {
+
 int pns_run(pns_ctx* ctx, int64_t steps)
 {
     g_error.clear();
     if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
     if (steps < 0) return fail(PNS_EINVAL, "steps must be >= 0");
     if (steps == 0) return PNS_OK;
+    if (ctx->prof_on) {
+        int rc = ctx->prof_collect();
+        if (rc) return rc;
+        ctx->prof_pending = true;
+    }
+    ctx->prof_active = ctx->prof_on;
+    const int rc = run_impl(ctx, steps);
+    ctx->prof_active = false;
+    return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+int run_impl(pns_ctx* ctx, int64_t steps)
+{
     if (ctx->launch == PNS_LAUNCH_PLAIN) {
         for (int64_t s = 0; s < steps; ++s) {
-            int rc = ctx->launch_chunk(1);
+            int rc = ctx->launch_chunk(1, 0, s == 0, s == steps - 1);
             if (rc) return rc;
         }
         return PNS_OK;
     }
     const int64_t chunk = ctx->chunk > 0 ? std::min<int64_t>(ctx->chunk, steps) : steps;
-    if (ctx->launch == PNS_LAUNCH_PERSISTENT) {
+    // with profiling on, the graph form queues its launches directly: events
+    // on the class streams cannot be timed inside a replayed graph here
+    if (ctx->launch == PNS_LAUNCH_PERSISTENT || (ctx->launch == PNS_LAUNCH_GRAPH && ctx->prof_on)) {
         for (int64_t done = 0; done < steps; done += chunk) {
-            int rc = ctx->launch_chunk(std::min(chunk, steps - done));
+            int rc = ctx->launch_chunk(std::min(chunk, steps - done), 0, done == 0, done + chunk >= steps);
             if (rc) return rc;
         }
         return PNS_OK;
@@ -1261,7 +1335,8 @@ int pns_run(pns_ctx* ctx, int64_t steps)
         ctx->graph_steps = -1;
         HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "begin capture");
         int rc = PNS_OK;
-        for (int64_t done = 0; done < steps && rc == PNS_OK; done += chunk) rc = ctx->launch_chunk(std::min(chunk, steps - done));
+        for (int64_t done = 0; done < steps && rc == PNS_OK; done += chunk)
+            rc = ctx->launch_chunk(std::min(chunk, steps - done), 0, done == 0, done + chunk >= steps);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->stream, &g);
         if (rc) {
@@ -1274,6 +1349,78 @@ int pns_run(pns_ctx* ctx, int64_t steps)
         ctx->graph_steps = steps;
     }
     HIP_TRY(hipGraphLaunch(ctx->graph_exec, ctx->stream), "graph launch");
+    return PNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pns_profile(pns_ctx* ctx, int32_t enable)
+{
+    g_error.clear();
+    if (!ctx) return fail(PNS_EINVAL, "ctx is NULL");
+    int rc = pns_sync(ctx);
+    if (rc) return rc;
+    const size_t K = ctx->classes.size();
+    if (ctx->prof_ev.empty()) {
+        ctx->prof_ev.assign(2 * K, nullptr);
+        for (auto& ev : ctx->prof_ev) HIP_TRY(hipEventCreate(&ev), "profile event create");
+    }
+    ctx->prof_on = enable != 0;
+    ctx->prof_pending = false;
+    ctx->prof_ms.assign(K, 0.0);
+    ctx->prof_launches.assign(K, 0);
+    ctx->prof_runs_now.assign(K, 0);
+    if ((rc = d2h(ctx->prof_base, ctx->counters, (size_t)ctx->num_chains * 6))) return rc;
+    return PNS_OK;
+}
+
+int pns_profile_read(pns_ctx* ctx, pns_class_profile* out, int32_t capacity, int32_t* count)
+{
+    g_error.clear();
+    if (!ctx || !count) return fail(PNS_EINVAL, "NULL argument");
+    const int32_t K = (int32_t)ctx->classes.size();
+    *count = K;
+    if (!out) return PNS_OK;
+    if (capacity < K) return fail(PNS_EINVAL, "%d launch classes, capacity %d", K, capacity);
+    if (ctx->prof_base.empty()) return fail(PNS_EINVAL, "profiling was never started (pns_profile)");
+    int rc = pns_sync(ctx);
+    if (rc) return rc;
+    if ((rc = ctx->prof_collect())) return rc;
+    std::vector<int64_t> cnt;
+    if ((rc = d2h(cnt, ctx->counters, (size_t)ctx->num_chains * 6))) return rc;
+    for (int32_t ki = 0; ki < K; ++ki) {
+        const LaunchClass& k = ctx->classes[ki];
+        pns_class_profile p{};
+        p.block = k.tile.block;
+        p.groups = k.tile.groups;
+        p.flavour = k.flav;
+        p.chains = (int32_t)k.chains.size();
+        p.N_min = INT32_MAX;
+        p.N_max = 0;
+        for (int32_t c : k.chains) {
+            const ProblemRun& P = ctx->probs[ctx->h_chain_problem[c]];
+            p.N_min = std::min(p.N_min, P.N);
+            p.N_max = std::max(p.N_max, P.N);
+            const int64_t fl = cnt[(size_t)c * 6 + 1] - ctx->prof_base[(size_t)c * 6 + 1];
+            p.flips += fl;
+            p.records += cnt[(size_t)c * 6 + 0] - ctx->prof_base[(size_t)c * 6 + 0];
+            p.row_bytes += (double)fl * (double)P.N * (double)qsize(ctx->qtype);
+        }
+        p.launches = ctx->prof_launches[ki];
+        p.kernel_ms = ctx->prof_ms[ki];
+        out[ki] = p;
+    }
+    return PNS_OK;
+}
+
+int pns_class_of_chain(const pns_ctx* ctx, int32_t* cls)
+{
+    g_error.clear();
+    if (!ctx || !cls) return fail(PNS_EINVAL, "NULL argument");
+    for (size_t ki = 0; ki < ctx->classes.size(); ++ki)
+        for (int32_t c : ctx->classes[ki].chains) cls[c] = (int32_t)ki;
     return PNS_OK;
 }
 

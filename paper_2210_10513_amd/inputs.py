@@ -114,14 +114,15 @@ def c3_unbiased_n8192(seed: int | None = None, replicas: int = 256, temps: int =
     return Workload("unbiased_n8192_f32", Q, betas, "unbiased_sys", 512, 100_000)
 
 
-def c4_batched(seed: int | None = None, problems: int = 64, chains_per: int = 64) -> Workload:
+def c4_batched(seed: int | None = None, problems: int = 64, chains_per: int = 64, only=None) -> Workload:
     """64 int16 QUBOs of uneven N, log-uniform in [256, 16384], entries
     U{-100..100} kept with probability 1/2, 64 chains each, beta scaled as
-    0.01 * sqrt(2048 / N) so that beta * std(local field) stays comparable."""
+    0.01 * sqrt(2048 / N) so that beta * std(local field) stays comparable.
+    ``only``: generate just these problems' matrices (the others are None)."""
     rng = _rng(4, seed)
     Ns = np.rint(np.exp(rng.uniform(np.log(256), np.log(16384), size=problems))).astype(int)
     Qs = [symmetric_int(int(N), -100, 100, np.int16, seed=SEED_BASE + 4000 + i if seed is None else seed + 4000 + i,
-                        density=0.5) for i, N in enumerate(Ns)]
+                        density=0.5) if only is None or i in only else None for i, N in enumerate(Ns)]
     betas = np.repeat(0.01 * np.sqrt(2048.0 / Ns), chains_per)
     return Workload("batched_64_uneven_int16", Qs, betas, "unbiased_sys", 0, 100_000,
                     extra={"Ns": Ns, "chains_per": chains_per})

@@ -152,7 +152,8 @@ def test_structs_match_header_layout(tmp_path):
     import subprocess
     from paper_2210_10513_amd import binding as b
     structs = {"pns_opts": b.pns_opts, "pns_problem": b.pns_problem, "pns_problem_info": b.pns_problem_info,
-               "pns_tune": b.pns_tune, "pns_chain_stats": b.pns_chain_stats, "pns_cont_opts": b.pns_cont_opts}
+               "pns_tune": b.pns_tune, "pns_chain_stats": b.pns_chain_stats, "pns_cont_opts": b.pns_cont_opts,
+               "pns_class_profile": b.pns_class_profile}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pns.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -176,3 +177,7 @@ def test_checkpoint_calls_reject_null_arguments():
     assert b.lib.pns_save(None, None, 0, ctypes.byref(size)) == b.PNS_EINVAL
     assert b.lib.pns_load(None, None, 0) == b.PNS_EINVAL
     assert "NULL" in b.pns_last_error()
+    n = ctypes.c_int32(0)
+    assert b.lib.pns_profile(None, 1) == b.PNS_EINVAL
+    assert b.lib.pns_profile_read(None, None, 0, ctypes.byref(n)) == b.PNS_EINVAL
+    assert b.lib.pns_class_of_chain(None, None) == b.PNS_EINVAL

@@ -56,3 +56,17 @@ def _current_sha():
     import hashlib
     src = os.path.join(ROOT, "paper_2210_10513_amd", "csrc", "pns_step.h")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def test_cpu_baseline_child_reports_one_core_and_all_cores():
+    """The oracle leg runs in a child process that never touches the GPU and
+    reports the CPU model, one core and one process per core."""
+    import json
+    spec = json.dumps({"workload": "rf_n1024_int16", "budget_s": 0.3})
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--cpu-baseline", spec],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["kind"] == "oracle" and out["cores"] == 1 and out["value"] > 0 and out["cpu_model"]
+    if "all_cores" in out:
+        assert out["all_cores"]["cores"] > 1 and out["all_cores"]["value"] > 0

@@ -202,3 +202,44 @@ def test_batched_workload_sampled_chains():
         info = g["info"][p]
         assert 16 <= info.subset_size <= info.N // 2
         _check_problem(g, p, probs[p], "unbiased_sys", K, seed=2210105134, L0=100, rows=[0, 63])
+
+
+def test_class_profiling_counts_and_times_every_class():
+    """pns_profile: per launch class, the flips, records and row bytes of its
+    chains since profiling started, and a positive kernel time per launch;
+    a graph context profiled (launches queued directly) continues exactly like
+    an unprofiled one."""
+    from paper_2210_10513_amd import binding as bd
+    from paper_2210_10513_amd.binding import BatchSampler
+    probs = _uneven([40, 260, 900, 1500], chains=3)
+    for pr in probs:
+        pr["subset_size"] = 24
+    a = BatchSampler(probs, "unbiased_sys", L0=20, seed=4, launch="graph")
+    b = BatchSampler(probs, "unbiased_sys", L0=20, seed=4, launch="graph")
+    a.run(50)
+    b.run(50)
+    st0 = a.stats()
+    bd.pns_profile(a.ctx, True)
+    for _ in range(3):
+        a.run(40)
+        b.run(40)
+    prof = bd.pns_profile_read(a.ctx)
+    st1 = a.stats()
+    cls = bd.pns_class_of_chain(a.ctx, a.num_chains)
+    Ns = np.concatenate([np.full(i.num_chains, i.N) for i in a.info])
+    assert len(prof) == cls.max() + 1 >= 3
+    for ki, k in enumerate(prof):
+        sel = cls == ki
+        assert k["launches"] == 3 and k["kernel_ms"] > 0 and k["chains"] == sel.sum()
+        assert k["flips"] == (st1["flips"] - st0["flips"])[sel].sum()
+        assert k["records"] == 120 * sel.sum()
+        assert k["row_bytes"] == float(((st1["flips"] - st0["flips"]) * Ns)[sel].sum() * 4)
+        assert k["N_min"] == Ns[sel].min() and k["N_max"] == Ns[sel].max()
+    bd.pns_profile(a.ctx, False)
+    a.run(40)
+    b.run(40)
+    for key in ("x", "h", "E"):
+        for p in range(len(probs)):
+            assert np.array_equal(a.read_current()[key][p], b.read_current()[key][p])
+    a.close()
+    b.close()
