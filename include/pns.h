@@ -548,6 +548,30 @@ int pns_moments_f64(const uint8_t* X, int64_t ldx, const double* w, int64_t K, i
                     void* stream);
 
 /*
+ * pns_moments without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid hipMalloc.  Same arguments, kernels and
+ * results as pns_moments, except:
+ *   - X, m, G and sum_m (or NULL) must be device memory (PNS_EINVAL
+ *     otherwise): nothing is staged, and the call only queues work on
+ *     `stream`;
+ *   - the workspace (weight pieces, packed records, partial tiles) is a
+ *     static 32 MiB array on each GPU, held until the process ends; a call
+ *     whose workspace would exceed it is refused with PNS_EINVAL (about
+ *     K * N / 8 bytes of packed records plus 16 KiB per 64 x 64 tile of the
+ *     upper triangle; K = 131072 records of N = 512 fit);
+ *   - every call on a GPU uses that GPU's one workspace: calls that overlap
+ *     on one GPU (other streams, other threads) race and must be ordered by
+ *     the caller.  The workspace keeps the last call's contents; each call
+ *     clears what it accumulates into.
+ * The device is the calling thread's current device (the stream's device).
+ * Errors: PNS_EINVAL (as pns_moments, host buffers, workspace too small),
+ * PNS_EDEVICE.
+ */
+int pns_moments_noalloc(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int32_t N, double* G,
+                        double* sum_m, void* stream);
+
+/*
  * Rao-Blackwell weights (Thm 3 (2), (5)): the expected multiplicity of a
  * record given its state J_k, its subset and, for a budgeted record
  * (Unbiased PNS, Alg 6, and runs of exact original time), the remaining

@@ -44,7 +44,7 @@ EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_cu
            "pns_moments_f64", "pns_read_rb_weights", "pns_snapshot_moments_rb", "pns_cont_opts_default",
            "pns_cont_create", "pns_cont_run", "pns_cont_read", "pns_cont_read_log", "pns_cont_read_sums",
            "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy", "pns_save", "pns_load", "pns_profile",
-           "pns_profile_read", "pns_class_of_chain"]
+           "pns_profile_read", "pns_class_of_chain", "pns_moments_noalloc"]
 
 
 class pns_class_profile(ctypes.Structure):
@@ -154,6 +154,7 @@ def _load() -> ctypes.CDLL:
     L.pns_pt_swap.argtypes = [vp, i32, i64, vp]
     L.pns_read_betas.argtypes = [vp, vp]
     L.pns_read_ladder.argtypes = [vp, vp]
+    L.pns_moments_noalloc.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
     L.pns_profile.argtypes = [vp, i32]
     L.pns_profile_read.argtypes = [vp, ctypes.POINTER(pns_class_profile), i32, ctypes.POINTER(i32)]
     L.pns_class_of_chain.argtypes = [vp, vp]
@@ -181,7 +182,8 @@ def _load() -> ctypes.CDLL:
                  "pns_pt_swap", "pns_read_betas", "pns_read_ladder", "pns_moments_f64", "pns_read_rb_weights",
                  "pns_snapshot_moments_rb", "pns_cont_create", "pns_cont_run", "pns_cont_read", "pns_cont_read_log",
                  "pns_cont_read_sums", "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy",
-                 "pns_save", "pns_load", "pns_profile", "pns_profile_read", "pns_class_of_chain"):
+                 "pns_save", "pns_load", "pns_profile", "pns_profile_read", "pns_class_of_chain",
+                 "pns_moments_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -412,6 +414,17 @@ def pns_read_betas(ctx, betas) -> None:
 
 def pns_read_ladder(ctx, ladder) -> None:
     _check(lib.pns_read_ladder(ctx, _addr(ladder)))
+
+
+def pns_moments_noalloc(X, m, G, sum_m=None, *, N: Optional[int] = None, ldx: Optional[int] = None,
+                        stream=None) -> None:
+    """G = X^T diag(m) X into device tensors without any allocation (the
+    library's static per-GPU workspace); X [K][ldx] uint8, m [K] int64,
+    G [N][N] float64 and sum_m [1] float64 (or None) must be device tensors."""
+    K = int(X.shape[0])
+    ld = int(X.shape[1]) if ldx is None else ldx
+    n = int(G.shape[0]) if N is None else N
+    _check(lib.pns_moments_noalloc(_addr(X), ld, _addr(m), K, n, _addr(G), _addr(sum_m), _stream_handle(stream)))
 
 
 def pns_profile(ctx, enable: bool = True) -> None:

@@ -133,6 +133,10 @@ hipError_t launch_pt_swap(const int64_t* E, int32_t is_float, double* beta, int3
 // Fill `count` 64-bit words with a value (graph-safe alternative to memset).
 hipError_t launch_fill64(void* p, int64_t count, int64_t value, hipStream_t stream);
 
+// Record the message of a failed call for pns_last_error() on this thread
+// and return `code` (printf-style message).
+int set_error(int code, const char* fmt, ...);
+
 }  // namespace pns
 
 namespace pns {

@@ -597,3 +597,108 @@ hipError_t launch_logz(int32_t qtype, const void* Q, int32_t N, int32_t layout, 
 }
 
 }  // namespace pns
+
+// ---- moments into a static workspace (pns_moments_noalloc) ----
+
+#include <mutex>
+
+#include "pns.h"
+
+namespace {
+
+// Workspace of pns_moments_noalloc on each GPU: weight pieces, counters,
+// packed records and partial tiles of one call.  A device global holds no
+// valid address on the host: host code uses the per-device address from
+// hipGetSymbolAddress, never this name.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Address of `scratch` on the current device, looked up on the first call
+// on that device.
+int scratch_address(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return pns::set_error(PNS_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return pns::set_error(PNS_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return pns::set_error(PNS_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PNS_OK;
+}
+
+bool on_device(const void* p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
+}  // namespace
+
+extern "C" int pns_moments_noalloc(const uint8_t* X, int64_t ldx, const int64_t* m, int64_t K, int32_t N, double* G,
+                                   double* sum_m, void* stream)
+{
+    using namespace pns;
+    if (!X || !m || !G) return set_error(PNS_EINVAL, "NULL argument");
+    if (N < 1 || N > 32768) return set_error(PNS_EINVAL, "N must be in [1, 32768]");
+    if (K < 0) return set_error(PNS_EINVAL, "K must be >= 0");
+    if (ldx < N) return set_error(PNS_EINVAL, "ldx must be >= N");
+    if (!on_device(X) || !on_device(m) || !on_device(G) || (sum_m && !on_device(sum_m)))
+        return set_error(PNS_EINVAL, "X, m, G and sum_m must be device memory (nothing is staged here)");
+    // the sizes of pns_moments' workspace
+    const int64_t kpad = std::max<int64_t>(64, (K + 63) / 64 * 64);
+    const int32_t npad = (N + 63) / 64 * 64;
+    const int64_t words = std::max<int64_t>(1, (K + 31) / 32);
+    const int64_t nt = npad / 64;
+    const int64_t tiles = nt * (nt + 1) / 2;
+    const size_t fixed = align256((size_t)3 * kpad * 2) + 256 + align256((size_t)words * npad * 4);
+    const size_t tile_bytes = (size_t)tiles * 64 * 64 * 4;
+    if (fixed + tile_bytes > kScratchBytes)
+        return set_error(PNS_EINVAL,
+                         "K = %lld records of N = %d need %zu bytes of workspace; the static workspace holds %zu "
+                         "(use pns_moments)",
+                         (long long)K, N, fixed + tile_bytes, kScratchBytes);
+    // about 2048 waves, as pns_moments, with no more chunks than fit
+    int64_t chunk_words = std::max<int64_t>(32, (words * tiles + 2047) / 2048);
+    const int64_t max_chunks = (int64_t)((kScratchBytes - fixed) / tile_bytes);
+    if ((words + chunk_words - 1) / chunk_words > max_chunks) chunk_words = (words + max_chunks - 1) / max_chunks;
+    void* base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    unsigned char* b = static_cast<unsigned char*>(base);
+    uint16_t* pieces = reinterpret_cast<uint16_t*>(b);
+    b += align256((size_t)3 * kpad * 2);
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(b);
+    b += 256;
+    uint32_t* Xb = reinterpret_cast<uint32_t*>(b);
+    b += align256((size_t)words * npad * 4);
+    float* part = reinterpret_cast<float*>(b);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // every buffer is written before it is read, except the counters and G:
+    // cleared here (the workspace keeps the previous call's contents)
+    hipError_t e = launch_fill64(G, (int64_t)N * N, 0, st);
+    if (e == hipSuccess) e = launch_fill64(cnt, 3, 0, st);
+    if (e == hipSuccess) e = launch_moments_prep(m, K, kpad, pieces, cnt, cnt + 1, st);
+    if (e == hipSuccess) e = launch_pack_bits(X, ldx, K, N, npad, words, Xb, st);
+    if (e == hipSuccess) e = launch_moments(Xb, npad, words, N, pieces, kpad, chunk_words, cnt + 1, part, G, st);
+    if (e == hipSuccess && sum_m) e = launch_moments_sum(cnt, sum_m, st);
+    if (e != hipSuccess) return set_error(PNS_EDEVICE, "moments kernels: %s", hipGetErrorString(e));
+    return PNS_OK;
+}
+

@@ -46,6 +46,21 @@ int hip_fail(hipError_t e, const char* what)
     return fail(PNS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+}  // namespace
+
+int pns::set_error(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+namespace {
+
 #define HIP_TRY(call, what)                              \
     do {                                                 \
         hipError_t e_ = (call);                          \
