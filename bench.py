@@ -389,6 +389,16 @@ def _bench_batch(args, wl, cpu_spec=None):
         "setup_s": r["setup_s"],
     }
     if not args.no_extras:
+        # the N >= 8192 problems on their own (same chains, same kernels):
+        # their rate when they do not share the GPU with the rest of the batch
+        big_wl = dict(wl, problems=[pr for pr in wl["problems"] if pr["Q"].shape[0] >= 8192])
+        b = _time_batch(big_wl, chain_steps, 1, 1, launch, seed=1)
+        bcl = _class_rows(b["prof"], 1.0)
+        out["n_ge_8192"]["alone"] = {
+            "flips_per_s": b["flips"] / b["sec"], "GB_per_s": b["qbytes"] / b["sec"] / 1e9,
+            "hbm_frac": b["qbytes"] / b["sec"] / 1e9 / HBM_PEAK_GBS, "ms_per_step": b["sec"] * 1e3,
+            "classes": [{k: c[k] for k in ("tile", "flavour", "chains", "kernel_avg_ms", "GB_per_s", "hbm_frac")}
+                        for c in bcl]}
         p = _time_batch(wl, 100, 1, 1, "plain", seed=3, profile=False)
         out["variants"] = {"plain_launch_flips_per_s": p["flips"] / p["sec"],
                            "batched_over_plain": (flips / sec) / (p["flips"] / p["sec"])}

@@ -106,9 +106,10 @@ typedef struct pns_opts {
     int32_t block;          /* threads per workgroup (one workgroup per chain);
                                0 = chosen from the tuned table.  Compiled tiles
                                (block x groups): 64x1, 64x2, 64x4, 128x1, 128x2,
-                               128x4, 256x1, 256x2, 256x4, 512x2, 512x4, 1024x2,
-                               1024x4; 4 * block * groups must reach N; another
-                               shape is PNS_EINVAL                                */
+                               128x4, 256x1, 256x2, 256x4, 256x8, 512x2, 512x4,
+                               1024x2, 1024x4, and 256x16 for 32-bit fields (I16,
+                               I32 with int32 fields); 4 * block * groups must
+                               reach N; another shape is PNS_EINVAL               */
     int32_t groups;         /* 4-field groups per lane; 0 = chosen with `block`   */
     void* stream;           /* hipStream_t to queue work on; NULL = a stream the
                                context creates and owns                           */

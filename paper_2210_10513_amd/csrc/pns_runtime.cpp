@@ -155,9 +155,17 @@ Tile default_tile(int32_t N)
     return {1024, 4};
 }
 
+// Tiles of four waves with 32 or 64 fields per lane: three (256 x 8) or two
+// (256 x 16) chains per compute unit where the table's tiles hold two or one,
+// for the subsets whose weights touch at most two 4-bit groups per wave
+// (compact and two-group windows); the other flavours weigh every group of a
+// lane and spill there.
+bool wide_tile(Tile t) { return t.block == 256 && t.groups >= 8; }
+
 // Every tile the step kernels are compiled for.
-const Tile kTiles[] = {{64, 1},  {64, 2},  {64, 4},  {128, 1}, {128, 2}, {128, 4},  {256, 1},
-                       {256, 2}, {256, 4}, {512, 2}, {512, 4}, {1024, 2}, {1024, 4}};
+// (256 x 16 exists for 32-bit fields only: have_tile tells.)
+const Tile kTiles[] = {{64, 1},  {64, 2},  {64, 4},  {128, 1}, {128, 2},  {128, 4},  {256, 1},  {256, 2},
+                       {256, 4}, {256, 8}, {256, 16}, {512, 2}, {512, 4}, {1024, 2}, {1024, 4}};
 
 // True if no window of n cyclically consecutive bits holds bits of two
 // different 4-bit groups within one wave: the lanes of wave w in group g hold
@@ -220,6 +228,22 @@ int32_t flavour_of(int32_t mode, int32_t N, int32_t n, int32_t block, int32_t gr
         return groups >= 2 && window_two_groups_ok(N, n, block, groups) ? 4 : 1;
     }
     return 2;
+}
+
+bool have_tile_any(int32_t qtype, int32_t htype, Tile t) { return have_tile(qtype, htype, t.block, t.groups); }
+
+// Default tile of a problem: above 4096 bits the wide tile of four waves when
+// the problem's windows run a compact or two-group kernel on it (and a kernel
+// exists for the field type), else the fixed table's.
+Tile default_tile_for(int32_t mode, int32_t N, int32_t n, int32_t qtype, int32_t htype)
+{
+    const Tile t = default_tile(N);
+    if (N > 4096) {
+        const Tile w = N <= 8192 ? Tile{256, 8} : Tile{256, 16};
+        const int32_t fl = flavour_of(mode, N, n, w.block, w.groups);
+        if ((fl == 3 || fl == 4) && have_tile_any(qtype, htype, w)) return w;
+    }
+    return t;
 }
 
 // A problem's matrix as the kernels read it, prepared on the host.
@@ -366,9 +390,15 @@ struct LaunchClass {
 };
 
 // Side streams of a context with several launch classes.  HIP spreads a
-// process's streams over 4 hardware queues by default, and kernels on one
-// queue run one after another, so classes are packed onto at most 4 streams.
-constexpr int kMaxSideStreams = 4;
+// process's streams over its hardware queues (GPU_MAX_HW_QUEUES, 4 by
+// default) and kernels on one queue run one after another, so classes are
+// packed onto one stream per hardware queue (at most 16).
+int max_side_streams()
+{
+    const char* e = std::getenv("GPU_MAX_HW_QUEUES");
+    const int q = e ? std::atoi(e) : 4;
+    return std::max(1, std::min(16, q > 0 ? q : 4));
+}
 
 struct SideStream {
     hipStream_t stream = nullptr;
@@ -656,11 +686,9 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         if ((int32_t)S.betas.size() != S.chains) return fail(PNS_EINVAL, "betas size mismatch");
         for (double b : S.betas)
             if (!(b >= 0.0) || !std::isfinite(b)) return fail(PNS_EINVAL, "beta must be finite and >= 0");
-        if (S.tile.block == 0) S.tile = default_tile(S.N);
-        if ((int64_t)S.tile.block * 4 * S.tile.groups < S.N) {
-            if (S.N > 16384) return fail(PNS_EUNSUPPORTED, "N=%d exceeds the largest tile (16384)", S.N);
+        if (S.N > 16384) return fail(PNS_EUNSUPPORTED, "N=%d exceeds the largest tile (16384)", S.N);
+        if (S.tile.block != 0 && (int64_t)S.tile.block * 4 * S.tile.groups < S.N)
             return fail(PNS_EINVAL, "tile %dx%d cannot hold N=%d", S.tile.block, S.tile.groups, S.N);
-        }
         total_chains += S.chains;
     }
     if (total_chains > (1 << 30)) return fail(PNS_EINVAL, "too many chains");
@@ -690,6 +718,8 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
     if (qtype == Q_F32) htype = H_F64;
     else if (qtype == Q_I16) htype = H_I32;
     else htype = (fbound_max < 2147483647.0 && ebound_max < 2147483647.0) ? H_I32 : H_I64;
+    for (auto& S : specs)
+        if (S.tile.block == 0) S.tile = default_tile_for(mode, S.N, S.n, qtype, htype);
     for (const auto& S : specs)
         if (!have_tile(qtype, htype, S.tile.block, S.tile.groups))
             return fail(PNS_EINVAL, "no kernel for tile %dx%d", S.tile.block, S.tile.groups);
@@ -725,6 +755,21 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
     int32_t c0 = 0;
     int64_t f0 = 0;
     std::map<std::pair<std::pair<int32_t, int32_t>, int32_t>, size_t> class_of;
+    // Kernel flavour of each problem.  The two-group window kernel also runs
+    // compact windows (a window in one group of a wave is a two-group window
+    // with both groups equal), so on a tile where both occur the compact
+    // problems join the two-group class: fewer launch classes to run
+    // concurrently.
+    std::vector<int32_t> flav(specs.size());
+    std::map<std::pair<int32_t, int32_t>, int32_t> tile_has4;
+    for (size_t p = 0; p < specs.size(); ++p) {
+        const ProblemSpec& S = specs[p];
+        flav[p] = flavour_of(mode, S.N, S.n, S.tile.block, S.tile.groups);
+        if (flav[p] == 4) tile_has4[{S.tile.block, S.tile.groups}] = 1;
+    }
+    for (size_t p = 0; p < specs.size(); ++p)
+        if (flav[p] == 3 && specs[p].tile.groups >= 2 && tile_has4.count({specs[p].tile.block, specs[p].tile.groups}))
+            flav[p] = 4;
     for (size_t p = 0; p < specs.size(); ++p) {
         const ProblemSpec& S = specs[p];
         ProblemRun R{};
@@ -738,7 +783,7 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         R.chain_begin = c0;
         R.chains = S.chains;
         R.tile = S.tile;
-        R.flav = flavour_of(mode, S.N, S.n, S.tile.block, S.tile.groups);
+        R.flav = flav[p];
         ctx->probs.push_back(R);
         ProblemRun& RR = ctx->probs.back();
         int r = dev_alloc(reinterpret_cast<uint8_t**>(&RR.A), pp[p]->A.size());
@@ -889,7 +934,7 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t a, int32_t b) { return ctx->classes[a].cost > ctx->classes[b].cost; });
-        ctx->sides.resize(std::min<size_t>(kMaxSideStreams, ctx->classes.size()));
+        ctx->sides.resize(std::min<size_t>((size_t)max_side_streams(), ctx->classes.size()));
         std::vector<double> load(ctx->sides.size(), 0.0);
         for (int32_t ki : order) {
             const size_t sdi = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -1040,20 +1085,24 @@ int autotune_impl(const ProblemSpec& base, int32_t mode, const pns_opts& o, int3
             return PNS_OK;
         }
     }
-    // Trials run at least 1024 chains (the problem's betas repeated) so that
-    // the device is loaded as in a real run: a few chains alone on an idle
-    // device measure step latency, not throughput.
+    // Trials run at least 3072 chains (the problem's betas repeated) so that
+    // the device is loaded as in a real run -- a few chains alone on an idle
+    // device measure step latency, not throughput -- and so that tiles of
+    // one to four chains per compute unit all run several full rounds.
     ProblemSpec spec = base;
-    spec.chains = std::min<int32_t>(4096, std::max<int32_t>(base.chains, 1024));
+    spec.chains = std::min<int32_t>(4096, std::max<int32_t>(base.chains, 3072));
     spec.betas.assign(spec.chains, 1.0);
     for (int32_t c = 0; c < spec.chains; ++c)
         spec.betas[c] = base.betas.empty() ? 1.0 : base.betas[c % base.betas.size()];
     const bool tune_n = mode != PNS_MODE_RF && base.n == 0;
-    // subset size used while choosing the tile
-    int32_t n0 = base.n;
-    if (mode == PNS_MODE_RF) n0 = base.N;
-    else if (tune_n) n0 = std::max(1, std::min(base.N, std::max(16, base.N / 8)));
-    spec.n = n0;
+    // subset sizes tried: powers of two 16 .. N/2 (or the one given; RF: N)
+    std::vector<int32_t> ns;
+    if (mode == PNS_MODE_RF) ns.push_back(base.N);
+    else if (!tune_n) ns.push_back(base.n);
+    else
+        for (int32_t n = 16; n <= base.N / 2; n *= 2) ns.push_back(n);
+    if (ns.empty()) ns.push_back(std::max(1, base.N / 2));
+    spec.n = ns.front();
     spec.tile = default_tile(base.N);
     if ((int64_t)spec.tile.block * 4 * spec.tile.groups < base.N)
         return fail(PNS_EUNSUPPORTED, "no tile holds N=%d", base.N);
@@ -1072,45 +1121,48 @@ int autotune_impl(const ProblemSpec& base, int32_t mode, const pns_opts& o, int3
     if (prep) preps.push_back(prep);
     int rc = create_impl(&ctx, one, mode, t, preps);
     if (rc) return rc;
-    pns_tune best{};
-    best.records_per_s = -1.0;
+    // Every (tile, subset size): tiles that hold N in at most twice its
+    // rounded size, wide tiles only where the subset runs a window kernel.
+    struct Trial {
+        Tile tile;
+        int32_t n;
+        double rate, frate;
+    };
+    std::vector<Trial> res;
     int trials = 0;
     for (const Tile& tl : kTiles) {
         const int64_t cap = (int64_t)tl.block * 4 * tl.groups;
-        if (cap < base.N || cap > 4 * round_up(base.N, 256)) continue;
+        if (cap < base.N || cap > 2 * round_up(base.N, 256)) continue;
         if (!have_tile(ctx->qtype, ctx->htype, tl.block, tl.groups)) continue;
-        double r = 0.0, fr = 0.0;
-        rc = reconfigure(ctx, tl, n0);
-        if (!rc) rc = time_config(ctx, trial_steps, &r, &fr);
-        if (rc) break;
-        ++trials;
-        if (r > best.records_per_s) {
-            best.block = tl.block;
-            best.groups = tl.groups;
-            best.subset_size = n0;
-            best.records_per_s = r;
-            best.flips_per_s = fr;
-        }
-    }
-    if (!rc && tune_n) {
-        // the largest subset whose step rate stays within 10% of the best (Sec 5)
-        const Tile bt{best.block, best.groups};
-        std::vector<std::pair<int32_t, std::pair<double, double>>> res;
-        double top = 0.0;
-        for (int32_t n = 16; n <= base.N / 2 && !rc; n *= 2) {
+        for (int32_t n : ns) {
+            const int32_t fl = flavour_of(mode, base.N, n, tl.block, tl.groups);
+            if (wide_tile(tl) && fl != 3 && fl != 4) continue;
             double r = 0.0, fr = 0.0;
-            rc = reconfigure(ctx, bt, n);
+            rc = reconfigure(ctx, tl, n);
             if (!rc) rc = time_config(ctx, trial_steps, &r, &fr);
             if (rc) break;
             ++trials;
-            res.push_back({n, {r, fr}});
-            top = std::max(top, r);
+            res.push_back({tl, n, r, fr});
         }
-        for (const auto& pr : res) {
-            if (pr.second.first >= 0.9 * top) {
-                best.subset_size = pr.first;
-                best.records_per_s = pr.second.first;
-                best.flips_per_s = pr.second.second;
+        if (rc) break;
+    }
+    pns_tune best{};
+    best.records_per_s = -1.0;
+    if (!rc && !res.empty()) {
+        // the largest subset (Sec 5: the largest partial neighbor set the
+        // hardware affords) whose step rate is within 10% of the best trial,
+        // on its fastest tile
+        double top = 0.0;
+        for (const Trial& r : res) top = std::max(top, r.rate);
+        for (const Trial& r : res) {
+            if (r.rate < 0.9 * top) continue;
+            if (best.records_per_s < 0.0 || r.n > best.subset_size ||
+                (r.n == best.subset_size && r.rate > best.records_per_s)) {
+                best.block = r.tile.block;
+                best.groups = r.tile.groups;
+                best.subset_size = r.n;
+                best.records_per_s = r.rate;
+                best.flips_per_s = r.frate;
             }
         }
     }

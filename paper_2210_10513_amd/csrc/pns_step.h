@@ -356,11 +356,17 @@ constexpr int kLsE = 0, kLsL = 1, kLsLastA = 2, kLsLastM = 3, kLsLastE = 4, kLsS
 
 // Occupancy asked of the compiler (waves per SIMD): compact-window kernels
 // of 512 lanes target two co-resident chains per compute unit (128 VGPRs);
+// compact and two-group windows on 256 x 8 tiles three chains of four waves
+// (168 VGPRs), on 256 x 16 tiles (64 fields per lane) two; the flavours that
+// weigh every group of a lane (all bits, general window, drawn subset) keep
+// two waves on the wide tiles (they are not what those tiles are for); other
 // 1024-lane kernels keep the register budget of one chain per unit.
 template <int BLOCK, int G, int FLAV>
 constexpr int min_waves_per_eu()
 {
-    return (((FLAV == FLAV_WINDOW_C || FLAV == FLAV_WINDOW_C2) && BLOCK == 512) || (G == 1 && BLOCK <= 512)) ? 4 : 1;
+    constexpr bool win = FLAV == FLAV_WINDOW_C || FLAV == FLAV_WINDOW_C2;
+    if (BLOCK == 256 && G >= 8) return (win && G == 8) ? 3 : 2;
+    return ((win && BLOCK == 512) || (G == 1 && BLOCK <= 512)) ? 4 : 1;
 }
 
 template <typename QT, typename HT, int BLOCK, int G, int FLAV, bool INSTR>
@@ -373,7 +379,9 @@ void step_kernel(const StepArgs a)
     constexpr int W = BLOCK / 64;
     constexpr int NSEG = G * W;
     static_assert(NSEG <= 64, "segment scan needs at most 64 segments");
-    static_assert(F <= 32, "bit masks are 32 bits");
+    static_assert(F <= 64, "bit masks are at most 64 bits");
+    // per-lane bit masks (state, membership, existing bits): one bit per field
+    using MT = std::conditional_t<(F > 32), uint64_t, uint32_t>;
 
     // dynamic LDS: [random-subset table, pitch entries (FLAV_DRAWN only)][diagonal, pitch entries]
     extern __shared__ uint32_t own[];
@@ -448,7 +456,7 @@ void step_kernel(const StepArgs a)
     // ---- chain state into registers ----
     HT h[F];
     QW dg[kLdsDiag ? 1 : F];
-    uint32_t xb = 0;
+    MT xb = 0;
     HT* hbase = reinterpret_cast<HT*>(a.h) + off;
     const QW* dbase = reinterpret_cast<const QW*>(P.diag);
 #pragma unroll
@@ -463,7 +471,7 @@ void step_kernel(const StepArgs a)
                 h[g * 4 + v] = hv.v[v];
                 if constexpr (kLdsDiag) dsh[fb + v] = dv.v[v];
                 else dg[g * 4 + v] = dv.v[v];
-                xb |= ((xw >> (8 * v)) & 1u) << (g * 4 + v);
+                xb |= (MT)((xw >> (8 * v)) & 1u) << (g * 4 + v);
             }
         } else {
 #pragma unroll
@@ -474,11 +482,11 @@ void step_kernel(const StepArgs a)
         }
     }
     // bits of this lane that exist (f < N)
-    uint32_t valid = 0;
+    MT valid = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) valid |= (uint32_t)((g * BLOCK + tid) * 4 + v < N) << (g * 4 + v);
+        for (int v = 0; v < 4; ++v) valid |= (MT)((g * BLOCK + tid) * 4 + v < N) << (g * 4 + v);
 
     // this lane's bits as bytes at dst[f] (the layout of x)
     auto store_bits = [&](uint8_t* dst) {
@@ -488,7 +496,7 @@ void step_kernel(const StepArgs a)
             if (fb < pitch) {
                 uint32_t xw = 0;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) xw |= ((xb >> (g * 4 + v)) & 1u) << (8 * v);
+                for (int v = 0; v < 4; ++v) xw |= (uint32_t)((xb >> (g * 4 + v)) & 1u) << (8 * v);
                 *reinterpret_cast<uint32_t*>(dst + fb) = xw;
             }
         }
@@ -515,6 +523,7 @@ void step_kernel(const StepArgs a)
     int32_t snap_n = 0;
     if constexpr (INSTR) snap_n = a.snap_every > 0 ? a.snap_count[chain] : 0;
     uint32_t pos_n = 0;
+    int32_t last_row = 0;  // the row loaded by the previous step
     const bool full = n >= N;
     int64_t sys_start = kWin ? (int64_t)(((sub % P.num_sets) * (int64_t)n) % N) : 0;
 
@@ -547,8 +556,8 @@ void step_kernel(const StepArgs a)
 
     // Membership of this lane's bits in the current subset.  It changes only
     // when the subset does (a new window or draw), so it is kept across steps.
-    auto compute_mem = [&]() -> uint32_t {
-        uint32_t m = valid;
+    auto compute_mem = [&]() -> MT {
+        MT m = valid;
         if constexpr (kWin) {
             if (!full) {
                 // bit f is in the window iff (f - start) mod N < n
@@ -560,7 +569,7 @@ void step_kernel(const StepArgs a)
                 for (int i = F - 1; i >= 0; --i) {
                     int32_t d = d0 + (i >> 2) * (BLOCK * 4) + (i & 3);
                     d += d < 0 ? N : 0;
-                    m = (m << 1) | (uint32_t)(d < n);
+                    m = (m << 1) | (MT)(d < n);
                 }
                 m &= valid;
             }
@@ -569,13 +578,13 @@ void step_kernel(const StepArgs a)
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 const int32_t f = ((i >> 2) * BLOCK + tid) * 4 + (i & 3);
-                if ((valid >> i) & 1u) m |= (uint32_t)(own[f] <= pos_n) << i;
+                if ((valid >> i) & 1u) m |= (MT)(own[f] <= pos_n) << i;
             }
         }
         return m;
     };
     const bool draw_each_step = mode == kModeBasic || mode == kModeOpt;
-    uint32_t mem = (FLAV == FLAV_DRAWN && draw_each_step) ? 0u : compute_mem();
+    MT mem = (FLAV == FLAV_DRAWN && draw_each_step) ? (MT)0 : compute_mem();
     // one group per lane, 32-bit integer fields: the table reads of the
     // weights by byte offset (below), with the offset of the zero slots of
     // tab_lo for each bit outside the subset kept with the membership
@@ -675,10 +684,10 @@ void step_kernel(const StepArgs a)
         double lsum = 0.0;
         int gw = 0;
         auto compact_weights = [&](double shift) {
-            const uint32_t gmask = (mem & 0x11111111u) | ((mem >> 1) & 0x11111111u) | ((mem >> 2) & 0x11111111u) |
-                                   ((mem >> 3) & 0x11111111u);
-            const int gs = gmask ? (__builtin_ctz(gmask) >> 2) : 0;
-            const uint32_t mg = (mem >> (4 * gs)) & 0xFu;
+            constexpr MT k1 = (MT)0x1111111111111111ull;
+            const MT gmask = (mem & k1) | ((mem >> 1) & k1) | ((mem >> 2) & k1) | ((mem >> 3) & k1);
+            const int gs = gmask ? (__builtin_ctzll((uint64_t)gmask) >> 2) : 0;
+            const uint32_t mg = (uint32_t)(mem >> (4 * gs)) & 0xFu;
             const uint64_t bm = __ballot(mg != 0);
             gw = bm ? __builtin_amdgcn_readlane(gs, (int)__builtin_ctzll(bm)) : 0;
             double w4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -695,7 +704,7 @@ void step_kernel(const StepArgs a)
                 }
                 const int32_t fb = (gw * BLOCK + tid) * 4;
                 const Four<QW> d4 = load4(dsh + (fb < pitch ? fb : 0));
-                const uint32_t x4 = (xb >> (4 * gw)) & 0xFu;
+                const uint32_t x4 = (uint32_t)(xb >> (4 * gw)) & 0xFu;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     double wv;
@@ -728,7 +737,7 @@ void step_kernel(const StepArgs a)
         double lsum2 = 0.0;
         int ga = 0, gb = 0;
         auto group_weights = [&](int gsel, double shift, double* w4) {
-            const uint32_t mg = (mem >> (4 * gsel)) & 0xFu;
+            const uint32_t mg = (uint32_t)(mem >> (4 * gsel)) & 0xFu;
             HT h4[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) h4[v] = h[v];
@@ -741,7 +750,7 @@ void step_kernel(const StepArgs a)
             }
             const int32_t fb = (gsel * BLOCK + tid) * 4;
             const Four<QW> d4 = load4(dsh + (fb < pitch ? fb : 0));
-            const uint32_t x4 = (xb >> (4 * gsel)) & 0xFu;
+            const uint32_t x4 = (uint32_t)(xb >> (4 * gsel)) & 0xFu;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 double wv;
@@ -868,7 +877,7 @@ void step_kernel(const StepArgs a)
         } else {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const uint32_t mg = (mem >> (4 * g)) & 0xFu;
+                const uint32_t mg = (uint32_t)(mem >> (4 * g)) & 0xFu;
                 double w4[4] = {0.0, 0.0, 0.0, 0.0};
                 if (__ballot(mg != 0)) {
 #pragma unroll
@@ -1012,7 +1021,7 @@ void step_kernel(const StepArgs a)
             // wave 0), handed to the leader through LDS
             if (a.hist_w != nullptr) {
                 if (wave == 0) {
-                    rec_idx = wave_or(tid < 8 ? ((xb & 0xFu) << (4 * tid)) : 0u);
+                    rec_idx = wave_or(tid < 8 ? ((uint32_t)(xb & 0xFu) << (4 * tid)) : 0u);
                     if (tid == 0) hist_idx = rec_idx;
                 }
             }
@@ -1026,7 +1035,7 @@ void step_kernel(const StepArgs a)
                     if (fb < a.snap_pitch) {
                         uint32_t wv = 0;
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) wv |= ((xb >> (g * 4 + v)) & 1u) << (8 * v);
+                        for (int v = 0; v < 4; ++v) wv |= (uint32_t)((xb >> (g * 4 + v)) & 1u) << (8 * v);
                         *reinterpret_cast<uint32_t*>(sx + fb) = wv;
                     }
                 }
@@ -1081,7 +1090,7 @@ void step_kernel(const StepArgs a)
 #pragma unroll
                         for (int v = 0; v < 4; ++v) wsel[v] = w[v];
                     } else {
-                        const uint32_t mg = (mem >> (4 * gstar)) & 0xFu;
+                        const uint32_t mg = (uint32_t)(mem >> (4 * gstar)) & 0xFu;
 #pragma unroll
                         for (int v = 0; v < 4; ++v)
                             wsel[v] = ((mg >> v) & 1u) ? member_weight(gstar * 4 + v, scaled ? mx : 0.0) : 0.0;
@@ -1151,10 +1160,15 @@ void step_kernel(const StepArgs a)
         const int64_t sv0 = sel[0];
         const int32_t csel = (int32_t)(sv0 & 0xFFFFFFFFll);  // in [0, N) on every step
         // Row csel: every lane loads (lanes past the pitch read the row's start
-        // and drop it), so no branch forces an early wait.  One group per
-        // lane: loaded whether or not the chain stays (a stay drops it), so
-        // that the loaded registers are not joined from two branches.
-        const QT* row = reinterpret_cast<const QT*>(P.A) + (int64_t)csel * pitch;
+        // and drop it), so no branch forces an early wait.  The early-load
+        // kernels load whether or not the chain stays (a stay drops it), so
+        // that the loaded registers are not joined from two branches; a stay
+        // reads the row loaded last, which the caches still hold, instead of
+        // the speculative choice's (in Unbiased PNS at low acceptance most
+        // steps are stays).
+        const int32_t rsel = (kEarly && stay) ? last_row : csel;
+        last_row = rsel;
+        const QT* row = reinterpret_cast<const QT*>(P.A) + (int64_t)rsel * pitch;
         if constexpr (kEarly) {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -1193,7 +1207,7 @@ void step_kernel(const StepArgs a)
             }
             const int cl = (c >> 2) % BLOCK;
             const int cg = (c >> 2) / BLOCK;
-            if (tid == cl) xb ^= 1u << (cg * 4 + (c & 3));
+            if (tid == cl) xb ^= (MT)1 << (cg * 4 + (c & 3));
             if constexpr (!kEarly) update_fields();
         }
         if constexpr (INSTR) {
@@ -1331,7 +1345,7 @@ void step_kernel(const StepArgs a)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 hv[v] = h[g * 4 + v];
-                xw |= ((xb >> (g * 4 + v)) & 1u) << (8 * v);
+                xw |= (uint32_t)((xb >> (g * 4 + v)) & 1u) << (8 * v);
                 if constexpr (FLAV == FLAV_DRAWN) mw |= (uint32_t)(own[fb + v] <= pos_n) << (8 * v);
             }
             store4(hbase + fb, hv);
@@ -1380,10 +1394,15 @@ hipError_t launch_one(int32_t grid, size_t dyn, hipStream_t st, const StepArgs& 
     X(QT, HT, 256, 1)            \
     X(QT, HT, 256, 2)            \
     X(QT, HT, 256, 4)            \
+    X(QT, HT, 256, 8)            \
     X(QT, HT, 512, 2)            \
     X(QT, HT, 512, 4)            \
     X(QT, HT, 1024, 2)           \
     X(QT, HT, 1024, 4)
+
+// 64 fields per lane: compiled for 32-bit fields only (int16 and int32
+// coefficients); N up to 16384 in four waves, two chains per compute unit.
+#define PNS_TILE_LIST_WIDE(X, QT, HT) X(QT, HT, 256, 16)
 
 // One tile of the dispatch: `probe` only asks whether the tile exists.
 #define PNS_DISPATCH_TILE(QT, HT, B, GG)                                                                     \

@@ -8,6 +8,7 @@ hipError_t launch_steps_i32(int flav, bool instr, int block, int groups, int gri
 {
     using namespace step;
     PNS_TILE_LIST(PNS_DISPATCH_TILE, int32_t, int32_t)
+    PNS_TILE_LIST_WIDE(PNS_DISPATCH_TILE, int32_t, int32_t)
     return hipErrorInvalidConfiguration;
 }
 

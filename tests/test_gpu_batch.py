@@ -243,3 +243,18 @@ def test_class_profiling_counts_and_times_every_class():
             assert np.array_equal(a.read_current()[key][p], b.read_current()[key][p])
     a.close()
     b.close()
+
+
+def test_compact_windows_join_the_two_group_class_of_their_tile():
+    """Two problems on the 256 x 8 tile, one with compact windows and one with
+    two-group windows: they share one launch class of the two-group kernel,
+    and every record of sampled chains equals the oracle's."""
+    probs = [{"Q": inputs.symmetric_int(6000, -100, 100, np.int16, seed=61, density=0.5), "num_chains": 3,
+              "beta": 0.006, "subset_size": 512},
+             {"Q": inputs.symmetric_int(5000, -100, 100, np.int16, seed=62, density=0.5), "num_chains": 2,
+              "beta": 0.007, "subset_size": 1000}]
+    K = 150
+    g = _batch(probs, "unbiased_sys", K, L0=100, seed=9)
+    assert [(i.block, i.groups, i.flavour) for i in g["info"]] == [(256, 8, 4), (256, 8, 4)]
+    for p, pr in enumerate(probs):
+        _check_problem(g, p, pr, "unbiased_sys", K, seed=9, L0=100, rows=[0, pr["num_chains"] - 1])

@@ -4,7 +4,7 @@ The timed runs are uninstrumented (no per-step log): the Rejection-Free
 N = 1024 int16 workload runs the all-bits kernel on a 256x1 tile with the
 multiplicities of up to 64 steps computed together, and the Unbiased PNS
 N = 8192 float32 workload runs the compact window kernel (flavour 3) on a
-512x4 tile with the split record.  Each is run over 2000 steps in two
+256x8 tile with the split record.  Each is run over 2000 steps in two
 launches, and
   - every chain's last record (pns_read), counters and final x, h, E equal
     those of the instrumented kernel on the same inputs, whose full log
@@ -84,7 +84,7 @@ def test_basic64_n1024_int16_timed_kernel():
 def test_unbiased_n8192_f32_timed_kernel():
     w = inputs.c3_unbiased_n8192()
     rows = [0, 5, 15, 1000, 2047, 4095]
-    _timed_vs_instrumented(w.Q, w.betas, 512, "unbiased_sys", 2000, 2210105133, rows, False, (512, 4), 3)
+    _timed_vs_instrumented(w.Q, w.betas, 512, "unbiased_sys", 2000, 2210105133, rows, False, (256, 8), 3)
 
 
 def test_float32_fields_after_1e5_steps_match_fp64_recomputation():

@@ -355,3 +355,38 @@ def test_uninstrumented_frozen_chain_saturates():
     o = oracle_run(Q, 10.0, "rf", 3, chains=[0, 1], seed=1)
     assert np.array_equal(m, o.M[:, -1])
     assert np.array_equal(st["saturated"], (o.M == np.iinfo(np.int64).max).sum(axis=1))
+
+
+# ---------------------------------------------------------------------------
+# Wide tiles: 256 x 8 (32 fields per lane) and 256 x 16 (64 fields per lane,
+# 64-bit lane masks; 32-bit fields only)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode,n,N,tile,dtype,flavour", [
+    ("unbiased_sys", 400, 12000, (256, 16), np.int16, 3),    # compact windows
+    ("unbiased_sys", 1500, 12000, (256, 16), np.int16, 4),   # two-group windows
+    ("rf", 0, 16384, (256, 16), np.int16, 0),
+    ("basic", 64, 9000, (256, 16), np.int32, 2),
+    ("unbiased_rand", 200, 10000, (256, 16), np.int16, 2),
+    ("unbiased_sys", 512, 6000, (256, 8), np.int16, 3),
+    ("unbiased_sys", 512, 8192, (256, 8), np.float32, 3),
+    ("rf", 0, 5000, (256, 8), np.float32, 0),
+])
+def test_wide_tiles_replay_against_oracle(mode, n, N, tile, dtype, flavour):
+    """Every record of sampled chains through the oracle, final states, and the
+    uninstrumented kernel of the same tile equal to the instrumented one."""
+    is_int = dtype != np.float32
+    Q = inputs.symmetric_int(N, -100, 100, dtype, seed=N + n, density=0.5) if is_int else \
+        inputs.symmetric_gauss(N, seed=N + n)
+    beta = 0.01 * np.sqrt(2048.0 / N) if is_int else 1.0
+    kw = dict(n=n, L0=100, seed=17, init="random", block=tile[0], groups=tile[1])
+    g = gpu_run(Q, beta, mode, 200, chains=6, **kw)
+    assert g["tile"] == tile and g["flavour"] == flavour
+    _, cov = replay_check(g["log"], Q, beta, mode, rows=[0, 5], is_int=is_int, gcur=g["cur"], n=n, L0=100, seed=17,
+                          init="random")
+    assert cov.compared == 2 * 200 and cov.finals == 2
+    u = gpu_run(Q, beta, mode, 200, chains=6, log=False, **kw)
+    for key in ("x", "h", "E", "L", "sub", "step"):
+        assert np.array_equal(u["cur"][key], g["cur"][key]), key
+    for key in ("flips", "stays", "sum_M", "anomalies"):
+        assert np.array_equal(u["stats"][key], g["stats"][key]), key
