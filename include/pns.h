@@ -187,7 +187,8 @@ void pns_opts_default(pns_opts* opts);
  * used for every chain unless opts->betas is given.  subset_size is n in
  * [1, N] for BASIC and the UNBIASED modes and is ignored by RF (n = N).
  * The initial fields h = Q_offdiag x0 and energies x0^T Q x0 are computed on
- * the GPU.  On success *out owns all device memory of the sampler until
+ * the GPU (one matrix product per problem on the matrix cores, see
+ * pns_refresh).  On success *out owns all device memory of the sampler until
  * pns_destroy.
  * Errors: PNS_EINVAL (N <= 0, n outside [1, N], beta < 0 or not finite,
  *         unknown dtype/layout/mode/launch, SYMMETRIC Q not symmetric, a field
@@ -408,6 +409,20 @@ int pns_read_betas(pns_ctx* ctx, double* betas);
 /* Tempering ladder [num_chains]: entry g*temps + t is the chain of group g
  * (0..temps-1) at temperature position t.  Errors: PNS_EINVAL (no swap yet). */
 int pns_read_ladder(pns_ctx* ctx, int32_t* ladder);
+
+/*
+ * Recompute every chain's local fields h = offdiag(Q) x and energy x^T Q x
+ * from its current state, overwriting the incrementally maintained values:
+ * H = X A for all chains of a problem as one matrix product on the matrix
+ * cores (integer Q on the int8 cores, split into bytes, exact; float Q on the
+ * FP64 cores), the computation that also gives the initial fields on
+ * creation.  Integer fields are exact either way; float32 Q fields are
+ * accumulated in FP64 each flip, so their drift over 1e5 flips stays near
+ * FP64 rounding, and a refresh resets it.  States, step counters and the
+ * last record are unchanged.  Asynchronous on the context's stream.
+ * Errors: PNS_EINVAL (NULL ctx), PNS_EDEVICE.
+ */
+int pns_refresh(pns_ctx* ctx);
 
 /* ---- kernel timing per launch class ----
  *

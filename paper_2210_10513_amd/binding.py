@@ -44,7 +44,7 @@ EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_cu
            "pns_moments_f64", "pns_read_rb_weights", "pns_snapshot_moments_rb", "pns_cont_opts_default",
            "pns_cont_create", "pns_cont_run", "pns_cont_read", "pns_cont_read_log", "pns_cont_read_sums",
            "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy", "pns_save", "pns_load", "pns_profile",
-           "pns_profile_read", "pns_class_of_chain", "pns_moments_noalloc"]
+           "pns_profile_read", "pns_class_of_chain", "pns_moments_noalloc", "pns_refresh"]
 
 
 class pns_class_profile(ctypes.Structure):
@@ -155,6 +155,7 @@ def _load() -> ctypes.CDLL:
     L.pns_read_betas.argtypes = [vp, vp]
     L.pns_read_ladder.argtypes = [vp, vp]
     L.pns_moments_noalloc.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
+    L.pns_refresh.argtypes = [vp]
     L.pns_profile.argtypes = [vp, i32]
     L.pns_profile_read.argtypes = [vp, ctypes.POINTER(pns_class_profile), i32, ctypes.POINTER(i32)]
     L.pns_class_of_chain.argtypes = [vp, vp]
@@ -183,7 +184,7 @@ def _load() -> ctypes.CDLL:
                  "pns_snapshot_moments_rb", "pns_cont_create", "pns_cont_run", "pns_cont_read", "pns_cont_read_log",
                  "pns_cont_read_sums", "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy",
                  "pns_save", "pns_load", "pns_profile", "pns_profile_read", "pns_class_of_chain",
-                 "pns_moments_noalloc"):
+                 "pns_moments_noalloc", "pns_refresh"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -427,6 +428,10 @@ def pns_moments_noalloc(X, m, G, sum_m=None, *, N: Optional[int] = None, ldx: Op
     _check(lib.pns_moments_noalloc(_addr(X), ld, _addr(m), K, n, _addr(G), _addr(sum_m), _stream_handle(stream)))
 
 
+def pns_refresh(ctx) -> None:
+    _check(lib.pns_refresh(ctx))
+
+
 def pns_profile(ctx, enable: bool = True) -> None:
     _check(lib.pns_profile(ctx, 1 if enable else 0))
 
@@ -632,6 +637,11 @@ class Sampler:
         l = np.zeros(self.num_chains, np.int32)
         pns_read_ladder(self.ctx, l)
         return l
+
+    def refresh(self) -> "Sampler":
+        """Recompute every chain's fields and energy from its state (pns_refresh)."""
+        pns_refresh(self.ctx)
+        return self
 
     def save(self) -> np.ndarray:
         """Checkpoint of every chain's state (pns_save) as a byte array."""

@@ -113,10 +113,12 @@ hipError_t launch_steps_f32(int flav, bool instr, int block, int groups, int gri
 // True if a kernel exists for this tile shape and types.
 bool have_tile(int32_t qtype, int32_t htype, int32_t block, int32_t groups);
 
-// Initial bits (random policy), fields h = A x and energies of every chain.
-// host_chain_problem mirrors args.chain_problem on the host.
+// Initial bits (random policy), fields h = A x (matrix-core products over
+// the chains of each problem) and energies of every chain.
+// host_chain_problem mirrors args.chain_problem on the host, host_pitch the
+// problems' pitches (indexed by problem).  last_E may be NULL (left as is).
 hipError_t launch_init_with_map(int32_t qtype, int32_t htype, int32_t max_pitch, hipStream_t stream,
-                                const InitArgs& args, const int32_t* host_chain_problem);
+                                const InitArgs& args, const int32_t* host_chain_problem, const int64_t* host_pitch);
 
 // A, diag of a coefficient matrix on the device (one workgroup per row) and
 // the checks of its entries: flags [4] (asymmetry, non-finite, max row sum

@@ -184,45 +184,175 @@ __global__ void init_random_bits_kernel(InitArgs a)
     a.x[a.foff[chain] + j] = bit;
 }
 
-// h[c][f] = sum_j x[c][j] A[j][f] for a tile of 16 chains of one problem and
-// 256 fields; each row segment of A read is reused by the 16 chains.
-template <typename QT, typename HT>
-__global__ __launch_bounds__(256) void init_fields_kernel(InitArgs a, int32_t cbeg, int32_t cend)
+// Fields of many chains as one matrix product, H = X A (X the chains' 0/1
+// states, [chains][N]; A the off-diagonal coefficients, symmetric), on the
+// matrix cores.  A workgroup of four waves computes 64 chains x 64 fields,
+// each wave 16 chains x four 16 x 16 tiles.  A is symmetric, so the operand
+// column of field f over k is row f of A, read contiguously.  Bits past N
+// (pitch padding of x) are masked out.
+
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+// 16 int8 (0/1) states x[row][k .. k+15] as the int8 operand, bytes at or
+// past N cleared; also their sum.
+__device__ __forceinline__ i32x4_t x_bytes16(const uint8_t* xrow, int64_t k, int64_t N, int32_t* sum)
 {
-    constexpr int CT = 16;
-    __shared__ uint8_t xs[CT][256];
-    const int tid = threadIdx.x;
-    const int c0 = cbeg + blockIdx.y * CT;
-    const Problem P = a.problems[a.chain_problem[c0]];
-    const int64_t f = (int64_t)blockIdx.x * 256 + tid;
-    HT acc[CT];
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (xrow != nullptr) v = *reinterpret_cast<const uint4*>(xrow + k);
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    int32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < CT; ++i) acc[i] = (HT)0;
-    const QT* A = reinterpret_cast<const QT*>(P.A);
-    for (int64_t j0 = 0; j0 < P.N; j0 += 256) {
-        __syncthreads();
-        for (int i = 0; i < CT; ++i) {
-            const int c = c0 + i;
-            const int64_t j = j0 + tid;
-            xs[i][tid] = (c < cend && j < P.N) ? a.x[a.foff[c] + j] : (uint8_t)0;
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (k + 4 * q + b >= N) w[q] &= ~(0xFFu << (8 * b));
         }
-        __syncthreads();
-        if (f < P.pitch) {
-            const int64_t jn = P.N - j0 < 256 ? P.N - j0 : 256;
-            for (int64_t jj = 0; jj < jn; ++jj) {
-                const HT v = (HT)A[(j0 + jj) * P.pitch + f];
+        w[q] &= 0x01010101u;  // states are 0/1 bytes
+        s += __builtin_popcount(w[q]);
+    }
+    *sum += s;
+    return (i32x4_t){(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+}
+
+// Integer coefficients on the int8 matrix cores (exact int32 sums): an entry
+// is split into bytes, the top one signed and the others offset by -128 into
+// int8, v = sum_p 256^p b_p + 128 (1 + 256 + ...), so
+// H = sum_p 256^p (X B_p) + 128 (1 + 256 + ...) rowsum(X).
+template <typename QT, typename HT>
+__global__ __launch_bounds__(256) void init_fields_i8_kernel(InitArgs a, int32_t cbeg, int32_t cend)
+{
+    constexpr int NP = (int)sizeof(QT);  // byte pieces of an entry: 2 (int16) or 4 (int32)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kg = lane >> 4;
+    const Problem P = a.problems[a.chain_problem[cbeg]];
+    const int32_t cw = cbeg + (int32_t)blockIdx.y * 64 + wave * 16;  // this wave's first chain
+    const int64_t f0 = (int64_t)blockIdx.x * 64;
+    const int32_t crow = cw + r16;  // chain of this lane's operand row
+    const uint8_t* xrow = crow < cend ? a.x + a.foff[crow] : nullptr;
+    const QT* A = reinterpret_cast<const QT*>(P.A);
+    i32x4_t acc[NP][4];
 #pragma unroll
-                for (int i = 0; i < CT; ++i)
-                    if (xs[i][jj]) acc[i] += v;
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[p][t] = (i32x4_t){0, 0, 0, 0};
+    int32_t xsum = 0;
+    for (int64_t k0 = 0; k0 < P.pitch; k0 += 64) {
+        const int64_t k = k0 + 16 * kg;  // this lane's 16 values of the 64-deep step
+        const i32x4_t xop = x_bytes16(xrow, k, P.N, &xsum);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            // A has N rows: the fields past N (pitch padding) read zeros
+            const int64_t fr = f0 + 16 * t + r16;
+            const bool rok = fr < P.N;
+            const QT* src = A + (rok ? fr : 0) * P.pitch + k;
+            uint32_t bw[NP][4];
+            if constexpr (NP == 2) {
+                uint4 u[2] = {make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u)};
+                if (rok) {
+                    u[0] = *reinterpret_cast<const uint4*>(src);
+                    u[1] = *reinterpret_cast<const uint4*>(src + 8);
+                }
+                const uint32_t wd[8] = {u[0].x, u[0].y, u[0].z, u[0].w, u[1].x, u[1].y, u[1].z, u[1].w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    // entries 4q .. 4q+3: two 16-bit entries per word
+                    const uint32_t e0 = wd[2 * q] & 0xFFFFu, e1 = wd[2 * q] >> 16;
+                    const uint32_t e2 = wd[2 * q + 1] & 0xFFFFu, e3 = wd[2 * q + 1] >> 16;
+                    bw[1][q] = (e0 >> 8) | ((e1 >> 8) << 8) | ((e2 >> 8) << 16) | ((e3 >> 8) << 24);
+                    bw[0][q] = ((e0 & 0xFFu) | ((e1 & 0xFFu) << 8) | ((e2 & 0xFFu) << 16) | ((e3 & 0xFFu) << 24)) ^
+                               0x80808080u;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint4 u = rok ? *reinterpret_cast<const uint4*>(src + 4 * q) : make_uint4(0u, 0u, 0u, 0u);
+                    const uint32_t e[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        uint32_t w = 0;
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) w |= ((e[b] >> (8 * p)) & 0xFFu) << (8 * b);
+                        bw[p][q] = p == 3 ? w : (w ^ 0x80808080u);
+                    }
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const i32x4_t bop = {(int)bw[p][0], (int)bw[p][1], (int)bw[p][2], (int)bw[p][3]};
+                acc[p][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xop, bop, acc[p][t], 0, 0, 0);
             }
         }
     }
-    if (f < P.pitch) {
+    // the states' sums of the 16 operand rows (four lanes hold each row)
+    xsum += __shfl_xor(xsum, 16, 64);
+    xsum += __shfl_xor(xsum, 32, 64);
+    constexpr int64_t kOff = NP == 2 ? 128 : 128 * (1 + 256 + 65536);  // offsets of the low bytes
 #pragma unroll
-        for (int i = 0; i < CT; ++i) {
-            const int c = c0 + i;
-            if (c < cend) reinterpret_cast<HT*>(a.h)[a.foff[c] + f] = acc[i];
+    for (int e = 0; e < 4; ++e) {
+        const int row = kg * 4 + e;  // output rows of this lane: chain cw + row, field f0 + 16t + r16
+        const int64_t rs = __shfl(xsum, row, 64);
+        const int32_t c = cw + row;
+        if (c >= cend) continue;
+        HT* hc = reinterpret_cast<HT*>(a.h) + a.foff[c];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            int64_t v = kOff * rs;
+            int64_t scale = 1;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                v += scale * (int64_t)acc[p][t][e];
+                scale *= 256;
+            }
+            hc[f0 + 16 * t + r16] = (HT)v;
         }
+    }
+}
+
+// Float coefficients on the FP64 matrix cores: x and A as FP64 (both exact),
+// FP64 accumulation, the precision of the FP64 fields.  Each lane takes four
+// consecutive k of its row (k0 + 4 kg + m); MFMA m of a 16-deep step sums over
+// the four lane groups.
+template <typename QT, typename HT>
+__global__ __launch_bounds__(256) void init_fields_f64_kernel(InitArgs a, int32_t cbeg, int32_t cend)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kg = lane >> 4;
+    const Problem P = a.problems[a.chain_problem[cbeg]];
+    const int32_t cw = cbeg + (int32_t)blockIdx.y * 64 + wave * 16;
+    const int64_t f0 = (int64_t)blockIdx.x * 64;
+    const int32_t crow = cw + r16;
+    const uint8_t* xrow = crow < cend ? a.x + a.foff[crow] : nullptr;
+    const float* A = reinterpret_cast<const float*>(P.A);
+    f64x4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
+    for (int64_t k0 = 0; k0 < P.pitch; k0 += 16) {
+        const int64_t k = k0 + 4 * kg;
+        uint32_t xw = xrow != nullptr ? *reinterpret_cast<const uint32_t*>(xrow + k) : 0u;
+        double xd[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) xd[m] = (k + m < P.N && ((xw >> (8 * m)) & 1u)) ? 1.0 : 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t fr = f0 + 16 * t + r16;  // A has N rows: fields past N read zeros
+            const float4 av = fr < P.N ? *reinterpret_cast<const float4*>(A + fr * P.pitch + k)
+                                       : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float am[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xd[m], (double)am[m], acc[t], 0, 0, 0);
+        }
+    }
+    // output register e of a lane holds row kg + 4 e (rows interleaved across
+    // the lane groups in the FP64 product), column r16
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int32_t c = cw + kg + 4 * e;
+        if (c >= cend) continue;
+        HT* hc = reinterpret_cast<HT*>(a.h) + a.foff[c];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) hc[f0 + 16 * t + r16] = (HT)acc[t][e];
     }
 }
 
@@ -263,7 +393,7 @@ __global__ __launch_bounds__(256) void init_energy_kernel(InitArgs a)
         if constexpr (std::is_floating_point<HT>::value) e = __double_as_longlong(sd[0]);
         else e = si[0] / 2;
         a.E[chain] = e;
-        a.last_E[chain] = e;
+        if (a.last_E != nullptr) a.last_E[chain] = e;
     }
 }
 
@@ -378,7 +508,8 @@ bool have_tile(int32_t qtype, int32_t htype, int32_t block, int32_t groups)
 }
 
 template <typename QT, typename HT>
-static hipError_t init_typed(int32_t max_pitch, hipStream_t st, const InitArgs& a, const int32_t* host_chain_problem)
+static hipError_t init_typed(int32_t max_pitch, hipStream_t st, const InitArgs& a, const int32_t* host_chain_problem,
+                             const int64_t* host_pitch)
 {
     if (a.init == 1) {
         hipLaunchKernelGGL(init_random_bits_kernel, dim3((max_pitch + 255) / 256, a.num_chains), dim3(256), 0, st, a);
@@ -390,10 +521,14 @@ static hipError_t init_typed(int32_t max_pitch, hipStream_t st, const InitArgs& 
     while (c < a.num_chains) {
         int32_t e = c + 1;
         while (e < a.num_chains && host_chain_problem[e] == host_chain_problem[c]) ++e;
-        for (int32_t t = c; t < e; t += 16 * 65535) {
-            const int32_t tend = t + 16 * 65535 < e ? t + 16 * 65535 : e;
-            hipLaunchKernelGGL((init_fields_kernel<QT, HT>), dim3((max_pitch + 255) / 256, (tend - t + 15) / 16),
-                               dim3(256), 0, st, a, t, tend);
+        for (int32_t t = c; t < e; t += 64 * 65535) {
+            const int32_t tend = t + 64 * 65535 < e ? t + 64 * 65535 : e;
+            // every chain of [t, tend) belongs to one problem: its pitch tiles the fields
+            const dim3 grid((unsigned)(host_pitch[host_chain_problem[c]] / 64), (unsigned)((tend - t + 63) / 64));
+            if constexpr (std::is_floating_point<QT>::value)
+                hipLaunchKernelGGL((init_fields_f64_kernel<QT, HT>), grid, dim3(256), 0, st, a, t, tend);
+            else
+                hipLaunchKernelGGL((init_fields_i8_kernel<QT, HT>), grid, dim3(256), 0, st, a, t, tend);
             hipError_t er = hipGetLastError();
             if (er != hipSuccess) return er;
         }
@@ -404,12 +539,16 @@ static hipError_t init_typed(int32_t max_pitch, hipStream_t st, const InitArgs& 
 }
 
 hipError_t launch_init_with_map(int32_t qtype, int32_t htype, int32_t max_pitch, hipStream_t stream,
-                                const InitArgs& args, const int32_t* host_chain_problem)
+                                const InitArgs& args, const int32_t* host_chain_problem, const int64_t* host_pitch)
 {
-    if (qtype == Q_I16 && htype == H_I32) return init_typed<int16_t, int32_t>(max_pitch, stream, args, host_chain_problem);
-    if (qtype == Q_I32 && htype == H_I32) return init_typed<int32_t, int32_t>(max_pitch, stream, args, host_chain_problem);
-    if (qtype == Q_I32 && htype == H_I64) return init_typed<int32_t, int64_t>(max_pitch, stream, args, host_chain_problem);
-    if (qtype == Q_F32 && htype == H_F64) return init_typed<float, double>(max_pitch, stream, args, host_chain_problem);
+    if (qtype == Q_I16 && htype == H_I32)
+        return init_typed<int16_t, int32_t>(max_pitch, stream, args, host_chain_problem, host_pitch);
+    if (qtype == Q_I32 && htype == H_I32)
+        return init_typed<int32_t, int32_t>(max_pitch, stream, args, host_chain_problem, host_pitch);
+    if (qtype == Q_I32 && htype == H_I64)
+        return init_typed<int32_t, int64_t>(max_pitch, stream, args, host_chain_problem, host_pitch);
+    if (qtype == Q_F32 && htype == H_F64)
+        return init_typed<float, double>(max_pitch, stream, args, host_chain_problem, host_pitch);
     return hipErrorInvalidConfiguration;
 }
 
