@@ -21,8 +21,8 @@
  * modes a step whose multiplicity exceeds the remaining budget L emits
  * (J, M = L), keeps the state and switches to the next set (Alg 6).
  * The next state is chosen with probability proportional to
- * min(1, exp(-beta dE_i)) by the inverse-CDF rule of App. C over the subset
- * in increasing bit order.  Randomness: Philox4x32-10 keyed by the 64-bit
+ * min(1, exp(-beta dE_i)) by the inverse-CDF rule of the appendix "How to
+ * Sample Proportionally" over the subset in increasing bit order.  Randomness: Philox4x32-10 keyed by the 64-bit
  * seed, counter (chain id, step low, step high, stream); the draws of a step
  * depend only on (seed, chain id, step), so results are identical whatever
  * the launch form, workgroup size or chunking.
@@ -337,7 +337,7 @@ int pns_snapshots_clear(pns_ctx* ctx);
 
 /*
  * Optimization Rejection-Free (Alg 9) / Optimization PNS (Alg 10) as burn-in
- * (Sec 7): advance every chain by `steps` jumps of the jump chain whose
+ * (Sec 8): advance every chain by `steps` jumps of the jump chain whose
  * acceptance is min{1, [pi(y)/pi(x)]^(1/T)} (the target at beta / T) with no
  * multiplicity, keeping per chain the state of largest pi seen, X_max
  * (initially the chain's state at the first call).  Problems whose subset
@@ -348,8 +348,8 @@ int pns_snapshots_clear(pns_ctx* ctx);
  * the chains' counters like pns_run (step k uses the same Philox numbers), and
  * the per-step log, histograms and snapshots record these jumps with M = 1.
  * Budgets and set indices of Unbiased chains are left as they are; pns_run
- * afterwards samples from the chains' current states (Sec 7.2), or from X_max
- * after pns_adopt_best (Sec 7.1).  Queued on the context's stream.
+ * afterwards samples from the chains' current states (Sec 8.2), or from X_max
+ * after pns_adopt_best (Sec 8.1).  Queued on the context's stream.
  * Errors: PNS_EINVAL (steps < 0, T not finite and > 0), PNS_ENOMEM,
  * PNS_EDEVICE.
  */
@@ -633,12 +633,12 @@ int pns_log_partition(const void* Q, int32_t N, int32_t dtype, int32_t layout, d
 
 /* ---- continuous states: Unbiased PNS for the continuous case (Alg 7) ----
  *
- * Target on R^dim (the donut of Sec 6, written for any dimension):
+ * Target on R^dim (the donut of Sec 7, written for any dimension):
  *     log pi(x) = -(|x|^2 - mu0)^2 / (2 sigma^2) + const.
- * Proposal: increments with i.i.d. N(0, 1) coordinates (Sec 6), symmetric,
+ * Proposal: increments with i.i.d. N(0, 1) coordinates (Sec 7), symmetric,
  * so every acceptance ratio is pi(y) / pi(x).  A partial neighbor set is
  * `pairs` offsets delta_1..delta_P drawn from the proposal, each used with
- * both signs (Sec 6: 25 pairs, 50 neighbours; the pairs make the set
+ * both signs (Sec 7: 25 pairs, 50 neighbours; the pairs make the set
  * reversible); neighbour j of x is x + delta_j (j < P) and x - delta_{j-P}
  * (P <= j < 2P).  As in Alg 6, with M = 1 + Geometric(p) and
  * p = (1 / 2P) sum_j min(1, pi(y_j) / pi(x)):  M <= L jumps to a neighbour
@@ -656,11 +656,11 @@ int pns_log_partition(const void* Q, int32_t N, int32_t dtype, int32_t layout, d
 typedef struct pns_cont pns_cont;
 
 typedef struct pns_cont_opts {
-    int32_t dim;            /* 1 .. 7 (Sec 6: 2)                                */
-    int32_t pairs;          /* P, 1 .. 32: 2P neighbours per set (Sec 6: 25)    */
-    double mu0;             /* squared radius of the donut (Sec 6: 9)           */
-    double sigma;           /* width (Sec 6: 0.1), > 0                          */
-    int64_t L0;             /* original samples per set, 1 .. 2^53 (Sec 6: 1000) */
+    int32_t dim;            /* 1 .. 7 (Sec 7: 2)                                */
+    int32_t pairs;          /* P, 1 .. 32: 2P neighbours per set (Sec 7: 25)    */
+    double mu0;             /* squared radius of the donut (Sec 7: 9)           */
+    double sigma;           /* width (Sec 7: 0.1), > 0                          */
+    int64_t L0;             /* original samples per set, 1 .. 2^53 (Sec 7: 1000) */
     uint64_t seed;
     int32_t num_chains;     /* >= 1                                             */
     uint32_t chain_id_base; /* chain c uses counter word chain_id_base + c      */
@@ -671,7 +671,7 @@ typedef struct pns_cont_opts {
     int32_t reserved[8];    /* must be zero                                       */
 } pns_cont_opts;
 
-/* Sec 6 defaults: dim 2, 25 pairs, mu0 9, sigma 0.1, L0 1000, one chain. */
+/* Sec 7 defaults: dim 2, 25 pairs, mu0 9, sigma 0.1, L0 1000, one chain. */
 void pns_cont_opts_default(pns_cont_opts* opts);
 
 /*
@@ -710,7 +710,7 @@ int pns_cont_read_log(pns_cont* ctx, int32_t* actions, int64_t* multiplicities, 
  * over every record since creation or the last pns_cont_clear_sums, with
  * weights M (row 0) and the expected multiplicities (row 1): sum w, then
  * sum w x_i, sum w x_i^2, sum w x_i^4 and sum w 1(x_i > 0) for
- * i = 0 .. dim-1.  Their ratios are the estimators of Sec 6 (E[x_i],
+ * i = 0 .. dim-1.  Their ratios are the estimators of Sec 7 (E[x_i],
  * E[x_i^2], E[x_i^4], P(x_i > 0)).  Host or device.  Synchronises.
  */
 int pns_cont_read_sums(pns_cont* ctx, double* sums);

@@ -1,4 +1,4 @@
-"""Exact moments of the donut target of Sec 6 (TEST INFRASTRUCTURE).
+"""Exact moments of the donut target of Sec 7 (TEST INFRASTRUCTURE).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU baseline
 may import this module.
@@ -15,7 +15,7 @@ So, for every coordinate i:
     E[x_i^4] = 3 E[u^2] / (d (d + 2))           (E[theta_i^4] = 3/(d(d+2))),
 
 with E[u], E[u^2] by adaptive quadrature (scipy.integrate.quad).  For d = 2
-these are E[u]/2 and 3 E[u^2]/8 (Sec 6 prints mu0^2/2 and 3/8 (mu0^4 +
+these are E[u]/2 and 3 E[u^2]/8 (Sec 7 prints mu0^2/2 and 3/8 (mu0^4 +
 sigma^2), garbled readings of mu0/2 and 3/8 (mu0^2 + sigma^2) when the
 truncation of the radial law is negligible).
 """

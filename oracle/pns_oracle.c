@@ -18,9 +18,10 @@
  *   - on the QUBO target of Sec 4 with single-bit-flip neighbours and a
  *     uniform proposal 1/N (so the proposal cancels in every ratio);
  *   - Unbiased PNS for continuous states (Alg 7) on the donut target of
- *     Sec 6 (orc_cont_run, at the end of this file);
- *   - proportional choice by the inverse-CDF rule of App. C (first index
- *     whose running sum exceeds U times the total).
+ *     Sec 7 (orc_cont_run, at the end of this file);
+ *   - proportional choice by the inverse-CDF rule of the appendix "How to
+ *     Sample Proportionally" (first index whose running sum exceeds U times
+ *     the total).
  * Conventions (each one a reading of the paper where it is silent):
  *   - target pi_beta(x) proportional to exp(-beta * x^T Q x); the paper's
  *     pi(x) = exp{x^T Q x} is beta = 1 with Q replaced by -Q;
@@ -826,15 +827,15 @@ int orc_basic_onestep(int64_t num_states, int32_t D, const int64_t* nbr, const d
 }
 
 /* ------------------------------------------------------------------------- */
-/* Continuous Unbiased PNS (Alg 7) on the donut target of Sec 6.             */
+/* Continuous Unbiased PNS (Alg 7) on the donut target of Sec 7.             */
 /* ------------------------------------------------------------------------- */
 /*
  * Target on R^d: log pi(x) = -(|x|^2 - mu0)^2 / (2 sigma^2) + const (the
- * density of Sec 6 written for any dimension d; d = 2 in the paper).
+ * density of Sec 7 written for any dimension d; d = 2 in the paper).
  * Proposal: standard normal increments, symmetric, so every acceptance ratio
  * is pi(y) / pi(x).  Partial neighbor set i of a chain: P offset vectors
  * delta_1..delta_P with i.i.d. N(0, 1) coordinates, each used with both signs
- * (the pairs of Sec 6 keep the set reversible); the neighbours of x are
+ * (the pairs of Sec 7 keep the set reversible); the neighbours of x are
  * x + delta_j (j = 0..P-1) then x - delta_j (j = P..2P-1), in that order,
  * and the set is drawn anew after each block of L0 original samples.
  * Reading: the proposal restricted to the finite set is uniform over its 2P

@@ -849,7 +849,7 @@ class BatchSampler:
 
 class ContSampler:
     """Unbiased PNS for continuous states (Alg 7) on the donut target of
-    Sec 6, ``num_chains`` chains on the device (pns_cont_*)."""
+    Sec 7, ``num_chains`` chains on the device (pns_cont_*)."""
 
     def __init__(self, num_chains: int = 1, *, dim: int = 2, pairs: int = 25, mu0: float = 9.0, sigma: float = 0.1,
                  L0: int = 1000, seed: int = 0, x0=None, chain_id_base: int = 0, log_capacity: int = 0, stream=None):

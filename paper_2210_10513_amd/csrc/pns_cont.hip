@@ -1,4 +1,4 @@
-// Unbiased PNS for continuous states (Alg 7) on the donut target of Sec 6:
+// Unbiased PNS for continuous states (Alg 7) on the donut target of Sec 7:
 // log pi(x) = -(|x|^2 - mu0)^2 / (2 sigma^2) on R^D, symmetric normal
 // increments as the proposal, so every acceptance ratio is pi(y) / pi(x).
 //
@@ -15,8 +15,8 @@
 // workgroup.  Lane r of a group holds the signed offsets of neighbours
 // j = r m .. r m + m - 1 (m = ceil(2P / 8) <= 8) in registers and evaluates
 // their weights one after the other; a segmented DPP scan over the group gives
-// S, p and the inverse-CDF choice (App. C: the first neighbour whose running
-// sum exceeds U2 S).  The per-record scalar work (the multiplicity, the
+// S, p and the inverse-CDF choice (appendix "How to Sample Proportionally":
+// the first neighbour whose running sum exceeds U2 S).  The per-record scalar work (the multiplicity, the
 // budget, the expected multiplicity) is then shared by 8 chains per wave
 // instruction instead of being repeated by a whole wave for one chain.  The
 // state, its log-density, the budget and the estimator sums stay in registers

@@ -22,8 +22,9 @@
 //             bit order alone, whatever the tile shape;
 //   p, M    : p = S / n, M = 1 + floor(log U1 / log1p(-p)) in FP64;
 //   budget  : Unbiased: stay with M = L when M > L, else L -= M (Alg 6);
-//   select  : inverse CDF (App. C) over the subset in increasing bit order,
-//             resolved segment -> lane -> bit, published through LDS;
+//   select  : inverse CDF (appendix "How to Sample Proportionally") over the
+//             subset in increasing bit order, resolved segment -> lane -> bit,
+//             published through LDS;
 //   update  : flip, E += dE_c, h_j +-= A[c][j] from one coalesced row read,
 //             overlapped with the next step's random numbers.
 #pragma once
@@ -1042,8 +1043,8 @@ void step_kernel(const StepArgs a)
             }
         }
 
-        // Proportional choice (App. C): first bit whose running sum exceeds
-        // U2 * S, resolved segment -> lane -> bit.
+        // Proportional choice (appendix "How to Sample Proportionally"): first
+        // bit whose running sum exceeds U2 * S, resolved segment -> lane -> bit.
         {
             const double t = U.U2 * S;
             const bool pos_seg = lane < NSEG && sv > 0.0;

@@ -3,7 +3,7 @@ oracle runs.  This module draws only the problem data (matrices, inverse
 temperatures, initial states); it holds none of the sampler's arithmetic.
 
 The paper's experiments use synthetic random QUBO matrices (Sec 4: 16x16
-upper-triangular Q_ij ~ N(0, 10^2); Sec 7.2: N(0, 1)) and the 16-state
+upper-triangular Q_ij ~ N(0, 10^2); Sec 8.2: N(0, 1)) and the 16-state
 example of Sec 2.2; the workloads below keep those generators and scale them
 to the sizes the sampler is benchmarked at.  Target convention throughout:
 pi_beta(x) proportional to exp(-beta x^T Q x).
@@ -57,7 +57,7 @@ def symmetric_gauss(N: int, seed: int | None = None, tag: int = 0, dtype=np.floa
 
 
 def paper_upper_gauss(N: int = 16, sigma: float = 10.0, seed: int | None = None, tag: int = 100) -> np.ndarray:
-    """Sec 4 / Sec 7.2 generator: upper-triangular Q_ij ~ N(0, sigma^2) for
+    """Sec 4 / Sec 8.2 generator: upper-triangular Q_ij ~ N(0, sigma^2) for
     i <= j.  Returned as the build's matrix (the paper's Q negated), to be
     used with the UPPER layout and beta = 1."""
     rng = _rng(tag, seed)
@@ -137,7 +137,7 @@ def c5_fit(N: int, seed: int | None = None, chains: int = 8192) -> Workload:
 
 def donut_draws(C: int, dim: int = 2, mu0: float = 9.0, sigma: float = 0.1, seed: int | None = None,
                 tag: int = 200) -> np.ndarray:
-    """C exact draws [C, dim] from the donut density of Sec 6,
+    """C exact draws [C, dim] from the donut density of Sec 7,
     f(x) proportional to exp(-(|x|^2 - mu0)^2 / (2 sigma^2)) on R^dim: the
     squared radius u = |x|^2 has density proportional to
     exp(-(u - mu0)^2 / (2 sigma^2)) u^(dim/2 - 1) on u > 0 (drawn by rejection

@@ -1,7 +1,7 @@
-"""GPU parity of the optimization burn-in (Alg 9 / Alg 10, Sec 7): jumps,
+"""GPU parity of the optimization burn-in (Alg 9 / Alg 10, Sec 8): jumps,
 energies and the best state X_max against the oracle's MODE_OPT, sampling
 after a burn-in against the oracle restarted from the burned-in states, and
-the hybrid burn-in of Sec 7.2 converging to the target."""
+the hybrid burn-in of Sec 8.2 converging to the target."""
 import numpy as np
 import pytest
 
@@ -98,7 +98,7 @@ def test_adopt_best_moves_chains_to_x_max():
 
 
 def test_hybrid_burn_in_converges():
-    """Sec 7.2: 16 x 16 upper-triangular Q_ij ~ N(0, 1); Optimization PNS
+    """Sec 8.2: 16 x 16 upper-triangular Q_ij ~ N(0, 1); Optimization PNS
     (halves, n = 8) for K0 = K1 / 20 steps, then Rejection-Free for K1 jumps.
     The last jump-chain states of 100000 chains approach the jump chain's
     stationary law, proportional to alpha(x) pi(x) with alpha the escape

@@ -188,7 +188,7 @@ def test_snapshot_moments_rb_equal_oracle_on_read_back_snapshots():
 
 def test_rb_histogram_is_closer_to_pi_than_the_multiplicity_histogram():
     """Thm 3 (5) at scale: 16 x 16 upper-triangular Q_ij ~ N(0, 1) (the
-    Sec 7.2 model), 20000 RF chains from exact draws of pi, 100 records each:
+    Sec 8.2 model), 20000 RF chains from exact draws of pi, 100 records each:
     both weightings estimate pi, the expected multiplicities with the
     sampling noise of M removed."""
     from paper_2210_10513_amd.binding import Sampler

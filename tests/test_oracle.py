@@ -403,7 +403,7 @@ def test_planted_mistake_is_caught(name, tmp_path):
 
 
 # --------------------------------------------------------------------------
-# Optimization RF / PNS (Alg 9, Alg 10) used as burn-in (Sec 7)
+# Optimization RF / PNS (Alg 9, Alg 10) used as burn-in (Sec 8)
 # --------------------------------------------------------------------------
 
 def test_optimization_at_unit_temperature_is_the_jump_chain_without_multiplicity():

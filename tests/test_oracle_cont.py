@@ -1,5 +1,5 @@
 """Pins for the continuous Unbiased PNS oracle (Alg 7 on the donut target of
-Sec 6).  The oracle is checked against: the standard normal law of its
+Sec 7).  The oracle is checked against: the standard normal law of its
 offset draws (Kolmogorov-Smirnov, moments); every step rebuilt by brute force
 in numpy from the logged states (target density, escape probability over the
 2P neighbours x +- delta_j of the current set, the budget of Alg 7, the
@@ -122,7 +122,7 @@ def test_exact_time_estimates_match_the_donut_moments(d, sigma, P, L0, T, K):
     """From exact draws of pi the original chain stays at pi (each set's
     kernel keeps it), so (1/T) sum_t h(X_t) is unbiased: 400 independent
     chains give z-scores below 5 for x, x^2, x^4, 1(x > 0), |x|^2 and
-    (|x|^2 - mu0)^2 (Sec 6's workload: d = 2, mu0 = 9, sigma = 0.1,
+    (|x|^2 - mu0)^2 (Sec 7's workload: d = 2, mu0 = 9, sigma = 0.1,
     |N| = 50, L0 = 1000; and a wide donut in d = 3)."""
     est, _ = _run_window(d, 9.0, sigma, P, L0, 400, T, K, seed=5)
     z = _z_scores(est, _exact(d, 9.0, sigma))
