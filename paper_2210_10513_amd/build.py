@@ -20,12 +20,16 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libpns.so")
 ARCH = os.environ.get("PNS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["pns_step_i16.hip", "pns_step_i32.hip", "pns_step_i64.hip", "pns_step_f32.hip", "pns_kernels.hip",
-           "pns_moments.hip", "pns_cont.hip", "pns_runtime.cpp"]
+SOURCES = ["pns_step_i16.hip", "pns_step_i32.hip", "pns_step_i64.hip", "pns_step_f32.hip", "pns_wave_i16.hip",
+           "pns_wave_i32.hip", "pns_kernels.hip", "pns_moments.hip", "pns_cont.hip", "pns_runtime.cpp"]
 
 # Per-source additions: the moment kernel adds FP64 partial sums with the
-# hardware atomic add (device memory only).
-EXTRA_FLAGS = {"pns_moments.hip": ["-munsafe-fp-atomics"]}
+# hardware atomic add (device memory only); the window kernels keep the
+# constants of their rare paths where they are used instead of in registers
+# across the step loop (machine loop-invariant code motion off).
+EXTRA_FLAGS = {"pns_moments.hip": ["-munsafe-fp-atomics"],
+               "pns_wave_i16.hip": ["-mllvm", "-disable-machine-licm"],
+               "pns_wave_i32.hip": ["-mllvm", "-disable-machine-licm"]}
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

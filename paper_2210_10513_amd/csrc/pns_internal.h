@@ -110,8 +110,22 @@ hipError_t launch_steps_i64(int flav, bool instr, int block, int groups, int gri
 hipError_t launch_steps_f32(int flav, bool instr, int block, int groups, int grid, size_t dyn, hipStream_t st,
                             const StepArgs& a, bool probe);
 
-// True if a kernel exists for this tile shape and types.
+// Window kernels of one, two or four waves per chain (flavour 5: Unbiased
+// PNS with systematic sets, integer coefficients with int32 fields).
+hipError_t launch_waves_i16(bool instr, int block, int groups, int grid, hipStream_t st, const StepArgs& a,
+                            bool probe);
+hipError_t launch_waves_i32(bool instr, int block, int groups, int grid, hipStream_t st, const StepArgs& a,
+                            bool probe);
+
+// True if a step kernel exists for this tile shape and types.
 bool have_tile(int32_t qtype, int32_t htype, int32_t block, int32_t groups);
+// True if a window kernel (flavour 5) exists for this tile shape and types.
+bool have_wave_tile(int32_t qtype, int32_t htype, int32_t block, int32_t groups);
+
+// Bytes of readable padding after the last row of a coefficient matrix: the
+// window kernels load whole tiles of a row (up to 16384 elements of 4 bytes
+// from its start) and drop what lies past the pitch.
+constexpr size_t kRowTailBytes = 16384 * 4;
 
 // Initial bits (random policy), fields h = A x (matrix-core products over
 // the chains of each problem) and energies of every chain.

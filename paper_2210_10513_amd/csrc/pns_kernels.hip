@@ -489,6 +489,11 @@ __global__ void fill64_kernel(int64_t* p, int64_t count, int64_t value)
 hipError_t launch_steps(int32_t qtype, int32_t htype, int32_t flav, bool instr, int32_t block, int32_t groups,
                         int32_t grid, size_t dyn_lds, hipStream_t stream, const StepArgs& args)
 {
+    if (flav == 5) {
+        if (qtype == Q_I16 && htype == H_I32) return launch_waves_i16(instr, block, groups, grid, stream, args, false);
+        if (qtype == Q_I32 && htype == H_I32) return launch_waves_i32(instr, block, groups, grid, stream, args, false);
+        return hipErrorInvalidConfiguration;
+    }
     if (qtype == Q_I16 && htype == H_I32) return launch_steps_i16(flav, instr, block, groups, grid, dyn_lds, stream, args, false);
     if (qtype == Q_I32 && htype == H_I32) return launch_steps_i32(flav, instr, block, groups, grid, dyn_lds, stream, args, false);
     if (qtype == Q_I32 && htype == H_I64) return launch_steps_i64(flav, instr, block, groups, grid, dyn_lds, stream, args, false);
@@ -504,6 +509,15 @@ bool have_tile(int32_t qtype, int32_t htype, int32_t block, int32_t groups)
     if (qtype == Q_I32 && htype == H_I32) e = launch_steps_i32(0, false, block, groups, 0, 0, nullptr, none, true);
     if (qtype == Q_I32 && htype == H_I64) e = launch_steps_i64(0, false, block, groups, 0, 0, nullptr, none, true);
     if (qtype == Q_F32 && htype == H_F64) e = launch_steps_f32(0, false, block, groups, 0, 0, nullptr, none, true);
+    return e == hipSuccess;
+}
+
+bool have_wave_tile(int32_t qtype, int32_t htype, int32_t block, int32_t groups)
+{
+    StepArgs none{};
+    hipError_t e = hipErrorInvalidConfiguration;
+    if (qtype == Q_I16 && htype == H_I32) e = launch_waves_i16(false, block, groups, 0, nullptr, none, true);
+    if (qtype == Q_I32 && htype == H_I32) e = launch_waves_i32(false, block, groups, 0, nullptr, none, true);
     return e == hipSuccess;
 }
 

@@ -155,17 +155,19 @@ Tile default_tile(int32_t N)
     return {1024, 4};
 }
 
-// Tiles of four waves with 32 or 64 fields per lane: three (256 x 8) or two
-// (256 x 16) chains per compute unit where the table's tiles hold two or one,
-// for the subsets whose weights touch at most two 4-bit groups per wave
-// (compact and two-group windows); the other flavours weigh every group of a
-// lane and spill there.
-bool wide_tile(Tile t) { return t.block == 256 && t.groups >= 8; }
+// Tiles of 32 or more fields per lane: the step kernel's four-wave tiles
+// (three (256 x 8) or two (256 x 16) chains per compute unit where the table's
+// tiles hold two or one) for the subsets whose weights touch at most two 4-bit
+// groups per wave (compact and two-group windows), and the window kernel's
+// tiles; the other flavours weigh every group of a lane and spill there.
+bool wide_tile(Tile t) { return t.groups >= 8; }
 
-// Every tile the step kernels are compiled for.
-// (256 x 16 exists for 32-bit fields only: have_tile tells.)
-const Tile kTiles[] = {{64, 1},  {64, 2},  {64, 4},  {128, 1}, {128, 2},  {128, 4},  {256, 1},  {256, 2},
-                       {256, 4}, {256, 8}, {256, 16}, {512, 2}, {512, 4}, {1024, 2}, {1024, 4}};
+// Every tile a kernel is compiled for: the step kernels' and (64 x 8 .. 24,
+// 128 x 16 and 24, 256 x 16) the window kernels'.
+// (Which exist for which types: have_tile and have_wave_tile tell.)
+const Tile kTiles[] = {{64, 1},   {64, 2},  {64, 4},  {64, 8},   {64, 16},  {64, 24}, {128, 1},  {128, 2},
+                       {128, 4},  {128, 16}, {128, 24}, {256, 1}, {256, 2},  {256, 4}, {256, 8},  {256, 16},
+                       {512, 2},  {512, 4},  {1024, 2}, {1024, 4}};
 
 // True if no window of n cyclically consecutive bits holds bits of two
 // different 4-bit groups within one wave: the lanes of wave w in group g hold
@@ -216,6 +218,29 @@ bool window_two_groups_ok(int32_t N, int32_t n, int32_t block, int32_t groups)
     return true;
 }
 
+// True if every systematic set of the run, S_i = {(i n + t) mod N : t < n},
+// meets at most four of any one wave's groups: the window kernel stages the
+// energy differences of that many groups per wave.
+bool window_slots_ok(int32_t N, int32_t n, int32_t block, int32_t groups)
+{
+    if (n >= N || N > 16384) return false;
+    const int32_t W = block / 64;
+    const int64_t sets = N / gcd64(N, n);
+    auto range = [](int64_t lo, int64_t hi) { return (~0ull >> (63 - hi)) & (~0ull << lo); };
+    for (int64_t i = 0; i < sets; ++i) {
+        const int64_t st = (i * n) % N;
+        const int64_t e0 = std::min<int64_t>(st + n, N);
+        uint64_t m = range(st >> 8, (e0 - 1) >> 8);
+        if (st + n > N) m |= range(0, (st + n - N - 1) >> 8);
+        for (int32_t w = 0; w < W; ++w) {
+            int hit = 0;
+            for (int32_t g = 0; g < groups && g * W + w < 64; ++g) hit += (m >> (g * W + w)) & 1ull ? 1 : 0;
+            if (hit > 4) return false;
+        }
+    }
+    return true;
+}
+
 // How the step kernel forms the subset: 0 every bit, 1 systematic window,
 // 2 random subset drawn in LDS, 3 compact systematic window, 4 two-group
 // systematic window.
@@ -232,6 +257,18 @@ int32_t flavour_of(int32_t mode, int32_t N, int32_t n, int32_t block, int32_t gr
 
 bool have_tile_any(int32_t qtype, int32_t htype, Tile t) { return have_tile(qtype, htype, t.block, t.groups); }
 
+// Kernel flavour of a problem on tile t, or -1 if no kernel runs it there:
+// the window kernel (5) where it exists and the run is Unbiased PNS with
+// systematic sets whose windows fit its slots, else the step kernel's.
+int32_t flavour_for(int32_t mode, int32_t N, int32_t n, Tile t, int32_t qtype, int32_t htype)
+{
+    if (mode == PNS_MODE_UNBIASED_SYS && have_wave_tile(qtype, htype, t.block, t.groups) &&
+        window_slots_ok(N, n, t.block, t.groups))
+        return 5;
+    if (!have_tile(qtype, htype, t.block, t.groups)) return -1;
+    return flavour_of(mode, N, n, t.block, t.groups);
+}
+
 // Default tile of a problem: above 4096 bits the wide tile of four waves when
 // the problem's windows run a compact or two-group kernel on it (and a kernel
 // exists for the field type), else the fixed table's.
@@ -240,8 +277,8 @@ Tile default_tile_for(int32_t mode, int32_t N, int32_t n, int32_t qtype, int32_t
     const Tile t = default_tile(N);
     if (N > 4096) {
         const Tile w = N <= 8192 ? Tile{256, 8} : Tile{256, 16};
-        const int32_t fl = flavour_of(mode, N, n, w.block, w.groups);
-        if ((fl == 3 || fl == 4) && have_tile_any(qtype, htype, w)) return w;
+        const int32_t fl = flavour_for(mode, N, n, w, qtype, htype);
+        if (fl == 3 || fl == 4 || fl == 5) return w;
     }
     return t;
 }
@@ -728,9 +765,11 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
     else htype = (fbound_max < 2147483647.0 && ebound_max < 2147483647.0) ? H_I32 : H_I64;
     for (auto& S : specs)
         if (S.tile.block == 0) S.tile = default_tile_for(mode, S.N, S.n, qtype, htype);
-    for (const auto& S : specs)
-        if (!have_tile(qtype, htype, S.tile.block, S.tile.groups))
-            return fail(PNS_EINVAL, "no kernel for tile %dx%d", S.tile.block, S.tile.groups);
+    for (const auto& S : specs) {
+        const int32_t fl = flavour_for(mode, S.N, S.n, S.tile, qtype, htype);
+        if (fl < 0) return fail(PNS_EINVAL, "no kernel for tile %dx%d", S.tile.block, S.tile.groups);
+        if (fl == 5 && o.hist) return fail(PNS_EINVAL, "histograms need a step-kernel tile (N <= 24)");
+    }
 
     pns_ctx* ctx = new pns_ctx();
     auto fail_free = [&](int r) {
@@ -772,7 +811,7 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
     std::map<std::pair<int32_t, int32_t>, int32_t> tile_has4;
     for (size_t p = 0; p < specs.size(); ++p) {
         const ProblemSpec& S = specs[p];
-        flav[p] = flavour_of(mode, S.N, S.n, S.tile.block, S.tile.groups);
+        flav[p] = flavour_for(mode, S.N, S.n, S.tile, qtype, htype);
         if (flav[p] == 4) tile_has4[{S.tile.block, S.tile.groups}] = 1;
     }
     for (size_t p = 0; p < specs.size(); ++p)
@@ -794,10 +833,11 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         R.flav = flav[p];
         ctx->probs.push_back(R);
         ProblemRun& RR = ctx->probs.back();
-        int r = dev_alloc(reinterpret_cast<uint8_t**>(&RR.A), pp[p]->A.size());
+        int r = dev_alloc(reinterpret_cast<uint8_t**>(&RR.A), pp[p]->A.size() + kRowTailBytes);
         if (!r) r = dev_alloc(reinterpret_cast<uint8_t**>(&RR.diag), pp[p]->D.size());
         if (r) return fail_free(r);
         hipError_t e = hipMemcpy(RR.A, pp[p]->A.data(), pp[p]->A.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(static_cast<uint8_t*>(RR.A) + pp[p]->A.size(), 0, kRowTailBytes);
         if (e == hipSuccess) e = hipMemcpy(RR.diag, pp[p]->D.data(), pp[p]->D.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return fail_free(hip_fail(e, "upload"));
         if (p < own.size()) {
@@ -825,8 +865,9 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
             ctx->classes.push_back(k);
         }
         LaunchClass& K = ctx->classes[class_of[key]];
-        // dynamic LDS: the diagonal, after the random-subset table for drawn subsets
-        K.dyn = std::max(K.dyn, (size_t)RR.pitch * 4 * (RR.flav == 2 ? 2 : 1));
+        // dynamic LDS: the diagonal, after the random-subset table for drawn
+        // subsets (the window kernel keeps neither)
+        K.dyn = std::max(K.dyn, RR.flav == 5 ? (size_t)0 : (size_t)RR.pitch * 4 * (RR.flav == 2 ? 2 : 1));
         for (int32_t c = 0; c < S.chains; ++c) {
             ctx->h_chain_problem[c0 + c] = (int32_t)p;
             ctx->h_foff[c0 + c] = f0 + (int64_t)c * RR.pitch;
@@ -1030,7 +1071,7 @@ int reconfigure(pns_ctx* ctx, Tile t, int32_t n)
     R.tile = t;
     R.n = n;
     R.num_sets = R.N / gcd64(R.N, n);
-    R.flav = flavour_of(ctx->mode, R.N, n, t.block, t.groups);
+    R.flav = flavour_for(ctx->mode, R.N, n, t, ctx->qtype, ctx->htype);
     Problem D{};
     D.A = R.A;
     D.diag = R.diag;
@@ -1045,7 +1086,7 @@ int reconfigure(pns_ctx* ctx, Tile t, int32_t n)
     LaunchClass& K = ctx->classes[0];
     K.tile = t;
     K.flav = R.flav;
-    K.dyn = (size_t)R.pitch * 4 * (R.flav == 2 ? 2 : 1);
+    K.dyn = R.flav == 5 ? 0 : (size_t)R.pitch * 4 * (R.flav == 2 ? 2 : 1);
     return reset_zero_state(ctx);
 }
 
@@ -1148,10 +1189,9 @@ int autotune_impl(const ProblemSpec& base, int32_t mode, const pns_opts& o, int3
     for (const Tile& tl : kTiles) {
         const int64_t cap = (int64_t)tl.block * 4 * tl.groups;
         if (cap < base.N || cap > 2 * round_up(base.N, 256)) continue;
-        if (!have_tile(ctx->qtype, ctx->htype, tl.block, tl.groups)) continue;
         for (int32_t n : ns) {
-            const int32_t fl = flavour_of(mode, base.N, n, tl.block, tl.groups);
-            if (wide_tile(tl) && fl != 3 && fl != 4) continue;
+            const int32_t fl = flavour_for(mode, base.N, n, tl, ctx->qtype, ctx->htype);
+            if (fl < 0 || (wide_tile(tl) && fl != 3 && fl != 4 && fl != 5)) continue;
             double r = 0.0, fr = 0.0;
             rc = reconfigure(ctx, tl, n);
             if (!rc) rc = time_config(ctx, trial_steps, &r, &fr);
@@ -2005,7 +2045,11 @@ int pns_set_q(pns_ctx* ctx, int32_t problem, const void* Q)
     const size_t abytes = (size_t)R.N * R.pitch * qb;
     const size_t dbytes = (size_t)R.pitch * 4;
     int rc = PNS_OK;
-    if (!R.A2 && (rc = dev_alloc(reinterpret_cast<uint8_t**>(&R.A2), abytes))) return rc;
+    if (!R.A2) {
+        // (with the tail padding the window kernels read past the last row)
+        if ((rc = dev_alloc(reinterpret_cast<uint8_t**>(&R.A2), abytes + kRowTailBytes))) return rc;
+        HIP_TRY(hipMemset(static_cast<uint8_t*>(R.A2) + abytes, 0, kRowTailBytes), "zero the row tail");
+    }
     if (!R.diag2 && (rc = dev_alloc(reinterpret_cast<uint8_t**>(&R.diag2), dbytes))) return rc;
     const void* dq = Q;
     void* tmp = nullptr;
@@ -2124,7 +2168,8 @@ int pns_optimize(pns_ctx* ctx, int64_t steps, double temperature)
             if (!class_of.count(key)) {
                 class_of[key] = ctx->opt_classes.size();
                 LaunchClass k;
-                k.tile = R.tile;
+                // (a window-kernel tile runs the optimization on the table's)
+                k.tile = have_tile(ctx->qtype, ctx->htype, R.tile.block, R.tile.groups) ? R.tile : default_tile(R.N);
                 k.flav = flav;
                 k.dyn = 0;
                 ctx->opt_classes.push_back(k);

@@ -263,6 +263,8 @@ __device__ __forceinline__ double delta_f64(float d, double h, int s, uint32_t x
 // L nor an integer, the estimate has the same floor and the same order
 // against L as the exact quotient and is returned; otherwise the exact
 // quotient is.  L < 0: no budget.
+__device__ __noinline__ double exact_quotient(double logU1, double p) { return logU1 / log1p(-p); }
+
 __device__ __forceinline__ double geometric_quotient(double logU1, double p, double L)
 {
     double l1p = 0.0, d = 1e-7;
@@ -280,7 +282,9 @@ __device__ __forceinline__ double geometric_quotient(double logU1, double p, dou
         const double lo = qe * (1.0 - d), hi = qe * (1.0 + d);
         if (qe < 0x1p52 && floor(lo) == floor(hi) && !(lo < L && hi >= L)) return qe;
     }
-    return logU1 / log1p(-p);
+    // (out of line: the logarithm's constants would otherwise be kept in
+    // registers across the step loop)
+    return exact_quotient(logU1, p);
 }
 
 // Mean multiplicity of a record given its state, subset and remaining budget

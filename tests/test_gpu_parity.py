@@ -359,12 +359,13 @@ def test_uninstrumented_frozen_chain_saturates():
 
 # ---------------------------------------------------------------------------
 # Wide tiles: 256 x 8 (32 fields per lane) and 256 x 16 (64 fields per lane,
-# 64-bit lane masks; 32-bit fields only)
+# 64-bit lane masks; 32-bit fields only; Unbiased PNS with systematic sets on
+# integer Q runs the window kernel there)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("mode,n,N,tile,dtype,flavour", [
-    ("unbiased_sys", 400, 12000, (256, 16), np.int16, 3),    # compact windows
-    ("unbiased_sys", 1500, 12000, (256, 16), np.int16, 4),   # two-group windows
+    ("unbiased_sys", 400, 12000, (256, 16), np.int16, 5),    # window kernel, one group per wave
+    ("unbiased_sys", 1500, 12000, (256, 16), np.int16, 5),   # window kernel, two groups per wave
     ("rf", 0, 16384, (256, 16), np.int16, 0),
     ("basic", 64, 9000, (256, 16), np.int32, 2),
     ("unbiased_rand", 200, 10000, (256, 16), np.int16, 2),
