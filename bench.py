@@ -40,16 +40,24 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def _kernel_sha() -> str:
+    """sha256 prefix of the sampling kernels' sources (step and window
+    kernels): a committed counter table applies while it is unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("pns_step.h", "pns_wave.h"):
+        h.update(open(os.path.join(ROOT, "paper_2210_10513_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def _measured_traffic(workload: str, chain_steps: int):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter runs (profiles/hbm_traffic.txt), or None when no run matches the
-    workload and launch length or the kernel source changed since."""
-    import hashlib
+    workload and launch length or the kernel sources changed since."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
-    src = os.path.join(ROOT, "paper_2210_10513_amd", "csrc", "pns_step.h")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = _kernel_sha()
     for line in open(path):
         f = line.split()
         if len(f) == 6 and not line.startswith("#") and f[0] == workload and int(f[1]) == chain_steps and f[2] == sha:
@@ -65,20 +73,33 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 def _valu_per_chain_step(workload: str, tile):
     """VALU instructions (wave64) per chain step of the step kernel from the
     committed SQ counter runs (profiles/valu_issue.txt), or None when no run
-    matches the workload and tile (block, groups) or the kernel source changed
+    matches the workload and tile (block, groups) or the kernel sources changed
     since."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "valu_issue.txt")
-    src = os.path.join(ROOT, "paper_2210_10513_amd", "csrc", "pns_step.h")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = _kernel_sha()
     for line in open(path):
         f = line.split()
         if (len(f) == 6 and not line.startswith("#") and f[0] == workload and f[1] == "%dx%d" % tuple(tile)
                 and f[2] == sha):
             return float(f[3]) / float(f[4])
     return None
+
+
+def _class_key(c) -> str:
+    """Counter-table key of a launch class of the batched workload: its tile,
+    kernel flavour and chains (the autotuner's choices, which a run may make
+    differently, decide which problems form a class)."""
+    return f"batched64_class_{c['tile']}_f{c['flavour']}_c{c['chains']}_N{c['N_min']}-{c['N_max']}"
+
+
+def _kernel_name(c) -> str:
+    """Kernel of a launch class of 16-bit coefficients with 32-bit fields."""
+    block, groups = (int(v) for v in c["tile"].split("x"))
+    if c["flavour"] == 5:
+        return f"wave_kernel<short, {block // 64}, {groups}, false>"
+    return f"step_kernel<short, int, {block}, {groups}, {c['flavour']}, false>"
 
 
 def _workload(name: str):
@@ -371,9 +392,9 @@ def _bench_batch(args, wl, cpu_spec=None):
         "records_per_s": r["records"] / sec,
         "roofline": {"bound": "hbm", "achieved": dk["GB_per_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dk["hbm_frac"],
-                     "traffic": _measured_traffic(f"batched64_class_{dk['tile']}_f{dk['flavour']}", chain_steps),
+                     "traffic": _measured_traffic(_class_key(dk), chain_steps),
                      "bytes_per_flip": "N * 2 of the flipping chain's problem",
-                     "kernel": f"step_kernel<short, int, {dk['tile'].replace('x', ', ')}, {dk['flavour']}, false> "
+                     "kernel": f"{_kernel_name(dk)} "
                                f"(launch class N {dk['N_min']}..{dk['N_max']}, {dk['chains']} chains)",
                      "kernel_avg_ms": dk["kernel_avg_ms"], "bytes_per_launch": dk["bytes_per_launch"],
                      "timing": f"HIP events on the class's stream over {args.steps} further timed steps with the "

@@ -104,12 +104,17 @@ typedef struct pns_opts {
     int32_t chunk;          /* steps per launch in PERSISTENT / GRAPH; 0 = all
                                steps of a pns_run in one launch                   */
     int32_t block;          /* threads per workgroup (one workgroup per chain);
-                               0 = chosen from the tuned table.  Compiled tiles
-                               (block x groups): 64x1, 64x2, 64x4, 128x1, 128x2,
-                               128x4, 256x1, 256x2, 256x4, 256x8, 512x2, 512x4,
-                               1024x2, 1024x4, and 256x16 for 32-bit fields (I16,
-                               I32 with int32 fields); 4 * block * groups must
-                               reach N; another shape is PNS_EINVAL               */
+                               0 = chosen from the tuned table.  Step-kernel
+                               tiles (block x groups): 64x1, 64x2, 64x4, 128x1,
+                               128x2, 128x4, 256x1, 256x2, 256x4, 256x8, 512x2,
+                               512x4, 1024x2, 1024x4, and 256x16 for 32-bit fields
+                               (I16, I32 with int32 fields).  Window-kernel tiles
+                               (PNS_MODE_UNBIASED_SYS on I16 / I32 with int32
+                               fields, flavour 5 of pns_problem_info): 64x8,
+                               64x16, 64x24, 128x16, 128x24 and 256x16, which
+                               then runs the window kernel.  4 * block * groups
+                               must reach N; another shape, or a window-kernel
+                               tile for another mode or type, is PNS_EINVAL       */
     int32_t groups;         /* 4-field groups per lane; 0 = chosen with `block`   */
     void* stream;           /* hipStream_t to queue work on; NULL = a stream the
                                context creates and owns                           */
@@ -152,7 +157,10 @@ typedef struct pns_problem_info {
     int32_t num_chains;
     int32_t flavour;        /* 0 all bits, 1 window, 2 drawn subset, 3 compact
                                window (one 4-bit group per wave), 4 two-group
-                               window (at most two groups per wave)             */
+                               window (at most two groups per wave), 5 window
+                               kernel (one to four waves per chain; systematic
+                               sets of integer Q; its records equal those of
+                               flavours 1, 3 and 4 bit for bit)                 */
     int32_t reserved;
 } pns_problem_info;
 
@@ -202,8 +210,9 @@ int pns_create(pns_ctx** out, const void* Q, int32_t N, double beta, int32_t sub
  * Create one context over several problems of the same element type and
  * method (QUBOs of uneven N, each with its own chains and temperatures):
  * chain c of problem p is numbered problems[0..p-1].num_chains + c.  Problems
- * are grouped by workgroup tile; each group runs in its own step kernel,
- * launched concurrently (in the graph form as parallel graph nodes).
+ * are grouped by workgroup tile and kernel flavour; each group (launch class)
+ * runs in its own kernel launch, the launches concurrent on side streams (in
+ * the graph form as parallel graph nodes).
  * Per-chain arrays of bits or fields (pns_read, pns_read_current,
  * pns_read_snapshots) are concatenated, chain c occupying the N of its
  * problem; pns_chain_offsets gives the offsets.  Histograms are not
@@ -217,15 +226,17 @@ int pns_create_batch(pns_ctx** out, int32_t num_problems, const pns_problem* pro
 /*
  * Choose the workgroup tile and, when subset_size is 0 in a subset mode, the
  * subset size for one problem by timed trials on the device: every compiled
- * tile that holds N (up to 4x the smallest such capacity) is run for
- * trial_steps steps (after a warmup) from x = 0 with max(1024,
- * opts->num_chains) chains, at most 4096 (the problem's betas repeated), so
- * that the device is loaded as in a real run; the tile with the most records
- * per second is kept, then subset sizes 16, 32, ... up to N/2 are timed on
- * it and the largest one within 10% of the best rate is chosen
- * (Sec 5: on parallel hardware, take the largest affordable partial neighbor
- * set).  Results are cached per process by (N, dtype, layout, mode, n,
- * chains).  Synchronises the device.  Errors: as pns_create.
+ * tile whose capacity 4 * block * groups lies between N and twice N rounded
+ * up to 256 (tiles of 32 or more fields per lane only where a window kernel
+ * runs the problem), with every subset size 16, 32, ... up to N/2, is run
+ * for trial_steps steps (after a warmup; the faster of two timed runs) from
+ * x = 0 with max(3072, opts->num_chains) chains, at most 4096 (the
+ * problem's betas repeated), so that the device is loaded as in a real run;
+ * the largest subset size whose rate is within 10% of the best trial is
+ * chosen, on its fastest tile (Sec 5: on parallel hardware, take the largest
+ * affordable partial neighbor set).  Results are cached per process by (N,
+ * dtype, layout, mode, n, chains, trial_steps).  Synchronises the device.
+ * Errors: as pns_create.
  */
 int pns_autotune(const void* Q, int32_t N, double beta, int32_t subset_size, int32_t mode, const pns_opts* opts,
                  int32_t trial_steps, pns_tune* out);

@@ -27,11 +27,17 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_hbm_traffic_rows_add_up():
-    # traffic_bytes = FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, both in KiB
+    # traffic_bytes = (FETCH_SIZE x f + WRITE_SIZE x w) x 1024, counters in KiB, with the copy calibration's
+    # factors f and w that the table's header states
+    import re
+    head = open(os.path.join(ROOT, "profiles", "hbm_traffic.txt")).read()
+    f = float(re.search(r"x ([0-9.]+) \(FETCH_SIZE\)", head).group(1))
+    w = float(re.search(r"x ([0-9.]+) \(WRITE_SIZE\)", head).group(1))
+    assert 1.5 < f < 2.5 and 0.5 < w < 1.5
     rows = list(_rows("hbm_traffic.txt", 6))
     assert {r[0] for r in rows} >= {"rf_n1024_int16", "unbiased_n8192_f32"}
     for r in rows:
-        assert int(r[5]) == int(float(r[3]) * 2048 + float(r[4]) * 1024)
+        assert abs(int(r[5]) - (float(r[3]) * f + float(r[4]) * w) * 1024) <= 1
 
 
 def test_valu_rows_divide_out_and_gate_on_the_kernel_source():
@@ -53,9 +59,12 @@ def test_issue_peak():
 
 
 def _current_sha():
+    # the step and window kernels' sources, in this order
     import hashlib
-    src = os.path.join(ROOT, "paper_2210_10513_amd", "csrc", "pns_step.h")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("pns_step.h", "pns_wave.h"):
+        h.update(open(os.path.join(ROOT, "paper_2210_10513_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def test_cpu_baseline_child_reports_one_core_and_all_cores():
