@@ -50,6 +50,9 @@ constexpr int waves_per_eu()
     return G <= 8 ? 4 : (G <= 16 ? 3 : 2);
 }
 
+// Two 16-bit integers of one register (operands of the 16-bit dot product).
+typedef int16_t v2i16 __attribute__((ext_vector_type(2)));
+
 // Bit i of a lane's packed state words (i a compile-time index).
 template <int NW>
 __device__ __forceinline__ uint32_t get_bit(const uint32_t (&xw)[NW], int i)
@@ -62,6 +65,25 @@ template <int... I, typename Fn>
 __device__ __forceinline__ void for_each_index(std::integer_sequence<int, I...>, Fn&& body)
 {
     (body(std::integral_constant<int, I>{}), ...);
+}
+
+// The lane's index in its wave, formed where it is used: a per-lane value
+// kept across the step loop takes a register or is spilled and reloaded.
+__device__ __forceinline__ int lane_here()
+{
+    uint32_t m = ~0u;
+    asm volatile("" : "+s"(m));
+    return (int)__builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m, 0u));
+}
+
+// A wave-uniform 64-bit value read from lane 0 into scalar registers (a
+// value formed from vector results would otherwise stay in a vector
+// register pair across the step loop).
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // Mask of the 256-bit segments [lo, hi] (0 <= lo <= hi <= 63).
@@ -122,8 +144,9 @@ void wave_kernel(const StepArgs a)
     __shared__ double mx_part[W];
     __shared__ int64_t xchg[2];
     // energy differences of the window's groups, per wave and slot (kOut
-    // outside the window)
+    // outside the window), and the inclusive scans of their four-bit sums
     __shared__ int4 eslot[W][kSlots][64];
+    __shared__ double islot[W][kSlots][64];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -178,34 +201,44 @@ void wave_kernel(const StepArgs a)
     }
 
     // ---- chain scalars (wave-uniform) ----
-    int64_t k = a.step[chain];
+    // (read into scalar registers: the arrays are written back at the end,
+    // so the compiler loads them as vector values)
+    int64_t k = uniform64(a.step[chain]);
     const int64_t kend = k + a.steps;
-    int64_t E = a.E[chain];
-    int64_t L = a.L[chain];
-    int64_t sub = a.sub[chain];
-    int32_t last_a = a.last_action[chain];
-    int64_t last_M = a.last_M[chain];
-    int64_t last_E = a.last_E[chain];
+    int64_t E = uniform64(a.E[chain]);
+    int64_t L = uniform64(a.L[chain]);
+    int64_t sub = uniform64(a.sub[chain]);
+    int32_t last_a = __builtin_amdgcn_readfirstlane(a.last_action[chain]);
+    int64_t last_M = uniform64(a.last_M[chain]);
+    int64_t last_E = uniform64(a.last_E[chain]);
     int64_t c_steps = 0, c_flips = 0, c_stays = 0, c_sat = 0, c_bad = 0;
-    double c_sumM = 0.0;
+    // running sum of M as the bits of a double in scalar registers (a
+    // uniform double would otherwise take a vector register pair)
+    int64_t c_sumM = 0;
     int32_t snap_n = 0;
     if constexpr (INSTR) snap_n = a.snap_every > 0 ? a.snap_count[chain] : 0;
     // window start (i n) mod N of set i = sub mod (number of sets); advanced
     // by n mod N per stay, which walks the same sets in the same order
     int32_t s0 = (int32_t)(((sub % P.num_sets) * (int64_t)n) % N);
+    // p = S / n: for n = 2^j the product S 2^-j (exact scaling, the same
+    // rounding as the division), formed from an integer exponent
     const bool n_pow2 = (n & (n - 1)) == 0;
-    const double inv_n = 1.0 / (double)n;
+    const int neg_log2n = -__builtin_ctz((unsigned)n);
 
     // The window: the 256-bit segments the cyclic window [st, st + n) meets
     // and the groups of this wave among them.  Bit f of the lane is in the
-    // window iff f < N and (f - st) mod N < n; f - st = wbase + (4 BLOCK g + v)
-    // and f < N iff f - st < wlim, values of the window rather than of the
-    // bit, so that no per-bit constant is kept live across the steps.
+    // window iff f < N and (f - st) mod N < n.  With d = f - st =
+    // wbase + (4 BLOCK g + v) that is 0 <= d < min(n, N - st) (the part up to
+    // the end of the bits) or d < n - N (the part wrapped to the start); both
+    // bounds are values of the window rather than of the bit, so that no
+    // per-bit constant is kept live across the steps.
     uint64_t smask = 0, gmask = 0;
-    int32_t wbase = 0, wlim = 0;
+    int32_t wbase = 0;
+    uint32_t wlo = 0;
+    const int32_t wneg = n - N;
     auto set_window = [&](int32_t st) {
-        wbase = tid * 4 - st;
-        wlim = __builtin_amdgcn_readfirstlane(N - st);
+        wbase = (wave * 64 + lane_here()) * 4 - st;
+        wlo = (uint32_t)__builtin_amdgcn_readfirstlane(n < N - st ? n : N - st);
         const int32_t e0 = st + n < N ? st + n : N;
         uint64_t m = seg_range(st >> 8, (e0 - 1) >> 8);
         if (st + n > N) m |= seg_range(0, (st + n - N - 1) >> 8);
@@ -261,6 +294,7 @@ void wave_kernel(const StepArgs a)
             double w4[4];
             const double ls = slot_sum(eslot[wave][r][lane], shift, w4);
             const double inc = wave_scan(ls);
+            islot[wave][r][lane] = inc;
             if (lane == 63) seg_sum[k & 1][g * W + wave] = inc;
             ++r;
         }
@@ -293,20 +327,26 @@ void wave_kernel(const StepArgs a)
                     double w4[4];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
+                        const int i = g * 4 + v;
                         const int32_t d = wbase + (g * BLOCK * 4 + v);
-                        const bool in = d < wlim && (d < 0 ? d + N : d) < n;
-                        const int32_t uu = u[g * 4 + v];
-                        const int32_t e = get_bit(xw, g * 4 + v) ? -uu : uu;
+                        const bool in = (uint32_t)d < wlo || d < wneg;
+                        // dE = (1 - 2 x) u: the bit as a sign mask (0 or -1)
+                        const int32_t sm = __builtin_amdgcn_sbfe((int32_t)xw[i >> 5], i & 31, 1);
+                        const int32_t e = (u[i] ^ sm) - sm;
                         es[v] = in ? e : kOut;
-                        const uint32_t ep = e > 0 ? (uint32_t)e : 0u;
-                        big |= in && ep >= (uint32_t)kTabMax;
-                        const uint32_t hi = ep >> 6 < (uint32_t)kTabHi ? ep >> 6 : (uint32_t)(kTabHi - 1);
-                        w4[v] = tab_hi[hi] * tab_lo[in ? (ep & 63u) : (uint32_t)kTabLo];
+                        big |= in && e >= (int32_t)kTabMax;
+                        // table index of max(dE, 0), clamped below kTabMax (a
+                        // window weight past the tables is recomputed: big)
+                        const uint32_t ep = (uint32_t)max(0, min(e, (int32_t)kTabMax - 1));
+                        w4[v] = tab_hi[ep >> 6] * tab_lo[in ? (ep & 63u) : (uint32_t)kTabLo];
                     }
-                    // (r < kSlots for every window the host lets run here)
-                    if (r < kSlots) eslot[wave][r][lane] = make_int4(es[0], es[1], es[2], es[3]);
                     const double ls = ((w4[0] + w4[1]) + w4[2]) + w4[3];
                     const double inc = wave_scan(ls);
+                    // (r < kSlots for every window the host lets run here)
+                    if (r < kSlots) {
+                        eslot[wave][r][lane] = make_int4(es[0], es[1], es[2], es[3]);
+                        islot[wave][r][lane] = inc;
+                    }
                     if (lane == 63) seg_sum[k & 1][g * W + wave] = inc;
                     ++r;
                 }
@@ -359,13 +399,13 @@ void wave_kernel(const StepArgs a)
 
         // ---- p, M and the budget decision of Alg 6 (uniform) ----
         const double Ss = scaled ? exp_of(mx) * S : S;
-        const double p = n_pow2 ? Ss * inv_n : Ss / (double)n;
+        const double p = n_pow2 ? ldexp(Ss, neg_log2n) : Ss / (double)n;
         double q;
         if (p >= 1.0) q = 0.0;
         else if (p <= 0.0) q = INFINITY;
         else q = step::geometric_quotient(logU1, p, (double)L);
-        const bool sat = !(q < 0x1p63);
-        const int64_t m = sat ? INT64_MAX : (int64_t)floor(q) + 1;
+        const bool sat = __builtin_amdgcn_readfirstlane((int)!(q < 0x1p63)) != 0;
+        const int64_t m = uniform64(sat ? INT64_MAX : (int64_t)floor(q) + 1);
         const bool stay = __builtin_amdgcn_readfirstlane((int)(q >= (double)L)) != 0;
 
         const int64_t Erec = E;
@@ -394,10 +434,15 @@ void wave_kernel(const StepArgs a)
 
         int32_t action = -1;
         int64_t M;
+        // the row of a move and, for 16-bit coefficients, the multiplier of
+        // its update, which runs after the two paths join (defined on both,
+        // so that the fields are not copied to other registers and back)
+        decltype(step::load_raw4(static_cast<const QT*>(nullptr))) raw[G];
+        [[maybe_unused]] int32_t mult = 0;
         if (stay) {
             // stay L times and move to the next systematic set
             M = L;
-            L = P.L0;
+            L = uniform64(P.L0);
             ++sub;
             s0 += n;
             s0 -= s0 >= N ? N : 0;
@@ -406,6 +451,11 @@ void wave_kernel(const StepArgs a)
             // (the fields stay where the move path updates them in place)
 #pragma unroll
             for (int i = 0; i < F; ++i) asm volatile("" : "+v"(u[i]));
+            if constexpr (sizeof(QT) == 2) {
+                // (no row: the registers as they are, unused on this path)
+#pragma unroll
+                for (int g = 0; g < G; ++g) asm volatile("" : "=v"(raw[g].x), "=v"(raw[g].y));
+            }
         } else {
             // ---- proportional choice (appendix "How to Sample
             // Proportionally"): first bit of the window, in bit order, whose
@@ -424,7 +474,8 @@ void wave_kernel(const StepArgs a)
                 const int4 ev = eslot[wave][rstar][lane];
                 double w4[4];
                 const double my_ls = slot_sum(ev, scaled ? mx : 0.0, w4);
-                const double my_inc = wave_scan(my_ls);
+                // (the scan of these sums, kept when the totals were formed)
+                const double my_inc = islot[wave][rstar][lane];
                 const double Gl = base + my_inc;
                 const uint64_t bl = __ballot(my_ls > 0.0 && Gl > t);
                 const uint64_t blp = __ballot(my_ls > 0.0);
@@ -449,7 +500,7 @@ void wave_kernel(const StepArgs a)
                     bad = 1;
                 }
                 const int32_t ec = vstar == 0 ? ev.x : (vstar == 1 ? ev.y : (vstar == 2 ? ev.z : ev.w));
-                int64_t c = ((int64_t)gstar * BLOCK + tid) * 4 + vstar;
+                int64_t c = ((int64_t)gstar * BLOCK + wave * 64 + lane_here()) * 4 + vstar;
                 if (c >= N) {
                     c = 0;
                     bad = 1;
@@ -475,58 +526,33 @@ void wave_kernel(const StepArgs a)
                 // (the next write of xchg follows the next step's segment
                 // barrier, which every wave passes after these reads)
                 __syncthreads();
-                selc = xchg[0];
-                seld = xchg[1];
+                selc = uniform64(xchg[0]);
+                seld = uniform64(xchg[1]);
             }
             const int32_t c = (int32_t)(selc & 0xFFFFFFFFll);
             const bool xc = (selc >> 40) & 1;
-            c_bad += (selc >> 41) & 1;
+            c_bad = uniform64(c_bad + ((selc >> 41) & 1));
             // ---- move: flip c, E += dE_c, u_j += s (1 - 2 x_c) A[c][j] ----
             // (lanes past the pitch read on into the next rows or the
             // matrix's tail padding and drop what they read)
-            const QT* row = reinterpret_cast<const QT*>(P.A) + (int64_t)c * pitch + tid * 4;
-            decltype(step::load_raw4(static_cast<const QT*>(nullptr))) raw[G];
+            const QT* row = reinterpret_cast<const QT*>(P.A) + (int64_t)c * pitch + (wave * 64 + lane_here()) * 4;
 #pragma unroll
             for (int g = 0; g < G; ++g) raw[g] = step::load_raw4(row + g * BLOCK * 4);
             const int cl = (c >> 2) % BLOCK;
             const int ci = ((c >> 2) / BLOCK) * 4 + (c & 3);
-            if (tid == cl) {
+            if (wave * 64 + lane_here() == cl) {
 #pragma unroll
                 for (int i = 0; i < NW; ++i)
                     if ((ci >> 5) == i) xw[i] ^= 1u << (ci & 31);
             }
-            E += seld;
-            L -= m;
-            c_sat += sat ? 1 : 0;
+            E = uniform64(E + seld);
+            L = uniform64(L - m);
+            c_sat = uniform64(c_sat + (sat ? 1 : 0));
             M = m;
             action = c;
             ++c_flips;
             if constexpr (sizeof(QT) == 2) {
-                // 16-bit coefficients times +-1 or +-2: sign extension and a
-                // 24-bit multiply-add per field, in place (written as one
-                // block per pair of fields, so that the sign-extended values
-                // are not all formed ahead of the multiply-adds and held at
-                // once next to the old and new fields)
-                const int32_t mult = __builtin_amdgcn_readfirstlane(xc ? -s : s);
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const uint32_t wlo = raw[g].x, whi = raw[g].y;
-                    int32_t t0, t1;
-                    asm volatile(
-                        "v_bfe_i32 %2, %4, 0, 16\n\t"
-                        "v_mad_i32_i24 %0, %2, %5, %0\n\t"
-                        "v_ashrrev_i32 %3, 16, %4\n\t"
-                        "v_mad_i32_i24 %1, %3, %5, %1"
-                        : "+v"(u[g * 4 + 0]), "+v"(u[g * 4 + 1]), "=&v"(t0), "=&v"(t1)
-                        : "v"(wlo), "s"(mult));
-                    asm volatile(
-                        "v_bfe_i32 %2, %4, 0, 16\n\t"
-                        "v_mad_i32_i24 %0, %2, %5, %0\n\t"
-                        "v_ashrrev_i32 %3, 16, %4\n\t"
-                        "v_mad_i32_i24 %1, %3, %5, %1"
-                        : "+v"(u[g * 4 + 2]), "+v"(u[g * 4 + 3]), "=&v"(t0), "=&v"(t1)
-                        : "v"(whi), "s"(mult));
-                }
+                mult = __builtin_amdgcn_readfirstlane(xc ? -s : s);
             } else {
                 const int sh = s - 1;
                 if (xc) {
@@ -546,8 +572,25 @@ void wave_kernel(const StepArgs a)
                 }
             }
         }
+        if constexpr (sizeof(QT) == 2) {
+            if (!stay) {
+                // 16-bit coefficients times +-1 or +-2: one two-term 16-bit
+                // dot product per field, accumulated in place (the pair of
+                // coefficients against (mult, 0) or (0, mult))
+                const v2i16 mlo = {(int16_t)mult, 0}, mhi = {0, (int16_t)mult};
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const v2i16 p0 = __builtin_bit_cast(v2i16, raw[g].x);
+                    const v2i16 p1 = __builtin_bit_cast(v2i16, raw[g].y);
+                    u[g * 4 + 0] = __builtin_amdgcn_sdot2(p0, mlo, u[g * 4 + 0], false);
+                    u[g * 4 + 1] = __builtin_amdgcn_sdot2(p0, mhi, u[g * 4 + 1], false);
+                    u[g * 4 + 2] = __builtin_amdgcn_sdot2(p1, mlo, u[g * 4 + 2], false);
+                    u[g * 4 + 3] = __builtin_amdgcn_sdot2(p1, mhi, u[g * 4 + 3], false);
+                }
+            }
+        }
         ++c_steps;
-        c_sumM += (double)M;
+        c_sumM = uniform64(__double_as_longlong(__longlong_as_double(c_sumM) + (double)M));
         last_a = action;
         last_M = M;
         last_E = Erec;
@@ -617,7 +660,7 @@ void wave_kernel(const StepArgs a)
         cn[1] += c_flips;
         cn[2] += c_stays;
         cn[3] += c_sat;
-        cn[4] = __double_as_longlong(__longlong_as_double(cn[4]) + c_sumM);
+        cn[4] = __double_as_longlong(__longlong_as_double(cn[4]) + __longlong_as_double(c_sumM));
         cn[5] += c_bad;
     }
 }
