@@ -127,9 +127,8 @@ void wave_kernel(const StepArgs a)
     constexpr int BLOCK = 64 * W;
     constexpr int F = 4 * G;
     constexpr int NSEG = G * W;
-    constexpr int NW = F / 32;
+    constexpr int NW = (F + 31) / 32;  // 32-bit state words (the last one partly used)
     static_assert(NSEG <= 64, "segment scan needs at most 64 segments");
-    static_assert(G % 8 == 0, "the state words hold 32 bits");
     using step::read_lane;
     using step::small_scan;
     using step::wave_scan;
@@ -673,9 +672,11 @@ hipError_t launch_one(int32_t grid, hipStream_t st, const StepArgs& a)
 }
 
 // Tiles of the window kernel (workgroup size, 4-bit groups per lane): one
-// wave up to 6144 bits, two up to 12288, four up to 16384 (at most 96 fields
-// per lane: more do not fit the registers of two waves per SIMD).
+// wave from 512 up to 6144 bits, two up to 12288, four up to 16384 (at most
+// 96 fields per lane: more do not fit the registers of two waves per SIMD).
 #define PNS_WAVE_TILE_LIST(X, QT) \
+    X(QT, 64, 2)                  \
+    X(QT, 64, 4)                  \
     X(QT, 64, 8)                  \
     X(QT, 64, 16)                 \
     X(QT, 64, 24)                 \

@@ -113,7 +113,7 @@ def test_tile_shape_does_not_change_results_at_n500(tile):
 @pytest.mark.parametrize("mode,N,n,tile,dtype,log", [
     ("unbiased_sys", 2400, 1024, (512, 2), np.int16, True),    # windows that wrap to bit 0
     ("unbiased_sys", 4398, 256, (1024, 2), np.int16, True),
-    ("unbiased_sys", 700, 100, (64, 4), np.int32, True),       # one wave holding four groups
+    ("unbiased_sys", 700, 100, (64, 4), np.float32, True),     # one wave holding four groups
     ("unbiased_sys", 7659, 2048, (512, 4), np.float32, True),
     ("unbiased_rand", 700, 700, (128, 2), np.int16, True),     # every bit, two groups per wave
     ("unbiased_sys", 2400, 1024, (512, 2), np.int16, False),   # uninstrumented kernel

@@ -28,6 +28,10 @@ def _replay(Q, beta, K, *, chains, n, L0, seed, tile, layout="symmetric", init="
 
 
 @pytest.mark.parametrize("N,n,tile,dtype,layout", [
+    (300, 64, (64, 2), np.int16, "symmetric"),      # 512-bit tile: ragged, windows wrap
+    (449, 100, (64, 2), np.int32, "upper"),
+    (700, 100, (64, 4), np.int32, "symmetric"),     # one wave, four groups, one state word
+    (1000, 128, (64, 4), np.int16, "symmetric"),
     (1000, 64, (64, 8), np.int16, "symmetric"),     # ragged last segment, windows wrap
     (700, 100, (64, 8), np.int32, "symmetric"),     # n not a power of two, idle groups
     (2047, 128, (64, 8), np.int32, "upper"),
@@ -46,7 +50,9 @@ def test_window_kernel_replays_against_oracle(N, n, tile, dtype, layout):
     _replay(Q, 0.01 * np.sqrt(2048.0 / N), 300, chains=3, n=n, L0=40, seed=17, tile=tile, layout=layout)
 
 
-@pytest.mark.parametrize("N,n,step_tile,wave_tile", [(3000, 256, (256, 4), (64, 16)),
+@pytest.mark.parametrize("N,n,step_tile,wave_tile", [(500, 64, (128, 1), (64, 2)),
+                                                     (900, 128, (256, 1), (64, 4)),
+                                                     (3000, 256, (256, 4), (64, 16)),
                                                      (1500, 128, (128, 4), (64, 8)),
                                                      (7000, 512, (256, 8), (128, 16)),
                                                      (12000, 256, (1024, 4), (128, 24))])
