@@ -403,8 +403,6 @@ void wave_kernel(const StepArgs a)
         if (p >= 1.0) q = 0.0;
         else if (p <= 0.0) q = INFINITY;
         else q = step::geometric_quotient(logU1, p, (double)L);
-        const bool sat = __builtin_amdgcn_readfirstlane((int)!(q < 0x1p63)) != 0;
-        const int64_t m = uniform64(sat ? INT64_MAX : (int64_t)floor(q) + 1);
         const bool stay = __builtin_amdgcn_readfirstlane((int)(q >= (double)L)) != 0;
 
         const int64_t Erec = E;
@@ -472,7 +470,20 @@ void wave_kernel(const StepArgs a)
                 const int rstar = min(__builtin_popcountll(gmask & ((1ull << gstar) - 1ull)), kSlots - 1);
                 const int4 ev = eslot[wave][rstar][lane];
                 double w4[4];
-                const double my_ls = slot_sum(ev, scaled ? mx : 0.0, w4);
+                double my_ls;
+                if (!slow && !scaled) {
+                    // every window weight from the tables: the pass's
+                    // branch-free lookups (the same products)
+                    const int32_t e4[4] = {ev.x, ev.y, ev.z, ev.w};
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const uint32_t ep = (uint32_t)max(0, min(e4[v], (int32_t)kTabMax - 1));
+                        w4[v] = tab_hi[ep >> 6] * tab_lo[e4[v] != kOut ? (ep & 63u) : (uint32_t)kTabLo];
+                    }
+                    my_ls = ((w4[0] + w4[1]) + w4[2]) + w4[3];
+                } else {
+                    my_ls = slot_sum(ev, scaled ? mx : 0.0, w4);
+                }
                 // (the scan of these sums, kept when the totals were formed)
                 const double my_inc = islot[wave][rstar][lane];
                 const double Gl = base + my_inc;
@@ -545,6 +556,9 @@ void wave_kernel(const StepArgs a)
                     if ((ci >> 5) == i) xw[i] ^= 1u << (ci & 31);
             }
             E = uniform64(E + seld);
+            // M = 1 + floor(q) (formed on this path only: a stay takes M = L)
+            const bool sat = __builtin_amdgcn_readfirstlane((int)!(q < 0x1p63)) != 0;
+            const int64_t m = uniform64(sat ? INT64_MAX : (int64_t)floor(q) + 1);
             L = uniform64(L - m);
             c_sat = uniform64(c_sat + (sat ? 1 : 0));
             M = m;
