@@ -37,27 +37,36 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# Hardware queues of this process (read when HIP starts; its default is 4):
+# the batched workload's launch classes, about eight, run on one stream each
+# and each stream takes a queue of its own, so that all of them run at once
+# (measured on one MI355X: 701-704 ms per step at 8 queues against 833-870 at
+# 4, 965 at 6 and 777 at 16).  A value set in the environment is kept.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 HBM_PEAK_GBS = 8000.0
 
 
-def _kernel_sha() -> str:
-    """sha256 prefix of the sampling kernels' sources (step and window
-    kernels): a committed counter table applies while it is unchanged."""
+def _kernel_sha(window: bool = False) -> str:
+    """sha256 prefix of a sampling kernel's sources: the step kernel's
+    (pns_step.h), or the window kernel's (pns_step.h, then pns_wave.h, which
+    includes it).  A committed counter row applies while it is unchanged."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("pns_step.h", "pns_wave.h"):
+    for name in ("pns_step.h", "pns_wave.h") if window else ("pns_step.h",):
         h.update(open(os.path.join(ROOT, "paper_2210_10513_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
-def _measured_traffic(workload: str, chain_steps: int):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter runs (profiles/hbm_traffic.txt), or None when no run matches the
-    workload and launch length or the kernel sources changed since."""
+def _measured_traffic(workload: str, chain_steps: int, window: bool = False):
+    """HBM bytes per launch of the step kernel (window: the window kernel)
+    from the committed rocprofv3 counter runs (profiles/hbm_traffic.txt), or
+    None when no run matches the workload and launch length or the kernel's
+    sources changed since."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
-    sha = _kernel_sha()
+    sha = _kernel_sha(window)
     for line in open(path):
         f = line.split()
         if len(f) == 6 and not line.startswith("#") and f[0] == workload and int(f[1]) == chain_steps and f[2] == sha:
@@ -387,12 +396,13 @@ def _bench_batch(args, wl, cpu_spec=None):
         "config": {"workload": wl["desc"], "problems": len(info), "chains": int(len(wl["betas"])),
                    "N_min": int(min(i[0] for i in info)), "N_max": int(max(i[0] for i in info)),
                    "mode": wl["mode"], "subset": "autotuned", "chain_steps_per_step": chain_steps, "launch": launch,
-                   "subset_sizes": [int(i[1]) for i in info], "tiles": sorted({f"{i[2]}x{i[3]}" for i in info})},
+                   "subset_sizes": [int(i[1]) for i in info], "tiles": sorted({f"{i[2]}x{i[3]}" for i in info}),
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "effective_mh_steps_per_s": r["sum_M"] / sec,
         "records_per_s": r["records"] / sec,
         "roofline": {"bound": "hbm", "achieved": dk["GB_per_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dk["hbm_frac"],
-                     "traffic": _measured_traffic(_class_key(dk), chain_steps),
+                     "traffic": _measured_traffic(_class_key(dk), chain_steps, dk["flavour"] == 5),
                      "bytes_per_flip": "N * 2 of the flipping chain's problem",
                      "kernel": f"{_kernel_name(dk)} "
                                f"(launch class N {dk['N_min']}..{dk['N_max']}, {dk['chains']} chains)",

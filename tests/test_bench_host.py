@@ -59,12 +59,19 @@ def test_issue_peak():
 
 
 def _current_sha():
-    # the step and window kernels' sources, in this order
+    # the step kernel's source (the VALU rows are step-kernel runs)
+    import hashlib
+    src = os.path.join(ROOT, "paper_2210_10513_amd", "csrc", "pns_step.h")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def test_window_kernel_rows_hash_both_sources():
     import hashlib
     h = hashlib.sha256()
     for name in ("pns_step.h", "pns_wave.h"):
         h.update(open(os.path.join(ROOT, "paper_2210_10513_amd", "csrc", name), "rb").read())
-    return h.hexdigest()[:16]
+    assert bench._kernel_sha(True) == h.hexdigest()[:16]
+    assert bench._kernel_sha() == _current_sha() != bench._kernel_sha(True)
 
 
 def test_cpu_baseline_child_reports_one_core_and_all_cores():
