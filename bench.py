@@ -37,12 +37,24 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Hardware queues of this process (read when HIP starts; its default is 4):
+# Hardware queues of this process (--hw-queues, default 8; read when HIP
+# starts, so taken from the command line before anything touches the GPU):
 # the batched workload's launch classes, about eight, run on one stream each
 # and each stream takes a queue of its own, so that all of them run at once
 # (measured on one MI355X: 701-704 ms per step at 8 queues against 833-870 at
-# 4, 965 at 6 and 777 at 16).  A value set in the environment is kept.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# HIP's default of 4, 965 at 6 and 777 at 16).
+
+
+def _hw_queues_arg() -> str:
+    for i, a in enumerate(sys.argv):
+        if a == "--hw-queues" and i + 1 < len(sys.argv):
+            return sys.argv[i + 1]
+        if a.startswith("--hw-queues="):
+            return a.split("=", 1)[1]
+    return "8"
+
+
+os.environ["GPU_MAX_HW_QUEUES"] = _hw_queues_arg()
 
 HBM_PEAK_GBS = 8000.0
 
@@ -630,6 +642,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batched64_uneven_int16")
+    ap.add_argument("--hw-queues", type=int, default=8, help="hardware queues of the process (GPU_MAX_HW_QUEUES)")
     ap.add_argument("--chain-steps", type=int, default=0, help="sampler steps per chain per bench step (0 = workload)")
     ap.add_argument("--launch", default="persistent")
     ap.add_argument("--tile", default="", help="workgroup size and 4-field groups per lane, e.g. 64,4")
@@ -640,7 +653,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: chains are independent, so nothing here runs on more than one "
-              "(see the sharding note in DESIGN.md); use --gpus 1", file=sys.stderr)
+              "(more GPUs would each take their own chains and a copy of Q); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

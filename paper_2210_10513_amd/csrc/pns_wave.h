@@ -86,6 +86,11 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    return __longlong_as_double(uniform64(__double_as_longlong(v)));
+}
+
 // Mask of the 256-bit segments [lo, hi] (0 <= lo <= hi <= 63).
 __device__ __forceinline__ uint64_t seg_range(int lo, int hi)
 {
@@ -398,7 +403,8 @@ void wave_kernel(const StepArgs a)
 
         // ---- p, M and the budget decision of Alg 6 (uniform) ----
         const double Ss = scaled ? exp_of(mx) * S : S;
-        const double p = n_pow2 ? ldexp(Ss, neg_log2n) : Ss / (double)n;
+        // (uniform: the branches on p below are then scalar branches)
+        const double p = uniform_f64(n_pow2 ? ldexp(Ss, neg_log2n) : Ss / (double)n);
         double q;
         if (p >= 1.0) q = 0.0;
         else if (p <= 0.0) q = INFINITY;
