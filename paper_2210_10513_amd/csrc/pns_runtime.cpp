@@ -1186,12 +1186,30 @@ int autotune_impl(const ProblemSpec& base, int32_t mode, const pns_opts& o, int3
     };
     std::vector<Trial> res;
     int trials = 0;
-    for (const Tile& tl : kTiles) {
+    // Where a window kernel tile holds the problem, only the smallest such
+    // tile is tried (over the subset sizes): the window kernel ran faster than
+    // the step kernel's tiles at every size measured, and its cost per step
+    // past the weighing (the move's row and field update) and its registers
+    // and LDS per chain grow with the tile, which in a batch limits how many
+    // chains are resident; a batch also forms one launch class per tile.
+    auto holds = [&](const Tile& tl) {
         const int64_t cap = (int64_t)tl.block * 4 * tl.groups;
-        if (cap < base.N || cap > 2 * round_up(base.N, 256)) continue;
+        return cap >= base.N && cap <= 2 * round_up(base.N, 256);
+    };
+    int64_t window_cap = 0;
+    for (const Tile& tl : kTiles)
+        for (int32_t n : ns)
+            if (holds(tl) && flavour_for(mode, base.N, n, tl, ctx->qtype, ctx->htype) == 5) {
+                const int64_t cap = (int64_t)tl.block * 4 * tl.groups;
+                if (window_cap == 0 || cap < window_cap) window_cap = cap;
+            }
+    for (const Tile& tl : kTiles) {
+        if (!holds(tl)) continue;
+        if (window_cap && (int64_t)tl.block * 4 * tl.groups != window_cap) continue;
         for (int32_t n : ns) {
             const int32_t fl = flavour_for(mode, base.N, n, tl, ctx->qtype, ctx->htype);
             if (fl < 0 || (wide_tile(tl) && fl != 3 && fl != 4 && fl != 5)) continue;
+            if (window_cap && fl != 5) continue;
             double r = 0.0, fr = 0.0;
             rc = reconfigure(ctx, tl, n);
             if (!rc) rc = time_config(ctx, trial_steps, &r, &fr);

@@ -322,11 +322,15 @@ void wave_kernel(const StepArgs a)
         // ---- S: window weights from the tables, four-bit sums, segment
         // scans; the energy differences go to the slots ----
         bool big = false;  // a window bit of this lane past the tables
+        // one wave: the sum of the window's segment totals in segment order
+        // (used when there are at most two, where it is what the segment
+        // scan gives)
+        double S2 = 0.0;
         {
             int r = 0;
-            for_each_index(std::make_integer_sequence<int, G>{}, [&](auto gc) {
+            auto weigh = [&](auto gc) {
                 constexpr int g = decltype(gc)::value;
-                if ((gmask >> g) & 1ull) {
+                {
                     int32_t es[4];
                     double w4[4];
 #pragma unroll
@@ -352,7 +356,20 @@ void wave_kernel(const StepArgs a)
                         islot[wave][r][lane] = inc;
                     }
                     if (lane == 63) seg_sum[k & 1][g * W + wave] = inc;
+                    if constexpr (W == 1) S2 = S2 + read_lane(inc, 63);
                     ++r;
+                }
+            };
+            // the groups the window meets, tested four at a time
+            for_each_index(std::make_integer_sequence<int, (G + 3) / 4>{}, [&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                if ((gmask >> (4 * q)) & 0xFull) {
+                    for_each_index(std::make_integer_sequence<int, 4>{}, [&](auto vc) {
+                        constexpr int g = 4 * q + decltype(vc)::value;
+                        if constexpr (g < G) {
+                            if ((gmask >> g) & 1ull) weigh(std::integral_constant<int, g>{});
+                        }
+                    });
                 }
             });
         }
@@ -360,17 +377,25 @@ void wave_kernel(const StepArgs a)
         if constexpr (W > 1) {
             if (lane == 0) slow_part[k & 1][wave] = slow ? 1 : 0;
         }
-        double sv = read_totals();
+        // one wave and at most two segments: S from the pass, and the
+        // segment scan only when the chain moves
+        const bool fast_S = W == 1 && __builtin_popcountll(smask) <= 2;
+        double sv = fast_S ? 0.0 : read_totals();
         if constexpr (W > 1) {
             int any = 0;
 #pragma unroll
             for (int ww = 0; ww < W; ++ww) any |= slow_part[k & 1][ww];
             slow = any != 0;
         }
+        double sinc = 0.0, S = S2;
+        bool scanned = false;
         // a weight past the tables: the window's sums with the exponential
         if (slow) sv = slot_totals(0.0);
-        double sinc = small_scan<NSEG>(sv);
-        double S = read_lane(sinc, NSEG - 1);
+        if (slow || !fast_S) {
+            sinc = small_scan<NSEG>(sv);
+            S = read_lane(sinc, NSEG - 1);
+            scanned = true;
+        }
         double mx = 0.0;
         bool scaled = false;
         if (S < 0x1p-1000) {
@@ -399,6 +424,7 @@ void wave_kernel(const StepArgs a)
             sv = slot_totals(mx);
             sinc = small_scan<NSEG>(sv);
             S = read_lane(sinc, NSEG - 1);
+            scanned = true;
         }
 
         // ---- p, M and the budget decision of Alg 6 (uniform) ----
@@ -463,6 +489,10 @@ void wave_kernel(const StepArgs a)
             // ---- proportional choice (appendix "How to Sample
             // Proportionally"): first bit of the window, in bit order, whose
             // running sum exceeds U2 S; segment -> lane -> bit ----
+            if (!scanned) {
+                sv = read_totals();
+                sinc = small_scan<NSEG>(sv);
+            }
             const double t = U2 * S;
             const bool pos_seg = lane < NSEG && sv > 0.0;
             const uint64_t bseg = __ballot(pos_seg && sinc > t);
