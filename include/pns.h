@@ -110,9 +110,10 @@ typedef struct pns_opts {
                                512x4, 1024x2, 1024x4, and 256x16 for 32-bit fields
                                (I16, I32 with int32 fields).  Window-kernel tiles
                                (PNS_MODE_UNBIASED_SYS on I16 / I32 with int32
-                               fields, flavour 5 of pns_problem_info): 64x8,
-                               64x16, 64x24, 128x16, 128x24 and 256x16, which
-                               then runs the window kernel.  4 * block * groups
+                               fields, flavour 5 of pns_problem_info): 64x2,
+                               64x4, 64x8, 64x16, 64x24, 128x16, 128x24 and
+                               256x16, which then run the window kernel (64x2
+                               and 64x4 no longer run the step kernel there).  4 * block * groups
                                must reach N; another shape, or a window-kernel
                                tile for another mode or type, is PNS_EINVAL       */
     int32_t groups;         /* 4-field groups per lane; 0 = chosen with `block`   */
@@ -212,7 +213,9 @@ int pns_create(pns_ctx** out, const void* Q, int32_t N, double beta, int32_t sub
  * chain c of problem p is numbered problems[0..p-1].num_chains + c.  Problems
  * are grouped by workgroup tile and kernel flavour; each group (launch class)
  * runs in its own kernel launch, the launches concurrent on side streams (in
- * the graph form as parallel graph nodes).
+ * the graph form as parallel graph nodes): one stream per class, up to the
+ * process's hardware queues (GPU_MAX_HW_QUEUES, read when HIP starts; at most
+ * 16), classes packed longest first when there are more.
  * Per-chain arrays of bits or fields (pns_read, pns_read_current,
  * pns_read_snapshots) are concatenated, chain c occupying the N of its
  * problem; pns_chain_offsets gives the offsets.  Histograms are not
@@ -228,7 +231,8 @@ int pns_create_batch(pns_ctx** out, int32_t num_problems, const pns_problem* pro
  * subset size for one problem by timed trials on the device: every compiled
  * tile whose capacity 4 * block * groups lies between N and twice N rounded
  * up to 256 (tiles of 32 or more fields per lane only where a window kernel
- * runs the problem), with every subset size 16, 32, ... up to N/2, is run
+ * runs the problem; where a window-kernel tile holds the problem, only the
+ * smallest such tile), with every subset size 16, 32, ... up to N/2, is run
  * for trial_steps steps (after a warmup; the faster of two timed runs) from
  * x = 0 with max(3072, opts->num_chains) chains, at most 4096 (the
  * problem's betas repeated), so that the device is loaded as in a real run;
