@@ -91,21 +91,40 @@ def _measured_traffic(workload: str, chain_steps: int, window: bool = False):
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
-def _valu_per_chain_step(workload: str, tile):
-    """VALU instructions (wave64) per chain step of the step kernel from the
-    committed SQ counter runs (profiles/valu_issue.txt), or None when no run
-    matches the workload and tile (block, groups) or the kernel sources changed
-    since."""
+def _valu_per_chain_step(workload: str, tile, window: bool = False):
+    """VALU instructions (wave64) per chain step of the step kernel (window:
+    the window kernel) from the committed SQ counter runs
+    (profiles/valu_issue.txt), or None when no run matches the workload and
+    tile (block, groups) or the kernel's sources changed since."""
     path = os.path.join(ROOT, "profiles", "valu_issue.txt")
     if not os.path.exists(path):
         return None
-    sha = _kernel_sha()
+    sha = _kernel_sha(window)
     for line in open(path):
         f = line.split()
         if (len(f) == 6 and not line.startswith("#") and f[0] == workload and f[1] == "%dx%d" % tuple(tile)
                 and f[2] == sha):
             return float(f[3]) / float(f[4])
     return None
+
+
+def _batch_issue_roofline(classes, chain_steps: int, sec_per_step: float):
+    """Wave64 VALU issue of the whole batch: every class's VALU instructions
+    per chain step (committed SQ counter runs) times its chain steps, over the
+    step time, against the issue peak; None unless every class has a row for
+    its current kernel source."""
+    total = 0.0
+    for c in classes:
+        b, g = (int(v) for v in c["tile"].split("x"))
+        vps = _valu_per_chain_step(_class_key(c), (b, g), c["flavour"] == 5)
+        if vps is None:
+            return None
+        total += vps * c["chains"] * chain_steps
+    achieved = total / sec_per_step
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_ISSUE_PEAK, "unit": "wave64 VALU instr/s",
+            "frac": achieved / VALU_ISSUE_PEAK, "valu_per_step": total,
+            "scope": "every launch class's VALU instructions per chain step (SQ counters) x its chain steps, "
+                     "over the step time"}
 
 
 def _class_key(c) -> str:
@@ -431,6 +450,9 @@ def _bench_batch(args, wl, cpu_spec=None):
         "classes": classes,
         "setup_s": r["setup_s"],
     }
+    issue = _batch_issue_roofline(classes, chain_steps, sec)
+    if issue is not None:
+        out["issue_roofline"] = issue
     if not args.no_extras:
         # the N >= 8192 problems on their own (same chains, same kernels):
         # their rate when they do not share the GPU with the rest of the batch
