@@ -171,6 +171,8 @@ def test_autotune_choice_is_valid_and_does_not_change_results():
     o.num_chains = 256
     t = b.pns_autotune(Q, 1000, 0.01, 0, b.PNS_MODE_UNBIASED_SYS, o, 32)
     assert t.block * 4 * t.groups >= 1000
+    # the smallest window-kernel tile that holds N = 1000 (1024 bits)
+    assert (t.block, t.groups) == (64, 4)
     assert 16 <= t.subset_size <= 500 and t.trials >= 2
     assert t.records_per_s > 0
     t2 = b.pns_autotune(Q, 1000, 0.01, 0, b.PNS_MODE_UNBIASED_SYS, o, 32)
