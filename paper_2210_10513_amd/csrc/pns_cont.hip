@@ -130,6 +130,47 @@ __device__ __forceinline__ double group_scan(double v, int r)
     return v;
 }
 
+// exp(l) for l <= 0 (the weights min(1, pi(y)/pi(x))): Cody-Waite reduction
+// l = k ln 2 + r with |r| <= ln 2 / 2 (ln 2 split in two so that k ln2_hi is
+// exact), exp(r) by its Taylor series to degree 13 (truncation below 2^-57
+// relative) in Horner form, scaled by 2^k with ldexp (gradual underflow; 0
+// below the smallest subnormal).  Within 2 ulp of the correctly rounded
+// value.  The constants are wave-uniform values passed in scalar registers,
+// read once before the step loop.
+struct ExpConsts {
+    double c[14];  // 1 / j!
+    double log2e, ln2_hi, ln2_lo;
+};
+
+__device__ __forceinline__ ExpConsts exp_consts()
+{
+    ExpConsts e;
+    double f = 1.0;
+#pragma unroll
+    for (int j = 0; j < 14; ++j) {
+        if (j > 0) f = f / (double)j;
+        e.c[j] = f;
+    }
+    e.log2e = 0x1.71547652b82fep+0;
+    e.ln2_hi = 0x1.62e42fee00000p-1;
+    e.ln2_lo = 0x1.a39ef35793c76p-33;
+#pragma unroll
+    for (int j = 0; j < 14; ++j) asm volatile("" : "+s"(e.c[j]));
+    asm volatile("" : "+s"(e.log2e), "+s"(e.ln2_hi), "+s"(e.ln2_lo));
+    return e;
+}
+
+__device__ __forceinline__ double exp_nonpos(double l, const ExpConsts& e)
+{
+    l = fmax(l, -746.0);
+    const double k = rint(l * e.log2e);
+    const double r = fma(-k, e.ln2_lo, fma(-k, e.ln2_hi, l));
+    double p = e.c[13];
+#pragma unroll
+    for (int j = 12; j >= 0; --j) p = fma(p, r, e.c[j]);
+    return ldexp(p, (int)k);
+}
+
 // MP: neighbours per lane the kernel is built for (m <= MP; the launcher
 // picks the smallest of 2, 4, 7, 8 that holds m), so that the weights of a
 // lane are straight-line code without branches and their exponentials
@@ -191,6 +232,7 @@ __global__ __launch_bounds__(256) void cont_kernel(const ContArgs a)
         acc[u] = akind[u] >= 0 ? a.sums[(int64_t)ch * 2 * NS + idx] : 0.0;
     }
 
+    const ExpConsts ek = exp_consts();
     double logU1b = 0.0, U2b = 0.0;
     for (int64_t it = 0; it < a.steps; ++it) {
         const int64_t k = k0 + it;
@@ -210,7 +252,7 @@ __global__ __launch_bounds__(256) void cont_kernel(const ContArgs a)
             for (int i = 0; i < D; ++i) y[i] = x[i] + s[t][i];
             const double l = fmin(log_density<D>(y, a.mu0, a.c) - lpx, 0.0);
             const bool on = t < m && r * m + t < n;
-            w[t] = on ? exp(l) : 0.0;
+            w[t] = on ? exp_nonpos(l, ek) : 0.0;
             ls += w[t];
         }
         const double incl = group_scan(ls, r);
