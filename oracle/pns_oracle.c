@@ -506,7 +506,10 @@ int orc_run(const orc_run_args* a)
     double* dEf = (double*)malloc(sizeof(double) * (size_t)N);
     double* lw = (double*)malloc(sizeof(double) * (size_t)N);
     double* w = (double*)malloc(sizeof(double) * (size_t)N);
-    if (!x || !xbest || !member || !hi || !hf || !dEi || !dEf || !lw || !w) return -3;
+    if (!x || !xbest || !member || !hi || !hf || !dEi || !dEf || !lw || !w) {
+        free(x); free(xbest); free(member); free(hi); free(hf); free(dEi); free(dEf); free(lw); free(w);
+        return -3;
+    }
 
     for (int32_t ch = 0; ch < a->num_chains; ++ch) {
         const uint32_t cid = a->chain_ids[ch];
