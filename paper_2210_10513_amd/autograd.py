@@ -161,7 +161,8 @@ class FitResult:
 
 
 def fit_qubo(data_moments: torch.Tensor, beta: float, iters: int, lr: float, opts: ChainOptions,
-             Q0: Optional[torch.Tensor] = None, momentum: float = 0.9, centered: bool = True) -> FitResult:
+             Q0: Optional[torch.Tensor] = None, momentum: float = 0.9, centered: bool = True,
+             average_from: Optional[int] = None) -> FitResult:
     """Maximum-likelihood fit of Q to data second moments D = E_data[x x^T]
     by gradient descent with momentum on beta <Q, D> + log Z(Q); every
     gradient of log Z comes from LogZ's backward (sampled moments on the
@@ -174,7 +175,13 @@ def fit_qubo(data_moments: torch.Tensor, beta: float, iters: int, lr: float, opt
     same (a fixed linear change of coordinates), but the gradient in W is
     the difference of covariances instead of second moments, which removes
     the collective direction driven by the means whose curvature grows like
-    N and would force a step size ~ 1/N."""
+    N and would force a step size ~ 1/N.
+
+    With ``average_from`` = t0 the result is the mean of the iterates after
+    the updates t0 .. iters-1 (tail averaging of Polyak and Juditsky, 1992)
+    instead of the last iterate: every gradient is a Monte Carlo estimate,
+    and the last iterate keeps the noise of its last steps, which the mean
+    averages out."""
     D = data_moments.to(torch.float32)
     N = int(D.shape[0])
     dev = D.device
@@ -195,8 +202,11 @@ def fit_qubo(data_moments: torch.Tensor, beta: float, iters: int, lr: float, opt
             return Ws + torch.diag(a - 2 * (Ws @ mu))
         return (Qp + Qp.T) * 0.5
 
+    if average_from is not None and not 0 <= average_from < iters:
+        raise ValueError(f"average_from must lie in [0, {iters})")
     vel = [torch.zeros_like(p) for p in params]
     res = FitResult(Q=Qinit)
+    Qsum, nsum = None, 0
     state = opts.state if opts.state is not None else {}
     o = ChainOptions(**{**opts.__dict__, "state": state})
     try:
@@ -214,9 +224,13 @@ def fit_qubo(data_moments: torch.Tensor, beta: float, iters: int, lr: float, opt
                 for p, v in zip(params, vel):
                     v.mul_(momentum).add_(p.grad)
                     p.sub_(lr * v)
+                if average_from is not None and it >= average_from:
+                    Qi = build_q()
+                    Qsum = Qi.clone() if Qsum is None else Qsum.add_(Qi)
+                    nsum += 1
     finally:
         if opts.state is None:
             release(state)
     with torch.no_grad():
-        res.Q = build_q().detach()
+        res.Q = build_q().detach() if Qsum is None else Qsum / nsum
     return res

@@ -207,6 +207,31 @@ def test_maximum_likelihood_fit_recovers_moments_n16():
     assert res.moment_gap[-1] < res.moment_gap[0]
 
 
+def test_fit_tail_average_reduces_gradient_noise():
+    """With exact data moments (N = 16, enumeration) the fit's remaining
+    parameter error is the Monte Carlo noise of its gradients: the mean of
+    the last 100 of 200 iterates lies closer to the truth than the last
+    iterate, and averaging over the last update alone returns the last
+    iterate itself (the sampler and the integer-weighted moments are
+    deterministic for fixed seeds)."""
+    import torch
+    from paper_2210_10513_amd.autograd import ChainOptions, fit_qubo
+    N = 16
+    Qt = inputs.symmetric_gauss(N, seed=77).astype(np.float64) * 1.5
+    D = torch.tensor(exact.second_moments(Qt, 1.0), device="cuda")
+    kw = dict(iters=200, lr=0.5, opts=ChainOptions(num_chains=4096, burn_in=100, samples=16, every=4, seed=11))
+    last = fit_qubo(D, 1.0, **kw)
+    one = fit_qubo(D, 1.0, average_from=199, **kw)
+    avg = fit_qubo(D, 1.0, average_from=100, **kw)
+    assert torch.equal(last.Q, one.Q)
+    Qtt = torch.tensor(Qt, dtype=torch.float32, device="cuda")
+    rel_last = float((last.Q - Qtt).norm() / Qtt.norm())
+    rel_avg = float((avg.Q - Qtt).norm() / Qtt.norm())
+    assert rel_avg < 0.7 * rel_last, (rel_avg, rel_last)
+    with pytest.raises(ValueError):
+        fit_qubo(D, 1.0, average_from=200, **kw)
+
+
 @pytest.mark.parametrize("N", [64, 512])
 def test_fit_workload_gradient_sampled_entries(N):
     """The fit workload's shape (8192 chains, float32 Q): the backward's G
