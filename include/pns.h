@@ -202,7 +202,8 @@ void pns_opts_default(pns_opts* opts);
  * Errors: PNS_EINVAL (N <= 0, n outside [1, N], beta < 0 or not finite,
  *         unknown dtype/layout/mode/launch, SYMMETRIC Q not symmetric, a field
  *         bound overflowing 62 bits, hist with N > 24), PNS_ENOMEM,
- *         PNS_EDEVICE, PNS_EUNSUPPORTED (N above the largest tuned tile).
+ *         PNS_EDEVICE, PNS_EUNSUPPORTED (N above 16384, the capacity of the
+ *         largest tile; checked before Q is read).
  */
 int pns_create(pns_ctx** out, const void* Q, int32_t N, double beta, int32_t subset_size, int32_t mode,
                const pns_opts* opts);

@@ -144,6 +144,9 @@ struct Tile {
 };
 
 // Fixed tile table: smallest capacity (block * 4 * groups) covering N.
+// Largest problem a tile holds (256 x 16: 64 fields per lane).
+constexpr int32_t kMaxN = 16384;
+
 Tile default_tile(int32_t N)
 {
     if (N <= 256) return {64, 1};
@@ -731,7 +734,7 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         if ((int32_t)S.betas.size() != S.chains) return fail(PNS_EINVAL, "betas size mismatch");
         for (double b : S.betas)
             if (!(b >= 0.0) || !std::isfinite(b)) return fail(PNS_EINVAL, "beta must be finite and >= 0");
-        if (S.N > 16384) return fail(PNS_EUNSUPPORTED, "N=%d exceeds the largest tile (16384)", S.N);
+        if (S.N > kMaxN) return fail(PNS_EUNSUPPORTED, "N=%d exceeds the largest tile (%d)", S.N, kMaxN);
         if (S.tile.block != 0 && (int64_t)S.tile.block * 4 * S.tile.groups < S.N)
             return fail(PNS_EINVAL, "tile %dx%d cannot hold N=%d", S.tile.block, S.tile.groups, S.N);
         total_chains += S.chains;
@@ -1284,6 +1287,8 @@ int pns_create(pns_ctx** out, const void* Q, int32_t N, double beta, int32_t sub
     if (rc) return rc;
     if (!Q) return fail(PNS_EINVAL, "Q is NULL");
     if (N <= 0) return fail(PNS_EINVAL, "N must be positive");
+    // (before the matrix is read: the autotuner prepares it first)
+    if (N > kMaxN) return fail(PNS_EUNSUPPORTED, "N=%d exceeds the largest tile (%d)", N, kMaxN);
     if (mode < PNS_MODE_RF || mode > PNS_MODE_UNBIASED_RAND) return fail(PNS_EINVAL, "unknown mode %d", mode);
     if (o.hist && N > 24) return fail(PNS_EINVAL, "histograms need N <= 24");
     const bool tune_n = o.autotune && mode != PNS_MODE_RF && subset_size == 0;
@@ -1344,6 +1349,8 @@ int pns_create_batch(pns_ctx** out, int32_t num_problems, const pns_problem* pro
         ProblemSpec& S = specs[p];
         if (!q.Q) return fail(PNS_EINVAL, "problem %d: Q is NULL", p);
         if (q.N <= 0) return fail(PNS_EINVAL, "problem %d: N must be positive", p);
+        if (q.N > kMaxN)
+            return fail(PNS_EUNSUPPORTED, "problem %d: N=%d exceeds the largest tile (%d)", p, q.N, kMaxN);
         if (q.layout != PNS_SYMMETRIC && q.layout != PNS_UPPER)
             return fail(PNS_EINVAL, "problem %d: unknown layout %d", p, q.layout);
         if (q.num_chains < 1) return fail(PNS_EINVAL, "problem %d: num_chains must be >= 1", p);
@@ -1401,6 +1408,7 @@ int pns_autotune(const void* Q, int32_t N, double beta, int32_t subset_size, int
     int rc = check_opts(&o);
     if (rc) return rc;
     if (N <= 0) return fail(PNS_EINVAL, "N must be positive");
+    if (N > kMaxN) return fail(PNS_EUNSUPPORTED, "N=%d exceeds the largest tile (%d)", N, kMaxN);
     if (mode < PNS_MODE_RF || mode > PNS_MODE_UNBIASED_RAND) return fail(PNS_EINVAL, "unknown mode %d", mode);
     if (subset_size < 0 || subset_size > N) return fail(PNS_EINVAL, "subset size %d outside [0, %d]", subset_size, N);
     ProblemSpec S;

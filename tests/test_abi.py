@@ -73,6 +73,32 @@ def test_create_rejects_bad_arguments(kw, expect):
     assert expect in str(ei.value)
 
 
+def test_sizes_beyond_the_largest_tile_are_rejected_before_q_is_read():
+    """N above 16384 is PNS_EUNSUPPORTED for pns_create (also with the
+    autotuner on, which prepares the matrix first), pns_create_batch and
+    pns_autotune, before the matrix is read: the buffer passed here holds a
+    single entry."""
+    from paper_2210_10513_amd import binding as b
+    Q = np.zeros(1, np.int16)
+    for autotune in (0, 1):
+        o = b.pns_opts_default()
+        o.dtype = b.PNS_I16
+        o.autotune = autotune
+        with pytest.raises(b.PNSError) as ei:
+            b.pns_create(Q, 16385, 0.1, 64, b.PNS_MODE_UNBIASED_SYS, o)
+        assert ei.value.code == b.PNS_EUNSUPPORTED and "16384" in str(ei.value)
+    probs = [b.pns_problem(Q=Q.ctypes.data, N=N, layout=0, subset_size=0, num_chains=2, L0=0, betas=None, beta=0.1)
+             for N in (100, 20000)]
+    o = b.pns_opts_default()
+    o.dtype = b.PNS_I16
+    with pytest.raises(b.PNSError) as ei:
+        b.pns_create_batch(probs, b.PNS_MODE_UNBIASED_SYS, o)
+    assert ei.value.code == b.PNS_EUNSUPPORTED and "problem 1" in str(ei.value)
+    with pytest.raises(b.PNSError) as ei:
+        b.pns_autotune(Q, 16385, 0.1, 0, b.PNS_MODE_UNBIASED_SYS, o)
+    assert ei.value.code == b.PNS_EUNSUPPORTED
+
+
 @pytest.mark.parametrize("kw,expect", [
     (dict(problems=0), "num_problems"),
     (dict(N=0), "N must be positive"),
