@@ -222,6 +222,61 @@ def test_saturation_when_every_weight_underflows():
     assert r.action[0, 0] == 0  # bit 0 costs least (1000)
 
 
+def _one_step_choice(lib_handle=None):
+    """One step of 200000 independent chains from one fixed state and the
+    first systematic set (bits 0 .. n-1): (weights w_j = min(1, exp(-beta
+    dE_j)) with dE_j = E(x ^ e_j) - E(x) from numpy energies x^T Q x, the
+    run's result)."""
+    N, n, beta, C = 12, 5, 0.08, 200000
+    Q = _small_int_q(N, 21, -20, 20)
+    x = np.array([1, 0, 1, 1, 0, 0, 1, 0, 1, 0, 0, 1], dtype=np.int64)
+
+    def energy(s):
+        return int(s @ Q @ s)
+
+    w = np.empty(n)
+    for j in range(n):
+        y = x.copy()
+        y[j] ^= 1
+        w[j] = min(1.0, np.exp(-beta * (energy(y) - energy(x))))
+    r = oracle.run(Q, beta, oracle.MODE_UNBIASED_SYS, 1, n=n, L0=10**15, seed=4, num_chains=C,
+                   x0=np.tile(x.astype(np.uint8), (C, 1)), lib_handle=lib_handle)
+    return w, r
+
+
+def _choice_chi2(w, actions):
+    counts = np.bincount(actions, minlength=len(w))[:len(w)]
+    expect = len(actions) * w / w.sum()
+    return ((counts - expect) ** 2 / expect).sum()
+
+
+def test_one_step_choice_is_proportional_to_the_weights():
+    """Proportional choice (appendix "How to Sample Proportionally", Prop 5):
+    from one fixed state and one systematic set, p equals sum_S w / n, the
+    chosen bit follows w_j / sum_S w (chi-square, n - 1 degrees of freedom),
+    no bit outside the set is chosen, and P(M = 1) = p."""
+    w, r = _one_step_choice()
+    n, C = len(w), r.action.shape[0]
+    assert w.min() < 0.5 < w.max()  # the weights differ, so the law is informative
+    p = w.sum() / n
+    assert np.allclose(r.p[:, 0], p, rtol=1e-13, atol=0)
+    a = r.action[:, 0]
+    assert ((a >= 0) & (a < n)).all()
+    chi2 = _choice_chi2(w, a)
+    assert chi2 < 25.0, chi2  # 99.99% quantile of chi2(4) is about 23.5
+    m1 = (r.M[:, 0] == 1).mean()
+    assert abs(m1 - p) < 5 * np.sqrt(p * (1 - p) / C)
+
+
+def test_planted_choice_mistake_is_caught(tmp_path):
+    """A choice whose running sum counts the candidates instead of adding
+    their weights (planted in a copy of the oracle) fails the
+    proportionality pin."""
+    L = oracle.load_mutant([("        run += w[j];\n", "        run += w[j] > 0.0 ? 1.0 : 0.0;\n")], str(tmp_path))
+    w, r = _one_step_choice(L)
+    assert _choice_chi2(w, r.action[:, 0]) > 100.0
+
+
 # --------------------------------------------------------------------------
 # Stationary laws against brute-force enumeration
 # --------------------------------------------------------------------------
