@@ -549,7 +549,7 @@ def _cpu_model() -> str:
 
 
 def _cpu_cores() -> int:
-    """Cores this process may use, at most 16 (a one-GPU machine's CPU share)."""
+    """Cores this process may use, at most 16 (the CPU share of one GPU on a shared host)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
