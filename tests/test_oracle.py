@@ -88,7 +88,7 @@ def test_random_state_bernoulli_half():
 # Partial neighbor sets
 # --------------------------------------------------------------------------
 
-def test_systematic_sets_match_paper_listing():
+def test_systematic_sets_match_the_sec5_example():
     g = _golden_json("paper_examples.json")["systematic_sets"]
     N, n = g["N"], g["n"]
     assert oracle.sys_count(N, n) == g["count"]
