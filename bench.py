@@ -37,12 +37,16 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Hardware queues of this process (--hw-queues, default 8; read when HIP
+# Hardware queues of this process (--hw-queues, default 12; read when HIP
 # starts, so taken from the command line before anything touches the GPU):
-# the batched workload's launch classes, about eight, run on one stream each
-# and each stream takes a queue of its own, so that all of them run at once
-# (measured on one MI355X: 701-704 ms per step at 8 queues against 833-870 at
-# HIP's default of 4, 965 at 6 and 777 at 16).
+# the batched workload's launch classes, eight, run on one stream each next
+# to the context's own stream, and each stream needs a queue of its own so
+# that all classes run at once.  Measured on one MI355X, ms per step of the
+# batch with its launches queued directly on the streams: 664-666 at 12
+# queues, 667-676 at 10, 794-816 at 9 and 770-805 at 8 (two classes share a
+# queue and run one after the other); replaying the captured graph instead,
+# which maps its branches onto queues itself: 670-705 at 8, 688-694 at 9,
+# 688-788 at 10, 846-861 at 12, 833-870 at HIP's default of 4.
 
 
 def _hw_queues_arg() -> str:
@@ -51,7 +55,7 @@ def _hw_queues_arg() -> str:
             return sys.argv[i + 1]
         if a.startswith("--hw-queues="):
             return a.split("=", 1)[1]
-    return "8"
+    return "12"
 
 
 os.environ["GPU_MAX_HW_QUEUES"] = _hw_queues_arg()
@@ -404,7 +408,7 @@ def _time_batch(wl, chain_steps: int, steps: int, warmup: int, launch: str, seed
 
 def _bench_batch(args, wl, cpu_spec=None):
     chain_steps = args.chain_steps or wl["steps"]
-    launch = args.launch if args.launch != "persistent" else "graph"
+    launch = args.launch
     r = _time_batch(wl, chain_steps, args.steps, args.warmup, launch, seed=1)
     sec, flips, info = r["sec"], r["flips"], r["info"]
     achieved_all = r["qbytes"] / sec / 1e9
@@ -438,9 +442,9 @@ def _bench_batch(args, wl, cpu_spec=None):
                      "kernel": f"{_kernel_name(dk)} "
                                f"(launch class N {dk['N_min']}..{dk['N_max']}, {dk['chains']} chains)",
                      "kernel_avg_ms": dk["kernel_avg_ms"], "bytes_per_launch": dk["bytes_per_launch"],
-                     "timing": f"HIP events on the class's stream over {args.steps} further timed steps with the "
-                               f"graph's launches queued directly (step {r['prof_sec'] * 1e3:.1f} ms vs "
-                               f"{sec * 1e3:.1f} ms in the graph form)"},
+                     "timing": f"HIP events on the class's stream over {args.steps} further steps with the "
+                               f"launches queued directly (step {r['prof_sec'] * 1e3:.1f} ms there, "
+                               f"{sec * 1e3:.1f} ms in the timed {launch} form)"},
         "n_ge_8192": {"problems": int(sum(1 for i in info if i[0] >= 8192)), "chains": int(big.sum()),
                       "flips_per_s": float(r["prof_dflips"][big].sum()) / (big_ms * 1e-3) if big_ms else 0.0,
                       "GB_per_s": big_gbs, "hbm_frac": big_gbs / HBM_PEAK_GBS, "kernel_ms": big_ms,
@@ -664,7 +668,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batched64_uneven_int16")
-    ap.add_argument("--hw-queues", type=int, default=8, help="hardware queues of the process (GPU_MAX_HW_QUEUES)")
+    ap.add_argument("--hw-queues", type=int, default=12, help="hardware queues of the process (GPU_MAX_HW_QUEUES)")
     ap.add_argument("--chain-steps", type=int, default=0, help="sampler steps per chain per bench step (0 = workload)")
     ap.add_argument("--launch", default="persistent")
     ap.add_argument("--tile", default="", help="workgroup size and 4-field groups per lane, e.g. 64,4")
