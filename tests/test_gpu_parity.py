@@ -181,6 +181,49 @@ def test_energy_differences_past_the_weight_tables(mode, n, N, tile):
     _both(Q, 2e-6, mode, 300, chains=3, n=n, L0=40, seed=9, init="random", block=tile[0], groups=tile[1])
 
 
+@pytest.mark.parametrize("mode,n,L0", [("basic", 1, 100), ("unbiased_sys", 1, 100), ("unbiased_rand", 1, 100),
+                                      ("unbiased_sys", 3, 1), ("unbiased_rand", 5, 1)])
+def test_single_bit_subsets_and_unit_budgets(mode, n, L0):
+    """The degenerate cases of the subset rules: a subset of one bit (every
+    step weighs a single neighbour, p = its weight) and a budget of one
+    original sample (every record is a move of multiplicity 1 or a stay
+    with M = 1 or 0).  Every record replays through the oracle."""
+    Q = inputs.symmetric_int(67, -50, 50, np.int32, seed=67 + n + L0)
+    g, _ = _both(Q, 0.05, mode, 500, chains=3, n=n, L0=L0, seed=12, init="random")
+    if L0 == 1:
+        assert (g["log"]["M"] <= 1).all()
+
+
+def test_zero_steps_change_nothing():
+    """run(0) on a single-problem and a batched context: states, fields,
+    energies, step counters and statistics stay as they were."""
+    from paper_2210_10513_amd.binding import BatchSampler, Sampler
+    Q = inputs.symmetric_int(100, -50, 50, np.int32, seed=16)
+    s = Sampler(Q, 0.05, 10, "unbiased_sys", num_chains=4, seed=2, init="random")
+    s.run(30)
+    before = (s.read_current(), s.stats())
+    s.run(0)
+    after = (s.read_current(), s.stats())
+    s.close()
+    for key in before[0]:
+        assert np.array_equal(before[0][key], after[0][key]), key
+    for key in before[1]:
+        assert np.array_equal(before[1][key], after[1][key]), key
+    Q2 = inputs.symmetric_int(40, -50, 50, np.int32, seed=17)
+    b = BatchSampler([{"Q": Q, "num_chains": 2, "beta": 0.05, "subset_size": 10},
+                      {"Q": Q2, "num_chains": 3, "beta": 0.1, "subset_size": 8}], "unbiased_sys", seed=3)
+    b.run(20)
+    cur0, st0 = b.read_current(), b.stats()
+    b.run(0)
+    cur1, st1 = b.read_current(), b.stats()
+    b.close()
+    for key in cur0:  # per problem: one array of its chains each
+        for x, y in zip(cur0[key], cur1[key]):
+            assert np.array_equal(x, y), key
+    for key in st0:
+        assert np.array_equal(st0[key], st1[key]), key
+
+
 def test_infinite_temperature_unbiased_schedule():
     Q = inputs.symmetric_int(8, -5, 5, np.int32, seed=1)
     g = gpu_run(Q, 0.0, "unbiased_sys", 40, chains=1, n=2, L0=3, seed=1)
