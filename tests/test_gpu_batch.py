@@ -191,19 +191,50 @@ def test_autotune_choice_is_valid_and_does_not_change_results():
 def test_batched_workload_sampled_chains():
     """The 64-problem uneven-N int16 workload (N log-uniform in [256, 16384],
     half the entries zero, 64 chains each), subset sizes from the
-    autotuner, graph launch form: sampled chains of sampled problems
-    against the oracle."""
+    autotuner, the launch form the benchmark times (launches queued
+    directly): sampled chains of sampled problems against the oracle."""
     w = inputs.c4_batched()
     probs = [{"Q": Q, "num_chains": 64, "beta": float(w.betas[64 * i]), "subset_size": 0}
              for i, Q in enumerate(w.Q)]
     K = 60
-    g = _batch(probs, "unbiased_sys", K, seed=2210105134, launch="graph", L0=100)
+    g = _batch(probs, "unbiased_sys", K, seed=2210105134, launch="persistent", L0=100)
     Ns = [i.N for i in g["info"]]
     order = np.argsort(Ns)
     for p in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
         info = g["info"][p]
         assert 16 <= info.subset_size <= info.N // 2
         _check_problem(g, p, probs[p], "unbiased_sys", K, seed=2210105134, L0=100, rows=[0, 63])
+
+
+def test_batched_workload_uninstrumented_equals_instrumented():
+    """The kernels the benchmark times (no per-step outputs) on the full
+    64-problem workload, in its timed launch form and across two launches,
+    reach the same states, fields, energies, last records and counters as
+    the instrumented kernels, whose records replay through the oracle (the
+    test above)."""
+    from paper_2210_10513_amd.binding import BatchSampler
+    w = inputs.c4_batched()
+    probs = [{"Q": Q, "num_chains": 64, "beta": float(w.betas[64 * i]), "subset_size": 0}
+             for i, Q in enumerate(w.Q)]
+    K = 200
+    out = []
+    for log in (0, K):
+        s = BatchSampler(probs, "unbiased_sys", L0=100, seed=2210105134, launch="persistent", log_capacity=log)
+        s.run(K // 2)
+        s.run(K // 2)
+        out.append((s.read_current(), s.read(), s.stats(), [(i.block, i.groups, i.subset_size) for i in s.info]))
+        s.close()
+    (cu, ru, su, tu), (ci, ri, si, ti) = out
+    assert tu == ti
+    for key in cu:
+        for x, y in zip(cu[key], ci[key]):
+            assert np.array_equal(x, y), key
+    for a, b in zip(ru, ri):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    for key in su:
+        assert np.array_equal(su[key], si[key]), key
+    assert (si["steps"] == K).all() and (si["anomalies"] == 0).all()
 
 
 def test_class_profiling_counts_and_times_every_class():
