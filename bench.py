@@ -37,8 +37,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Hardware queues of this process (--hw-queues, default 12; read when HIP
-# starts, so taken from the command line before anything touches the GPU):
+# Hardware queues of this process (--hw-queues, default 12, or 8 with
+# --launch graph; read when HIP starts, so taken from the command line before
+# anything touches the GPU):
 # the batched workload's launch classes, eight, run on one stream each next
 # to the context's own stream, and each stream needs a queue of its own so
 # that all classes run at once.  Measured on one MI355X, ms per step of the
@@ -50,12 +51,15 @@ sys.path.insert(0, ROOT)
 
 
 def _hw_queues_arg() -> str:
+    graph = False
     for i, a in enumerate(sys.argv):
         if a == "--hw-queues" and i + 1 < len(sys.argv):
             return sys.argv[i + 1]
         if a.startswith("--hw-queues="):
             return a.split("=", 1)[1]
-    return "12"
+        if (a == "--launch" and i + 1 < len(sys.argv) and sys.argv[i + 1] == "graph") or a == "--launch=graph":
+            graph = True
+    return "8" if graph else "12"
 
 
 os.environ["GPU_MAX_HW_QUEUES"] = _hw_queues_arg()
@@ -668,7 +672,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batched64_uneven_int16")
-    ap.add_argument("--hw-queues", type=int, default=12, help="hardware queues of the process (GPU_MAX_HW_QUEUES)")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="hardware queues of the process (GPU_MAX_HW_QUEUES; default 12, 8 with --launch graph)")
     ap.add_argument("--chain-steps", type=int, default=0, help="sampler steps per chain per bench step (0 = workload)")
     ap.add_argument("--launch", default="persistent")
     ap.add_argument("--tile", default="", help="workgroup size and 4-field groups per lane, e.g. 64,4")
