@@ -1,4 +1,4 @@
-"""Host-side checks of bench.py: the one-GPU guard and the committed counter
+"""Host-side checks of bench.py: the one-GPU guard, the hardware-queue default and the committed counter
 tables it reads (HBM bytes per launch, VALU instructions per chain step).
 CPU only: nothing here launches a kernel."""
 import os
@@ -86,3 +86,15 @@ def test_cpu_baseline_child_reports_one_core_and_all_cores():
     assert out["kind"] == "oracle" and out["cores"] == 1 and out["value"] > 0 and out["cpu_model"]
     if "all_cores" in out:
         assert out["all_cores"]["cores"] > 1 and out["all_cores"]["value"] > 0
+
+
+def test_hardware_queue_default_follows_the_launch_form(monkeypatch):
+    """Twelve queues for launches queued directly (one per class stream and
+    the context's stream), eight for graph replays, and an explicit
+    --hw-queues wins."""
+    import bench
+    for argv, want in ((["bench.py"], "12"), (["bench.py", "--launch", "graph"], "8"),
+                       (["bench.py", "--launch=graph"], "8"), (["bench.py", "--launch", "graph", "--hw-queues", "6"], "6"),
+                       (["bench.py", "--hw-queues=10"], "10")):
+        monkeypatch.setattr(sys, "argv", argv)
+        assert bench._hw_queues_arg() == want, argv
