@@ -591,6 +591,20 @@ hipError_t launch_pt_swap(const int64_t* E, int32_t is_float, double* beta, int3
     return hipGetLastError();
 }
 
+// One wave that waits `ticks` of the constant-rate wall clock (100 MHz on
+// this device) and exits: a bounded delay on a stream.
+__global__ void hold_kernel(uint64_t ticks)
+{
+    const uint64_t t0 = wall_clock64();
+    while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
+}
+
+hipError_t launch_hold(uint64_t ticks, hipStream_t st)
+{
+    hipLaunchKernelGGL(hold_kernel, dim3(1), dim3(64), 0, st, ticks);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill64(void* p, int64_t count, int64_t value, hipStream_t stream)
 {
     if (count <= 0) return hipSuccess;

@@ -457,6 +457,7 @@ struct pns_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipEvent_t fork = nullptr;
+    hipEvent_t fork_small = nullptr;  // release of the one-wave classes after a short hold
     std::vector<SideStream> sides;
     std::vector<ProblemRun> probs;
     std::vector<int32_t> h_chain_problem;
@@ -634,15 +635,27 @@ struct pns_ctx {
     {
         if (classes.size() == 1) return launch_class(classes[0], steps, stream, orig_time, first, last);
         HIP_TRY(hipEventRecord(fork, stream), "fork record");
+        // The side streams are ordered largest workgroups first; the streams
+        // of one-wave classes start 200 us later, so that the workgroups of
+        // several waves find whole compute units before the one-wave
+        // workgroups fill them (all queues released at once would race).
+        bool held = false;
         for (auto& sd : sides) {
-            HIP_TRY(hipStreamWaitEvent(sd.stream, fork, 0), "fork wait");
+            const bool small = classes[sd.classes.front()].tile.block <= 64;
+            if (small && !held && &sd != &sides.front()) {
+                HIP_TRY(launch_hold(20000, stream), "hold");
+                HIP_TRY(hipEventRecord(fork_small, stream), "fork record");
+                held = true;
+            }
+            HIP_TRY(hipStreamWaitEvent(sd.stream, held ? fork_small : fork, 0), "fork wait");
             for (int32_t ki : sd.classes) {
                 int rc = launch_class(classes[ki], steps, sd.stream, orig_time, first, last);
                 if (rc) return rc;
             }
             HIP_TRY(hipEventRecord(sd.done, sd.stream), "join record");
-            HIP_TRY(hipStreamWaitEvent(stream, sd.done, 0), "join wait");
         }
+        // (the joins after every launch: the hold above sits on this stream)
+        for (auto& sd : sides) HIP_TRY(hipStreamWaitEvent(stream, sd.done, 0), "join wait");
         return PNS_OK;
     }
 
@@ -675,6 +688,7 @@ struct pns_ctx {
             if (sd.done) (void)hipEventDestroy(sd.done);
         }
         if (fork) (void)hipEventDestroy(fork);
+        if (fork_small) (void)hipEventDestroy(fork_small);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -979,7 +993,8 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         if (e != hipSuccess) return fail_free(hip_fail(e, "hipMemset"));
     }
     if (ctx->classes.size() > 1) {
-        if ((e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming)) != hipSuccess)
+        if ((e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&ctx->fork_small, hipEventDisableTiming)) != hipSuccess)
             return fail_free(hip_fail(e, "hipEventCreate"));
         // longest-processing-time-first packing of the classes onto the side streams
         std::vector<int32_t> order(ctx->classes.size());
@@ -993,6 +1008,17 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
             ctx->sides[sdi].classes.push_back(ki);
             load[sdi] += ctx->classes[ki].cost;
         }
+        // Launch order of the side streams: the largest workgroups first
+        // (waves per workgroup, then fields per lane).  Every workgroup keeps
+        // its chain for the whole launch, and a workgroup of several waves
+        // needs room on one compute unit at once; started after smaller ones
+        // it finds the compute units fragmented and waits for them.
+        auto footprint = [&](const SideStream& sd) {
+            const Tile t = ctx->classes[sd.classes.front()].tile;
+            return std::make_pair(t.block, t.groups);
+        };
+        std::stable_sort(ctx->sides.begin(), ctx->sides.end(),
+                         [&](const SideStream& a, const SideStream& b) { return footprint(a) > footprint(b); });
         for (auto& sd : ctx->sides) {
             if ((e = hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking)) != hipSuccess)
                 return fail_free(hip_fail(e, "hipStreamCreate"));
