@@ -591,8 +591,8 @@ hipError_t launch_pt_swap(const int64_t* E, int32_t is_float, double* beta, int3
     return hipGetLastError();
 }
 
-// One wave that waits `ticks` of the constant-rate wall clock (100 MHz on
-// this device) and exits: a bounded delay on a stream.
+// One wave that waits `ticks` of the constant-rate wall clock and exits: a
+// bounded delay on a stream.
 __global__ void hold_kernel(uint64_t ticks)
 {
     const uint64_t t0 = wall_clock64();

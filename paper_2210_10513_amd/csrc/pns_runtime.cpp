@@ -458,6 +458,7 @@ struct pns_ctx {
     bool own_stream = false;
     hipEvent_t fork = nullptr;
     hipEvent_t fork_small = nullptr;  // release of the one-wave classes after a short hold
+    uint64_t hold_ticks = 20000;      // 200 us of the device's wall clock (100 MHz unless it says otherwise)
     std::vector<SideStream> sides;
     std::vector<ProblemRun> probs;
     std::vector<int32_t> h_chain_problem;
@@ -643,7 +644,7 @@ struct pns_ctx {
         for (auto& sd : sides) {
             const bool small = classes[sd.classes.front()].tile.block <= 64;
             if (small && !held && &sd != &sides.front()) {
-                HIP_TRY(launch_hold(20000, stream), "hold");
+                HIP_TRY(launch_hold(hold_ticks, stream), "hold");
                 HIP_TRY(hipEventRecord(fork_small, stream), "fork record");
                 held = true;
             }
@@ -996,6 +997,12 @@ int create_impl(pns_ctx** out, std::vector<ProblemSpec>& specs, int32_t mode, co
         if ((e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&ctx->fork_small, hipEventDisableTiming)) != hipSuccess)
             return fail_free(hip_fail(e, "hipEventCreate"));
+        {
+            int dev = 0, khz = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+                ctx->hold_ticks = (uint64_t)khz / 5;  // kHz x 0.2 ms
+        }
         // longest-processing-time-first packing of the classes onto the side streams
         std::vector<int32_t> order(ctx->classes.size());
         for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
