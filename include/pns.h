@@ -639,6 +639,23 @@ int pns_read_rb_weights(pns_ctx* ctx, double* log_w, double* snap_w, double* his
 int pns_snapshot_moments_rb(pns_ctx* ctx, int32_t problem, double* G, double* sum_w);
 
 /*
+ * Gradient of log Z(Q, beta) = log sum_x exp(-beta x^T Q x) from the
+ * snapshots of one problem: d log Z / d Q_ij = -beta E_pi[x_i x_j], with
+ * E_pi estimated by the weighted average of the snapshot states (the ratio
+ * estimator of Thm 3 (5), h = x_i x_j), i.e.
+ *     grad = -beta * G / sum_w,  G = pns_snapshot_moments (rb = 0: weights
+ *     M) or pns_snapshot_moments_rb (rb != 0: expected multiplicities).
+ *   grad   [N][N] FP64, device memory: receives the gradient (the full
+ *          matrix; only Q_ij + Q_ji is identifiable, as x_i^2 = x_i).
+ *   sum_w  one FP64, device memory: receives sum_w (a zero sum gives
+ *          non-finite entries).
+ * Queued on the context's stream; no host wait.
+ * Errors: PNS_EINVAL (NULL or host buffers, beta not finite, as
+ * pns_snapshot_moments), PNS_EDEVICE.
+ */
+int pns_logz_grad(pns_ctx* ctx, int32_t problem, double beta, int32_t rb, double* grad, double* sum_w);
+
+/*
  * log Z(Q, beta) = log sum_x exp(-beta x^T Q x) by enumeration of all 2^N
  * states on the device (Gray-code order, incremental energies: exact int64
  * for integer Q, FP64 for float Q; FP64 log-sum-exp).  Q [N][N] of `dtype`

@@ -109,9 +109,10 @@ class LogZ(torch.autograd.Function):
         dev = grad_out.device
         G = torch.empty((ctx.N, ctx.N), dtype=torch.float64, device=dev)
         sm = torch.empty(1, dtype=torch.float64, device=dev)
-        # queued on the sampler's stream (the current stream): no host wait
-        binding.pns_snapshot_moments(s.ctx, 0, G, sum_m=sm, rb=ctx.rb)
-        grad = (G * (-ctx.beta / sm)).to(ctx.qdtype)
+        # -beta * G / sum_w on the device, queued on the sampler's stream
+        # (the current stream): no host wait
+        binding.pns_logz_grad(s.ctx, 0, ctx.beta, G, sm, rb=ctx.rb)
+        grad = G.to(ctx.qdtype)
         if ctx.owned:
             s.close()
         ctx.sampler = None

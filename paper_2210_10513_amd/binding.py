@@ -44,7 +44,7 @@ EXPORTS = ["pns_opts_default", "pns_create", "pns_run", "pns_read", "pns_read_cu
            "pns_moments_f64", "pns_read_rb_weights", "pns_snapshot_moments_rb", "pns_cont_opts_default",
            "pns_cont_create", "pns_cont_run", "pns_cont_read", "pns_cont_read_log", "pns_cont_read_sums",
            "pns_cont_clear_sums", "pns_cont_stats", "pns_cont_sync", "pns_cont_destroy", "pns_save", "pns_load", "pns_profile",
-           "pns_profile_read", "pns_class_of_chain", "pns_moments_noalloc", "pns_refresh"]
+           "pns_profile_read", "pns_class_of_chain", "pns_moments_noalloc", "pns_refresh", "pns_logz_grad"]
 
 
 class pns_class_profile(ctypes.Structure):
@@ -164,6 +164,7 @@ def _load() -> ctypes.CDLL:
     L.pns_moments_f64.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
     L.pns_read_rb_weights.argtypes = [vp, vp, vp, vp]
     L.pns_snapshot_moments_rb.argtypes = [vp, i32, vp, vp]
+    L.pns_logz_grad.argtypes = [vp, i32, dbl, i32, vp, vp]
     L.pns_cont_opts_default.argtypes = [ctypes.POINTER(pns_cont_opts)]
     L.pns_cont_opts_default.restype = None
     L.pns_cont_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(pns_cont_opts)]
@@ -360,6 +361,12 @@ def pns_snapshot_moments(ctx, problem: int, G, sum_m=None, *, rb: bool = False):
     sm = np.zeros(1, np.float64)
     _check(fn(ctx, problem, _addr(G), sm.ctypes.data))
     return float(sm[0])
+
+
+def pns_logz_grad(ctx, problem: int, beta: float, grad, sum_w, *, rb: bool = False) -> None:
+    """-beta * G / sum_w of one problem's snapshots into device buffers
+    (grad [N][N] FP64, sum_w [1] FP64), queued on the context's stream."""
+    _check(lib.pns_logz_grad(ctx, problem, beta, 1 if rb else 0, _addr(grad), _addr(sum_w)))
 
 
 def pns_read_rb_weights(ctx, log_w=None, snap_w=None, hist_rb=None) -> None:

@@ -146,6 +146,9 @@ hipError_t launch_prepare_rows(int32_t qtype, const void* Q, int32_t N, int32_t 
 hipError_t launch_pt_swap(const int64_t* E, int32_t is_float, double* beta, int32_t* ladder, int32_t groups, int32_t T,
                           uint64_t seed, uint64_t round, int32_t* accepted, hipStream_t st);
 
+// G <- G * (-beta / *sum) on the device (G [n], sum one FP64 in device memory).
+hipError_t launch_moments_to_grad(double* G, int64_t n, double beta, const double* sum, hipStream_t st);
+
 // A single wave that waits `ticks` of the device's wall clock on `st` and
 // exits (a bounded delay between two groups of launches).
 hipError_t launch_hold(uint64_t ticks, hipStream_t st);

@@ -533,6 +533,23 @@ hipError_t launch_moments_prep_f64(const double* w, int64_t K, int64_t kpad, uin
     return hipGetLastError();
 }
 
+// G <- G * (-beta / sum): the weighted second moments to the gradient of
+// log Z, the weight sum read on the device.
+__global__ void moments_to_grad_kernel(double* G, int64_t n, double beta, const double* sum)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double f = -beta / *sum;
+    G[i] = G[i] * f;
+}
+
+hipError_t launch_moments_to_grad(double* G, int64_t n, double beta, const double* sum, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(moments_to_grad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, G, n, beta, sum);
+    return hipGetLastError();
+}
+
 hipError_t launch_moments_unscale(double* G, int64_t n, const unsigned long long* maxbits, hipStream_t st)
 {
     hipLaunchKernelGGL(moments_unscale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, G, n, maxbits);

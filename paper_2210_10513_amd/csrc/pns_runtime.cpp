@@ -2024,6 +2024,19 @@ int pns_snapshot_moments_rb(pns_ctx* ctx, int32_t problem, double* G, double* su
     return snapshot_moments(ctx, problem, true, G, sum_w);
 }
 
+int pns_logz_grad(pns_ctx* ctx, int32_t problem, double beta, int32_t rb, double* grad, double* sum_w)
+{
+    g_error.clear();
+    if (!ctx || !grad || !sum_w) return fail(PNS_EINVAL, "NULL argument");
+    if (!is_device_ptr(grad) || !is_device_ptr(sum_w)) return fail(PNS_EINVAL, "grad and sum_w must be device memory");
+    if (!std::isfinite(beta)) return fail(PNS_EINVAL, "beta must be finite");
+    int rc = snapshot_moments(ctx, problem, rb != 0, grad, sum_w);
+    if (rc) return rc;
+    const int64_t N = ctx->probs[problem].N;
+    HIP_TRY(launch_moments_to_grad(grad, N * N, beta, sum_w, ctx->stream), "gradient");
+    return PNS_OK;
+}
+
 int pns_read_rb_weights(pns_ctx* ctx, double* log_w, double* snap_w, double* hist_rb)
 {
     g_error.clear();

@@ -75,6 +75,35 @@ def test_snapshot_moments_equal_oracle_on_read_back_snapshots():
     assert np.array_equal(G, moments.weighted_moments(X, m).astype(np.float64))
 
 
+def test_logz_grad_is_the_scaled_snapshot_moments():
+    """pns_logz_grad: -beta * G / sum_w of the snapshots on the device, equal
+    bit for bit to the same expression formed from pns_snapshot_moments (and
+    _rb) read back to the host; host buffers are rejected."""
+    import torch
+    from paper_2210_10513_amd import binding as b
+    from paper_2210_10513_amd.binding import Sampler
+    N, beta = 40, 0.3
+    Q = inputs.symmetric_int(N, -20, 20, np.int32, seed=41)
+    s = Sampler(Q, beta, 0, "rf", num_chains=64, seed=5, init="random", snapshot_every=3, snapshot_capacity=16)
+    s.run(60)
+    for rb in (False, True):
+        Gd = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        sd = torch.empty(1, dtype=torch.float64, device="cuda")
+        b.pns_snapshot_moments(s.ctx, 0, Gd, sum_m=sd, rb=rb)
+        ref = Gd.cpu().numpy() * (-beta / sd.cpu().numpy()[0])
+        gd = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        sw = torch.empty(1, dtype=torch.float64, device="cuda")
+        b.pns_logz_grad(s.ctx, 0, beta, gd, sw, rb=rb)
+        torch.cuda.synchronize()
+        assert sw.item() == sd.item()
+        assert np.array_equal(gd.cpu().numpy(), ref)
+        assert np.allclose(ref, ref.T)
+    with pytest.raises(b.PNSError) as ei:
+        b.pns_logz_grad(s.ctx, 0, beta, np.zeros((N, N)), np.zeros(1))
+    assert ei.value.code == b.PNS_EINVAL
+    s.close()
+
+
 def test_snapshot_moments_before_the_ring_fills():
     from paper_2210_10513_amd.binding import Sampler
     Q = inputs.symmetric_int(20, -30, 30, np.int32, seed=5)
