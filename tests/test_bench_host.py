@@ -98,3 +98,29 @@ def test_hardware_queue_default_follows_the_launch_form(monkeypatch):
                        (["bench.py", "--hw-queues=10"], "10")):
         monkeypatch.setattr(sys, "argv", argv)
         assert bench._hw_queues_arg() == want, argv
+
+
+def test_batch_issue_roofline_adds_the_classes_committed_rows():
+    """The batch's VALU issue figure is the sum over launch classes of the
+    committed VALU instructions per chain step times the class's chain steps,
+    over the step time; a class without a row for its current kernel source
+    gives no figure."""
+    rows = [f for f in _rows("valu_issue.txt", 6) if f[0].startswith("batched64_class_")]
+    assert rows
+    classes = []
+    for f in rows[:3]:
+        key = f[0][len("batched64_class_"):]
+        tile, flav, chains, nr = key.split("_")
+        n0, n1 = nr[1:].split("-")
+        classes.append({"tile": tile, "flavour": int(flav[1:]), "chains": int(chains[1:]), "N_min": int(n0),
+                        "N_max": int(n1)})
+    r = bench._batch_issue_roofline(classes, 1000, 0.5)
+    if r is None:  # rows of an older kernel source: nothing to check against
+        return
+    want = sum(bench._valu_per_chain_step(bench._class_key(c), tuple(int(v) for v in c["tile"].split("x")),
+                                          c["flavour"] == 5) * c["chains"] * 1000 for c in classes)
+    assert abs(r["valu_per_step"] - want) <= 1e-9 * want
+    assert abs(r["achieved"] - want / 0.5) <= 1e-9 * want / 0.5
+    assert abs(r["frac"] - r["achieved"] / bench.VALU_ISSUE_PEAK) < 1e-12
+    unknown = dict(classes[0], chains=classes[0]["chains"] + 1)
+    assert bench._batch_issue_roofline(classes + [unknown], 1000, 0.5) is None
