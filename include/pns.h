@@ -217,9 +217,10 @@ int pns_create(pns_ctx** out, const void* Q, int32_t N, double beta, int32_t sub
  * the graph form as parallel graph nodes): one stream per class, up to the
  * process's hardware queues (GPU_MAX_HW_QUEUES, read when HIP starts; at most
  * 16), classes packed longest first when there are more.  The streams start
- * largest workgroups first, and those of one-wave classes 200 us after the
- * others (a one-wave delay kernel on the context's stream), so that
- * workgroups of several waves find whole compute units.
+ * largest workgroups first, and in launches of 4096 steps or more those of
+ * one-wave classes 200 us after the others (a one-wave delay kernel on the
+ * context's stream), so that workgroups of several waves find whole compute
+ * units.
  * Per-chain arrays of bits or fields (pns_read, pns_read_current,
  * pns_read_snapshots) are concatenated, chain c occupying the N of its
  * problem; pns_chain_offsets gives the offsets.  Histograms are not

@@ -636,14 +636,17 @@ struct pns_ctx {
     {
         if (classes.size() == 1) return launch_class(classes[0], steps, stream, orig_time, first, last);
         HIP_TRY(hipEventRecord(fork, stream), "fork record");
-        // The side streams are ordered largest workgroups first; the streams
-        // of one-wave classes start 200 us later, so that the workgroups of
-        // several waves find whole compute units before the one-wave
-        // workgroups fill them (all queues released at once would race).
+        // The side streams are ordered largest workgroups first; in launches
+        // long enough for the order to matter (4096 steps and more, tens of
+        // milliseconds) the streams of one-wave classes start 200 us later,
+        // so that the workgroups of several waves find whole compute units
+        // before the one-wave workgroups fill them (all queues released at
+        // once would race).
+        const bool stagger = steps >= 4096;
         bool held = false;
         for (auto& sd : sides) {
             const bool small = classes[sd.classes.front()].tile.block <= 64;
-            if (small && !held && &sd != &sides.front()) {
+            if (stagger && small && !held && &sd != &sides.front()) {
                 HIP_TRY(launch_hold(hold_ticks, stream), "hold");
                 HIP_TRY(hipEventRecord(fork_small, stream), "fork record");
                 held = true;

@@ -237,6 +237,36 @@ def test_batched_workload_uninstrumented_equals_instrumented():
     assert (si["steps"] == K).all() and (si["anomalies"] == 0).all()
 
 
+def test_staggered_release_gives_the_same_chains():
+    """Launches of 4096 steps or more start the one-wave classes' streams
+    after a short delay kernel: a batch with a one-wave and a two-wave window
+    tile ends exactly where the same steps in two launches of 2048 (no
+    delay) end."""
+    from paper_2210_10513_amd.binding import BatchSampler
+    probs = [{"Q": inputs.symmetric_int(300, -100, 100, np.int16, seed=301, density=0.5), "num_chains": 8,
+              "beta": 0.02, "subset_size": 0},
+             {"Q": inputs.symmetric_int(7000, -100, 100, np.int16, seed=7001, density=0.5), "num_chains": 4,
+              "beta": 0.005, "subset_size": 0}]
+    out = []
+    for parts in ((4096,), (2048, 2048)):
+        s = BatchSampler(probs, "unbiased_sys", L0=100, seed=8, launch="persistent")
+        for k in parts:
+            s.run(k)
+        out.append((s.read_current(), s.read(), s.stats(), sorted({i.block for i in s.info})))
+        s.close()
+    (c1, r1, s1, b1), (c2, r2, s2, b2) = out
+    assert b1 == b2 and b1[0] == 64 and b1[-1] > 64
+    for key in c1:
+        for x, y in zip(c1[key], c2[key]):
+            assert np.array_equal(x, y), key
+    for a, b in zip(r1, r2):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    for key in s1:
+        assert np.array_equal(s1[key], s2[key]), key
+    assert (s1["steps"] == 4096).all() and (s1["anomalies"] == 0).all()
+
+
 def test_class_profiling_counts_and_times_every_class():
     """pns_profile: per launch class, the flips, records and row bytes of its
     chains since profiling started, and a positive kernel time per launch;
